@@ -1,0 +1,236 @@
+/*
+ * dpf.h -- C ABI of libdpf, an MI355X (gfx950) implementation of the hot path of
+ * Differentiable Power-Flow (DPF, arXiv 2603.28203): the batched AC power
+ * mismatch, the bus-type-masked squared-mismatch loss, its gradient with respect
+ * to voltage magnitudes and angles, and the Adam iteration that drives the
+ * mismatch to zero.
+ *
+ * Conventions (all entry points)
+ * -----------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller unless marked
+ *    "host".  The library keeps no pointer after a call returns.
+ *  - All arithmetic is FP64.  Complex arrays are interleaved (re, im) doubles,
+ *    the layout of std::complex<double> / torch.complex128.
+ *  - Per-case per-bus arrays are case-major: element (case c, bus i) is at
+ *    x[c * ld + i] (complex arrays: doubles 2*(c*ld+i) and 2*(c*ld+i)+1), with
+ *    ld >= n_bus.
+ *  - Bus types: 0 = PQ (P and Q specified), 1 = PV (P and |V| specified),
+ *    2 = slack (V specified, angle 0) -- the three bus kinds of Sec. 2.1.
+ *    Exactly one slack per grid (per sub-grid for concatenated grids).
+ *  - Every call is ordered on `stream` (a hipStream_t; NULL = default stream)
+ *    and returns after enqueueing, unless documented as synchronising.
+ *  - Return value: DPF_OK (0) or a negative error code; dpf_last_error()
+ *    returns a text for the calling thread's last error.  On error nothing
+ *    has been enqueued, except for DPF_EHIP, which reports a HIP runtime
+ *    failure (the stream may then hold partial work).
+ *  - Scratch memory: the solve and the gradient evaluation take a caller
+ *    workspace (query its size first); dpf_build_ybus allocates and frees its
+ *    own temporaries.  Nothing else is allocated per call.
+ */
+#ifndef DPF_H
+#define DPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define DPF_OK 0
+#define DPF_EINVAL (-1)      /* bad argument: null pointer, size, index, bus types */
+#define DPF_ECAP (-2)        /* nnz_cap too small */
+#define DPF_EHIP (-3)        /* HIP runtime error (text in dpf_last_error) */
+#define DPF_ENOMEM (-4)      /* workspace too small */
+#define DPF_EUNSUPPORTED (-5) /* combination of options not implemented */
+
+#define DPF_BUS_PQ 0
+#define DPF_BUS_PV 1
+#define DPF_BUS_SLACK 2
+
+/* per-case solve status (an output, not an error) */
+#define DPF_CONVERGED 0
+#define DPF_MAX_ITER 1
+#define DPF_NONFINITE 2
+
+/* learning-rate schedules (Table 2 and Table 3 of the paper use the last two) */
+#define DPF_SCHED_CONSTANT 0
+#define DPF_SCHED_PLATEAU 1  /* reduce-on-plateau, mode min, relative threshold */
+#define DPF_SCHED_STEP 2     /* lr *= factor every `patience` iterations */
+
+/*
+ * A bus admittance matrix in CSR form plus (optionally) the branch list it was
+ * built from.  row_ptr/col_idx/val as produced by dpf_build_ybus: rows sorted
+ * by column, the diagonal always stored.  The branch arrays are only read by
+ * the N-1 outage correction and may be NULL (n_branch = 0) otherwise.
+ * Several independent grids can be concatenated into one block-diagonal CSR
+ * (column indices global); see `sub_offset` of dpf_solve_batch.
+ */
+typedef struct dpf_grid {
+    int32_t n_bus;
+    int32_t nnz;
+    const int32_t *row_ptr; /* [n_bus + 1] */
+    const int32_t *col_idx; /* [nnz] */
+    const double *val;      /* [2 * nnz] complex */
+    int32_t n_branch;
+    const int32_t *from;    /* [n_branch] */
+    const int32_t *to;      /* [n_branch] */
+    const double *r;        /* [n_branch] series resistance (pu) */
+    const double *x;        /* [n_branch] series reactance (pu) */
+    const double *b;        /* [n_branch] total line charging (pu) */
+} dpf_grid_t;
+
+/*
+ * Optimizer settings (Algorithm 1: optimizer + scheduler + tolerance).
+ * Adam as in Kingma & Ba: m <- b1 m + (1-b1) g; s <- b2 s + (1-b2) g^2;
+ * x <- x - lr * (m/(1-b1^t)) / (sqrt(s/(1-b2^t)) + eps), on learnable entries only.
+ * Stop test: the largest absolute masked residual max|dS| (pu) < tol, tested
+ * before each update.  Schedules:
+ *   PLATEAU: after each step, with the iteration's loss L: if L < best*(1-threshold)
+ *            {best = L; bad = 0} else bad++; during cooldown bad is reset;
+ *            if bad > patience {lr = max(lr*factor, min_lr) when the decrease
+ *            exceeds sched_eps; cooldown restarts; bad = 0}.
+ *   STEP:    lr *= factor after every `patience` iterations.
+ */
+typedef struct dpf_opts {
+    double lr;
+    double beta1;
+    double beta2;
+    double eps;
+    double tol;
+    int32_t max_iter;
+    int32_t sched;
+    double factor;
+    int32_t patience;
+    double threshold;
+    int32_t cooldown;
+    double min_lr;
+    double sched_eps;
+} dpf_opts_t;
+
+/* Text of the calling thread's last error ("" if none).  Host string owned by the library. */
+const char *dpf_last_error(void);
+
+/* Library version string (host, static). */
+const char *dpf_version(void);
+
+/*
+ * dpf_build_ybus -- bus admittance matrix Y from pi-model branches (Sec. 2.1,
+ * power-balance equation; the branch model is the standard pi model: series
+ * y = 1/(r + jx), total charging b split b/2 to each end, no transformers):
+ *     Y_ff += y + j b/2,   Y_tt += y + j b/2,   Y_ft += -y,   Y_tf += -y.
+ * Parallel branches are summed (in branch order); every diagonal is stored.
+ *   from, to, r, x, b : device [n_branch]
+ *   row_ptr           : device [n_bus + 1] out
+ *   col_idx, val      : device [nnz_cap], [2*nnz_cap] out; nnz_cap >= n_bus + 2*n_branch
+ *                       always suffices
+ *   nnz_out           : host out; this call SYNCHRONISES `stream` to return it
+ * Errors: DPF_EINVAL for n_bus <= 0, n_branch < 0, a bus index out of range,
+ * from == to, or r = x = 0 (detected on the device); DPF_ECAP if the result
+ * does not fit (nnz_out still receives the needed size).  Temporaries are
+ * allocated with hipMalloc and freed before the call returns.
+ */
+int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                   const double *r, const double *x, const double *b, int32_t nnz_cap,
+                   int32_t *row_ptr, int32_t *col_idx, double *val, int32_t *nnz_out,
+                   void *stream);
+
+/*
+ * dpf_mismatch_grad -- one evaluation of the DPF forward and backward pass for
+ * B cases on one grid (Algorithm 1 forward pass and loss.backward(); the
+ * gradient is the reverse-mode J^T F product of Sec. 5.1, computed by one
+ * transposed-Y product plus elementwise terms):
+ *   dS_i   = V_i conj((Y V)_i) - S_spec,i,           V_i = vm_i e^{j va_i}
+ *   r_i    = [Re dS_i if bus i is PV or PQ] , [Im dS_i if bus i is PQ]
+ *   loss   = (1/m) sum r^2, m = n_pv + 2 n_pq;  max_mis = max |r|
+ *   g_vm   = d loss / d vm  (zero except at PQ buses)
+ *   g_va   = d loss / d va  (zero at the slack)
+ * Arguments:
+ *   g        : grid (host struct, device arrays); one grid, B cases
+ *   B, ld    : cases (1..65535) and leading dimension of vm, va, dS, g_vm, g_va (ld >= n_bus)
+ *   bus_type : device int8 [n_bus], shared by all cases
+ *   s_spec   : device complex, [B][s_ld] or shared [n_bus] when s_ld == 0
+ *   outage   : device int32 [B] branch index removed in case c (-1: none), or NULL.
+ *              The branch's whole pi-model admittance is subtracted as a rank-2
+ *              correction; requires g->n_branch > 0 and branch arrays.
+ *   vm, va   : device [B][ld]
+ *   dS       : device complex [B][ld] out, nullable
+ *   loss, max_mis : device [B] out
+ *   g_vm, g_va    : device [B][ld] out, nullable (both or neither)
+ *   workspace     : device, >= dpf_mismatch_grad_workspace_bytes(n_bus, B) bytes
+ * Results are deterministic (fixed reduction order).  Errors: DPF_EINVAL,
+ * DPF_ENOMEM, DPF_EHIP.  Outage indices are not range-checked on the host:
+ * an index outside [0, n_branch) is treated as "no outage" by the kernels.
+ */
+int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus_type,
+                      const double *s_spec, int32_t s_ld, const int32_t *outage,
+                      const double *vm, const double *va, double *dS, double *loss,
+                      double *max_mis, double *g_vm, double *g_va, void *workspace,
+                      size_t ws_bytes, void *stream);
+
+size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B);
+
+/*
+ * dpf_solve_batch -- the DPF iteration (Algorithm 1 with Adam) run to
+ * convergence for many independent problems in ONE kernel launch.
+ *
+ * Work items: B cases x n_sub sub-grids.  Item (c, s) solves sub-grid s of case
+ * c: buses [sub_offset[s], sub_offset[s+1]) of the (block-diagonal) grid `g`.
+ * With sub_offset == NULL there is one sub-grid, [0, n_bus).  Every item keeps
+ * its own Adam moments, step count, learning-rate schedule and stop test, so a
+ * batch equals B*n_sub separate solves (Sec. 4.2 batches problems; here they
+ * do not share a loss).  An item stops when max|dS| < tol (status 0), when its
+ * iteration count reaches max_iter (status 1), or when its mismatch becomes
+ * non-finite (status 2); a stopped item leaves the kernel while others go on.
+ *
+ *   g             : grid
+ *   n_sub, sub_offset, sub_offset_dev : sub-grid bus offsets [n_sub + 1], the
+ *                   same values on the host (sizes, kernel choice) and on the
+ *                   device (read by the kernel); both NULL for one sub-grid
+ *                   [0, n_bus) with n_sub = 1.  Offsets must start at 0, end at
+ *                   n_bus and not decrease; every CSR row of a sub-grid must
+ *                   only reference columns of the same sub-grid (entries that
+ *                   do not are ignored).  Items start in the order
+ *                   (sub-grid major, case minor): list large sub-grids first.
+ *   B, ld         : cases; leading dimension of per-case arrays
+ *   bus_type      : device int8 [n_bus] (one slack per sub-grid)
+ *   s_spec, s_ld  : as in dpf_mismatch_grad
+ *   outage        : device int32 [B] or NULL (requires n_sub == 1)
+ *   vm, va        : device [B][ld] in: start point (flat or warm), out: result
+ *                   (the voltages of the last stop test).  Entries that are not
+ *                   learnable (|V| at PV/slack, angle at the slack) are unchanged.
+ *   adam_state    : device [4][B][ld] in/out (m_vm, m_va, s_vm, s_va) or NULL
+ *                   (fresh zero moments, discarded at the end)
+ *   sched_state   : device [B*n_sub][6] in/out, per item: step count t, current
+ *                   lr, best plateau loss, bad + 2^20 * cooldown counters, b1^t,
+ *                   b2^t; or NULL (t = 0, lr = opts->lr, fresh schedule).  A fresh
+ *                   state is {0, lr, +inf, 0, 1, 1}.  Passing the state (and
+ *                   adam_state) of a previous call continues the same iteration
+ *                   bit for bit.
+ *   opts          : host
+ *   iters, status : device int32 [B*n_sub] out (index c*n_sub + s); iters = number
+ *                   of Adam updates applied in this call
+ *   max_mis, loss : device double [B*n_sub] out, at the returned voltages
+ *   workspace     : device, >= dpf_solve_workspace_bytes(...) bytes
+ * Errors: DPF_EINVAL (sizes, pointers, opts out of range, a sub-grid larger than
+ * the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
+ */
+int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
+                    const int32_t *sub_offset_dev, int32_t B,
+                    int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
+                    const int32_t *outage, double *vm, double *va, double *adam_state,
+                    double *sched_state, const dpf_opts_t *opts, int32_t *iters,
+                    int32_t *status, double *max_mis, double *loss, void *workspace,
+                    size_t ws_bytes, void *stream);
+
+size_t dpf_solve_workspace_bytes(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset,
+                                 int32_t B, int32_t ld);
+
+/* Largest sub-grid (buses) one solve item can hold on this device. */
+int32_t dpf_solve_max_sub_buses(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DPF_H */

@@ -1,0 +1,291 @@
+"""Python binding of libdpf (include/dpf.h): argument marshalling only.
+
+Every numerical step runs in the HIP kernels of libdpf.so; torch provides the
+device memory and the current stream.  If the library is missing the import
+fails loudly -- there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdpf.so")
+
+DPF_OK, DPF_EINVAL, DPF_ECAP, DPF_EHIP, DPF_ENOMEM, DPF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
+CONVERGED, MAX_ITER, NONFINITE = 0, 1, 2
+SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
+PQ, PV, SLACK = 0, 1, 2
+
+
+class DPFError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"libdpf error {code}: {msg}")
+        self.code = code
+
+
+_P = ctypes.c_void_p
+_i32 = ctypes.c_int32
+_f64 = ctypes.c_double
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("n_bus", _i32), ("nnz", _i32), ("row_ptr", _P), ("col_idx", _P), ("val", _P),
+                ("n_branch", _i32), ("from_", _P), ("to", _P), ("r", _P), ("x", _P), ("b", _P)]
+
+
+class _Opts(ctypes.Structure):
+    _fields_ = [("lr", _f64), ("beta1", _f64), ("beta2", _f64), ("eps", _f64), ("tol", _f64),
+                ("max_iter", _i32), ("sched", _i32), ("factor", _f64), ("patience", _i32),
+                ("threshold", _f64), ("cooldown", _i32), ("min_lr", _f64), ("sched_eps", _f64)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libdpf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2603_28203_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        L.dpf_last_error.restype = ctypes.c_char_p
+        L.dpf_version.restype = ctypes.c_char_p
+        L.dpf_build_ybus.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P]
+        L.dpf_build_ybus.restype = ctypes.c_int
+        L.dpf_mismatch_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P,
+                                        _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+        L.dpf_mismatch_grad.restype = ctypes.c_int
+        L.dpf_mismatch_grad_workspace_bytes.argtypes = [_i32, _i32]
+        L.dpf_mismatch_grad_workspace_bytes.restype = ctypes.c_size_t
+        L.dpf_solve_batch.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _P, _i32, _i32, _P, _P, _i32, _P,
+                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), _P, _P, _P, _P, _P,
+                                      ctypes.c_size_t, _P]
+        L.dpf_solve_batch.restype = ctypes.c_int
+        L.dpf_solve_workspace_bytes.argtypes = [_i32, _i32, _P, _i32, _i32]
+        L.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
+        L.dpf_solve_max_sub_buses.restype = _i32
+        _lib = L
+    return _lib
+
+
+def _check(rc: int):
+    if rc != DPF_OK:
+        raise DPFError(rc, lib().dpf_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, device):
+    t = torch.as_tensor(t)
+    return t.to(device=device, dtype=dtype).contiguous()
+
+
+@dataclass
+class DeviceGrid:
+    """Y-bus CSR plus branch list, resident on the GPU."""
+    n_bus: int
+    nnz: int
+    row_ptr: torch.Tensor
+    col_idx: torch.Tensor
+    val: torch.Tensor  # complex128
+    f: torch.Tensor | None = None
+    t: torch.Tensor | None = None
+    r: torch.Tensor | None = None
+    x: torch.Tensor | None = None
+    b: torch.Tensor | None = None
+    _c: _Grid | None = field(default=None, repr=False)
+
+    @property
+    def n_branch(self) -> int:
+        return 0 if self.f is None else int(self.f.numel())
+
+    def c(self) -> _Grid:
+        if self._c is None:
+            nb = self.n_branch
+            self._c = _Grid(self.n_bus, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val), nb,
+                            _ptr(self.f) if nb else None, _ptr(self.t) if nb else None,
+                            _ptr(self.r) if nb else None, _ptr(self.x) if nb else None,
+                            _ptr(self.b) if nb else None)
+        return self._c
+
+
+def build_ybus(n_bus: int, f, t, r, x, b, device="cuda") -> DeviceGrid:
+    """dpf_build_ybus on device copies of the branch arrays (synchronises)."""
+    f, t = _dev(f, torch.int32, device), _dev(t, torch.int32, device)
+    r, x, b = (_dev(v, torch.float64, device) for v in (r, x, b))
+    nbr = int(f.numel())
+    cap = n_bus + 2 * nbr
+    row_ptr = torch.empty(n_bus + 1, dtype=torch.int32, device=device)
+    col = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
+    val = torch.empty(max(cap, 1), dtype=torch.complex128, device=device)
+    nnz = ctypes.c_int32(0)
+    _check(lib().dpf_build_ybus(n_bus, nbr, _ptr(f), _ptr(t), _ptr(r), _ptr(x), _ptr(b), cap, _ptr(row_ptr),
+                                _ptr(col), _ptr(val), ctypes.byref(nnz), _stream()))
+    k = nnz.value
+    return DeviceGrid(n_bus, k, row_ptr, col[:k].clone(), val[:k].clone(), f, t, r, x, b)
+
+
+def mismatch_grad(grid: DeviceGrid, bus_type, s_spec, vm, va, outage=None, want_dS=True, want_grad=True):
+    """One forward + fused-adjoint evaluation for B cases (vm, va: [B, n] float64 on the GPU).
+
+    Returns dict(dS [B,n] complex128 | None, loss [B], max_mis [B], g_vm, g_va [B,n] | None)."""
+    dev = vm.device
+    B, ld = vm.shape
+    bt = _dev(bus_type, torch.int8, dev)
+    s = _dev(s_spec, torch.complex128, dev)
+    s_ld = 0 if s.dim() == 1 else s.shape[1]
+    vm = vm.contiguous()
+    va = va.contiguous()
+    out = _dev(outage, torch.int32, dev) if outage is not None else None
+    dS = torch.empty((B, ld), dtype=torch.complex128, device=dev) if want_dS else None
+    loss = torch.empty(B, dtype=torch.float64, device=dev)
+    mx = torch.empty(B, dtype=torch.float64, device=dev)
+    gv = torch.empty((B, ld), dtype=torch.float64, device=dev) if want_grad else None
+    ga = torch.empty((B, ld), dtype=torch.float64, device=dev) if want_grad else None
+    wsb = lib().dpf_mismatch_grad_workspace_bytes(grid.n_bus, B)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    g = grid.c()
+    _check(lib().dpf_mismatch_grad(ctypes.byref(g), B, ld, _ptr(bt), _ptr(s), s_ld, _ptr(out), _ptr(vm), _ptr(va),
+                                   _ptr(dS), _ptr(loss), _ptr(mx), _ptr(gv), _ptr(ga), _ptr(ws), wsb, _stream()))
+    return {"dS": dS, "loss": loss, "max_mis": mx, "g_vm": gv, "g_va": ga}
+
+
+@dataclass
+class Options:
+    """Optimizer settings of Algorithm 1 (Adam + schedule + tolerance)."""
+    lr: float = 1e-2
+    beta1: float = 0.9
+    beta2: float = 0.999
+    eps: float = 1e-8
+    tol: float = 1e-6
+    max_iter: int = 1000
+    sched: int = SCHED_CONSTANT
+    factor: float = 0.1
+    patience: int = 10
+    threshold: float = 1e-4
+    cooldown: int = 0
+    min_lr: float = 0.0
+    sched_eps: float = 1e-8
+
+    def c(self) -> _Opts:
+        return _Opts(self.lr, self.beta1, self.beta2, self.eps, self.tol, int(self.max_iter), int(self.sched),
+                     self.factor, int(self.patience), self.threshold, int(self.cooldown), self.min_lr,
+                     self.sched_eps)
+
+
+class SolveWorkspace:
+    """Reusable device workspace for dpf_solve_batch (grown on demand)."""
+
+    def __init__(self):
+        self.buf = None
+
+    def get(self, nbytes: int, device) -> torch.Tensor:
+        if self.buf is None or self.buf.numel() < nbytes or self.buf.device != torch.device(device):
+            self.buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        return self.buf
+
+
+_default_ws = SolveWorkspace()
+
+
+def solve_workspace_bytes(n_bus, B, ld=None, sub_offset=None) -> int:
+    ld = n_bus if ld is None else ld
+    if sub_offset is None:
+        return int(lib().dpf_solve_workspace_bytes(n_bus, 1, None, B, ld))
+    so = (ctypes.c_int32 * len(sub_offset))(*[int(v) for v in sub_offset])
+    return int(lib().dpf_solve_workspace_bytes(n_bus, len(sub_offset) - 1, so, B, ld))
+
+
+def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = None, outage=None,
+          sub_offset=None, adam_state=None, sched_state=None, workspace: SolveWorkspace | None = None,
+          outputs=None):
+    """dpf_solve_batch: Adam-DPF to convergence for B cases x n_sub sub-grids.
+
+    vm, va ([B, ld] float64, GPU) are updated in place.  Returns dict with
+    iters, status, max_mis, loss ([B * n_sub], index c * n_sub + s)."""
+    opts = opts or Options()
+    dev = vm.device
+    B, ld = vm.shape
+    assert vm.is_contiguous() and va.is_contiguous() and vm.dtype == torch.float64
+    bt = bus_type if (torch.is_tensor(bus_type) and bus_type.dtype == torch.int8 and bus_type.device == dev) \
+        else _dev(bus_type, torch.int8, dev)
+    s = s_spec if (torch.is_tensor(s_spec) and s_spec.dtype == torch.complex128 and s_spec.device == dev
+                   and s_spec.is_contiguous()) else _dev(s_spec, torch.complex128, dev)
+    s_ld = 0 if s.dim() == 1 else s.shape[1]
+    out = None if outage is None else (outage if (torch.is_tensor(outage) and outage.dtype == torch.int32
+                                                  and outage.device == dev) else _dev(outage, torch.int32, dev))
+    if sub_offset is None:
+        n_sub, so_h, so_d = 1, None, None
+    else:
+        so_list = [int(v) for v in (sub_offset.tolist() if torch.is_tensor(sub_offset) else sub_offset)]
+        n_sub = len(so_list) - 1
+        so_h = (ctypes.c_int32 * len(so_list))(*so_list)
+        so_d = torch.tensor(so_list, dtype=torch.int32, device=dev)
+    items = B * n_sub
+    if outputs is None:
+        outputs = {"iters": torch.empty(items, dtype=torch.int32, device=dev),
+                   "status": torch.empty(items, dtype=torch.int32, device=dev),
+                   "max_mis": torch.empty(items, dtype=torch.float64, device=dev),
+                   "loss": torch.empty(items, dtype=torch.float64, device=dev)}
+    wsb = int(lib().dpf_solve_workspace_bytes(grid.n_bus, n_sub, so_h, B, ld))
+    ws = (workspace or _default_ws).get(wsb, dev)
+    g = grid.c()
+    o = opts.c()
+    _check(lib().dpf_solve_batch(ctypes.byref(g), n_sub, so_h, _ptr(so_d), B, ld, _ptr(bt), _ptr(s), s_ld,
+                                 _ptr(out), _ptr(vm), _ptr(va), _ptr(adam_state), _ptr(sched_state),
+                                 ctypes.byref(o), _ptr(outputs["iters"]), _ptr(outputs["status"]),
+                                 _ptr(outputs["max_mis"]), _ptr(outputs["loss"]), _ptr(ws), ws.numel(),
+                                 _stream()))
+    if so_d is not None:
+        outputs["_keep"] = so_d  # keep the device offsets alive until the stream has used them
+    return outputs
+
+
+SCHED_WORDS = 6
+
+
+def fresh_sched_state(items: int, lr: float, device="cuda") -> torch.Tensor:
+    """Per-item schedule state {t, lr, best, counters, b1^t, b2^t} of a fresh solve."""
+    st = torch.zeros((items, SCHED_WORDS), dtype=torch.float64, device=device)
+    st[:, 1] = lr
+    st[:, 2] = float("inf")
+    st[:, 4] = 1.0
+    st[:, 5] = 1.0
+    return st
+
+
+def max_sub_buses() -> int:
+    return int(lib().dpf_solve_max_sub_buses())
+
+
+class DPFLoss(torch.autograd.Function):
+    """Per-case DPF loss whose backward is the fused adjoint of libdpf.
+
+    forward(vm, va, grid, bus_type, s_spec, outage) -> loss [B];
+    backward returns grad_out[c] * d loss_c / d(vm, va) (zeros at fixed
+    coordinates), computed in the same kernel pass as the loss."""
+
+    @staticmethod
+    def forward(ctx, vm, va, grid, bus_type, s_spec, outage=None):
+        r = mismatch_grad(grid, bus_type, s_spec, vm.detach(), va.detach(), outage=outage, want_dS=False,
+                          want_grad=True)
+        ctx.save_for_backward(r["g_vm"], r["g_va"])
+        ctx.mark_non_differentiable(r["max_mis"])
+        return r["loss"], r["max_mis"]
+
+    @staticmethod
+    def backward(ctx, grad_loss, grad_mx):
+        gv, ga = ctx.saved_tensors
+        return grad_loss[:, None] * gv, grad_loss[:, None] * ga, None, None, None, None

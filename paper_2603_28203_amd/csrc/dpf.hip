@@ -1,0 +1,356 @@
+// libdpf: C ABI entry points (include/dpf.h) and the host side of the kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "../../include/dpf.h"
+#include "common.hpp"
+#include "eval.hpp"
+#include "solve.hpp"
+#include "ybus.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define DPF_HIP(call)                                                                      \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            return fail(DPF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));     \
+    } while (0)
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Per-device limits, queried once per device.
+struct DeviceInfo {
+    int lds_per_block = 0;  // bytes
+    int n_cu = 0;
+    bool ok = false;
+};
+std::mutex g_dev_mu;
+DeviceInfo g_dev[64];
+
+int device_info(DeviceInfo &out) {
+    int dev = 0;
+    DPF_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) return fail(DPF_EHIP, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_dev_mu);
+    if (!g_dev[dev].ok) {
+        int lds = 0, ncu = 0;
+        DPF_HIP(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev));
+        DPF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+        g_dev[dev].lds_per_block = lds;
+        g_dev[dev].n_cu = ncu;
+        g_dev[dev].ok = true;
+    }
+    out = g_dev[dev];
+    return DPF_OK;
+}
+
+// Bytes of static LDS the solve kernels use besides the dynamic exchange array.
+constexpr int kSolveStaticLds = 2 * (1024 / dpf::kWave) * 8 + 256;
+
+int32_t max_sub_buses_for(const DeviceInfo &d) {
+    int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
+    return std::min<int32_t>(cap, 10 * 1024);
+}
+
+// ---------------------------------------------------------------- solve variants
+
+using KernelFn = void (*)(dpf::SolveArgs);
+
+struct Variant {
+    int nt;
+    int k;
+    int mode;
+    KernelFn fn;
+};
+
+template <int NT, int K>
+Variant make_variant() {
+    return Variant{NT, K, dpf::kReg, dpf::team_solve_kernel<NT, K, dpf::kReg>};
+}
+template <int NT>
+Variant make_stream_variant() {
+    return Variant{NT, 1 << 20, dpf::kGlobal, dpf::team_solve_stream_kernel<NT>};
+}
+
+// Register-resident variants up to 2048 buses per item, streaming above.
+const Variant *pick_variant(int32_t n_max) {
+    static const Variant table[] = {
+        make_variant<64, 1>(),  make_variant<128, 1>(), make_variant<256, 1>(), make_variant<256, 2>(),
+        make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<1024>(),
+    };
+    for (const Variant &v : table)
+        if ((int64_t)n_max <= (int64_t)v.nt * v.k) return &v;
+    return nullptr;
+}
+
+bool valid_opts(const dpf_opts_t *o) {
+    if (!o) return false;
+    if (!(o->lr >= 0.0) || !(o->beta1 >= 0.0 && o->beta1 < 1.0) || !(o->beta2 >= 0.0 && o->beta2 < 1.0))
+        return false;
+    if (!(o->eps >= 0.0) || !(o->tol >= 0.0) || o->max_iter < 0) return false;
+    if (o->sched < DPF_SCHED_CONSTANT || o->sched > DPF_SCHED_STEP) return false;
+    if (o->sched != DPF_SCHED_CONSTANT && (!(o->factor >= 0.0) || o->patience < 0 || o->cooldown < 0))
+        return false;
+    return true;
+}
+
+bool valid_grid(const dpf_grid_t *g) {
+    return g && g->n_bus > 0 && g->nnz >= 0 && g->row_ptr && g->col_idx && g->val;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dpf_last_error(void) { return g_err.c_str(); }
+
+const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64)"; }
+
+int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
+                   const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
+                   double *val, int32_t *nnz_out, void *stream) {
+    g_err.clear();
+    if (n_bus <= 0 || n_branch < 0) return fail(DPF_EINVAL, "n_bus must be > 0 and n_branch >= 0");
+    if (n_branch > 0 && (!from || !to || !r || !x || !b)) return fail(DPF_EINVAL, "null branch array");
+    if (!row_ptr || !nnz_out || (nnz_cap > 0 && (!col_idx || !val)) || nnz_cap < 0)
+        return fail(DPF_EINVAL, "null output array or negative nnz_cap");
+    if ((int64_t)n_bus + 2 * (int64_t)n_branch > INT32_MAX) return fail(DPF_EINVAL, "grid too large");
+    hipStream_t st = (hipStream_t)stream;
+    const int32_t nslot = n_bus + 2 * n_branch;
+    // temporaries: deg[n+1] fill[n+1] soff[n+1] ucount[n+1] err[1], slots, diag
+    size_t bytes_i = align_up(sizeof(int32_t) * (4 * (size_t)(n_bus + 1) + 64), 256);
+    size_t bytes_s = align_up(sizeof(int2) * (size_t)nslot, 256);
+    size_t bytes_d = align_up(sizeof(double2) * (size_t)n_bus, 256);
+    char *tmp = nullptr;
+    DPF_HIP(hipStreamSynchronize(st));
+    DPF_HIP(hipMalloc((void **)&tmp, bytes_i + bytes_s + bytes_d));
+    int32_t *deg = (int32_t *)tmp;
+    int32_t *fill = deg + (n_bus + 1);
+    int32_t *soff = fill + (n_bus + 1);
+    int32_t *ucount = soff + (n_bus + 1);
+    int32_t *err = ucount + (n_bus + 1);
+    int2 *slot = (int2 *)(tmp + bytes_i);
+    double2 *diag = (double2 *)(tmp + bytes_i + bytes_s);
+    int rc = DPF_OK;
+    int32_t herr = 0, nnz = 0;
+    auto cleanup = [&]() {
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(tmp);
+    };
+    do {
+        hipError_t e = hipMemsetAsync(tmp, 0, bytes_i, st);
+        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e)); break; }
+        const int bs = 256;
+        int gb = std::max(1, (n_branch + bs - 1) / bs);
+        if (n_branch > 0)
+            hipLaunchKernelGGL(dpf::ybus_count_kernel, dim3(gb), dim3(bs), 0, st, n_bus, n_branch, from, to, r, x,
+                               deg, err);
+        e = hipMemcpyAsync(&herr, err, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("branch validation: ") + hipGetErrorString(e)); break; }
+        if (herr) { rc = fail(DPF_EINVAL, "branch with bus index out of range, from == to, or r = x = 0"); break; }
+        hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_bus, deg, 1, soff);
+        int gmax = std::max(1, (std::max(n_bus, n_branch) + bs - 1) / bs);
+        hipLaunchKernelGGL(dpf::ybus_scatter_kernel, dim3(gmax), dim3(bs), 0, st, n_bus, n_branch, from, to, soff,
+                           fill, slot);
+        int gn = (n_bus + bs - 1) / bs;
+        hipLaunchKernelGGL(dpf::ybus_row_order_kernel, dim3(gn), dim3(bs), 0, st, n_bus, soff, slot, r, x, b, diag,
+                           ucount);
+        hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_bus, ucount, 0, row_ptr);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&nnz, row_ptr + n_bus, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("ybus pattern: ") + hipGetErrorString(e)); break; }
+        *nnz_out = nnz;
+        if (nnz > nnz_cap) { rc = fail(DPF_ECAP, "nnz_cap too small"); break; }
+        hipLaunchKernelGGL(dpf::ybus_emit_kernel, dim3(gn), dim3(bs), 0, st, n_bus, soff, slot, r, x, diag, row_ptr,
+                           nnz_cap, col_idx, (double2 *)val);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("ybus values: ") + hipGetErrorString(e)); break; }
+    } while (0);
+    cleanup();
+    return rc;
+}
+
+size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B) {
+    if (n_bus <= 0 || B <= 0) return 0;
+    size_t per = sizeof(double2) * (size_t)n_bus * (size_t)B;
+    int32_t nblk = (n_bus + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
+    return 256 + 3 * align_up(per, 256) + align_up(sizeof(double2) * (size_t)B * nblk, 256);
+}
+
+int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec,
+                      int32_t s_ld, const int32_t *outage, const double *vm, const double *va, double *dS,
+                      double *loss, double *max_mis, double *g_vm, double *g_va, void *workspace, size_t ws_bytes,
+                      void *stream) {
+    g_err.clear();
+    if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
+    if (B <= 0 || ld < g->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
+    if (B > 65535) return fail(DPF_EINVAL, "B must be <= 65535 for one evaluation call");
+    if (s_ld != 0 && s_ld < g->n_bus) return fail(DPF_EINVAL, "s_ld must be 0 or >= n_bus");
+    if (!bus_type || !s_spec || !vm || !va || !loss || !max_mis) return fail(DPF_EINVAL, "null argument");
+    if ((g_vm == nullptr) != (g_va == nullptr)) return fail(DPF_EINVAL, "g_vm and g_va: both or neither");
+    if (outage && (g->n_branch <= 0 || !g->from || !g->to || !g->r || !g->x || !g->b))
+        return fail(DPF_EINVAL, "outage needs the grid's branch arrays");
+    const int32_t n = g->n_bus;
+    size_t need = dpf_mismatch_grad_workspace_bytes(n, B);
+    if (!workspace || ws_bytes < need) return fail(DPF_ENOMEM, "workspace too small");
+    if ((int64_t)B * ld > ((int64_t)1 << 40)) return fail(DPF_EINVAL, "batch too large");
+    hipStream_t st = (hipStream_t)stream;
+    size_t per = align_up(sizeof(double2) * (size_t)n * (size_t)B, 256);
+    char *ws = (char *)workspace;
+    double *m_res = (double *)ws;
+    double2 *Vw = (double2 *)(ws + 256);
+    double2 *ww = (double2 *)(ws + 256 + per);
+    double2 *aI = (double2 *)(ws + 256 + 2 * per);
+    double2 *part = (double2 *)(ws + 256 + 3 * per);
+    const int32_t nblk = (n + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
+    dpf::OutageView ov{outage, g->from, g->to, g->r, g->x, g->b, g->n_branch};
+    hipLaunchKernelGGL(dpf::residual_count_kernel, dim3(1), dim3(1024), 0, st, n, bus_type, m_res);
+    hipLaunchKernelGGL(dpf::polar_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, (int64_t)ld, vm, va, Vw);
+    hipLaunchKernelGGL(dpf::forward_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr, g->col_idx,
+                       (const double2 *)g->val, bus_type, (const double2 *)s_spec, (int64_t)s_ld, ov, Vw, m_res,
+                       (int64_t)ld, (double2 *)dS, ww, aI, part);
+    if (g_vm)
+        hipLaunchKernelGGL(dpf::adjoint_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr,
+                           g->col_idx, (const double2 *)g->val, bus_type, ov, Vw, vm, (int64_t)ld, ww, aI, g_vm,
+                           g_va);
+    hipLaunchKernelGGL(dpf::finalize_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, nblk, part, m_res, loss,
+                       max_mis);
+    DPF_HIP(hipGetLastError());
+    return DPF_OK;
+}
+
+int32_t dpf_solve_max_sub_buses(void) {
+    DeviceInfo d;
+    if (device_info(d) != DPF_OK) return 0;
+    return max_sub_buses_for(d);
+}
+
+static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset) {
+    if (!sub_offset) return n_bus;
+    int32_t m = 0;
+    for (int32_t s = 0; s < n_sub; ++s) m = std::max(m, sub_offset[s + 1] - sub_offset[s]);
+    return m;
+}
+
+size_t dpf_solve_workspace_bytes(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset, int32_t B, int32_t ld) {
+    if (n_bus <= 0 || B <= 0 || ld < n_bus) return 0;
+    const Variant *v = pick_variant(max_sub_size(n_bus, sub_offset ? n_sub : 1, sub_offset));
+    if (!v || v->mode == dpf::kReg) return 256;
+    // moments [4][B][ld] + scratch [3][B][ld] complex
+    return 256 + align_up(sizeof(double) * 4 * (size_t)B * ld, 256) + align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
+}
+
+int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
+                    int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
+                    const int32_t *outage, double *vm, double *va, double *adam_state, double *sched_state,
+                    const dpf_opts_t *opts, int32_t *iters, int32_t *status, double *max_mis, double *loss,
+                    void *workspace, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
+    if (B <= 0 || ld < g->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
+    if (s_ld != 0 && s_ld < g->n_bus) return fail(DPF_EINVAL, "s_ld must be 0 or >= n_bus");
+    if (!bus_type || !s_spec || !vm || !va || !iters || !status || !max_mis || !loss)
+        return fail(DPF_EINVAL, "null argument");
+    if (!valid_opts(opts)) return fail(DPF_EINVAL, "invalid optimizer options");
+    if ((sub_offset == nullptr) != (sub_offset_dev == nullptr))
+        return fail(DPF_EINVAL, "sub_offset and sub_offset_dev: both or neither");
+    if (!sub_offset) n_sub = 1;
+    if (n_sub <= 0) return fail(DPF_EINVAL, "n_sub must be > 0");
+    if (sub_offset) {
+        if (sub_offset[0] != 0 || sub_offset[n_sub] != g->n_bus)
+            return fail(DPF_EINVAL, "sub_offset must start at 0 and end at n_bus");
+        for (int32_t s = 0; s < n_sub; ++s)
+            if (sub_offset[s + 1] < sub_offset[s]) return fail(DPF_EINVAL, "sub_offset must not decrease");
+    }
+    if (outage && n_sub != 1) return fail(DPF_EUNSUPPORTED, "outages need a single sub-grid");
+    if (outage && (g->n_branch <= 0 || !g->from || !g->to || !g->r || !g->x || !g->b))
+        return fail(DPF_EINVAL, "outage needs the grid's branch arrays");
+    if ((int64_t)B * n_sub > INT32_MAX / 2) return fail(DPF_EINVAL, "too many work items");
+    DeviceInfo dev;
+    int rc = device_info(dev);
+    if (rc != DPF_OK) return rc;
+    const int32_t n_max = max_sub_size(g->n_bus, n_sub, sub_offset);
+    const int32_t cap = max_sub_buses_for(dev);
+    if (n_max > cap) return fail(DPF_EUNSUPPORTED, "a sub-grid has more buses than one solve item holds (" +
+                                                        std::to_string(cap) + ")");
+    const Variant *v = pick_variant(n_max);
+    if (!v) return fail(DPF_EUNSUPPORTED, "sub-grid too large");
+    size_t need = dpf_solve_workspace_bytes(g->n_bus, n_sub, sub_offset, B, ld);
+    if (!workspace || ws_bytes < need) return fail(DPF_ENOMEM, "workspace too small");
+    hipStream_t st = (hipStream_t)stream;
+
+    dpf::SolveArgs a{};
+    a.rp = g->row_ptr;
+    a.ci = g->col_idx;
+    a.yv = (const double2 *)g->val;
+    a.bt = bus_type;
+    a.s_spec = (const double2 *)s_spec;
+    a.s_ld = s_ld;
+    a.ov = dpf::OutageView{outage, g->from, g->to, g->r, g->x, g->b, g->n_branch};
+    a.vm = vm;
+    a.va = va;
+    a.ld = ld;
+    a.st_stride = (int64_t)B * ld;
+    char *ws = (char *)workspace;
+    if (v->mode == dpf::kGlobal) {
+        double *mom = (double *)(ws + 256);
+        a.scratch = (double2 *)(ws + 256 + align_up(sizeof(double) * 4 * (size_t)B * ld, 256));
+        a.st = adam_state ? adam_state : mom;
+    } else {
+        a.scratch = nullptr;
+        a.st = adam_state;  // may be null: fresh moments kept in registers only
+    }
+    a.st_fresh = adam_state ? 0 : 1;
+    a.sched = sched_state;
+    a.sub_off = sub_offset_dev;
+    a.n_bus = g->n_bus;
+    a.n_sub = n_sub;
+    a.B = B;
+    a.lr = opts->lr;
+    a.b1 = opts->beta1;
+    a.b2 = opts->beta2;
+    a.eps = opts->eps;
+    a.tol = opts->tol;
+    a.max_iter = opts->max_iter;
+    a.sch = opts->sched;
+    a.factor = opts->factor;
+    a.patience = opts->patience;
+    a.threshold = opts->threshold;
+    a.cooldown = opts->cooldown;
+    a.min_lr = opts->min_lr;
+    a.sched_eps = opts->sched_eps;
+    a.iters = iters;
+    a.status = status;
+    a.mu_out = max_mis;
+    a.loss_out = loss;
+
+    // dynamic LDS: two exchange arrays when they fit, else one
+    const int32_t lds_entries_max = (dev.lds_per_block - kSolveStaticLds) / 16;
+    int32_t entries = 2 * n_max <= lds_entries_max ? 2 * n_max : n_max;
+    entries = std::max<int32_t>(entries, 1);
+    a.lds_cap = entries;
+    const size_t lds_bytes = (size_t)entries * 16;
+    DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+    const int32_t items = B * n_sub;
+    hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
+    DPF_HIP(hipGetLastError());
+    return DPF_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,684 @@
+// Persistent DPF solve: one workgroup owns one work item (a case of a sub-grid)
+// and runs the whole Adam iteration of Algorithm 1 for it inside the kernel.
+//
+// Why this shape on gfx950: a solve needs two grid-wide exchanges per
+// iteration (the adjoint product needs every neighbour's residual seed, the next
+// forward product needs every neighbour's updated voltage).  Keeping one item
+// inside one workgroup turns both into LDS traffic plus workgroup barriers: the
+// complex exchange vector X (16 B per bus) lives in LDS, so a sub-grid of up to
+// ~10k buses fits in the 160 KB of one CU.  Converged items simply leave the
+// kernel; the hardware dispatcher then starts the next item on that CU.
+//
+// Per iteration, for every bus i owned by the thread (i = lo + tid + k*NT):
+//   A: I_i = sum_j Y_ij X_j (X = V) [- outage block];  dS_i = V_i conj(I_i) - S_i
+//      r^P = [PV|PQ] Re dS, r^Q = [PQ] Im dS; loss and max|r| (workgroup reduce)
+//      a_i = (2/m)(r^P + j r^Q); w_i = a_i conj(V_i); keep a_i I_i
+//   stop test on max|r| (before the update, as the loop's convergence check)
+//   B: h_i = sum_j Y_ij X_j (X = w; Y^T = Y) [- outage block]
+//      G_i = a_i I_i + conj(h_i); g_vm = Re(conj(G) V)/vm at PQ; g_va = Im(G conj V)
+//      Adam on the learnable entries; V_i = vm e^{j va}
+// Two storage modes:
+//   kReg    : the item's state (vm, va, Adam moments, S_spec, V, aI) stays in
+//             registers for the whole solve (small sub-grids, K <= 2).
+//   kGlobal : state in global memory (the caller's vm/va/adam arrays, scratch
+//             for V and a*I), streamed once per iteration (large sub-grids).
+// LDS is double-buffered (separate V and w arrays, 2 barriers per iteration)
+// when 2n complex values fit, single-buffered (4 barriers) otherwise.
+#pragma once
+
+#include "../../include/dpf.h"
+#include "common.hpp"
+#include "eval.hpp"
+
+namespace dpf {
+
+enum StoreMode { kReg = 0, kGlobal = 1 };
+
+constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched
+
+struct SolveArgs {
+    const int32_t *rp;
+    const int32_t *ci;
+    const double2 *yv;
+    const int8_t *bt;
+    const double2 *s_spec;
+    int64_t s_ld;
+    OutageView ov;
+    double *vm;
+    double *va;
+    int64_t ld;
+    double *st;          // Adam moments [4][B][ld]
+    int64_t st_stride;   // B * ld
+    int32_t st_fresh;    // moments start at zero
+    double2 *scratch;    // streaming: [3][B][ld] complex (V, a*I, w)
+    double *sched;       // [items][6] (t, lr, best, bad + cooldown * 2^20, b1^t, b2^t) or null
+    const int32_t *sub_off;  // device [n_sub + 1] or null
+    int32_t n_bus;
+    int32_t n_sub;
+    int32_t B;
+    int32_t lds_cap;     // complex entries available in dynamic LDS
+    double lr, b1, b2, eps, tol;
+    int32_t max_iter;
+    int32_t sch;
+    double factor;
+    int32_t patience;
+    double threshold;
+    int32_t cooldown;
+    double min_lr;
+    double sched_eps;
+    int32_t *iters;
+    int32_t *status;
+    double *mu_out;
+    double *loss_out;
+};
+
+template <int NT>
+__device__ __forceinline__ void block_reduce2(double &s, double &m, double (*red)[NT / kWave]) {
+    s = wave_sum(s);
+    m = wave_max(m);
+    const int wv = threadIdx.x / kWave;
+    if ((threadIdx.x & (kWave - 1)) == 0) {
+        red[0][wv] = s;
+        red[1][wv] = m;
+    }
+}
+
+template <int NT>
+__device__ __forceinline__ void block_reduce2_finish(double &s, double &m, double (*red)[NT / kWave]) {
+    s = 0.0;
+    m = 0.0;
+#pragma unroll
+    for (int k = 0; k < NT / kWave; ++k) {
+        s += red[0][k];
+        m = fmax(m, red[1][k]);
+    }
+}
+
+template <int NT, int K, int MODE>
+__global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
+    extern __shared__ double2 X[];
+    __shared__ double red[2][NT / kWave];
+    constexpr bool REG = MODE == kReg;
+
+    const int tid = threadIdx.x;
+    const int item = blockIdx.x;
+    const int sidx = item / a.B;
+    const int c = item - sidx * a.B;
+    const int lo = a.sub_off ? a.sub_off[sidx] : 0;
+    const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
+    const int n = hi - lo;
+    const int out_idx = c * a.n_sub + sidx;
+    if (n < 0 || n > NT * K || n > a.lds_cap) {  // host guarantees this never happens
+        if (tid == 0) a.status[out_idx] = -1;
+        return;
+    }
+    const bool dbl = 2 * n <= a.lds_cap;
+    double2 *Xv = X;
+    double2 *Xw = dbl ? X + n : X;
+
+    // schedule state and Adam step count (a resumed solve continues them)
+    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
+    int bad = 0, cool = 0;
+    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
+    if (a.sched) {
+        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+        t_step = ss[0];
+        lr = ss[1];
+        best = ss[2];
+        const int packed = (int)ss[3];
+        bad = packed & 0xFFFFF;
+        cool = packed >> 20;
+        b1t = ss[4];
+        b2t = ss[5];
+    }
+
+    // residual count m of this sub-grid
+    double m_res;
+    {
+        double cnt = 0.0, dummy = 0.0;
+        for (int i = lo + tid; i < hi; i += NT) {
+            int8_t t = a.bt[i];
+            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
+        }
+        block_reduce2<NT>(cnt, dummy, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(cnt, dummy, red);
+        m_res = cnt;
+        __syncthreads();
+    }
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+
+    // N-1 outage of this case (only meaningful for a single sub-grid)
+    int of = -1, ot = -1;
+    double2 oy = make_double2(0.0, 0.0), oyd = oy;
+    if (a.ov.outage) {
+        int32_t k = a.ov.outage[c];
+        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
+            int32_t f = a.ov.from[k], t = a.ov.to[k];
+            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
+                of = f - lo;
+                ot = t - lo;
+                double2 ysh;
+                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
+                oyd = cadd(oy, ysh);
+            }
+        }
+    }
+
+    const int64_t cb = (int64_t)c * a.ld;
+    const int64_t sb = (int64_t)c * a.s_ld;
+    double *vm_c = a.vm + cb;
+    double *va_c = a.va + cb;
+    double *mv_c = a.st + cb;
+    double *ma_c = a.st + a.st_stride + cb;
+    double *sv_c = a.st + 2 * a.st_stride + cb;
+    double *sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *Vg = a.scratch ? a.scratch + cb : nullptr;
+    double2 *aIg = a.scratch ? a.scratch + a.st_stride + cb : nullptr;
+
+    // Per-bus registers.  kReg keeps the whole item state; kGlobal keeps only
+    // `hold` (w or the new V across the single-buffer barrier).
+    constexpr int KR = REG ? K : 1;
+    double2 V[KR], aI[KR], Sr[KR];
+    double vmr[KR], var_[KR], mvr[KR], mar[KR], svr[KR], sar[KR];
+    int8_t ty[KR];
+    int r0[KR], r1[KR];
+    double2 hold[K];
+
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int i = lo + tid + k * NT;
+        hold[k] = make_double2(0.0, 0.0);
+        if (REG) {
+            ty[k % KR] = kSlack;
+            r0[k % KR] = r1[k % KR] = 0;
+            V[k % KR] = aI[k % KR] = Sr[k % KR] = make_double2(0.0, 0.0);
+            vmr[k % KR] = var_[k % KR] = mvr[k % KR] = mar[k % KR] = svr[k % KR] = sar[k % KR] = 0.0;
+        }
+        if (i < hi) {
+            const double vmi = vm_c[i], vai = va_c[i];
+            double sn, cs;
+            fast_sincos(vai, sn, cs);
+            const double2 v = make_double2(vmi * cs, vmi * sn);
+            if (REG) {
+                ty[k % KR] = a.bt[i];
+                r0[k % KR] = a.rp[i];
+                r1[k % KR] = a.rp[i + 1];
+                V[k % KR] = v;
+                vmr[k % KR] = vmi;
+                var_[k % KR] = vai;
+                Sr[k % KR] = a.s_spec[sb + i];
+                if (!a.st_fresh) {
+                    mvr[k % KR] = mv_c[i];
+                    mar[k % KR] = ma_c[i];
+                    svr[k % KR] = sv_c[i];
+                    sar[k % KR] = sa_c[i];
+                }
+            } else {
+                Vg[i] = v;
+                if (a.st_fresh) {
+                    mv_c[i] = 0.0;
+                    ma_c[i] = 0.0;
+                    sv_c[i] = 0.0;
+                    sa_c[i] = 0.0;
+                }
+            }
+            Xv[i - lo] = v;
+        }
+    }
+    __syncthreads();
+
+    int it = 0, stat = DPF_MAX_ITER;
+    double mu = 0.0, loss = 0.0;
+    for (;; ++it) {
+        // ---------------- phase A: forward product, residual, loss, seed
+        double lsum = 0.0, lmax = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = lo + tid + k * NT;
+            if (i < hi) {
+                const int q0 = REG ? r0[k % KR] : a.rp[i];
+                const int q1 = REG ? r1[k % KR] : a.rp[i + 1];
+                const int8_t tk = REG ? ty[k % KR] : a.bt[i];
+                const int il = i - lo;
+                double2 acc = make_double2(0.0, 0.0);
+                for (int q = q0; q < q1; ++q) {
+                    const int j = a.ci[q] - lo;
+                    if ((uint32_t)j < (uint32_t)n) acc = cfma(a.yv[q], Xv[j], acc);
+                }
+                if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
+                else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
+                const double2 v = REG ? V[k % KR] : Xv[il];
+                const double2 s = REG ? Sr[k % KR] : a.s_spec[sb + i];
+                const double2 d = csub(cmulc(v, acc), s);
+                const double rP = tk != kSlack ? d.x : 0.0;
+                const double rQ = tk == kPQ ? d.y : 0.0;
+                lsum += rP * rP + rQ * rQ;
+                lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+                const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
+                const double2 w = cmulc(av, v);
+                if (REG) aI[k % KR] = cmul(av, acc);
+                else aIg[i] = cmul(av, acc);
+                if (dbl) Xw[il] = w;
+                else hold[k] = w;
+            }
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        if (!dbl) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = lo + tid + k * NT;
+                if (i < hi) Xw[i - lo] = hold[k];
+            }
+        }
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!dbl) __syncthreads();  // w fully in X before phase B reads it
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+
+        // ---------------- phase B: adjoint product, gradient, Adam
+        t_step += 1.0;
+        b1t *= a.b1;
+        b2t *= a.b2;
+        const double bc1 = 1.0 - b1t;
+        const double bc2 = 1.0 - b2t;
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = lo + tid + k * NT;
+            if (i < hi) {
+                const int q0 = REG ? r0[k % KR] : a.rp[i];
+                const int q1 = REG ? r1[k % KR] : a.rp[i + 1];
+                const int8_t tk = REG ? ty[k % KR] : a.bt[i];
+                const int il = i - lo;
+                double2 h = make_double2(0.0, 0.0);
+                for (int q = q0; q < q1; ++q) {
+                    const int j = a.ci[q] - lo;
+                    if ((uint32_t)j < (uint32_t)n) h = cfma(a.yv[q], Xw[j], h);
+                }
+                if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
+                else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
+                double2 v, ai;
+                double vmi, vai, mv = 0.0, ma = 0.0, sv = 0.0, sa = 0.0;
+                if (REG) {
+                    v = V[k % KR];
+                    ai = aI[k % KR];
+                    vmi = vmr[k % KR];
+                    vai = var_[k % KR];
+                    mv = mvr[k % KR];
+                    ma = mar[k % KR];
+                    sv = svr[k % KR];
+                    sa = sar[k % KR];
+                } else {
+                    v = Vg[i];
+                    ai = aIg[i];
+                    vmi = vm_c[i];
+                    vai = va_c[i];
+                }
+                const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+                if (tk == kPQ) {
+                    if (!REG) {
+                        mv = mv_c[i];
+                        sv = sv_c[i];
+                    }
+                    const double g = (G.x * v.x + G.y * v.y) / vmi;
+                    mv = a.b1 * mv + (1.0 - a.b1) * g;
+                    sv = a.b2 * sv + (1.0 - a.b2) * (g * g);
+                    vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                    if (!REG) {
+                        vm_c[i] = vmi;
+                        mv_c[i] = mv;
+                        sv_c[i] = sv;
+                    }
+                }
+                if (tk != kSlack) {
+                    if (!REG) {
+                        ma = ma_c[i];
+                        sa = sa_c[i];
+                    }
+                    const double g = G.y * v.x - G.x * v.y;
+                    ma = a.b1 * ma + (1.0 - a.b1) * g;
+                    sa = a.b2 * sa + (1.0 - a.b2) * (g * g);
+                    vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                    if (!REG) {
+                        va_c[i] = vai;
+                        ma_c[i] = ma;
+                        sa_c[i] = sa;
+                    }
+                }
+                double sn, cs;
+                fast_sincos(vai, sn, cs);
+                v = make_double2(vmi * cs, vmi * sn);
+                if (REG) {
+                    V[k % KR] = v;
+                    vmr[k % KR] = vmi;
+                    var_[k % KR] = vai;
+                    mvr[k % KR] = mv;
+                    mar[k % KR] = ma;
+                    svr[k % KR] = sv;
+                    sar[k % KR] = sa;
+                } else {
+                    Vg[i] = v;
+                }
+                if (dbl) Xv[il] = v;
+                else hold[k] = v;
+            }
+        }
+        // ---------------- schedule step (uniform across the workgroup)
+        if (a.sch == DPF_SCHED_PLATEAU) {
+            if (loss < best * (1.0 - a.threshold)) {
+                best = loss;
+                bad = 0;
+            } else {
+                bad += 1;
+            }
+            if (cool > 0) {
+                cool -= 1;
+                bad = 0;
+            }
+            if (bad > a.patience) {
+                double nl = lr * a.factor;
+                if (nl < a.min_lr) nl = a.min_lr;
+                if (lr - nl > a.sched_eps) lr = nl;
+                cool = a.cooldown;
+                bad = 0;
+            }
+        } else if (a.sch == DPF_SCHED_STEP) {
+            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
+        }
+        if (!dbl) {
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const int i = lo + tid + k * NT;
+                if (i < hi) Xv[i - lo] = hold[k];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---------------- write back
+    if (REG) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int i = lo + tid + k * NT;
+            if (i < hi) {
+                if (ty[k % KR] == kPQ) vm_c[i] = vmr[k % KR];
+                if (ty[k % KR] != kSlack) va_c[i] = var_[k % KR];
+                if (!a.st_fresh) {
+                    mv_c[i] = mvr[k % KR];
+                    ma_c[i] = mar[k % KR];
+                    sv_c[i] = svr[k % KR];
+                    sa_c[i] = sar[k % KR];
+                }
+            }
+        }
+    }
+    if (tid == 0) {
+        a.iters[out_idx] = it;
+        a.status[out_idx] = stat;
+        a.mu_out[out_idx] = mu;
+        a.loss_out[out_idx] = loss;
+        if (a.sched) {
+            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+            ss[0] = t_step;
+            ss[1] = lr;
+            ss[2] = best;
+            ss[3] = (double)(bad + (cool << 20));
+            ss[4] = b1t;
+            ss[5] = b2t;
+        }
+    }
+}
+
+// Streaming variant for large sub-grids: the per-bus loop is a runtime loop
+// (no per-bus registers), every per-bus value lives in global memory: the
+// caller's vm/va/Adam arrays and the scratch arrays V, a*I and w.  LDS holds
+// the exchange vector (double-buffered when it fits).
+template <int NT>
+__global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
+    extern __shared__ double2 X[];
+    __shared__ double red[2][NT / kWave];
+
+    const int tid = threadIdx.x;
+    const int item = blockIdx.x;
+    const int sidx = item / a.B;
+    const int c = item - sidx * a.B;
+    const int lo = a.sub_off ? a.sub_off[sidx] : 0;
+    const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
+    const int n = hi - lo;
+    const int out_idx = c * a.n_sub + sidx;
+    if (n < 0 || n > a.lds_cap) {  // host guarantees this never happens
+        if (tid == 0) a.status[out_idx] = -1;
+        return;
+    }
+    const bool dbl = 2 * n <= a.lds_cap;
+    double2 *Xv = X;
+    double2 *Xw = dbl ? X + n : X;
+
+    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
+    int bad = 0, cool = 0;
+    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
+    if (a.sched) {
+        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+        t_step = ss[0];
+        lr = ss[1];
+        best = ss[2];
+        const int packed = (int)ss[3];
+        bad = packed & 0xFFFFF;
+        cool = packed >> 20;
+        b1t = ss[4];
+        b2t = ss[5];
+    }
+
+    double m_res;
+    {
+        double cnt = 0.0, dummy = 0.0;
+        for (int i = lo + tid; i < hi; i += NT) {
+            int8_t t = a.bt[i];
+            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
+        }
+        block_reduce2<NT>(cnt, dummy, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(cnt, dummy, red);
+        m_res = cnt;
+        __syncthreads();
+    }
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+
+    int of = -1, ot = -1;
+    double2 oy = make_double2(0.0, 0.0), oyd = oy;
+    if (a.ov.outage) {
+        int32_t k = a.ov.outage[c];
+        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
+            int32_t f = a.ov.from[k], t = a.ov.to[k];
+            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
+                of = f - lo;
+                ot = t - lo;
+                double2 ysh;
+                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
+                oyd = cadd(oy, ysh);
+            }
+        }
+    }
+
+    const int64_t cb = (int64_t)c * a.ld;
+    const int64_t sb = (int64_t)c * a.s_ld;
+    double *vm_c = a.vm + cb;
+    double *va_c = a.va + cb;
+    double *mv_c = a.st + cb;
+    double *ma_c = a.st + a.st_stride + cb;
+    double *sv_c = a.st + 2 * a.st_stride + cb;
+    double *sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *Vg = a.scratch + cb;
+    double2 *aIg = a.scratch + a.st_stride + cb;
+    double2 *Wg = a.scratch + 2 * a.st_stride + cb;
+    const double2 *Sc = a.s_spec + sb;
+
+    for (int i = lo + tid; i < hi; i += NT) {
+        double sn, cs;
+        const double vmi = vm_c[i];
+        fast_sincos(va_c[i], sn, cs);
+        const double2 v = make_double2(vmi * cs, vmi * sn);
+        Vg[i] = v;
+        Xv[i - lo] = v;
+        if (a.st_fresh) {
+            mv_c[i] = 0.0;
+            ma_c[i] = 0.0;
+            sv_c[i] = 0.0;
+            sa_c[i] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    int it = 0, stat = DPF_MAX_ITER;
+    double mu = 0.0, loss = 0.0;
+    for (;; ++it) {
+        double lsum = 0.0, lmax = 0.0;
+#pragma unroll 1
+        for (int i = lo + tid; i < hi; i += NT) {
+            const int il = i - lo;
+            const int q1 = a.rp[i + 1];
+            double2 acc = make_double2(0.0, 0.0);
+            for (int q = a.rp[i]; q < q1; ++q) {
+                const int j = a.ci[q] - lo;
+                if ((uint32_t)j < (uint32_t)n) acc = cfma(a.yv[q], Xv[j], acc);
+            }
+            if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
+            else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
+            const int8_t tk = a.bt[i];
+            const double2 v = Xv[il];
+            const double2 d = csub(cmulc(v, acc), Sc[i]);
+            const double rP = tk != kSlack ? d.x : 0.0;
+            const double rQ = tk == kPQ ? d.y : 0.0;
+            lsum += rP * rP + rQ * rQ;
+            lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+            const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
+            aIg[i] = cmul(av, acc);
+            if (dbl) Xw[il] = cmulc(av, v);
+            else Wg[i] = cmulc(av, v);
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        if (!dbl)
+            for (int i = lo + tid; i < hi; i += NT) Xw[i - lo] = Wg[i];
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!dbl) __syncthreads();
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+
+        t_step += 1.0;
+        b1t *= a.b1;
+        b2t *= a.b2;
+        const double bc1 = 1.0 - b1t;
+        const double bc2 = 1.0 - b2t;
+#pragma unroll 1
+        for (int i = lo + tid; i < hi; i += NT) {
+            const int il = i - lo;
+            const int q1 = a.rp[i + 1];
+            double2 h = make_double2(0.0, 0.0);
+            for (int q = a.rp[i]; q < q1; ++q) {
+                const int j = a.ci[q] - lo;
+                if ((uint32_t)j < (uint32_t)n) h = cfma(a.yv[q], Xw[j], h);
+            }
+            if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
+            else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
+            const int8_t tk = a.bt[i];
+            const double2 ai = aIg[i];
+            double2 v = Vg[i];
+            const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+            double vmi = vm_c[i], vai = va_c[i];
+            if (tk == kPQ) {
+                const double g = (G.x * v.x + G.y * v.y) / vmi;
+                const double mv = a.b1 * mv_c[i] + (1.0 - a.b1) * g;
+                const double sv = a.b2 * sv_c[i] + (1.0 - a.b2) * (g * g);
+                vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                vm_c[i] = vmi;
+                mv_c[i] = mv;
+                sv_c[i] = sv;
+            }
+            if (tk != kSlack) {
+                const double g = G.y * v.x - G.x * v.y;
+                const double ma = a.b1 * ma_c[i] + (1.0 - a.b1) * g;
+                const double sa = a.b2 * sa_c[i] + (1.0 - a.b2) * (g * g);
+                vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                va_c[i] = vai;
+                ma_c[i] = ma;
+                sa_c[i] = sa;
+            }
+            double sn, cs;
+            fast_sincos(vai, sn, cs);
+            v = make_double2(vmi * cs, vmi * sn);
+            Vg[i] = v;
+            if (dbl) Xv[il] = v;
+        }
+        if (a.sch == DPF_SCHED_PLATEAU) {
+            if (loss < best * (1.0 - a.threshold)) {
+                best = loss;
+                bad = 0;
+            } else {
+                bad += 1;
+            }
+            if (cool > 0) {
+                cool -= 1;
+                bad = 0;
+            }
+            if (bad > a.patience) {
+                double nl = lr * a.factor;
+                if (nl < a.min_lr) nl = a.min_lr;
+                if (lr - nl > a.sched_eps) lr = nl;
+                cool = a.cooldown;
+                bad = 0;
+            }
+        } else if (a.sch == DPF_SCHED_STEP) {
+            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
+        }
+        if (!dbl) {
+            __syncthreads();
+            for (int i = lo + tid; i < hi; i += NT) Xv[i - lo] = Vg[i];
+        }
+        __syncthreads();
+    }
+
+    if (tid == 0) {
+        a.iters[out_idx] = it;
+        a.status[out_idx] = stat;
+        a.mu_out[out_idx] = mu;
+        a.loss_out[out_idx] = loss;
+        if (a.sched) {
+            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+            ss[0] = t_step;
+            ss[1] = lr;
+            ss[2] = best;
+            ss[3] = (double)(bad + (cool << 20));
+            ss[4] = b1t;
+            ss[5] = b2t;
+        }
+    }
+}
+
+}  // namespace dpf

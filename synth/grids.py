@@ -34,6 +34,7 @@ X_RANGE = (0.05, 0.3)
 B_RANGE = (0.0, 0.05)
 VM_RANGE = (0.95, 1.05)
 VA_MAX = 0.2
+PV_REPLANT = 0.01  # relative re-planting of PV setpoints per case
 
 
 @dataclass
@@ -230,30 +231,39 @@ def plant_iid(rng: np.random.Generator, n_bus: int, bus_type: np.ndarray):
     return vm, va
 
 
-def plant_smooth(rng: np.random.Generator, n_bus, f, t, x, bus_type):
-    """|V| ~ U(0.95, 1.05); angles are a DC-like field.
-
-    Zero-mean random nodal injections are spread over the graph through the
-    branch-susceptance Laplacian (weights 1/x) grounded at the slack; the
-    resulting angle field is rescaled so that max|angle| = 0.2 rad.  This is
-    input synthesis only (a smooth, physically plausible angle profile), not a
-    power-flow solve of the workload.
-    """
-    vm = rng.uniform(*VM_RANGE, size=n_bus)
-    p = rng.standard_normal(n_bus)
-    p -= p.mean()
-    w = 1.0 / x
-    lap = sp.coo_matrix(
+def _laplacian(n_bus, f, t, w):
+    return sp.coo_matrix(
         (np.concatenate([w, w, -w, -w]),
          (np.concatenate([f, t, f, t]), np.concatenate([f, t, t, f]))),
         shape=(n_bus, n_bus)).tocsc()
+
+
+def plant_smooth(rng: np.random.Generator, n_bus, f, t, x, bus_type):
+    """Smooth planted voltage profile for meshed grids.
+
+    Angles: zero-mean random nodal injections spread over the graph through
+    the branch-susceptance Laplacian (weights 1/x) grounded at the slack,
+    rescaled so that max|angle| = 0.2 rad.  Magnitudes: a second random
+    injection pattern spread the same way (Laplacian + 1e-3 I), mapped affinely
+    onto [0.95, 1.05].  This is input synthesis (a smooth, physically plausible
+    profile whose injections stay well inside the loadability limit), not a
+    power-flow solve of the workload.
+    """
+    lap = _laplacian(n_bus, f, t, 1.0 / x)
     s = int(np.flatnonzero(bus_type == SLACK)[0])
     keep = np.flatnonzero(np.arange(n_bus) != s)
-    red = lap[keep][:, keep].tocsc()
+    p = rng.standard_normal(n_bus)
+    p -= p.mean()
     va = np.zeros(n_bus)
-    va[keep] = spla.spsolve(red, p[keep])
+    va[keep] = spla.spsolve(lap[keep][:, keep].tocsc(), p[keep])
     va *= VA_MAX / np.max(np.abs(va))
     va[s] = 0.0
+    q = rng.standard_normal(n_bus)
+    q -= q.mean()
+    fld = spla.spsolve((lap + 1e-3 * sp.identity(n_bus, format="csc")).tocsc(), q)
+    span = fld.max() - fld.min()
+    fld = (fld - fld.min()) / span if span > 0 else np.full(n_bus, 0.5)
+    vm = VM_RANGE[0] + (VM_RANGE[1] - VM_RANGE[0]) * fld
     return vm, va
 
 
@@ -300,7 +310,7 @@ def config0(seed: int = 0) -> dict:
 def config1(seed: int = 1000, B: int = 64, n_bus: int = 1354, n_branch: int = 1991,
             n_pv: int = 260) -> dict:
     """B cases on one meshed grid; per case PQ loads x U(0.9, 1.1) per bus and
-    PV setpoints redrawn from U(0.95, 1.05); flat start."""
+    PV setpoints re-planted as the planted |V| x (1 + U(-0.01, 0.01)); flat start."""
     rng = np.random.default_rng(seed)
     g = _make_grid(rng, n_bus, n_branch, n_pv, geometric=True, smooth=True,
                    name=f"synthetic-{n_bus}")
@@ -311,7 +321,7 @@ def config1(seed: int = 1000, B: int = 64, n_bus: int = 1354, n_branch: int = 19
     for c, child in enumerate(np.random.SeedSequence(seed).spawn(B)):
         cr = np.random.default_rng(child)
         load_scale[c, pq] = cr.uniform(0.9, 1.1, size=int(pq.sum()))
-        vm_set[c, pv] = cr.uniform(*VM_RANGE, size=int(pv.sum()))
+        vm_set[c, pv] = g.vm[pv] * (1.0 + cr.uniform(-PV_REPLANT, PV_REPLANT, size=int(pv.sum())))
     vm0, va0 = flat_start(g, vm_set)
     return {"name": "cfg1", "grid": g, "B": B, "vm0": vm0, "va0": va0,
             "load_scale": load_scale, "seed": seed}

@@ -1,0 +1,475 @@
+"""GPU parity: libdpf (HIP, gfx950) against the FP64 CPU oracle.
+
+Tolerances: 1e-10 normwise relative on mismatch and gradient (per case,
+||x - x_ref||_inf / ||x_ref||_inf, evaluated away from the solution);
+bit-exact on the Y-bus pattern; 1e-6 relative against central finite
+differences of the GPU loss."""
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def dpf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2603_28203_amd as m
+    m.lib()
+    return m
+
+
+def dgrid(dpf, g):
+    return dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
+
+
+def relerr(x, ref):
+    x = np.asarray(x)
+    ref = np.asarray(ref)
+    return np.abs(x - ref).max() / max(np.abs(ref).max(), 1e-300)
+
+
+def perturbed_states(g, B, seed, sd=0.02):
+    rng = np.random.default_rng(seed)
+    vm = g.vm[None, :] + rng.normal(0, sd, (B, g.n_bus))
+    va = g.va[None, :] + rng.normal(0, sd, (B, g.n_bus))
+    va[:, g.bus_type == 2] = 0.0
+    return vm, va
+
+
+def cu(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+# ---------------------------------------------------------------- Y-bus
+
+
+@pytest.mark.parametrize("which", ["cfg0", "cfg1", "cfg2"])
+def test_build_ybus_matches_oracle(dpf, which):
+    g = {"cfg0": lambda: synth.config0(0)["grid"], "cfg1": lambda: synth.config1(B=1)["grid"],
+         "cfg2": lambda: synth.config2(B=1)["grid"]}[which]()
+    print(f"ybus {which} n={g.n_bus}", flush=True)
+    Yg = dgrid(dpf, g)
+    Yo = oracle.ybus_of(g)
+    assert Yg.nnz == Yo.nnz
+    assert np.array_equal(Yg.row_ptr.cpu().numpy(), Yo.row_ptr)
+    assert np.array_equal(Yg.col_idx.cpu().numpy(), Yo.col)
+    v = Yg.val.cpu().numpy()
+    assert np.max(np.abs(v - Yo.val) / np.abs(Yo.val).max()) <= 1e-15
+
+
+def test_build_ybus_parallel_branches(dpf):
+    g = synth.config0(4)["grid"]
+    f = np.append(g.f, [g.f[3], g.f[3]]); t = np.append(g.t, [g.t[3], g.f[3] * 0 + g.t[3]])
+    r = np.append(g.r, [0.07, 0.02]); x = np.append(g.x, [0.11, 0.3]); b = np.append(g.b, [0.02, 0.0])
+    Yg = dpf.build_ybus(g.n_bus, f, t, r, x, b)
+    Yo = oracle.build_ybus(g.n_bus, f, t, r, x, b)
+    assert np.array_equal(Yg.col_idx.cpu().numpy(), Yo.col)
+    assert np.max(np.abs(Yg.val.cpu().numpy() - Yo.val)) <= 1e-15 * np.abs(Yo.val).max()
+
+
+def test_build_ybus_errors(dpf):
+    with pytest.raises(dpf.DPFError) as e:
+        dpf.build_ybus(3, [0], [0], [0.1], [0.1], [0.0])
+    assert e.value.code == -1
+    with pytest.raises(dpf.DPFError):
+        dpf.build_ybus(3, [0], [5], [0.1], [0.1], [0.0])
+    with pytest.raises(dpf.DPFError):
+        dpf.build_ybus(3, [0], [1], [0.0], [0.0], [0.0])
+
+
+# ---------------------------------------------------------------- evaluation
+
+
+def _oracle_eval(Y, g, S, vm, va):
+    dS = oracle.mismatch(Y, vm, va, S)
+    loss, mu, gv, ga = oracle.loss_grad(Y, g.bus_type, vm, va, S)
+    return dS, loss, mu, gv, ga
+
+
+@pytest.mark.parametrize("which,B,shared", [("cfg0", 3, False), ("cfg1", 5, False), ("cfg1", 4, True),
+                                            ("cfg2", 2, True)])
+def test_mismatch_grad_parity(dpf, which, B, shared):
+    cfg = {"cfg0": lambda: synth.config0(1), "cfg1": lambda: synth.config1(B=B),
+           "cfg2": lambda: synth.config2(B=2)}[which]()
+    g = cfg["grid"]
+    print(f"mismatch_grad {which} n={g.n_bus} B={B} shared={shared}", flush=True)
+    Yo = oracle.ybus_of(g)
+    S0 = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(9)
+    S = S0[None, :] * rng.uniform(0.9, 1.1, (B, g.n_bus)) if not shared else S0
+    vm, va = perturbed_states(g, B, 3)
+    Yg = dgrid(dpf, g)
+    r = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va))
+    torch.cuda.synchronize()
+    for c in range(B):
+        Sc = S if shared else S[c]
+        dS, loss, mu, gv, ga = _oracle_eval(Yo, g, Sc, vm[c], va[c])
+        assert relerr(r["dS"][c].cpu().numpy(), dS) < REL
+        assert abs(r["loss"][c].item() - loss) <= REL * loss
+        assert abs(r["max_mis"][c].item() - mu) <= REL * mu
+        assert relerr(r["g_vm"][c].cpu().numpy(), gv) < REL
+        assert relerr(r["g_va"][c].cpu().numpy(), ga) < REL
+        # fixed coordinates have exactly zero gradient
+        gvc = r["g_vm"][c].cpu().numpy()
+        gac = r["g_va"][c].cpu().numpy()
+        assert np.all(gvc[g.bus_type != 0] == 0) and np.all(gac[g.bus_type == 2] == 0)
+
+
+def test_mismatch_grad_outage_parity(dpf):
+    cfg = synth.config2(B=6)
+    g = cfg["grid"]
+    out = cfg["outage"]
+    Yo0 = oracle.ybus_of(g)
+    S = oracle.injections(Yo0, g.vm, g.va)
+    vm, va = perturbed_states(g, 6, 5, sd=0.01)
+    out = out.copy()
+    out[2] = -1  # a case without outage in the same batch
+    print(f"outage parity n={g.n_bus} outages={out.tolist()}", flush=True)
+    Yg = dgrid(dpf, g)
+    r = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va), outage=cu(out, torch.int32))
+    torch.cuda.synchronize()
+    for c in range(6):
+        Yc = oracle.ybus_of(g, skip=int(out[c]))
+        dS, loss, mu, gv, ga = _oracle_eval(Yc, g, S, vm[c], va[c])
+        assert relerr(r["dS"][c].cpu().numpy(), dS) < REL
+        assert abs(r["loss"][c].item() - loss) <= REL * loss
+        assert relerr(r["g_vm"][c].cpu().numpy(), gv) < REL
+        assert relerr(r["g_va"][c].cpu().numpy(), ga) < REL
+
+
+def test_gradient_matches_central_fd_on_gpu(dpf):
+    cfg = synth.config1(B=1)
+    g = cfg["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va) * cfg["load_scale"][0]
+    vm, va = perturbed_states(g, 1, 8)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    base = dpf.mismatch_grad(Yg, g.bus_type, Sd, cu(vm), cu(va))
+    gv = base["g_vm"][0].cpu().numpy()
+    ga = base["g_va"][0].cpu().numpy()
+    rng = np.random.default_rng(2)
+    h = 1e-6
+    cv = rng.choice(np.flatnonzero(g.bus_type == 0), 32, replace=False)
+    ca = rng.choice(np.flatnonzero(g.bus_type != 2), 32, replace=False)
+    # all perturbed states in one batched call: rows 2k / 2k+1 = +h / -h
+    coords = [("v", i) for i in cv] + [("a", i) for i in ca]
+    P = len(coords)
+    vmb = np.repeat(vm, 2 * P, axis=0)
+    vab = np.repeat(va, 2 * P, axis=0)
+    for k, (kind, i) in enumerate(coords):
+        arr = vmb if kind == "v" else vab
+        arr[2 * k, i] += h
+        arr[2 * k + 1, i] -= h
+    rr = dpf.mismatch_grad(Yg, g.bus_type, Sd, cu(vmb), cu(vab), want_dS=False, want_grad=False)
+    L = rr["loss"].cpu().numpy()
+    for k, (kind, i) in enumerate(coords):
+        fd = (L[2 * k] - L[2 * k + 1]) / (2 * h)
+        an = gv[i] if kind == "v" else ga[i]
+        scale = np.abs(gv).max() if kind == "v" else np.abs(ga).max()
+        assert abs(an - fd) <= 1e-6 * max(abs(fd), 1e-3 * scale)
+
+
+def test_mismatch_grad_deterministic(dpf):
+    cfg = synth.config1(B=3)
+    g = cfg["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm, va = perturbed_states(g, 3, 1)
+    Yg = dgrid(dpf, g)
+    a = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va))
+    b = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va))
+    for k in ("dS", "loss", "max_mis", "g_vm", "g_va"):
+        assert torch.equal(a[k], b[k])
+
+
+# ---------------------------------------------------------------- solve
+
+
+def test_solve_fixed_iterations_track_oracle(dpf):
+    """Short runs with tol = 0: the GPU iterates follow the oracle's."""
+    cfg = synth.config0(0)
+    g = cfg["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    steps = 40
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(tol=0.0, max_iter=steps))
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["status"].item() == 1 and out["iters"].item() == steps
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
+    assert abs(out["max_mis"].item() - ref["mu"]) <= 1e-8 * ref["mu"]
+
+
+@pytest.mark.parametrize("seed", [0, 5])
+def test_solve_converges_like_oracle_cfg0(dpf, seed):
+    cfg = synth.config0(seed)
+    g = cfg["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    o = oracle.AdamOptions(max_iter=20000)
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, o)
+    print(f"cfg0 seed {seed}: oracle status {ref['status']} iters {ref['iters']}", flush=True)
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(max_iter=20000))
+    torch.cuda.synchronize()
+    assert out["status"].item() == ref["status"] == 0
+    # Iteration counts are not pinned: GPU and oracle round differently (FMA,
+    # adjoint vs J^T f summation order), and over thousands of Adam steps the
+    # trajectories drift apart at that level; the exit step moves by a few %.
+    assert abs(out["iters"].item() - ref["iters"]) <= max(3, ref["iters"] // 20)
+    assert out["max_mis"].item() < 1e-6
+    # both land on the planted (high-voltage) solution within tolerance
+    assert np.abs(vm[0].cpu().numpy() - g.vm).max() < 1e-5
+    assert np.abs(va[0].cpu().numpy() - g.va).max() < 1e-5
+
+
+def _cfg1_problem(B):
+    cfg = synth.config1(B=B)
+    g = cfg["grid"]
+    Yo = oracle.ybus_of(g)
+    S0 = oracle.injections(Yo, g.vm, g.va)
+    S = S0[None, :] * cfg["load_scale"]
+    return cfg, g, Yo, S
+
+
+def test_solve_batch_parity_cfg1_short(dpf):
+    """Per-case Adam state in a batch: 64 cases x 1354 buses, 30 iterations."""
+    B = 64
+    cfg, g, Yo, S = _cfg1_problem(B)
+    steps = 30
+    Yg = dgrid(dpf, g)
+    vm = cu(cfg["vm0"]); va = cu(cfg["va0"])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    vmh = vm.cpu().numpy(); vah = va.cpu().numpy()
+    for c in (0, 17, 63):
+        ref = oracle.solve_adam(Yo, g.bus_type, S[c], cfg["vm0"][c], cfg["va0"][c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps))
+        assert np.abs(vmh[c] - ref["vm"]).max() < 1e-9
+        assert np.abs(vah[c] - ref["va"]).max() < 1e-9
+        assert abs(out["loss"][c].item() - ref_loss(Yo, g, S[c], ref)) <= 1e-8 * ref_loss(Yo, g, S[c], ref)
+
+
+def ref_loss(Yo, g, S, ref):
+    return oracle.loss_from_mismatch(g.bus_type, oracle.mismatch(Yo, ref["vm"], ref["va"], S))[0]
+
+
+def test_solve_batch_equals_single_items(dpf):
+    B = 6
+    cfg, g, Yo, S = _cfg1_problem(B)
+    Yg = dgrid(dpf, g)
+    opts = dpf.Options(tol=0.0, max_iter=25)
+    vm = cu(cfg["vm0"]); va = cu(cfg["va0"])
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=opts)
+    for c in (1, 4):
+        v1 = cu(cfg["vm0"][c:c + 1]); a1 = cu(cfg["va0"][c:c + 1])
+        dpf.solve(Yg, g.bus_type, cu(S[c:c + 1], torch.complex128), v1, a1, opts=opts)
+        torch.cuda.synchronize()
+        assert torch.equal(v1[0], vm[c]) and torch.equal(a1[0], va[c])
+
+
+def test_solve_resume_equals_single_call(dpf):
+    cfg = synth.config0(2)
+    g = cfg["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    vm0, va0 = synth.flat_start(g)
+    opts = dpf.Options(tol=0.0, max_iter=120, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05,
+                       cooldown=3)
+    vmA = cu(vm0[None]); vaA = cu(va0[None])
+    dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=opts)
+    vmB = cu(vm0[None]); vaB = cu(va0[None])
+    st = torch.zeros((4, 1, g.n_bus), dtype=torch.float64, device="cuda")
+    sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]], dtype=torch.float64, device="cuda")
+    half = dpf.Options(**{**opts.__dict__, "max_iter": 60})
+    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+    torch.cuda.synchronize()
+    assert torch.equal(vmA, vmB) and torch.equal(vaA, vaB)
+    assert sch[0, 0].item() == 120
+
+
+def test_solve_plateau_schedule_tracks_oracle(dpf):
+    cfg = synth.config0(2)
+    g = cfg["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    pl = dict(factor=0.547, patience=41, threshold=0.0673, cooldown=97)
+    steps = 400
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0,
+                            oracle.AdamOptions(lr=1e-2, beta1=0.979, beta2=0.963, tol=0.0, max_iter=steps,
+                                               sched=oracle.SCHED_PLATEAU, **pl))
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    sch = torch.tensor([[0.0, 1e-2, float("inf"), 0.0, 1.0, 1.0]], dtype=torch.float64, device="cuda")
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, sched_state=sch,
+              opts=dpf.Options(lr=1e-2, beta1=0.979, beta2=0.963, tol=0.0, max_iter=steps,
+                               sched=dpf.SCHED_PLATEAU, **pl))
+    torch.cuda.synchronize()
+    assert sch[0, 1].item() == pytest.approx(ref["lr"], rel=1e-15)
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-9
+
+
+def test_solve_nonfinite_and_max_iter_status(dpf):
+    B = 3
+    cfg = synth.config0(0)
+    g = cfg["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Sb = np.tile(S, (B, 1))
+    Sb[1, 4] = np.nan
+    Yg = dgrid(dpf, g)
+    vm0, va0 = synth.flat_start(g)
+    vm = cu(np.tile(vm0, (B, 1))); va = cu(np.tile(va0, (B, 1)))
+    vm[2] = cu(g.vm); va[2] = cu(g.va)  # case 2 starts at the solution
+    out = dpf.solve(Yg, g.bus_type, cu(Sb, torch.complex128), vm, va, opts=dpf.Options(max_iter=7))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [1, 2, 0]
+    assert out["iters"].tolist() == [7, 0, 0]
+
+
+def test_solve_outage_tracks_oracle(dpf):
+    # The start is the planted point plus 1e-3 noise, not the planted point
+    # itself: there the oracle's residual is exactly zero (S comes from the same
+    # oracle arithmetic) while the GPU sees rounding-level residuals, and Adam
+    # with gradients far below eps acts like gradient descent with step lr/eps,
+    # which amplifies rounding differences by ~1e8 per step.
+    cfg = synth.config2(B=4)
+    g = cfg["grid"]
+    out = cfg["outage"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    steps = 20
+    Yg = dgrid(dpf, g)
+    rng = np.random.default_rng(12)
+    cfg["vm0"] = cfg["vm0"] + rng.normal(0, 1e-3, cfg["vm0"].shape) * (g.bus_type == 0)
+    cfg["va0"] = cfg["va0"] + rng.normal(0, 1e-3, cfg["va0"].shape) * (g.bus_type != 2)
+    vm = cu(cfg["vm0"]); va = cu(cfg["va0"])
+    print(f"outage solve n={g.n_bus} (kGlobal path)", flush=True)
+    o = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(out, torch.int32),
+                  opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    for c in (0, 3):
+        Yc = oracle.ybus_of(g, skip=int(out[c]))
+        ref = oracle.solve_adam(Yc, g.bus_type, S, cfg["vm0"][c], cfg["va0"][c],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-9
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-9
+        assert o["status"][c].item() == 1
+
+
+def test_solve_sub_grids_equal_separate_solves(dpf):
+    """Uneven concatenated grids in one launch equal separate solves."""
+    grids = [synth.config0(s)["grid"] for s in (0, 1, 2)]
+    big = synth.config1(B=1, n_bus=300, n_branch=420, n_pv=50)["grid"]
+    grids = [big] + grids
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    f = np.concatenate([gg.f + o for gg, o in zip(grids, off)])
+    t = np.concatenate([gg.t + o for gg, o in zip(grids, off)])
+    r = np.concatenate([gg.r for gg in grids]); x = np.concatenate([gg.x for gg in grids])
+    b = np.concatenate([gg.b for gg in grids]); bt = np.concatenate([gg.bus_type for gg in grids])
+    S = np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids])
+    vm0 = np.concatenate([synth.flat_start(gg)[0] for gg in grids])
+    va0 = np.zeros_like(vm0)
+    Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    opts = dpf.Options(tol=0.0, max_iter=30)
+    out = dpf.solve(Yg, bt, cu(S[None], torch.complex128), vm, va, sub_offset=off.tolist(), opts=opts)
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [30] * 4
+    for k, gg in enumerate(grids):
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[off[k]:off[k + 1]], vm0[off[k]:off[k + 1]],
+                                va0[off[k]:off[k + 1]], oracle.AdamOptions(tol=0.0, max_iter=30))
+        assert np.abs(vm[0, off[k]:off[k + 1]].cpu().numpy() - ref["vm"]).max() < 1e-9
+        assert np.abs(va[0, off[k]:off[k + 1]].cpu().numpy() - ref["va"]).max() < 1e-9
+
+
+def test_solve_rejects_bad_arguments(dpf):
+    g = synth.config0(0)["grid"]
+    Yg = dgrid(dpf, g)
+    S = cu(np.zeros(g.n_bus), torch.complex128)
+    vm = cu(np.ones((1, g.n_bus))); va = cu(np.zeros((1, g.n_bus)))
+    with pytest.raises(dpf.DPFError):
+        dpf.solve(Yg, g.bus_type, S, vm, va, opts=dpf.Options(beta1=1.5))
+    with pytest.raises(dpf.DPFError):
+        dpf.solve(Yg, g.bus_type, S, vm, va, sub_offset=[0, 5, 3, g.n_bus])
+
+
+def test_dpfloss_autograd_function(dpf):
+    cfg = synth.config1(B=2)
+    g = cfg["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm, va = perturbed_states(g, 2, 4)
+    Yg = dgrid(dpf, g)
+    v = cu(vm).requires_grad_(True)
+    a = cu(va).requires_grad_(True)
+    loss, mx = dpf.DPFLoss.apply(v, a, Yg, g.bus_type, cu(S, torch.complex128), None)
+    (3.0 * loss[0] + loss[1]).backward()
+    for c, w in ((0, 3.0), (1, 1.0)):
+        _, _, gv, ga = oracle.loss_grad(oracle.ybus_of(g), g.bus_type, vm[c], va[c], S)
+        assert relerr(v.grad[c].cpu().numpy(), w * gv) < REL
+        assert relerr(a.grad[c].cpu().numpy(), w * ga) < REL
+
+
+@pytest.mark.parametrize("n_bus", [14, 100, 200, 300, 700, 1354, 2000, 3000, 6000, 9241])
+def test_solve_every_variant_tracks_oracle(dpf, n_bus):
+    """Each size class selects a different kernel variant (threads x buses per
+    thread, register-resident or streaming, double- or single-buffered LDS)."""
+    if n_bus == 14:
+        g = synth.config0(3)["grid"]
+    else:
+        g = synth.config1(B=1, seed=7000 + n_bus, n_bus=n_bus, n_branch=int(1.47 * n_bus),
+                          n_pv=max(1, n_bus // 6))["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(n_bus)
+    vm0 = g.vm + rng.normal(0, 0.01, g.n_bus) * (g.bus_type == 0)
+    va0 = g.va + rng.normal(0, 0.01, g.n_bus) * (g.bus_type != 2)
+    steps = 6
+    print(f"variant test n={g.n_bus}", flush=True)
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va,
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+    assert out["iters"].item() == steps and out["status"].item() == 1
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-11
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-11
+    assert abs(out["max_mis"].item() - ref["mu"]) <= 1e-9 * ref["mu"]
+
+
+def test_large_angles_use_correct_reduction(dpf):
+    """Angles far outside [-pi, pi] (including the out-of-line wide path)
+    give the same mismatch as the oracle's libm sin/cos."""
+    g = synth.config0(2)["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(0)
+    B = 6
+    vm = np.tile(g.vm, (B, 1))
+    va = np.tile(g.va, (B, 1))
+    shifts = [0.0, 2 * np.pi * 3, -2 * np.pi * 1000, 12345.678, -5.0e5, 3.0e6]
+    for c, sft in enumerate(shifts):
+        va[c] = va[c] + sft + rng.uniform(-4, 4, g.n_bus)
+    Yg = dgrid(dpf, g)
+    r = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va))
+    torch.cuda.synchronize()
+    for c in range(B):
+        dS = oracle.mismatch(Yo, vm[c], va[c], S)
+        assert relerr(r["dS"][c].cpu().numpy(), dS) < 1e-12
