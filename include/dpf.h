@@ -52,6 +52,7 @@ extern "C" {
 #define DPF_CONVERGED 0
 #define DPF_MAX_ITER 1
 #define DPF_NONFINITE 2
+#define DPF_BAD_GRID 3   /* a CSR row is longer than the grid's declared max_row_nnz */
 
 /* learning-rate schedules (Table 2 and Table 3 of the paper use the last two) */
 #define DPF_SCHED_CONSTANT 0
@@ -64,11 +65,13 @@ extern "C" {
  * by column, the diagonal always stored.  The branch arrays are only read by
  * the N-1 outage correction and may be NULL (n_branch = 0) otherwise.
  * Several independent grids can be concatenated into one block-diagonal CSR
- * (column indices global); see `sub_offset` of dpf_solve_batch.
+ * (column indices global); see `sub_offset` of dpf_solve_batch.  max_row_nnz
+ * sizes the solve workspace; 0 makes the library assume the worst case (nnz).
  */
 typedef struct dpf_grid {
     int32_t n_bus;
     int32_t nnz;
+    int32_t max_row_nnz;    /* longest CSR row (as returned by dpf_build_ybus), or 0 if unknown */
     const int32_t *row_ptr; /* [n_bus + 1] */
     const int32_t *col_idx; /* [nnz] */
     const double *val;      /* [2 * nnz] complex */
@@ -125,6 +128,7 @@ const char *dpf_version(void);
  *   col_idx, val      : device [nnz_cap], [2*nnz_cap] out; nnz_cap >= n_bus + 2*n_branch
  *                       always suffices
  *   nnz_out           : host out; this call SYNCHRONISES `stream` to return it
+ *   max_row_nnz_out   : host out (nullable): the longest row, for dpf_grid_t.max_row_nnz
  * Errors: DPF_EINVAL for n_bus <= 0, n_branch < 0, a bus index out of range,
  * from == to, or r = x = 0 (detected on the device); DPF_ECAP if the result
  * does not fit (nnz_out still receives the needed size).  Temporaries are
@@ -133,7 +137,7 @@ const char *dpf_version(void);
 int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
                    const double *r, const double *x, const double *b, int32_t nnz_cap,
                    int32_t *row_ptr, int32_t *col_idx, double *val, int32_t *nnz_out,
-                   void *stream);
+                   int32_t *max_row_nnz_out, void *stream);
 
 /*
  * dpf_mismatch_grad -- one evaluation of the DPF forward and backward pass for
@@ -182,6 +186,10 @@ size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B);
  * do not share a loss).  An item stops when max|dS| < tol (status 0), when its
  * iteration count reaches max_iter (status 1), or when its mismatch becomes
  * non-finite (status 2); a stopped item leaves the kernel while others go on.
+ * Status 3 (DPF_BAD_GRID, iters 0) reports a CSR row longer than g->max_row_nnz.
+ * Per call the library re-lays Y out in the workspace as 64-row slices
+ * (column-major within a slice) so that each wave reads its rows' neighbour
+ * entries with coalesced loads.
  *
  *   g             : grid
  *   n_sub, sub_offset, sub_offset_dev : sub-grid bus offsets [n_sub + 1], the
@@ -211,7 +219,7 @@ size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B);
  *   iters, status : device int32 [B*n_sub] out (index c*n_sub + s); iters = number
  *                   of Adam updates applied in this call
  *   max_mis, loss : device double [B*n_sub] out, at the returned voltages
- *   workspace     : device, >= dpf_solve_workspace_bytes(...) bytes
+ *   workspace     : device, >= dpf_solve_workspace_bytes(g, n_sub, sub_offset, B, ld) bytes
  * Errors: DPF_EINVAL (sizes, pointers, opts out of range, a sub-grid larger than
  * the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
  */
@@ -223,11 +231,32 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                     int32_t *status, double *max_mis, double *loss, void *workspace,
                     size_t ws_bytes, void *stream);
 
-size_t dpf_solve_workspace_bytes(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset,
+size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
                                  int32_t B, int32_t ld);
 
 /* Largest sub-grid (buses) one solve item can hold on this device. */
 int32_t dpf_solve_max_sub_buses(void);
+
+/*
+ * Kernel variants and the autotune cache.  dpf_solve_batch picks a kernel
+ * variant (workgroup size, buses per thread, register-resident or streaming
+ * state) from the largest sub-grid of the call.  Sizes are grouped into
+ * classes (the smallest variant that holds them); dpf_autotune_set records,
+ * for the class of n_max, which variant to use instead -- a project-side
+ * autotuner times the eligible variants on real inputs and stores the fastest.
+ * The cache is process-wide and guarded by a mutex.
+ *   dpf_solve_variant_count : number of variants
+ *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
+ *                             streaming (1) or register-resident (0); host outs
+ *   dpf_solve_variant_for   : variant index dpf_solve_batch would use, -1 if none
+ *   dpf_autotune_set        : DPF_EINVAL if the variant cannot hold n_max buses
+ *   dpf_autotune_reset      : forget every choice
+ */
+int dpf_solve_variant_count(void);
+int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming);
+int dpf_solve_variant_for(int32_t n_max);
+int dpf_autotune_set(int32_t n_max, int variant);
+void dpf_autotune_reset(void);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpf.so")
 
 DPF_OK, DPF_EINVAL, DPF_ECAP, DPF_EHIP, DPF_ENOMEM, DPF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CONVERGED, MAX_ITER, NONFINITE = 0, 1, 2
+CONVERGED, MAX_ITER, NONFINITE, BAD_GRID = 0, 1, 2, 3
 SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
 PQ, PV, SLACK = 0, 1, 2
 
@@ -34,7 +34,7 @@ _f64 = ctypes.c_double
 
 
 class _Grid(ctypes.Structure):
-    _fields_ = [("n_bus", _i32), ("nnz", _i32), ("row_ptr", _P), ("col_idx", _P), ("val", _P),
+    _fields_ = [("n_bus", _i32), ("nnz", _i32), ("max_row_nnz", _i32), ("row_ptr", _P), ("col_idx", _P), ("val", _P),
                 ("n_branch", _i32), ("from_", _P), ("to", _P), ("r", _P), ("x", _P), ("b", _P)]
 
 
@@ -56,7 +56,7 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.dpf_last_error.restype = ctypes.c_char_p
         L.dpf_version.restype = ctypes.c_char_p
-        L.dpf_build_ybus.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P]
+        L.dpf_build_ybus.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]
         L.dpf_build_ybus.restype = ctypes.c_int
         L.dpf_mismatch_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P,
                                         _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
@@ -67,9 +67,17 @@ def lib():
                                       _P, _P, _P, _P, ctypes.POINTER(_Opts), _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P]
         L.dpf_solve_batch.restype = ctypes.c_int
-        L.dpf_solve_workspace_bytes.argtypes = [_i32, _i32, _P, _i32, _i32]
+        L.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _i32, _i32]
         L.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_solve_max_sub_buses.restype = _i32
+        L.dpf_solve_variant_count.restype = ctypes.c_int
+        L.dpf_solve_variant_info.argtypes = [ctypes.c_int, _P, _P, _P]
+        L.dpf_solve_variant_info.restype = ctypes.c_int
+        L.dpf_solve_variant_for.argtypes = [_i32]
+        L.dpf_solve_variant_for.restype = ctypes.c_int
+        L.dpf_autotune_set.argtypes = [_i32, ctypes.c_int]
+        L.dpf_autotune_set.restype = ctypes.c_int
+        L.dpf_autotune_reset.restype = None
         _lib = L
     return _lib
 
@@ -100,6 +108,7 @@ class DeviceGrid:
     row_ptr: torch.Tensor
     col_idx: torch.Tensor
     val: torch.Tensor  # complex128
+    max_row_nnz: int = 0
     f: torch.Tensor | None = None
     t: torch.Tensor | None = None
     r: torch.Tensor | None = None
@@ -114,7 +123,8 @@ class DeviceGrid:
     def c(self) -> _Grid:
         if self._c is None:
             nb = self.n_branch
-            self._c = _Grid(self.n_bus, self.nnz, _ptr(self.row_ptr), _ptr(self.col_idx), _ptr(self.val), nb,
+            self._c = _Grid(self.n_bus, self.nnz, int(self.max_row_nnz), _ptr(self.row_ptr), _ptr(self.col_idx),
+                            _ptr(self.val), nb,
                             _ptr(self.f) if nb else None, _ptr(self.t) if nb else None,
                             _ptr(self.r) if nb else None, _ptr(self.x) if nb else None,
                             _ptr(self.b) if nb else None)
@@ -131,10 +141,11 @@ def build_ybus(n_bus: int, f, t, r, x, b, device="cuda") -> DeviceGrid:
     col = torch.empty(max(cap, 1), dtype=torch.int32, device=device)
     val = torch.empty(max(cap, 1), dtype=torch.complex128, device=device)
     nnz = ctypes.c_int32(0)
+    mrow = ctypes.c_int32(0)
     _check(lib().dpf_build_ybus(n_bus, nbr, _ptr(f), _ptr(t), _ptr(r), _ptr(x), _ptr(b), cap, _ptr(row_ptr),
-                                _ptr(col), _ptr(val), ctypes.byref(nnz), _stream()))
+                                _ptr(col), _ptr(val), ctypes.byref(nnz), ctypes.byref(mrow), _stream()))
     k = nnz.value
-    return DeviceGrid(n_bus, k, row_ptr, col[:k].clone(), val[:k].clone(), f, t, r, x, b)
+    return DeviceGrid(n_bus, k, row_ptr, col[:k].clone(), val[:k].clone(), mrow.value, f, t, r, x, b)
 
 
 def mismatch_grad(grid: DeviceGrid, bus_type, s_spec, vm, va, outage=None, want_dS=True, want_grad=True):
@@ -200,12 +211,13 @@ class SolveWorkspace:
 _default_ws = SolveWorkspace()
 
 
-def solve_workspace_bytes(n_bus, B, ld=None, sub_offset=None) -> int:
-    ld = n_bus if ld is None else ld
+def solve_workspace_bytes(grid: DeviceGrid, B, ld=None, sub_offset=None) -> int:
+    ld = grid.n_bus if ld is None else ld
+    g = grid.c()
     if sub_offset is None:
-        return int(lib().dpf_solve_workspace_bytes(n_bus, 1, None, B, ld))
+        return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, B, ld))
     so = (ctypes.c_int32 * len(sub_offset))(*[int(v) for v in sub_offset])
-    return int(lib().dpf_solve_workspace_bytes(n_bus, len(sub_offset) - 1, so, B, ld))
+    return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), len(sub_offset) - 1, so, B, ld))
 
 
 def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = None, outage=None,
@@ -239,9 +251,9 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
                    "status": torch.empty(items, dtype=torch.int32, device=dev),
                    "max_mis": torch.empty(items, dtype=torch.float64, device=dev),
                    "loss": torch.empty(items, dtype=torch.float64, device=dev)}
-    wsb = int(lib().dpf_solve_workspace_bytes(grid.n_bus, n_sub, so_h, B, ld))
-    ws = (workspace or _default_ws).get(wsb, dev)
     g = grid.c()
+    wsb = int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), n_sub, so_h, B, ld))
+    ws = (workspace or _default_ws).get(wsb, dev)
     o = opts.c()
     _check(lib().dpf_solve_batch(ctypes.byref(g), n_sub, so_h, _ptr(so_d), B, ld, _ptr(bt), _ptr(s), s_ld,
                                  _ptr(out), _ptr(vm), _ptr(va), _ptr(adam_state), _ptr(sched_state),
@@ -289,3 +301,56 @@ class DPFLoss(torch.autograd.Function):
     def backward(ctx, grad_loss, grad_mx):
         gv, ga = ctx.saved_tensors
         return grad_loss[:, None] * gv, grad_loss[:, None] * ga, None, None, None, None
+
+
+# ---------------------------------------------------------------- autotuner
+
+
+def variants():
+    """The solve kernel variants: list of dicts (index, threads, buses_per_thread, streaming)."""
+    L = lib()
+    out = []
+    for i in range(L.dpf_solve_variant_count()):
+        t, k, st = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(L.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)))
+        out.append({"index": i, "threads": t.value, "buses_per_thread": k.value, "streaming": bool(st.value)})
+    return out
+
+
+def variant_for(n_max: int) -> int:
+    return int(lib().dpf_solve_variant_for(int(n_max)))
+
+
+def autotune_reset():
+    lib().dpf_autotune_reset()
+
+
+def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,
+             iters: int = 40, reps: int = 2):
+    """Time every kernel variant that can hold the largest sub-grid on copies of
+    the real inputs (``iters`` Adam iterations, no stop test) and record the
+    fastest in the library's autotune cache.  Returns {variant: seconds}."""
+    opts = opts or Options()
+    n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))
+    probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
+    times = {}
+    for v in variants():
+        if not (v["buses_per_thread"] == 0 or v["threads"] * v["buses_per_thread"] >= n_max):
+            continue
+        _check(lib().dpf_autotune_set(n_max, v["index"]))
+        best = None
+        for _ in range(reps):
+            vm1, va1 = vm.clone(), va.clone()
+            torch.cuda.synchronize()
+            st = torch.cuda.Event(enable_timing=True)
+            en = torch.cuda.Event(enable_timing=True)
+            st.record()
+            solve(grid, bus_type, s_spec, vm1, va1, opts=probe, outage=outage, sub_offset=sub_offset)
+            en.record()
+            torch.cuda.synchronize()
+            dt = st.elapsed_time(en) * 1e-3
+            best = dt if best is None else min(best, dt)
+        times[v["index"]] = best
+    pick = min(times, key=times.get)
+    _check(lib().dpf_autotune_set(n_max, pick))
+    return {"choice": pick, "seconds": times, "n_max": n_max, "iters": iters}

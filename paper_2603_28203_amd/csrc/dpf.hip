@@ -10,6 +10,7 @@
 #include "../../include/dpf.h"
 #include "common.hpp"
 #include "eval.hpp"
+#include "sell.hpp"
 #include "solve.hpp"
 #include "ybus.hpp"
 
@@ -80,20 +81,48 @@ template <int NT, int K>
 Variant make_variant() {
     return Variant{NT, K, dpf::kReg, dpf::team_solve_kernel<NT, K, dpf::kReg>};
 }
-template <int NT>
+template <int NT, int K>
 Variant make_stream_variant() {
-    return Variant{NT, 1 << 20, dpf::kGlobal, dpf::team_solve_stream_kernel<NT>};
+    return Variant{NT, K, dpf::kGlobal, dpf::team_solve_stream_kernel<NT, K>};
 }
 
-// Register-resident variants up to 2048 buses per item, streaming above.
-const Variant *pick_variant(int32_t n_max) {
+// Register-resident variants up to 2048 buses per item, streaming above (512 threads
+// keep 256 VGPRs per thread, enough for 20 buses of held exchange values; the
+// 1024-thread streaming variant takes any size with holds in scratch).
+const Variant *variant_table(int *count) {
     static const Variant table[] = {
         make_variant<64, 1>(),  make_variant<128, 1>(), make_variant<256, 1>(), make_variant<256, 2>(),
-        make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<1024>(),
+        make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<512, 8>(),
+        make_stream_variant<512, 12>(), make_stream_variant<512, 16>(), make_stream_variant<512, 20>(),
+        make_stream_variant<1024, 0>(),
     };
-    for (const Variant &v : table)
-        if ((int64_t)n_max <= (int64_t)v.nt * v.k) return &v;
-    return nullptr;
+    *count = (int)(sizeof(table) / sizeof(table[0]));
+    return table;
+}
+
+bool variant_fits(const Variant &v, int32_t n_max) { return v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k; }
+
+// Autotune cache: size class (index of the default variant) -> chosen variant.
+std::mutex g_tune_mu;
+int g_tune[64];
+bool g_tune_init = false;
+
+int default_variant_index(int32_t n_max) {
+    int cnt = 0;
+    const Variant *t = variant_table(&cnt);
+    for (int i = 0; i < cnt; ++i)
+        if (variant_fits(t[i], n_max)) return i;
+    return -1;
+}
+
+const Variant *pick_variant(int32_t n_max) {
+    int cnt = 0;
+    const Variant *t = variant_table(&cnt);
+    int d = default_variant_index(n_max);
+    if (d < 0) return nullptr;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (g_tune_init && g_tune[d] >= 0 && g_tune[d] < cnt && variant_fits(t[g_tune[d]], n_max)) return &t[g_tune[d]];
+    return &t[d];
 }
 
 bool valid_opts(const dpf_opts_t *o) {
@@ -121,7 +150,7 @@ const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64)"; }
 
 int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
                    const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
-                   double *val, int32_t *nnz_out, void *stream) {
+                   double *val, int32_t *nnz_out, int32_t *max_row_nnz_out, void *stream) {
     g_err.clear();
     if (n_bus <= 0 || n_branch < 0) return fail(DPF_EINVAL, "n_bus must be > 0 and n_branch >= 0");
     if (n_branch > 0 && (!from || !to || !r || !x || !b)) return fail(DPF_EINVAL, "null branch array");
@@ -170,11 +199,15 @@ int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const i
         hipLaunchKernelGGL(dpf::ybus_row_order_kernel, dim3(gn), dim3(bs), 0, st, n_bus, soff, slot, r, x, b, diag,
                            ucount);
         hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_bus, ucount, 0, row_ptr);
+        hipLaunchKernelGGL(dpf::imax_kernel, dim3(1), dim3(1024), 0, st, n_bus, ucount, err + 1);
+        int32_t hmax = 0;
         e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(&hmax, err + 1, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipMemcpyAsync(&nnz, row_ptr + n_bus, sizeof(int32_t), hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("ybus pattern: ") + hipGetErrorString(e)); break; }
         *nnz_out = nnz;
+        if (max_row_nnz_out) *max_row_nnz_out = hmax;
         if (nnz > nnz_cap) { rc = fail(DPF_ECAP, "nnz_cap too small"); break; }
         hipLaunchKernelGGL(dpf::ybus_emit_kernel, dim3(gn), dim3(bs), 0, st, n_bus, soff, slot, r, x, diag, row_ptr,
                            nnz_cap, col_idx, (double2 *)val);
@@ -235,10 +268,98 @@ int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *
     return DPF_OK;
 }
 
+int dpf_solve_variant_count(void) {
+    int cnt = 0;
+    variant_table(&cnt);
+    return cnt;
+}
+
+int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming) {
+    g_err.clear();
+    int cnt = 0;
+    const Variant *t = variant_table(&cnt);
+    if (idx < 0 || idx >= cnt || !threads || !buses_per_thread || !streaming)
+        return fail(DPF_EINVAL, "variant index out of range or null output");
+    *threads = t[idx].nt;
+    *buses_per_thread = t[idx].k;
+    *streaming = t[idx].mode == dpf::kGlobal;
+    return DPF_OK;
+}
+
+int dpf_solve_variant_for(int32_t n_max) {
+    const Variant *v = pick_variant(n_max);
+    if (!v) return -1;
+    int cnt = 0;
+    return (int)(v - variant_table(&cnt));
+}
+
+int dpf_autotune_set(int32_t n_max, int variant) {
+    g_err.clear();
+    int cnt = 0;
+    const Variant *t = variant_table(&cnt);
+    int d = default_variant_index(n_max);
+    if (d < 0) return fail(DPF_EINVAL, "no variant holds a sub-grid of this size");
+    if (variant < 0 || variant >= cnt || !variant_fits(t[variant], n_max))
+        return fail(DPF_EINVAL, "variant cannot hold a sub-grid of this size");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    if (!g_tune_init) {
+        for (int &x : g_tune) x = -1;
+        g_tune_init = true;
+    }
+    g_tune[d] = variant;
+    return DPF_OK;
+}
+
+void dpf_autotune_reset(void) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int &x : g_tune) x = -1;
+    g_tune_init = true;
+}
+
 int32_t dpf_solve_max_sub_buses(void) {
     DeviceInfo d;
     if (device_info(d) != DPF_OK) return 0;
     return max_sub_buses_for(d);
+}
+
+struct SolveLayout {
+    int32_t n_slices = 0;
+    int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
+    size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
+    size_t off_mom = 0, off_scr = 0, total = 0;
+};
+
+static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
+                                int32_t ld, bool streaming) {
+    SolveLayout L;
+    if (!sub_offset) {
+        L.n_slices = (g->n_bus + 63) / 64;
+    } else {
+        for (int32_t s = 0; s < n_sub; ++s) L.n_slices += (sub_offset[s + 1] - sub_offset[s] + 63) / 64;
+    }
+    int64_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
+    L.entries = std::min<int64_t>((int64_t)L.n_slices * 64 * wmax, (int64_t)64 * std::max<int32_t>(g->nnz, 1));
+    size_t o = 256;  // [0]: bad-grid flag
+    L.off_nslice = o;
+    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+    L.off_slice_off = o;
+    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+    L.off_width = o;
+    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
+    L.off_start = o;
+    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
+    L.off_col = o;
+    o += align_up(sizeof(int32_t) * (size_t)L.entries, 256);
+    L.off_val = o;
+    o += align_up(sizeof(double2) * (size_t)L.entries, 256);
+    if (streaming) {
+        L.off_mom = o;  // Adam moments [4][B][ld] when the caller passes none
+        o += align_up(sizeof(double) * 4 * (size_t)B * ld, 256);
+        L.off_scr = o;  // V, a*I and w [3][B][ld] complex
+        o += align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
+    }
+    L.total = o;
+    return L;
 }
 
 static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset) {
@@ -248,12 +369,12 @@ static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_off
     return m;
 }
 
-size_t dpf_solve_workspace_bytes(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset, int32_t B, int32_t ld) {
-    if (n_bus <= 0 || B <= 0 || ld < n_bus) return 0;
-    const Variant *v = pick_variant(max_sub_size(n_bus, sub_offset ? n_sub : 1, sub_offset));
-    if (!v || v->mode == dpf::kReg) return 256;
-    // moments [4][B][ld] + scratch [3][B][ld] complex
-    return 256 + align_up(sizeof(double) * 4 * (size_t)B * ld, 256) + align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
+size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
+                                 int32_t ld) {
+    if (!g || g->n_bus <= 0 || B <= 0 || ld < g->n_bus) return 0;
+    if (!sub_offset) n_sub = 1;
+    const Variant *v = pick_variant(max_sub_size(g->n_bus, n_sub, sub_offset));
+    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode == dpf::kGlobal).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -291,9 +412,32 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                                                         std::to_string(cap) + ")");
     const Variant *v = pick_variant(n_max);
     if (!v) return fail(DPF_EUNSUPPORTED, "sub-grid too large");
-    size_t need = dpf_solve_workspace_bytes(g->n_bus, n_sub, sub_offset, B, ld);
-    if (!workspace || ws_bytes < need) return fail(DPF_ENOMEM, "workspace too small");
+    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode == dpf::kGlobal);
+    if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    int32_t *bad = (int32_t *)ws;
+    int32_t *nslice = (int32_t *)(ws + L.off_nslice);
+    int32_t *slice_off = (int32_t *)(ws + L.off_slice_off);
+    int32_t *width = (int32_t *)(ws + L.off_width);
+    int32_t *start = (int32_t *)(ws + L.off_start);
+    int32_t *scol = (int32_t *)(ws + L.off_col);
+    double2 *sval = (double2 *)(ws + L.off_val);
+    const int32_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
+    // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
+    // so that the whole call can be captured in a graph)
+    hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
+                       g->n_bus, nslice, bad);
+    hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
+    if (L.n_slices > 0) {
+        hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
+                           g->n_bus, slice_off, g->row_ptr, wmax, width, bad);
+        hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, L.n_slices, width, 0, start);
+        hipLaunchKernelGGL(dpf::sell_fill_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
+                           g->n_bus, slice_off, g->row_ptr, g->col_idx, (const double2 *)g->val, width, start, scol,
+                           sval);
+    }
+    DPF_HIP(hipGetLastError());
 
     dpf::SolveArgs a{};
     a.rp = g->row_ptr;
@@ -307,10 +451,11 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.va = va;
     a.ld = ld;
     a.st_stride = (int64_t)B * ld;
-    char *ws = (char *)workspace;
+    a.sell = dpf::SellView{slice_off, width, start, scol, sval};
+    a.bad_grid = bad;
     if (v->mode == dpf::kGlobal) {
-        double *mom = (double *)(ws + 256);
-        a.scratch = (double2 *)(ws + 256 + align_up(sizeof(double) * 4 * (size_t)B * ld, 256));
+        double *mom = (double *)(ws + L.off_mom);
+        a.scratch = (double2 *)(ws + L.off_scr);
         a.st = adam_state ? adam_state : mom;
     } else {
         a.scratch = nullptr;

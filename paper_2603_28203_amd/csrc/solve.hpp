@@ -29,6 +29,7 @@
 #include "../../include/dpf.h"
 #include "common.hpp"
 #include "eval.hpp"
+#include "sell.hpp"
 
 namespace dpf {
 
@@ -53,6 +54,8 @@ struct SolveArgs {
     double2 *scratch;    // streaming: [3][B][ld] complex (V, a*I, w)
     double *sched;       // [items][6] (t, lr, best, bad + cooldown * 2^20, b1^t, b2^t) or null
     const int32_t *sub_off;  // device [n_sub + 1] or null
+    SellView sell;           // sliced-ELL copy of Y (local columns)
+    const int32_t *bad_grid; // set when a row exceeded the declared width bound
     int32_t n_bus;
     int32_t n_sub;
     int32_t B;
@@ -108,10 +111,15 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
-    if (n < 0 || n > NT * K || n > a.lds_cap) {  // host guarantees this never happens
-        if (tid == 0) a.status[out_idx] = -1;
+    if (n < 0 || n > NT * K || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
+        if (tid == 0) {
+            a.status[out_idx] = DPF_BAD_GRID;
+            a.iters[out_idx] = 0;
+        }
         return;
     }
+    const int slice0 = a.sell.slice_off[sidx];
+    const int lane = tid & (kWave - 1);
     const bool dbl = 2 * n <= a.lds_cap;
     double2 *Xv = X;
     double2 *Xw = dbl ? X + n : X;
@@ -182,7 +190,6 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     double2 V[KR], aI[KR], Sr[KR];
     double vmr[KR], var_[KR], mvr[KR], mar[KR], svr[KR], sar[KR];
     int8_t ty[KR];
-    int r0[KR], r1[KR];
     double2 hold[K];
 
 #pragma unroll
@@ -191,7 +198,6 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         hold[k] = make_double2(0.0, 0.0);
         if (REG) {
             ty[k % KR] = kSlack;
-            r0[k % KR] = r1[k % KR] = 0;
             V[k % KR] = aI[k % KR] = Sr[k % KR] = make_double2(0.0, 0.0);
             vmr[k % KR] = var_[k % KR] = mvr[k % KR] = mar[k % KR] = svr[k % KR] = sar[k % KR] = 0.0;
         }
@@ -202,8 +208,6 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
             const double2 v = make_double2(vmi * cs, vmi * sn);
             if (REG) {
                 ty[k % KR] = a.bt[i];
-                r0[k % KR] = a.rp[i];
-                r1[k % KR] = a.rp[i + 1];
                 V[k % KR] = v;
                 vmr[k % KR] = vmi;
                 var_[k % KR] = vai;
@@ -237,15 +241,15 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         for (int k = 0; k < K; ++k) {
             const int i = lo + tid + k * NT;
             if (i < hi) {
-                const int q0 = REG ? r0[k % KR] : a.rp[i];
-                const int q1 = REG ? r1[k % KR] : a.rp[i + 1];
                 const int8_t tk = REG ? ty[k % KR] : a.bt[i];
                 const int il = i - lo;
+                const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                const int wdt = a.sell.width[gsl];
+                const int base = a.sell.start[gsl] * kWave + lane;
                 double2 acc = make_double2(0.0, 0.0);
-                for (int q = q0; q < q1; ++q) {
-                    const int j = a.ci[q] - lo;
-                    if ((uint32_t)j < (uint32_t)n) acc = cfma(a.yv[q], Xv[j], acc);
-                }
+#pragma unroll 4
+                for (int q = 0; q < wdt; ++q)
+                    acc = cfma(a.sell.val[base + q * kWave], Xv[a.sell.col[base + q * kWave]], acc);
                 if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
                 else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
                 const double2 v = REG ? V[k % KR] : Xv[il];
@@ -299,15 +303,15 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         for (int k = 0; k < K; ++k) {
             const int i = lo + tid + k * NT;
             if (i < hi) {
-                const int q0 = REG ? r0[k % KR] : a.rp[i];
-                const int q1 = REG ? r1[k % KR] : a.rp[i + 1];
                 const int8_t tk = REG ? ty[k % KR] : a.bt[i];
                 const int il = i - lo;
+                const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                const int wdt = a.sell.width[gsl];
+                const int base = a.sell.start[gsl] * kWave + lane;
                 double2 h = make_double2(0.0, 0.0);
-                for (int q = q0; q < q1; ++q) {
-                    const int j = a.ci[q] - lo;
-                    if ((uint32_t)j < (uint32_t)n) h = cfma(a.yv[q], Xw[j], h);
-                }
+#pragma unroll 4
+                for (int q = 0; q < wdt; ++q)
+                    h = cfma(a.sell.val[base + q * kWave], Xw[a.sell.col[base + q * kWave]], h);
                 if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
                 else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
                 double2 v, ai;
@@ -443,12 +447,27 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     }
 }
 
-// Streaming variant for large sub-grids: the per-bus loop is a runtime loop
-// (no per-bus registers), every per-bus value lives in global memory: the
-// caller's vm/va/Adam arrays and the scratch arrays V, a*I and w.  LDS holds
-// the exchange vector (double-buffered when it fits).
-template <int NT>
+// Streaming variant for large sub-grids.  Every per-bus value lives in global
+// memory (the caller's vm/va/Adam arrays and the scratch arrays V and a*I) and
+// is streamed once per iteration; the only per-bus registers are `hold`, which
+// carry w (after phase A) and the new V (after phase B) across the barrier of
+// the single-buffered LDS exchange.  K = buses per thread is a compile-time
+// bound so that `hold` stays in registers; the per-bus address arithmetic is
+// re-derived inside the iteration (opaque_index) instead of being kept live.
+__device__ __forceinline__ uint32_t opaque_index(uint32_t i) {
+    asm volatile("" : "+v"(i));
+    return i;
+}
+
+template <int NT, int K>
 __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
+    // K > 0: each thread owns at most K buses and holds w / new V in registers.
+    // K == 0: runtime loop over any number of buses per thread; w goes through
+    // the scratch array W and the new V is re-read from V (both L2-resident),
+    // which keeps the register count low enough for 1024-thread workgroups.
+    constexpr bool HOLD = K > 0;
+    constexpr int KH = HOLD ? K : 1;
+    constexpr int KLOOP = HOLD ? K : (1 << 30);
     extern __shared__ double2 X[];
     __shared__ double red[2][NT / kWave];
 
@@ -460,10 +479,15 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
-    if (n < 0 || n > a.lds_cap) {  // host guarantees this never happens
-        if (tid == 0) a.status[out_idx] = -1;
+    if (n < 0 || (HOLD && n > NT * K) || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
+        if (tid == 0) {
+            a.status[out_idx] = DPF_BAD_GRID;
+            a.iters[out_idx] = 0;
+        }
         return;
     }
+    const int slice0 = a.sell.slice_off[sidx];
+    const int lane = tid & (kWave - 1);
     const bool dbl = 2 * n <= a.lds_cap;
     double2 *Xv = X;
     double2 *Xw = dbl ? X + n : X;
@@ -516,23 +540,26 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 
     const int64_t cb = (int64_t)c * a.ld;
     const int64_t sb = (int64_t)c * a.s_ld;
-    double *vm_c = a.vm + cb;
-    double *va_c = a.va + cb;
-    double *mv_c = a.st + cb;
-    double *ma_c = a.st + a.st_stride + cb;
-    double *sv_c = a.st + 2 * a.st_stride + cb;
-    double *sa_c = a.st + 3 * a.st_stride + cb;
-    double2 *Vg = a.scratch + cb;
-    double2 *aIg = a.scratch + a.st_stride + cb;
-    double2 *Wg = a.scratch + 2 * a.st_stride + cb;
-    const double2 *Sc = a.s_spec + sb;
+    double2 *__restrict__ Wg = HOLD ? nullptr : a.scratch + 2 * a.st_stride + cb;
+    double *__restrict__ vm_c = a.vm + cb;
+    double *__restrict__ va_c = a.va + cb;
+    double *__restrict__ mv_c = a.st + cb;
+    double *__restrict__ ma_c = a.st + a.st_stride + cb;
+    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb;
+    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *__restrict__ aIg = a.scratch + a.st_stride + cb;
+    const double2 *__restrict__ Sc = a.s_spec + sb;
+    const int32_t *__restrict__ swidth = a.sell.width;
+    const int32_t *__restrict__ sstart = a.sell.start;
+    const int32_t *__restrict__ scol = a.sell.col;
+    const double2 *__restrict__ sval = a.sell.val;
+    const int8_t *__restrict__ btp = a.bt;
 
     for (int i = lo + tid; i < hi; i += NT) {
         double sn, cs;
         const double vmi = vm_c[i];
         fast_sincos(va_c[i], sn, cs);
         const double2 v = make_double2(vmi * cs, vmi * sn);
-        Vg[i] = v;
         Xv[i - lo] = v;
         if (a.st_fresh) {
             mv_c[i] = 0.0;
@@ -543,37 +570,63 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     }
     __syncthreads();
 
+    double2 hold[KH];
+#pragma unroll
+    for (int k = 0; k < KH; ++k) hold[k] = make_double2(0.0, 0.0);
+    // bus loop of one phase: unrolled over the K owned buses, or a runtime loop
+#define DPF_BUS_LOOP_BEGIN                                                              \
+    _Pragma("unroll KH") for (int kk = 0; kk < KLOOP; ++kk) {                           \
+        const uint32_t i = opaque_index((uint32_t)(lo + tid + kk * NT));                \
+        if (!HOLD && (int)i >= hi) break;                                               \
+        if ((int)i < hi) {
+#define DPF_BUS_LOOP_END \
+    }                    \
+    }
+
     int it = 0, stat = DPF_MAX_ITER;
     double mu = 0.0, loss = 0.0;
     for (;; ++it) {
+        // ---------------- phase A
         double lsum = 0.0, lmax = 0.0;
-#pragma unroll 1
-        for (int i = lo + tid; i < hi; i += NT) {
-            const int il = i - lo;
-            const int q1 = a.rp[i + 1];
-            double2 acc = make_double2(0.0, 0.0);
-            for (int q = a.rp[i]; q < q1; ++q) {
-                const int j = a.ci[q] - lo;
-                if ((uint32_t)j < (uint32_t)n) acc = cfma(a.yv[q], Xv[j], acc);
-            }
-            if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
-            else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
-            const int8_t tk = a.bt[i];
-            const double2 v = Xv[il];
-            const double2 d = csub(cmulc(v, acc), Sc[i]);
-            const double rP = tk != kSlack ? d.x : 0.0;
-            const double rQ = tk == kPQ ? d.y : 0.0;
-            lsum += rP * rP + rQ * rQ;
-            lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
-            const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
-            aIg[i] = cmul(av, acc);
-            if (dbl) Xw[il] = cmulc(av, v);
-            else Wg[i] = cmulc(av, v);
-        }
+        DPF_BUS_LOOP_BEGIN
+                const int il = (int)i - lo;
+                // global loads of this bus first, so that they overlap the gather below
+                const int8_t tk = btp[i];
+                const double2 sp = Sc[i];
+                const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                const int wdt = swidth[gsl];
+                const int base = sstart[gsl] * kWave + lane;
+                double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+                for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], Xv[scol[base + q * kWave]], acc);
+                if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
+                else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
+                const double2 v = Xv[il];
+                const double2 d = csub(cmulc(v, acc), sp);
+                const double rP = tk != kSlack ? d.x : 0.0;
+                const double rQ = tk == kPQ ? d.y : 0.0;
+                lsum += rP * rP + rQ * rQ;
+                lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+                const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
+                aIg[i] = cmul(av, acc);
+                const double2 w = cmulc(av, v);
+                if (dbl) Xw[il] = w;
+                else if (HOLD) hold[kk % KH] = w;
+                else Wg[i] = w;
+        DPF_BUS_LOOP_END
         block_reduce2<NT>(lsum, lmax, red);
         __syncthreads();
-        if (!dbl)
-            for (int i = lo + tid; i < hi; i += NT) Xw[i - lo] = Wg[i];
+        if (!dbl) {
+            if (HOLD) {
+#pragma unroll
+                for (int k = 0; k < KH; ++k) {
+                    const int i = lo + tid + k * NT;
+                    if (i < hi) Xw[i - lo] = hold[k];
+                }
+            } else {
+                for (int i = lo + tid; i < hi; i += NT) Xw[i - lo] = Wg[i];
+            }
+        }
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
@@ -591,51 +644,58 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
             break;
         }
 
+        // ---------------- phase B
         t_step += 1.0;
         b1t *= a.b1;
         b2t *= a.b2;
         const double bc1 = 1.0 - b1t;
         const double bc2 = 1.0 - b2t;
-#pragma unroll 1
-        for (int i = lo + tid; i < hi; i += NT) {
-            const int il = i - lo;
-            const int q1 = a.rp[i + 1];
-            double2 h = make_double2(0.0, 0.0);
-            for (int q = a.rp[i]; q < q1; ++q) {
-                const int j = a.ci[q] - lo;
-                if ((uint32_t)j < (uint32_t)n) h = cfma(a.yv[q], Xw[j], h);
-            }
-            if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
-            else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
-            const int8_t tk = a.bt[i];
-            const double2 ai = aIg[i];
-            double2 v = Vg[i];
-            const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
-            double vmi = vm_c[i], vai = va_c[i];
-            if (tk == kPQ) {
-                const double g = (G.x * v.x + G.y * v.y) / vmi;
-                const double mv = a.b1 * mv_c[i] + (1.0 - a.b1) * g;
-                const double sv = a.b2 * sv_c[i] + (1.0 - a.b2) * (g * g);
-                vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
-                vm_c[i] = vmi;
-                mv_c[i] = mv;
-                sv_c[i] = sv;
-            }
-            if (tk != kSlack) {
-                const double g = G.y * v.x - G.x * v.y;
-                const double ma = a.b1 * ma_c[i] + (1.0 - a.b1) * g;
-                const double sa = a.b2 * sa_c[i] + (1.0 - a.b2) * (g * g);
-                vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
-                va_c[i] = vai;
-                ma_c[i] = ma;
-                sa_c[i] = sa;
-            }
-            double sn, cs;
-            fast_sincos(vai, sn, cs);
-            v = make_double2(vmi * cs, vmi * sn);
-            Vg[i] = v;
-            if (dbl) Xv[il] = v;
-        }
+        DPF_BUS_LOOP_BEGIN
+                const int il = (int)i - lo;
+                // every global load of this bus first, so that they overlap the gather
+                const int8_t tk = btp[i];
+                const double2 ai = aIg[i];
+                double vmi = vm_c[i], vai = va_c[i];
+                const double mv0 = mv_c[i], sv0 = sv_c[i], ma0 = ma_c[i], sa0 = sa_c[i];
+                const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                const int wdt = swidth[gsl];
+                const int base = sstart[gsl] * kWave + lane;
+                double2 h = make_double2(0.0, 0.0);
+#pragma unroll 4
+                for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], Xw[scol[base + q * kWave]], h);
+                if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
+                else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
+                const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+                double2 v;
+                {
+                    double sn0, cs0;
+                    fast_sincos(vai, sn0, cs0);
+                    v = make_double2(vmi * cs0, vmi * sn0);
+                }
+                if (tk == kPQ) {
+                    const double g = (G.x * v.x + G.y * v.y) / vmi;
+                    const double mv = a.b1 * mv0 + (1.0 - a.b1) * g;
+                    const double sv = a.b2 * sv0 + (1.0 - a.b2) * (g * g);
+                    vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                    vm_c[i] = vmi;
+                    mv_c[i] = mv;
+                    sv_c[i] = sv;
+                }
+                if (tk != kSlack) {
+                    const double g = G.y * v.x - G.x * v.y;
+                    const double ma = a.b1 * ma0 + (1.0 - a.b1) * g;
+                    const double sa = a.b2 * sa0 + (1.0 - a.b2) * (g * g);
+                    vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                    va_c[i] = vai;
+                    ma_c[i] = ma;
+                    sa_c[i] = sa;
+                }
+                double sn, cs;
+                fast_sincos(vai, sn, cs);
+                v = make_double2(vmi * cs, vmi * sn);
+                if (dbl) Xv[il] = v;
+                else if (HOLD) hold[kk % KH] = v;
+        DPF_BUS_LOOP_END
         if (a.sch == DPF_SCHED_PLATEAU) {
             if (loss < best * (1.0 - a.threshold)) {
                 best = loss;
@@ -659,10 +719,25 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
         }
         if (!dbl) {
             __syncthreads();
-            for (int i = lo + tid; i < hi; i += NT) Xv[i - lo] = Vg[i];
+            if (HOLD) {
+#pragma unroll
+                for (int k = 0; k < KH; ++k) {
+                    const int i = lo + tid + k * NT;
+                    if (i < hi) Xv[i - lo] = hold[k];
+                }
+            } else {
+                for (int i = lo + tid; i < hi; i += NT) {
+                    double sn, cs;
+                    const double vmi = vm_c[i];
+                    fast_sincos(va_c[i], sn, cs);
+                    Xv[i - lo] = make_double2(vmi * cs, vmi * sn);
+                }
+            }
         }
         __syncthreads();
     }
+#undef DPF_BUS_LOOP_BEGIN
+#undef DPF_BUS_LOOP_END
 
     if (tid == 0) {
         a.iters[out_idx] = it;

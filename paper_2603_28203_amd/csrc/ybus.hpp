@@ -60,6 +60,22 @@ __global__ __launch_bounds__(1024) void scan_kernel(int32_t n, const int32_t *__
     if (tid == 1023) out[n] = part[1023];
 }
 
+// max over in[0..n) into *out (one workgroup of 1024 threads)
+__global__ __launch_bounds__(1024) void imax_kernel(int32_t n, const int32_t *__restrict__ in, int32_t *__restrict__ out) {
+    __shared__ int32_t part[1024 / kWave];
+    int32_t m = 0;
+    for (int32_t i = threadIdx.x; i < n; i += 1024) m = max(m, in[i]);
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) m = max(m, __shfl_xor(m, o, kWave));
+    if ((threadIdx.x & (kWave - 1)) == 0) part[threadIdx.x / kWave] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t t = 0;
+        for (int k = 0; k < 1024 / kWave; ++k) t = max(t, part[k]);
+        *out = t;
+    }
+}
+
 __global__ void ybus_scatter_kernel(int32_t n_bus, int32_t n_branch, const int32_t *__restrict__ from,
                                     const int32_t *__restrict__ to, const int32_t *__restrict__ soff,
                                     int32_t *__restrict__ fill, int2 *__restrict__ slot) {

@@ -473,3 +473,20 @@ def test_large_angles_use_correct_reduction(dpf):
     for c in range(B):
         dS = oracle.mismatch(Yo, vm[c], va[c], S)
         assert relerr(r["dS"][c].cpu().numpy(), dS) < 1e-12
+
+
+def test_solve_reports_bad_grid_row_bound(dpf):
+    """A grid whose declared longest row is too short is reported per item
+    (status 3) instead of reading past the sliced copy."""
+    g = synth.config0(1)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    assert Yg.max_row_nnz == int(np.diff(Yg.row_ptr.cpu().numpy()).max())
+    Yg.max_row_nnz = 2
+    Yg._c = None
+    vm0, va0 = synth.flat_start(g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(max_iter=5))
+    torch.cuda.synchronize()
+    assert out["status"].item() == dpf.BAD_GRID and out["iters"].item() == 0
+    assert np.array_equal(vm[0].cpu().numpy(), vm0)
