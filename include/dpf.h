@@ -234,7 +234,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
                                  int32_t B, int32_t ld);
 
-/* Largest sub-grid (buses) one solve item can hold on this device. */
+/* Largest sub-grid (buses) one workgroup can hold on this device; larger sub-grids
+ * are solved by several workgroups (see dpf_autotune_set_team_cap). */
 int32_t dpf_solve_max_sub_buses(void);
 
 /*
@@ -250,12 +251,19 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             streaming (1) or register-resident (0); host outs
  *   dpf_solve_variant_for   : variant index dpf_solve_batch would use, -1 if none
  *   dpf_autotune_set        : DPF_EINVAL if the variant cannot hold n_max buses
- *   dpf_autotune_reset      : forget every choice
+ *   dpf_autotune_set_team_cap : sub-grids above `buses` take the multi-workgroup
+ *                             path (several workgroups per item, three kernels per
+ *                             iteration, host polls every 32 iterations) even when
+ *                             they would fit one workgroup's LDS; 0 = the LDS limit
+ *   dpf_autotune_reset      : forget every choice (and the team cap)
+ * Items larger than the LDS limit always take the multi-workgroup path; a call
+ * that has such items returns only after they have finished.
  */
 int dpf_solve_variant_count(void);
 int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming);
 int dpf_solve_variant_for(int32_t n_max);
 int dpf_autotune_set(int32_t n_max, int variant);
+int dpf_autotune_set_team_cap(int32_t buses);
 void dpf_autotune_reset(void);
 
 #ifdef __cplusplus

@@ -78,6 +78,8 @@ def lib():
         L.dpf_autotune_set.argtypes = [_i32, ctypes.c_int]
         L.dpf_autotune_set.restype = ctypes.c_int
         L.dpf_autotune_reset.restype = None
+        L.dpf_autotune_set_team_cap.argtypes = [_i32]
+        L.dpf_autotune_set_team_cap.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -323,6 +325,11 @@ def variant_for(n_max: int) -> int:
 
 def autotune_reset():
     lib().dpf_autotune_reset()
+
+
+def set_team_cap(buses: int):
+    """Route sub-grids above `buses` to the multi-workgroup path (0 = LDS limit)."""
+    _check(lib().dpf_autotune_set_team_cap(int(buses)))
 
 
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,

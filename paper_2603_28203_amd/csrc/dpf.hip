@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -12,6 +13,7 @@
 #include "eval.hpp"
 #include "sell.hpp"
 #include "solve.hpp"
+#include "wide.hpp"
 #include "ybus.hpp"
 
 namespace {
@@ -37,6 +39,9 @@ struct DeviceInfo {
     int lds_per_block = 0;  // bytes
     int n_cu = 0;
     bool ok = false;
+    hipStream_t side = nullptr;      // stream of the multi-workgroup path
+    hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
+    int32_t *pinned_count = nullptr; // host-pinned poll target
 };
 std::mutex g_dev_mu;
 DeviceInfo g_dev[64];
@@ -52,18 +57,29 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         g_dev[dev].lds_per_block = lds;
         g_dev[dev].n_cu = ncu;
+        DPF_HIP(hipStreamCreateWithFlags(&g_dev[dev].side, hipStreamNonBlocking));
+        DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_in, hipEventDisableTiming));
+        DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_out, hipEventDisableTiming));
+        DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_poll, hipEventDisableTiming));
+        DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, sizeof(int32_t), hipHostMallocDefault));
         g_dev[dev].ok = true;
     }
     out = g_dev[dev];
     return DPF_OK;
 }
 
+constexpr int kGfx950LdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
+
 // Bytes of static LDS the solve kernels use besides the dynamic exchange array.
 constexpr int kSolveStaticLds = 2 * (1024 / dpf::kWave) * 8 + 256;
 
+std::atomic<int32_t> g_team_cap_override{0};
+
 int32_t max_sub_buses_for(const DeviceInfo &d) {
     int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
-    return std::min<int32_t>(cap, 10 * 1024);
+    cap = std::min<int32_t>(cap, 10 * 1024);
+    const int32_t o = g_team_cap_override.load();
+    return o > 0 ? std::min(cap, o) : cap;
 }
 
 // ---------------------------------------------------------------- solve variants
@@ -138,6 +154,144 @@ bool valid_opts(const dpf_opts_t *o) {
 
 bool valid_grid(const dpf_grid_t *g) {
     return g && g->n_bus > 0 && g->nnz >= 0 && g->row_ptr && g->col_idx && g->val;
+}
+
+struct SolveLayout {
+    int32_t n_slices = 0;
+    int32_t w_total = 0;  // slices of the wide sub-grids (per case)
+    int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
+    size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
+    size_t off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0, off_items = 0;
+    size_t total = 0;
+};
+
+static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
+                                int32_t ld, bool streaming, int32_t team_cap) {
+    SolveLayout L;
+    for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
+        int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
+        L.n_slices += (ns + 63) / 64;
+        if (ns > team_cap) L.w_total += (ns + 63) / 64;
+    }
+    const bool wide = L.w_total > 0;
+    streaming = streaming || wide;
+    int64_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
+    L.entries = std::min<int64_t>((int64_t)L.n_slices * 64 * wmax, (int64_t)64 * std::max<int32_t>(g->nnz, 1));
+    size_t o = 256;  // [0]: bad-grid flag
+    L.off_nslice = o;
+    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+    L.off_slice_off = o;
+    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+    L.off_width = o;
+    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
+    L.off_start = o;
+    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
+    L.off_col = o;
+    o += align_up(sizeof(int32_t) * (size_t)L.entries, 256);
+    L.off_val = o;
+    o += align_up(sizeof(double2) * (size_t)L.entries, 256);
+    if (streaming) {
+        L.off_mom = o;  // Adam moments [4][B][ld] when the caller passes none
+        o += align_up(sizeof(double) * 4 * (size_t)B * ld, 256);
+        L.off_scr = o;  // V, a*I and w [3][B][ld] complex
+        o += align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
+    }
+    if (wide) {
+        L.off_wcount = o;
+        o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+        L.off_woff = o;
+        o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+        L.off_mres = o;
+        o += align_up(sizeof(double) * (size_t)n_sub, 256);
+        L.off_part = o;
+        o += align_up(sizeof(double2) * (size_t)B * L.w_total, 256);
+        L.off_items = o;
+        o += align_up(sizeof(dpf::WideItem) * (size_t)B * n_sub, 256);
+    }
+    L.total = o;
+    return L;
+}
+
+// Multi-workgroup path for sub-grids above the LDS capacity (see wide.hpp).
+// Runs on the device's side stream; the host enqueues chunks of iterations and
+// polls the number of active items, so this part of the call blocks the host.
+int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_sub, const int32_t *sub_offset_dev,
+             int32_t B, int32_t ld, int32_t cap, const DeviceInfo &dev) {
+    hipStream_t sd = dev.side;
+    dpf::WideArgs w{};
+    w.sell = a.sell;
+    w.sub_off = sub_offset_dev;
+    w.wide_off = (const int32_t *)(ws + L.off_woff);
+    w.nslice = (const int32_t *)(ws + L.off_nslice);
+    w.n_sub = n_sub;
+    w.B = B;
+    w.n_bus = a.n_bus;
+    w.w_total = L.w_total;
+    w.bt = a.bt;
+    w.s_spec = a.s_spec;
+    w.s_ld = a.s_ld;
+    w.ov = a.ov;
+    w.vm = a.vm;
+    w.va = a.va;
+    w.ld = ld;
+    w.st = a.st;
+    w.st_stride = a.st_stride;
+    w.st_fresh = a.st_fresh;
+    w.Vg = a.scratch;
+    w.aIg = a.scratch + a.st_stride;
+    w.Wg = a.scratch + 2 * a.st_stride;
+    w.part = (double2 *)(ws + L.off_part);
+    w.items = (dpf::WideItem *)(ws + L.off_items);
+    w.m_res = (const double *)(ws + L.off_mres);
+    w.sched = a.sched;
+    w.lr = a.lr;
+    w.b1 = a.b1;
+    w.b2 = a.b2;
+    w.eps = a.eps;
+    w.tol = a.tol;
+    w.max_iter = a.max_iter;
+    w.sch = a.sch;
+    w.factor = a.factor;
+    w.patience = a.patience;
+    w.threshold = a.threshold;
+    w.cooldown = a.cooldown;
+    w.min_lr = a.min_lr;
+    w.sched_eps = a.sched_eps;
+    w.iters = a.iters;
+    w.status = a.status;
+    w.mu_out = a.mu_out;
+    w.loss_out = a.loss_out;
+    int32_t *wcount = (int32_t *)(ws + L.off_wcount);
+    // the active counter sits in the 256-byte header of the workspace (word 1; word 0 is the bad-grid flag)
+    w.active_count = (int32_t *)ws + 1;
+    const int items = B * n_sub;
+    hipLaunchKernelGGL(dpf::wide_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, sd, n_sub, sub_offset_dev,
+                       a.n_bus, cap, w.nslice, wcount);
+    hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, sd, n_sub, wcount, 0, (int32_t *)w.wide_off);
+    hipLaunchKernelGGL(dpf::sub_residual_count_kernel, dim3(n_sub), dim3(256), 0, sd, n_sub, sub_offset_dev, a.n_bus,
+                       a.bt, (double *)w.m_res);
+    hipLaunchKernelGGL(dpf::wide_item_init_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
+    const int units = B * L.w_total;
+    const int ublocks = (units + 3) / 4;
+    hipLaunchKernelGGL(dpf::wide_init_rows_kernel, dim3(ublocks), dim3(256), 0, sd, w);
+    DPF_HIP(hipGetLastError());
+    const int chunk = 32;
+    for (int64_t done = 0; done <= (int64_t)a.max_iter; done += chunk) {
+        for (int k = 0; k < chunk && done + k <= (int64_t)a.max_iter; ++k) {
+            hipLaunchKernelGGL(dpf::wide_phase_a_kernel, dim3(ublocks), dim3(256), 0, sd, w);
+            hipLaunchKernelGGL(dpf::wide_reduce_kernel, dim3(items), dim3(dpf::kWave), 0, sd, w);
+            hipLaunchKernelGGL(dpf::wide_phase_b_kernel, dim3(ublocks), dim3(256), 0, sd, w);
+        }
+        hipLaunchKernelGGL(dpf::wide_active_count_kernel, dim3(1), dim3(256), 0, sd, w);
+        DPF_HIP(hipGetLastError());
+        DPF_HIP(hipMemcpyAsync(dev.pinned_count, w.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, sd));
+        DPF_HIP(hipEventRecord(dev.ev_poll, sd));
+        DPF_HIP(hipEventSynchronize(dev.ev_poll));
+        if (*dev.pinned_count == 0) break;
+    }
+    hipLaunchKernelGGL(dpf::wide_finish_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
+    DPF_HIP(hipGetLastError());
+    return DPF_OK;
 }
 
 }  // namespace
@@ -310,7 +464,15 @@ int dpf_autotune_set(int32_t n_max, int variant) {
     return DPF_OK;
 }
 
+int dpf_autotune_set_team_cap(int32_t buses) {
+    g_err.clear();
+    if (buses < 0) return fail(DPF_EINVAL, "team cap must be >= 0");
+    g_team_cap_override.store(buses);
+    return DPF_OK;
+}
+
 void dpf_autotune_reset(void) {
+    g_team_cap_override.store(0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (int &x : g_tune) x = -1;
     g_tune_init = true;
@@ -322,46 +484,6 @@ int32_t dpf_solve_max_sub_buses(void) {
     return max_sub_buses_for(d);
 }
 
-struct SolveLayout {
-    int32_t n_slices = 0;
-    int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
-    size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
-    size_t off_mom = 0, off_scr = 0, total = 0;
-};
-
-static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
-                                int32_t ld, bool streaming) {
-    SolveLayout L;
-    if (!sub_offset) {
-        L.n_slices = (g->n_bus + 63) / 64;
-    } else {
-        for (int32_t s = 0; s < n_sub; ++s) L.n_slices += (sub_offset[s + 1] - sub_offset[s] + 63) / 64;
-    }
-    int64_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
-    L.entries = std::min<int64_t>((int64_t)L.n_slices * 64 * wmax, (int64_t)64 * std::max<int32_t>(g->nnz, 1));
-    size_t o = 256;  // [0]: bad-grid flag
-    L.off_nslice = o;
-    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
-    L.off_slice_off = o;
-    o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
-    L.off_width = o;
-    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
-    L.off_start = o;
-    o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
-    L.off_col = o;
-    o += align_up(sizeof(int32_t) * (size_t)L.entries, 256);
-    L.off_val = o;
-    o += align_up(sizeof(double2) * (size_t)L.entries, 256);
-    if (streaming) {
-        L.off_mom = o;  // Adam moments [4][B][ld] when the caller passes none
-        o += align_up(sizeof(double) * 4 * (size_t)B * ld, 256);
-        L.off_scr = o;  // V, a*I and w [3][B][ld] complex
-        o += align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
-    }
-    L.total = o;
-    return L;
-}
-
 static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset) {
     if (!sub_offset) return n_bus;
     int32_t m = 0;
@@ -369,12 +491,27 @@ static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_off
     return m;
 }
 
+static int32_t max_small_sub(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset, int32_t cap) {
+    int32_t m = 0;
+    for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
+        int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : n_bus;
+        if (ns <= cap) m = std::max(m, ns);
+    }
+    return m;
+}
+
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
                                  int32_t ld) {
     if (!g || g->n_bus <= 0 || B <= 0 || ld < g->n_bus) return 0;
     if (!sub_offset) n_sub = 1;
-    const Variant *v = pick_variant(max_sub_size(g->n_bus, n_sub, sub_offset));
-    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode == dpf::kGlobal).total;
+    DeviceInfo dev;
+    if (device_info(dev) != DPF_OK) {
+        g_err.clear();
+        dev.lds_per_block = kGfx950LdsBytes;  // no device visible: size for gfx950
+    }
+    const int32_t cap = max_sub_buses_for(dev);
+    const Variant *v = pick_variant(std::max(1, max_small_sub(g->n_bus, n_sub, sub_offset, cap)));
+    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode == dpf::kGlobal, cap).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -406,13 +543,20 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     DeviceInfo dev;
     int rc = device_info(dev);
     if (rc != DPF_OK) return rc;
-    const int32_t n_max = max_sub_size(g->n_bus, n_sub, sub_offset);
-    const int32_t cap = max_sub_buses_for(dev);
-    if (n_max > cap) return fail(DPF_EUNSUPPORTED, "a sub-grid has more buses than one solve item holds (" +
-                                                        std::to_string(cap) + ")");
-    const Variant *v = pick_variant(n_max);
-    if (!v) return fail(DPF_EUNSUPPORTED, "sub-grid too large");
-    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode == dpf::kGlobal);
+    const int32_t n_max_all = max_sub_size(g->n_bus, n_sub, sub_offset);
+    const int32_t cap = max_sub_buses_for(dev);  // larger sub-grids take the multi-workgroup path
+    const int32_t n_max = max_small_sub(g->n_bus, n_sub, sub_offset, cap);
+    const bool has_small = sub_offset ? [&] {
+        for (int32_t s = 0; s < n_sub; ++s)
+            if (sub_offset[s + 1] - sub_offset[s] <= cap) return true;
+        return false;
+    }()
+                                      : g->n_bus <= cap;
+    const Variant *v = pick_variant(std::max(1, n_max));
+    if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
+    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode == dpf::kGlobal, cap);
+    const bool has_wide = L.w_total > 0;
+    (void)n_max_all;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;
@@ -453,7 +597,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.st_stride = (int64_t)B * ld;
     a.sell = dpf::SellView{slice_off, width, start, scol, sval};
     a.bad_grid = bad;
-    if (v->mode == dpf::kGlobal) {
+    a.team_cap = cap;
+    if (v->mode == dpf::kGlobal || has_wide) {
         double *mom = (double *)(ws + L.off_mom);
         a.scratch = (double2 *)(ws + L.off_scr);
         a.st = adam_state ? adam_state : mom;
@@ -491,10 +636,22 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     entries = std::max<int32_t>(entries, 1);
     a.lds_cap = entries;
     const size_t lds_bytes = (size_t)entries * 16;
-    DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
     const int32_t items = B * n_sub;
-    hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
-    DPF_HIP(hipGetLastError());
+    if (has_wide) {
+        DPF_HIP(hipEventRecord(dev.ev_in, st));
+        DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
+    }
+    if (has_small) {
+        DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
+        hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
+        DPF_HIP(hipGetLastError());
+    }
+    if (has_wide) {
+        int rc2 = run_wide(a, L, ws, n_sub, sub_offset_dev, B, ld, cap, dev);
+        if (rc2 != DPF_OK) return rc2;
+        DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
+        DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+    }
     return DPF_OK;
 }
 

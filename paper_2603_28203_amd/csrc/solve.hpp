@@ -55,6 +55,7 @@ struct SolveArgs {
     double *sched;       // [items][6] (t, lr, best, bad + cooldown * 2^20, b1^t, b2^t) or null
     const int32_t *sub_off;  // device [n_sub + 1] or null
     SellView sell;           // sliced-ELL copy of Y (local columns)
+    int32_t team_cap;        // items above this size belong to the multi-workgroup path
     const int32_t *bad_grid; // set when a row exceeded the declared width bound
     int32_t n_bus;
     int32_t n_sub;
@@ -111,6 +112,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
+    if (n > a.team_cap) return;  // handled by the multi-workgroup path
     if (n < 0 || n > NT * K || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
         if (tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;
@@ -479,6 +481,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
+    if (n > a.team_cap) return;  // handled by the multi-workgroup path
     if (n < 0 || (HOLD && n > NT * K) || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
         if (tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;

@@ -490,3 +490,117 @@ def test_solve_reports_bad_grid_row_bound(dpf):
     torch.cuda.synchronize()
     assert out["status"].item() == dpf.BAD_GRID and out["iters"].item() == 0
     assert np.array_equal(vm[0].cpu().numpy(), vm0)
+
+
+# ---------------------------------------------------------------- multi-workgroup path
+
+
+@pytest.fixture
+def wide_cap(dpf):
+    """Route sub-grids above 500 buses to the multi-workgroup path."""
+    dpf.set_team_cap(500)
+    yield 500
+    dpf.autotune_reset()
+
+
+def _perturbed_start(g, seed, sd=0.01):
+    rng = np.random.default_rng(seed)
+    vm0 = g.vm + rng.normal(0, sd, g.n_bus) * (g.bus_type == 0)
+    va0 = g.va + rng.normal(0, sd, g.n_bus) * (g.bus_type != 2)
+    return vm0, va0
+
+
+def test_wide_path_tracks_oracle(dpf, wide_cap):
+    g = synth.config1(B=1)["grid"]  # 1354 buses > 500
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    vm0, va0 = _perturbed_start(g, 1)
+    steps = 25
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+    assert out["status"].item() == 1 and out["iters"].item() == steps
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
+    assert abs(out["max_mis"].item() - ref["mu"]) <= 1e-9 * ref["mu"]
+
+
+def test_wide_path_outage_and_schedule(dpf, wide_cap):
+    cfg = synth.config2(B=3, n_bus=900, n_branch=1320, n_pv=140)
+    g = cfg["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    out = cfg["outage"]
+    rng = np.random.default_rng(4)
+    vm0 = cfg["vm0"] + rng.normal(0, 1e-3, cfg["vm0"].shape) * (g.bus_type == 0)
+    va0 = cfg["va0"] + rng.normal(0, 1e-3, cfg["va0"].shape) * (g.bus_type != 2)
+    kw = dict(lr=1e-3, sched=1, factor=0.5, patience=3, threshold=0.05, cooldown=2)
+    steps = 30
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0); va = cu(va0)
+    sch = dpf.fresh_sched_state(3, 1e-3)
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(out, torch.int32), sched_state=sch,
+              opts=dpf.Options(tol=0.0, max_iter=steps, **kw))
+    torch.cuda.synchronize()
+    for c in range(3):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(out[c])), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps, **kw))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10
+        assert sch[c, 1].item() == pytest.approx(ref["lr"], rel=1e-15)
+
+
+def test_mixed_team_and_wide_items(dpf, wide_cap):
+    """One call with sub-grids on both paths equals separate oracle solves."""
+    small = [synth.config0(s)["grid"] for s in (0, 1)]
+    big = [synth.config1(B=1, seed=8100 + k, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
+           for k, n in enumerate((1200, 700))]
+    grids = [big[0], small[0], big[1], small[1]]
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    f = np.concatenate([gg.f + o for gg, o in zip(grids, off)])
+    t = np.concatenate([gg.t + o for gg, o in zip(grids, off)])
+    r = np.concatenate([gg.r for gg in grids]); x = np.concatenate([gg.x for gg in grids])
+    b = np.concatenate([gg.b for gg in grids]); bt = np.concatenate([gg.bus_type for gg in grids])
+    S = np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids])
+    starts = [_perturbed_start(gg, 10 + k) for k, gg in enumerate(grids)]
+    vm0 = np.concatenate([s_[0] for s_ in starts]); va0 = np.concatenate([s_[1] for s_ in starts])
+    Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    steps = 20
+    o = dpf.solve(Yg, bt, cu(S[None], torch.complex128), vm, va, sub_offset=off.tolist(),
+                  opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert o["iters"].tolist() == [steps] * 4 and o["status"].tolist() == [1] * 4
+    for k, gg in enumerate(grids):
+        sl = slice(off[k], off[k + 1])
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[sl], vm0[sl], va0[sl],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[0, sl].cpu().numpy() - ref["vm"]).max() < 1e-10
+        assert np.abs(va[0, sl].cpu().numpy() - ref["va"]).max() < 1e-10
+
+
+def test_wide_path_resume_and_status(dpf, wide_cap):
+    g = synth.config1(B=1, seed=8200, n_bus=800, n_branch=1170, n_pv=130)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    vm0, va0 = _perturbed_start(g, 3)
+    Sd = cu(np.stack([S, S, S]), torch.complex128)
+    Sd[1, 5] = float("nan")
+    base = dpf.Options(lr=1e-3, tol=0.0, max_iter=40)
+    vmA = cu(np.tile(vm0, (3, 1))); vaA = cu(np.tile(va0, (3, 1)))
+    vmA[2] = cu(g.vm); vaA[2] = cu(g.va)
+    oA = dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=dpf.Options(**{**base.__dict__, "tol": 1e-6}))
+    torch.cuda.synchronize()
+    assert oA["status"].tolist() == [1, 2, 0] and oA["iters"].tolist() == [40, 0, 0]
+    # resume: 2 x 20 iterations == 40 iterations, bit for bit
+    vmB = cu(vm0[None]); vaB = cu(va0[None])
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmB, vaB, opts=base)
+    vmC = cu(vm0[None]); vaC = cu(va0[None])
+    st = torch.zeros((4, 1, g.n_bus), dtype=torch.float64, device="cuda")
+    sch = dpf.fresh_sched_state(1, base.lr)
+    half = dpf.Options(**{**base.__dict__, "max_iter": 20})
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
+    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
+    torch.cuda.synchronize()
+    assert torch.equal(vmB, vmC) and torch.equal(vaB, vaC)
