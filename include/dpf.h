@@ -219,6 +219,8 @@ size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B);
  *   iters, status : device int32 [B*n_sub] out (index c*n_sub + s); iters = number
  *                   of Adam updates applied in this call
  *   max_mis, loss : device double [B*n_sub] out, at the returned voltages
+ *   done_ns       : device int64 [B*n_sub] out, nullable: nanoseconds from the start of
+ *                   the call's kernels to the item's stop (time to converge per item)
  *   workspace     : device, >= dpf_solve_workspace_bytes(g, n_sub, sub_offset, B, ld) bytes
  * Errors: DPF_EINVAL (sizes, pointers, opts out of range, a sub-grid larger than
  * the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
@@ -228,11 +230,33 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                     int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
                     const int32_t *outage, double *vm, double *va, double *adam_state,
                     double *sched_state, const dpf_opts_t *opts, int32_t *iters,
-                    int32_t *status, double *max_mis, double *loss, void *workspace,
-                    size_t ws_bytes, void *stream);
+                    int32_t *status, double *max_mis, double *loss, int64_t *done_ns,
+                    void *workspace, size_t ws_bytes, void *stream);
 
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
                                  int32_t B, int32_t ld);
+
+/*
+ * dpf_solve_series -- a time series of T power flows on one grid (Sec. 6.4: time
+ * series reuse the previous solution).  Steps run in windows of `window`: all
+ * steps of a window start from the solution of the step before the window (step
+ * 0 from vm0/va0) and are solved together as one dpf_solve_batch of `window`
+ * cases; window = 1 gives the sequential warm-started chain.  Every step starts
+ * with fresh Adam moments and schedule.
+ *   s_series : device complex [T][s_ld] injections per step
+ *   vm0, va0 : device [n_bus] start of step 0
+ *   vm, va   : device [T][ld] out: the solution returned for each step
+ *   iters, status, max_mis, loss, done_ns : [T] as in dpf_solve_batch (done_ns per
+ *              window start, nullable)
+ *   workspace: >= dpf_solve_series_workspace_bytes(g, window, ld)
+ */
+int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_t *bus_type,
+                     const double *s_series, int32_t s_ld, const double *vm0, const double *va0,
+                     double *vm, double *va, int32_t ld, const dpf_opts_t *opts, int32_t *iters,
+                     int32_t *status, double *max_mis, double *loss, int64_t *done_ns,
+                     void *workspace, size_t ws_bytes, void *stream);
+
+size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld);
 
 /* Largest sub-grid (buses) one workgroup can hold on this device; larger sub-grids
  * are solved by several workgroups (see dpf_autotune_set_team_cap). */

@@ -64,8 +64,13 @@ def lib():
         L.dpf_mismatch_grad_workspace_bytes.argtypes = [_i32, _i32]
         L.dpf_mismatch_grad_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_solve_batch.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _P, _i32, _i32, _P, _P, _i32, _P,
-                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), _P, _P, _P, _P, _P,
+                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P]
+        L.dpf_solve_series.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P, _i32,
+                                       ctypes.POINTER(_Opts), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+        L.dpf_solve_series.restype = ctypes.c_int
+        L.dpf_solve_series_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _i32]
+        L.dpf_solve_series_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_solve_batch.restype = ctypes.c_int
         L.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _i32, _i32]
         L.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
@@ -252,7 +257,8 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
         outputs = {"iters": torch.empty(items, dtype=torch.int32, device=dev),
                    "status": torch.empty(items, dtype=torch.int32, device=dev),
                    "max_mis": torch.empty(items, dtype=torch.float64, device=dev),
-                   "loss": torch.empty(items, dtype=torch.float64, device=dev)}
+                   "loss": torch.empty(items, dtype=torch.float64, device=dev),
+                   "done_ns": torch.empty(items, dtype=torch.int64, device=dev)}
     g = grid.c()
     wsb = int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), n_sub, so_h, B, ld))
     ws = (workspace or _default_ws).get(wsb, dev)
@@ -260,8 +266,8 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
     _check(lib().dpf_solve_batch(ctypes.byref(g), n_sub, so_h, _ptr(so_d), B, ld, _ptr(bt), _ptr(s), s_ld,
                                  _ptr(out), _ptr(vm), _ptr(va), _ptr(adam_state), _ptr(sched_state),
                                  ctypes.byref(o), _ptr(outputs["iters"]), _ptr(outputs["status"]),
-                                 _ptr(outputs["max_mis"]), _ptr(outputs["loss"]), _ptr(ws), ws.numel(),
-                                 _stream()))
+                                 _ptr(outputs["max_mis"]), _ptr(outputs["loss"]), _ptr(outputs.get("done_ns")),
+                                 _ptr(ws), ws.numel(), _stream()))
     if so_d is not None:
         outputs["_keep"] = so_d  # keep the device offsets alive until the stream has used them
     return outputs
@@ -278,6 +284,40 @@ def fresh_sched_state(items: int, lr: float, device="cuda") -> torch.Tensor:
     st[:, 4] = 1.0
     st[:, 5] = 1.0
     return st
+
+
+def solve_series(grid: DeviceGrid, bus_type, s_series, vm0, va0, *, window: int = 1,
+                 opts: Options | None = None, workspace: SolveWorkspace | None = None):
+    """dpf_solve_series: T warm-started power flows in windows of `window` steps.
+
+    s_series: [T, n] complex128 (GPU); vm0, va0: [n].  Returns dict with vm, va
+    ([T, n] solutions) and per-step iters, status, max_mis, loss, done_ns."""
+    opts = opts or Options()
+    dev = s_series.device
+    T, n = s_series.shape
+    s = s_series.contiguous()
+    bt = bus_type if (torch.is_tensor(bus_type) and bus_type.dtype == torch.int8 and bus_type.device == dev) \
+        else _dev(bus_type, torch.int8, dev)
+    vm0 = _dev(vm0, torch.float64, dev)
+    va0 = _dev(va0, torch.float64, dev)
+    vm = torch.empty((T, n), dtype=torch.float64, device=dev)
+    va = torch.empty((T, n), dtype=torch.float64, device=dev)
+    out = {"iters": torch.empty(T, dtype=torch.int32, device=dev),
+           "status": torch.empty(T, dtype=torch.int32, device=dev),
+           "max_mis": torch.empty(T, dtype=torch.float64, device=dev),
+           "loss": torch.empty(T, dtype=torch.float64, device=dev),
+           "done_ns": torch.empty(T, dtype=torch.int64, device=dev)}
+    g = grid.c()
+    wsb = int(lib().dpf_solve_series_workspace_bytes(ctypes.byref(g), int(window), n))
+    ws = (workspace or _default_ws).get(wsb, dev)
+    o = opts.c()
+    _check(lib().dpf_solve_series(ctypes.byref(g), T, int(window), _ptr(bt), _ptr(s), n, _ptr(vm0), _ptr(va0),
+                                  _ptr(vm), _ptr(va), n, ctypes.byref(o), _ptr(out["iters"]),
+                                  _ptr(out["status"]), _ptr(out["max_mis"]), _ptr(out["loss"]),
+                                  _ptr(out["done_ns"]), _ptr(ws), ws.numel(), _stream()))
+    out["vm"] = vm
+    out["va"] = va
+    return out
 
 
 def max_sub_buses() -> int:

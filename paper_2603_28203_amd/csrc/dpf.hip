@@ -38,6 +38,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 struct DeviceInfo {
     int lds_per_block = 0;  // bytes
     int n_cu = 0;
+    double ns_per_tick = 10.0;  // wall-clock counter period
     bool ok = false;
     hipStream_t side = nullptr;      // stream of the multi-workgroup path
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
@@ -57,6 +58,9 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
         g_dev[dev].lds_per_block = lds;
         g_dev[dev].n_cu = ncu;
+        int khz = 0;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev) == hipSuccess && khz > 0)
+            g_dev[dev].ns_per_tick = 1e6 / (double)khz;
         DPF_HIP(hipStreamCreateWithFlags(&g_dev[dev].side, hipStreamNonBlocking));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_in, hipEventDisableTiming));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_out, hipEventDisableTiming));
@@ -261,6 +265,9 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.status = a.status;
     w.mu_out = a.mu_out;
     w.loss_out = a.loss_out;
+    w.done_ns = a.done_ns;
+    w.stamp = a.stamp;
+    w.ns_per_tick = a.ns_per_tick;
     int32_t *wcount = (int32_t *)(ws + L.off_wcount);
     // the active counter sits in the 256-byte header of the workspace (word 1; word 0 is the bad-grid flag)
     w.active_count = (int32_t *)ws + 1;
@@ -518,7 +525,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                     int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
                     const int32_t *outage, double *vm, double *va, double *adam_state, double *sched_state,
                     const dpf_opts_t *opts, int32_t *iters, int32_t *status, double *max_mis, double *loss,
-                    void *workspace, size_t ws_bytes, void *stream) {
+                    int64_t *done_ns, void *workspace, size_t ws_bytes, void *stream) {
     g_err.clear();
     if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
     if (B <= 0 || ld < g->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
@@ -568,6 +575,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     int32_t *scol = (int32_t *)(ws + L.off_col);
     double2 *sval = (double2 *)(ws + L.off_val);
     const int32_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
+    if (done_ns) hipLaunchKernelGGL(dpf::stamp_kernel, dim3(1), dim3(64), 0, st, (int64_t *)(ws + 8));
     // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
     // so that the whole call can be captured in a graph)
     hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
@@ -629,6 +637,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.status = status;
     a.mu_out = max_mis;
     a.loss_out = loss;
+    a.done_ns = done_ns;
+    a.stamp = (const int64_t *)(ws + 8);  // header words 2-3
+    a.ns_per_tick = dev.ns_per_tick;
 
     // dynamic LDS: two exchange arrays when they fit, else one
     const int32_t lds_entries_max = (dev.lds_per_block - kSolveStaticLds) / 16;
@@ -651,6 +662,39 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         if (rc2 != DPF_OK) return rc2;
         DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
         DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+    }
+    return DPF_OK;
+}
+
+size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld) {
+    return dpf_solve_workspace_bytes(g, 1, nullptr, window, ld);
+}
+
+int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_t *bus_type,
+                     const double *s_series, int32_t s_ld, const double *vm0, const double *va0, double *vm,
+                     double *va, int32_t ld, const dpf_opts_t *opts, int32_t *iters, int32_t *status,
+                     double *max_mis, double *loss, int64_t *done_ns, void *workspace, size_t ws_bytes,
+                     void *stream) {
+    g_err.clear();
+    if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
+    if (T <= 0 || window <= 0 || ld < g->n_bus || s_ld < g->n_bus)
+        return fail(DPF_EINVAL, "T and window must be > 0, ld and s_ld >= n_bus");
+    if (!s_series || !vm0 || !va0 || !vm || !va || !bus_type || !iters || !status || !max_mis || !loss)
+        return fail(DPF_EINVAL, "null argument");
+    hipStream_t st = (hipStream_t)stream;
+    for (int32_t t0 = 0; t0 < T; t0 += window) {
+        const int32_t bw = std::min(window, T - t0);
+        const double *src_m = t0 == 0 ? vm0 : vm + (int64_t)(t0 - 1) * ld;
+        const double *src_a = t0 == 0 ? va0 : va + (int64_t)(t0 - 1) * ld;
+        const int blocks = (g->n_bus + 255) / 256;
+        hipLaunchKernelGGL(dpf::row_broadcast_kernel, dim3(blocks, bw), dim3(256), 0, st, g->n_bus, src_m, src_a,
+                           vm + (int64_t)t0 * ld, va + (int64_t)t0 * ld, (int64_t)ld);
+        DPF_HIP(hipGetLastError());
+        int rc = dpf_solve_batch(g, 1, nullptr, nullptr, bw, ld, bus_type, s_series + 2 * (int64_t)t0 * s_ld, s_ld,
+                                 nullptr, vm + (int64_t)t0 * ld, va + (int64_t)t0 * ld, nullptr, nullptr, opts,
+                                 iters + t0, status + t0, max_mis + t0, loss + t0,
+                                 done_ns ? done_ns + t0 : nullptr, workspace, ws_bytes, stream);
+        if (rc != DPF_OK) return rc;
     }
     return DPF_OK;
 }

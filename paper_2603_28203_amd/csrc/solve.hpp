@@ -74,6 +74,9 @@ struct SolveArgs {
     int32_t *status;
     double *mu_out;
     double *loss_out;
+    int64_t *done_ns;         // per item: ns from the call's start stamp to completion, or null
+    const int64_t *stamp;     // wall clock at the start of the call
+    double ns_per_tick;
 };
 
 template <int NT>
@@ -437,6 +440,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         a.status[out_idx] = stat;
         a.mu_out[out_idx] = mu;
         a.loss_out[out_idx] = loss;
+        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
         if (a.sched) {
             double *ss = a.sched + kSchedWords * (int64_t)out_idx;
             ss[0] = t_step;
@@ -747,6 +751,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
         a.status[out_idx] = stat;
         a.mu_out[out_idx] = mu;
         a.loss_out[out_idx] = loss;
+        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
         if (a.sched) {
             double *ss = a.sched + kSchedWords * (int64_t)out_idx;
             ss[0] = t_step;
@@ -757,6 +762,22 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
             ss[5] = b2t;
         }
     }
+}
+
+// start point of every step of a time-series window: rows [0, gridDim.y) of dst
+// receive the source voltages
+__global__ void row_broadcast_kernel(int32_t n, const double *__restrict__ src_m, const double *__restrict__ src_a,
+                                     double *__restrict__ dst_m, double *__restrict__ dst_a, int64_t ld) {
+    int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double m = src_m[i], v = src_a[i];
+    dst_m[blockIdx.y * ld + i] = m;
+    dst_a[blockIdx.y * ld + i] = v;
+}
+
+// wall-clock stamp at the start of a solve call (for per-item completion times)
+__global__ void stamp_kernel(int64_t *stamp) {
+    if (threadIdx.x == 0) *stamp = wall_clock64();
 }
 
 }  // namespace dpf

@@ -22,7 +22,8 @@ namespace dpf {
 // scalar state of one item (indexed like the outputs: c * n_sub + s)
 struct WideItem {
     double t, lr, best, b1t, b2t, loss, mu, lr_use;
-    int32_t bad, cool, iters, status, active, pad0, pad1, pad2;
+    int64_t done;  // wall clock when the item stopped
+    int32_t bad, cool, iters, status, active, pad0;
 };
 
 struct WideArgs {
@@ -55,6 +56,9 @@ struct WideArgs {
     int32_t *iters, *status;
     double *mu_out, *loss_out;
     int32_t *active_count;
+    int64_t *done_ns;
+    const int64_t *stamp;
+    double ns_per_tick;
 };
 
 struct WideUnit {
@@ -215,12 +219,15 @@ __global__ __launch_bounds__(kWave) void wide_reduce_kernel(WideArgs a) {
     if (!(isfinite(it.loss) && isfinite(it.mu))) {
         it.status = DPF_NONFINITE;
         it.active = 0;
+        it.done = wall_clock64();
     } else if (it.mu < a.tol) {
         it.status = DPF_CONVERGED;
         it.active = 0;
+        it.done = wall_clock64();
     } else if (it.iters >= a.max_iter) {
         it.status = DPF_MAX_ITER;
         it.active = 0;
+        it.done = wall_clock64();
     } else {
         // this iteration's update uses the current lr; the schedule step after it
         it.t += 1.0;
@@ -323,6 +330,7 @@ __global__ void wide_finish_kernel(WideArgs a, int32_t cap) {
     a.status[idx] = it.status;
     a.mu_out[idx] = it.mu;
     a.loss_out[idx] = it.loss;
+    if (a.done_ns) a.done_ns[idx] = (int64_t)((double)(it.done - *a.stamp) * a.ns_per_tick);
     if (a.sched) {
         double *ss = a.sched + 6 * (int64_t)idx;
         ss[0] = it.t;

@@ -57,7 +57,9 @@ def test_host_side_validation(lib):
     assert rc == -1 and b"n_bus" in lib.dpf_last_error()
     # mismatch_grad / solve reject a null grid
     assert lib.dpf_mismatch_grad(None, 1, 1, *([None] * 12), ctypes.c_size_t(0), None) == -1
-    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 14), ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 15), ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_solve_series(None, 1, 1, *([None] * 3), 1, *([None] * 4), 1, *([None] * 7),
+                                ctypes.c_size_t(0), None) == -1
     # workspace sizing is pure host arithmetic
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t

@@ -604,3 +604,59 @@ def test_wide_path_resume_and_status(dpf, wide_cap):
     dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
     torch.cuda.synchronize()
     assert torch.equal(vmB, vmC) and torch.equal(vaB, vaC)
+
+
+# ---------------------------------------------------------------- time series
+
+
+def _series_problem(T=7):
+    cfg = synth.config3(n_bus=400, n_branch=590, n_pv=60, T=T)
+    g = cfg["grid"]
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    S = S0[None, :] * cfg["load_scale"] + cfg["solar_p"]
+    return g, S
+
+
+@pytest.mark.parametrize("window", [1, 3])
+def test_series_windows_follow_the_warm_start_rule(dpf, window):
+    g, S = _series_problem()
+    T = S.shape[0]
+    Yo = oracle.ybus_of(g)
+    steps = 12
+    opts = oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)
+    # Start away from the planted point: at a bus whose residual is exactly zero
+    # in the oracle (a PV bus tied only to the slack) the device sees a
+    # rounding-level gradient that Adam, with g << eps, turns into real steps.
+    rng = np.random.default_rng(33)
+    vm0 = g.vm + np.where(g.bus_type == 0, rng.normal(0, 1e-3, g.n_bus), 0.0)
+    va0 = g.va + np.where(g.bus_type != 2, rng.normal(0, 1e-3, g.n_bus), 0.0)
+    # oracle composition: every step of window w starts from step w*window - 1
+    ref_vm = np.zeros((T, g.n_bus)); ref_va = np.zeros((T, g.n_bus))
+    for t0 in range(0, T, window):
+        sm, sa = (vm0, va0) if t0 == 0 else (ref_vm[t0 - 1], ref_va[t0 - 1])
+        for t in range(t0, min(T, t0 + window)):
+            r = oracle.solve_adam(Yo, g.bus_type, S[t], sm, sa, opts)
+            ref_vm[t], ref_va[t] = r["vm"], r["va"]
+    Yg = dgrid(dpf, g)
+    out = dpf.solve_series(Yg, g.bus_type, cu(S, torch.complex128), vm0, va0, window=window,
+                           opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * T
+    assert np.abs(out["vm"].cpu().numpy() - ref_vm).max() < 1e-10
+    assert np.abs(out["va"].cpu().numpy() - ref_va).max() < 1e-10
+    assert np.all(out["done_ns"].cpu().numpy() > 0)
+
+
+def test_done_ns_orders_items_by_work(dpf):
+    """Items that stop earlier report earlier completion times."""
+    g = synth.config0(0)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    vm0, va0 = synth.flat_start(g)
+    vm = cu(np.tile(vm0, (2, 1))); va = cu(np.tile(va0, (2, 1)))
+    vm[1] = cu(g.vm); va[1] = cu(g.va)  # case 1 is converged at the start
+    out = dpf.solve(Yg, g.bus_type, cu(np.tile(S, (2, 1)), torch.complex128), vm, va,
+                    opts=dpf.Options(max_iter=3000))
+    torch.cuda.synchronize()
+    d = out["done_ns"].cpu().numpy()
+    assert out["iters"].tolist()[1] == 0 and d[1] > 0 and d[0] > d[1]
