@@ -258,6 +258,31 @@ int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_
 
 size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld);
 
+/*
+ * dpf_order_rcm -- a bus numbering of small bandwidth (reverse Cuthill-McKee on
+ * the branch graph), for grids that the caller renumbers before building Y: the
+ * banded solve kernels need max|row - col| of every sub-grid at most their block.
+ * With group > 1 the buses of every aligned window of `group` consecutive new
+ * indices are then ordered by degree (stable), so that the 64-row slices of the
+ * solve kernels' sliced-ELL matrix hold rows of similar length (less padding);
+ * each bus moves by less than group, so the bandwidth grows by at most 2 (group - 1).
+ * Bus numbering is arbitrary in the power-flow problem (Sec. 2: the equations are
+ * per bus and per branch), so renumbering changes no result beyond rounding.
+ *   n_bus, n_branch : sizes;  from, to : host int32 [n_branch] branch ends
+ *   sub_offset      : host int32 [n_sub + 1] or NULL; each range [sub_offset[s],
+ *                     sub_offset[s+1]) is ordered on its own and keeps its place;
+ *                     branches between ranges are ignored; windows start at the
+ *                     range start
+ *   group           : degree-grouping window (0 or 1: plain RCM)
+ *   perm            : host int32 [n_bus] out: perm[k] = old index of new bus k
+ *   bandwidth_out   : host, nullable: max|new(f) - new(t)| over the branches
+ * Host-only, synchronous, allocates host memory for the adjacency lists.
+ * Errors: DPF_EINVAL (sizes, null pointers, branch end out of range, sub_offset
+ * not increasing from 0 to n_bus), DPF_ENOMEM.
+ */
+int dpf_order_rcm(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, int32_t n_sub,
+                  const int32_t *sub_offset, int32_t group, int32_t *perm, int32_t *bandwidth_out);
+
 /* Largest sub-grid (buses) one workgroup can hold on this device; larger sub-grids
  * are solved by several workgroups (see dpf_autotune_set_team_cap). */
 int32_t dpf_solve_max_sub_buses(void);
@@ -272,7 +297,13 @@ int32_t dpf_solve_max_sub_buses(void);
  * The cache is process-wide and guarded by a mutex.
  *   dpf_solve_variant_count : number of variants
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
- *                             streaming (1) or register-resident (0); host outs
+ *                             and the kind: register-resident (0), streaming (1)
+ *                             or banded (2); host outs.  A banded variant (buses
+ *                             per thread = buses per thread per block) serves the
+ *                             sub-grids whose bandwidth max|row - col| is at most
+ *                             threads * buses_per_thread (see dpf_order_rcm); the
+ *                             same call runs the other sub-grids with the default
+ *                             variant of their size
  *   dpf_solve_variant_for   : variant index dpf_solve_batch would use, -1 if none
  *   dpf_autotune_set        : DPF_EINVAL if the variant cannot hold n_max buses
  *   dpf_autotune_set_team_cap : sub-grids above `buses` take the multi-workgroup

@@ -11,6 +11,7 @@ import ctypes
 import os
 from dataclasses import dataclass, field
 
+import numpy as np
 import torch
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -83,6 +84,8 @@ def lib():
         L.dpf_autotune_set.argtypes = [_i32, ctypes.c_int]
         L.dpf_autotune_set.restype = ctypes.c_int
         L.dpf_autotune_reset.restype = None
+        L.dpf_order_rcm.argtypes = [_i32, _i32, _P, _P, _i32, _P, _i32, _P, _P]
+        L.dpf_order_rcm.restype = ctypes.c_int
         L.dpf_autotune_set_team_cap.argtypes = [_i32]
         L.dpf_autotune_set_team_cap.restype = ctypes.c_int
         _lib = L
@@ -348,15 +351,43 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
+VARIANT_KINDS = ("register", "streaming", "banded")
+
+
 def variants():
-    """The solve kernel variants: list of dicts (index, threads, buses_per_thread, streaming)."""
+    """The solve kernel variants: list of dicts (index, threads, buses_per_thread,
+    kind, streaming).  For a banded variant buses_per_thread counts the buses of
+    one block; it serves sub-grids of bandwidth <= threads * buses_per_thread."""
     L = lib()
     out = []
     for i in range(L.dpf_solve_variant_count()):
         t, k, st = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         _check(L.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)))
-        out.append({"index": i, "threads": t.value, "buses_per_thread": k.value, "streaming": bool(st.value)})
+        out.append({"index": i, "threads": t.value, "buses_per_thread": k.value, "kind": VARIANT_KINDS[st.value],
+                    "streaming": st.value != 0})
     return out
+
+
+def rcm_order(n_bus: int, f, t, sub_offset=None, group: int = 0):
+    """dpf_order_rcm: a small-bandwidth bus numbering (reverse Cuthill-McKee),
+    optionally with buses grouped by degree inside windows of ``group``.
+
+    Returns (perm, bandwidth) with perm[k] = old index of new bus k.  Renumber a
+    grid with inv = argsort(perm): branch ends become inv[f], inv[t] and every
+    per-bus array a becomes a[..., perm]."""
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    perm = np.empty(int(n_bus), dtype=np.int32)
+    bw = ctypes.c_int32(0)
+    if sub_offset is None:
+        n_sub, so = 1, None
+    else:
+        so_arr = np.ascontiguousarray(sub_offset, dtype=np.int32)
+        n_sub, so = len(so_arr) - 1, so_arr.ctypes.data_as(ctypes.c_void_p)
+    _check(lib().dpf_order_rcm(int(n_bus), len(f), f.ctypes.data_as(ctypes.c_void_p),
+                               t.ctypes.data_as(ctypes.c_void_p), n_sub, so, int(group),
+                               perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(bw)))
+    return perm, int(bw.value)
 
 
 def variant_for(n_max: int) -> int:
@@ -382,7 +413,8 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
     times = {}
     for v in variants():
-        if not (v["buses_per_thread"] == 0 or v["threads"] * v["buses_per_thread"] >= n_max):
+        if not (v["kind"] == "banded" or v["buses_per_thread"] == 0
+                or v["threads"] * v["buses_per_thread"] >= n_max):
             continue
         _check(lib().dpf_autotune_set(n_max, v["index"]))
         best = None

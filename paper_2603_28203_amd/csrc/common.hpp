@@ -45,6 +45,14 @@ __device__ __forceinline__ double wave_max(double v) {
     for (int o = kWave / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
     return v;
 }
+// A value that every lane of the wave holds identically, moved to scalar
+// registers: lets the compiler treat what depends on it as uniform.
+__device__ __forceinline__ double uniform(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffLL));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
 __device__ __forceinline__ int wave_isum(int v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
@@ -62,10 +70,87 @@ __device__ __forceinline__ void branch_admittance(double r, double x, double b, 
 // ---------------------------------------------------------------- sin / cos
 // sincos for the voltage angles, after fdlibm (Sun Microsystems, 1993): a
 // three-step Cody-Waite reduction by pi/2 (valid for |x| < 2^19 pi/2) and the
-// fdlibm minimax polynomials on [-pi/4, pi/4] (error < 1 ulp).  It needs far
-// fewer registers than a general-purpose routine; arguments outside the
-// reduction range (and NaN/Inf) go to the HIP library routine, out of line.
-__device__ __noinline__ void sincos_wide(double x, double *s, double *c) { ::sincos(x, s, c); }
+// fdlibm minimax polynomials on [-pi/4, pi/4] (error < 1 ulp).  Larger finite
+// arguments are reduced exactly by the Payne-Hanek method (multiplication by a
+// 192-bit window of the binary expansion of 2/pi), inline and without a call,
+// so that the solve kernels keep their registers.
+
+// 2/pi = 0.A2F9836E... in hexadecimal: 1280 bits, most significant first
+// (computed with integer arithmetic from Machin's formula; checked by a test).
+__constant__ const unsigned long long kTwoOverPiBits[20] = {
+    0xA2F9836E4E441529ULL, 0xFC2757D1F534DDC0ULL, 0xDB6295993C439041ULL, 0xFE5163ABDEBBC561ULL,
+    0xB7246E3A424DD2E0ULL, 0x06492EEA09D1921CULL, 0xFE1DEB1CB129A73EULL, 0xE88235F52EBB4484ULL,
+    0xE99C7026B45F7E41ULL, 0x3991D639835339F4ULL, 0x9C845F8BBDF9283BULL, 0x1FF897FFDE05980FULL,
+    0xEF2F118B5A0A6D1FULL, 0x6D367ECF27CB09B7ULL, 0x4F463F669E5FEA2DULL, 0x7527BAC7EBE5F17BULL,
+    0x3D0739F78A5292EAULL, 0x6BFB5FB11F8D5D08ULL, 0x56033046FC7B6BABULL, 0xF0CFBC209AF4361DULL,
+};
+
+// 64 bits of 2/pi starting at bit z (bit 0 = weight 1/2)
+__device__ __forceinline__ unsigned long long two_over_pi_bits(int z) {
+    const int q = z >> 6, off = z & 63;
+    const unsigned long long hi = kTwoOverPiBits[q];
+    return off ? (hi << off) | (kTwoOverPiBits[q + 1] >> (64 - off)) : hi;
+}
+
+// bits [pos, pos + 64) of the 256-bit number p3:p2:p1:p0
+__device__ __forceinline__ unsigned long long bits_at(unsigned long long p0, unsigned long long p1,
+                                                      unsigned long long p2, unsigned long long p3, int pos) {
+    const int q = pos >> 6, off = pos & 63;
+    const unsigned long long w0 = q == 0 ? p0 : q == 1 ? p1 : q == 2 ? p2 : p3;
+    const unsigned long long w1 = q == 0 ? p1 : q == 1 ? p2 : q == 2 ? p3 : 0ULL;
+    return off ? (w0 >> off) | (w1 << (64 - off)) : w0;
+}
+
+// Payne-Hanek reduction of a finite x with |x| >= 2^19 pi/2: x = n pi/2 + (y0 + y1),
+// |y0 + y1| <= pi/4, returns n mod 4.  |x| = m 2^E (m a 53-bit integer, E >= -33);
+// bits of 2/pi of weight 2^-k with k <= E - 2 contribute multiples of 4 to
+// x * 2/pi and are skipped, the next 192 bits give the quadrant and a fraction
+// accurate to ~2^-137, far below the closest approach of a double to a multiple
+// of pi/2.
+__device__ __forceinline__ int reduce_payne_hanek(double x, double &y0, double &y1) {
+    const unsigned long long bits = (unsigned long long)__double_as_longlong(x);
+    const int E = (int)((bits >> 52) & 0x7ff) - 1075;
+    const unsigned long long m = (bits & 0xFFFFFFFFFFFFFULL) | (1ULL << 52);
+    const int k0 = E - 1 > 1 ? E - 1 : 1;  // first bit (1-based) of the window
+    const unsigned long long W2 = two_over_pi_bits(k0 - 1), W1 = two_over_pi_bits(k0 + 63),
+                             W0 = two_over_pi_bits(k0 + 127);
+    // P = m * (W2:W1:W0), 245 bits; x 2/pi = P 2^(E - k0 - 191) (mod 4)
+    const unsigned long long l0 = m * W0, h0 = __umul64hi(m, W0);
+    const unsigned long long l1 = m * W1, h1 = __umul64hi(m, W1);
+    const unsigned long long l2 = m * W2, h2 = __umul64hi(m, W2);
+    const unsigned long long p0 = l0;
+    const unsigned long long p1 = h0 + l1;
+    const unsigned long long c1 = p1 < l1 ? 1ULL : 0ULL;
+    const unsigned long long t2 = h1 + c1;  // h1 < 2^53: no carry out
+    const unsigned long long p2 = t2 + l2;
+    const unsigned long long p3 = h2 + (p2 < l2 ? 1ULL : 0ULL);
+    const int sh = k0 + 191 - E;  // binary point of P, in [190, 225]
+    int n = (int)(bits_at(p0, p1, p2, p3, sh) & 3ULL);
+    unsigned long long fh = bits_at(p0, p1, p2, p3, sh - 64);   // fraction, top 64 bits
+    const unsigned long long fl = bits_at(p0, p1, p2, p3, sh - 128);
+    // centre the fraction on [-1/2, 1/2): a set top bit means fraction - 1 in two's complement
+    if (fh >> 63) n += 1;
+    // fraction as a double pair: the top word with its low 11 bits cleared is exact
+    const long long fhs = (long long)fh;
+    const double a = (double)(fhs & ~0x7FFLL) * 0x1p-64;
+    const unsigned long long low = ((fh & 0x7FFULL) << 53) | (fl >> 11);
+    const double b = (double)low * 0x1p-117;
+    const double f = a + b, fe = b - (f - a);
+    // times pi/2 in double-double
+    const double pio2_hi = 1.57079632679489655800e+00, pio2_lo = 6.12323399573676603587e-17;
+    const double rh = f * pio2_hi;
+    const double rl = fma(f, pio2_hi, -rh) + (fe * pio2_hi + f * pio2_lo);
+    double r0 = rh + rl;
+    double r1 = rl - (r0 - rh);
+    if (x < 0.0) {
+        r0 = -r0;
+        r1 = -r1;
+        n = -n;
+    }
+    y0 = r0;
+    y1 = r1;
+    return n;
+}
 
 __device__ __forceinline__ double ksin(double x, double y) {
     const double S1 = -1.66666666666666324348e-01, S2 = 8.33333333332248946124e-03,
@@ -92,10 +177,6 @@ __device__ __forceinline__ double kcos(double x, double y) {
 }
 
 __device__ __forceinline__ void fast_sincos(double x, double &s, double &c) {
-    if (!(fabs(x) <= 823550.0)) {  // 2^19 * pi/2, also catches NaN and Inf
-        sincos_wide(x, &s, &c);
-        return;
-    }
     const double invpio2 = 6.36619772367581382433e-01;
     const double p1 = 1.57079632673412561417e+00, p2 = 6.07710050630396597660e-11,
                  p2t = 2.02226624879595063154e-21, p3 = 2.02226624871116645580e-21,
@@ -105,6 +186,13 @@ __device__ __forceinline__ void fast_sincos(double x, double &s, double &c) {
     if (fabs(x) <= 0.785398163397448279) {
         y0 = x;
         y1 = 0.0;
+    } else if (!(fabs(x) <= 823550.0)) {  // 2^19 pi/2, also catches NaN and Inf
+        if (fabs(x) <= 1.79769313486231570815e+308) {
+            n = reduce_payne_hanek(x, y0, y1);
+        } else {
+            s = c = x - x;  // NaN for NaN and +-Inf
+            return;
+        }
     } else {
         double fn = rint(x * invpio2);
         n = (int)fn;

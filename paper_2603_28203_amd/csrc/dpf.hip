@@ -7,6 +7,7 @@
 #include <cstring>
 #include <mutex>
 #include <string>
+#include <vector>
 
 #include "../../include/dpf.h"
 #include "common.hpp"
@@ -105,33 +106,43 @@ template <int NT, int K>
 Variant make_stream_variant() {
     return Variant{NT, K, dpf::kGlobal, dpf::team_solve_stream_kernel<NT, K>};
 }
+template <int NT, int J>
+Variant make_band_variant() {
+    return Variant{NT, J, dpf::kBand, dpf::team_solve_band_kernel<NT, J>};
+}
 
 // Register-resident variants up to 2048 buses per item, streaming above (512 threads
 // keep 256 VGPRs per thread, enough for 20 buses of held exchange values; the
-// 1024-thread streaming variant takes any size with holds in scratch).
+// 1024-thread streaming variant takes any size with holds in scratch).  The banded
+// variants (k = buses per thread per block) serve sub-grids whose bandwidth is at
+// most threads * k; the others go to the default variant of the size in the same call.
 const Variant *variant_table(int *count) {
     static const Variant table[] = {
         make_variant<64, 1>(),  make_variant<128, 1>(), make_variant<256, 1>(), make_variant<256, 2>(),
         make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<512, 8>(),
         make_stream_variant<512, 12>(), make_stream_variant<512, 16>(), make_stream_variant<512, 20>(),
-        make_stream_variant<1024, 0>(),
+        make_stream_variant<1024, 0>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
+        make_band_variant<512, 2>(),
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;
 }
 
-bool variant_fits(const Variant &v, int32_t n_max) { return v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k; }
+bool variant_fits(const Variant &v, int32_t n_max) {
+    return v.mode == dpf::kBand || v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k;
+}
 
 // Autotune cache: size class (index of the default variant) -> chosen variant.
 std::mutex g_tune_mu;
 int g_tune[64];
 bool g_tune_init = false;
 
+// first general (non-banded) variant that holds n_max buses
 int default_variant_index(int32_t n_max) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     for (int i = 0; i < cnt; ++i)
-        if (variant_fits(t[i], n_max)) return i;
+        if (t[i].mode != dpf::kBand && variant_fits(t[i], n_max)) return i;
     return -1;
 }
 
@@ -165,7 +176,8 @@ struct SolveLayout {
     int32_t w_total = 0;  // slices of the wide sub-grids (per case)
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
-    size_t off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0, off_items = 0;
+    size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
+           off_items = 0;
     size_t total = 0;
 };
 
@@ -186,6 +198,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
     o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
     L.off_slice_off = o;
     o += align_up(sizeof(int32_t) * (size_t)(n_sub + 1), 256);
+    L.off_bw = o;
+    o += align_up(sizeof(int32_t) * (size_t)n_sub, 256);
     L.off_width = o;
     o += align_up(sizeof(int32_t) * (size_t)(L.n_slices + 1), 256);
     L.off_start = o;
@@ -443,7 +457,7 @@ int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread,
         return fail(DPF_EINVAL, "variant index out of range or null output");
     *threads = t[idx].nt;
     *buses_per_thread = t[idx].k;
-    *streaming = t[idx].mode == dpf::kGlobal;
+    *streaming = t[idx].mode;
     return DPF_OK;
 }
 
@@ -485,6 +499,134 @@ void dpf_autotune_reset(void) {
     g_tune_init = true;
 }
 
+int dpf_order_rcm(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, int32_t n_sub,
+                  const int32_t *sub_offset, int32_t group, int32_t *perm, int32_t *bandwidth_out) {
+    g_err.clear();
+    if (n_bus <= 0 || n_branch < 0 || group < 0 || !perm || (n_branch > 0 && (!from || !to)))
+        return fail(DPF_EINVAL, "invalid sizes or null pointer");
+    if (!sub_offset) n_sub = 1;
+    if (n_sub <= 0) return fail(DPF_EINVAL, "n_sub must be > 0");
+    if (sub_offset) {
+        if (sub_offset[0] != 0 || sub_offset[n_sub] != n_bus)
+            return fail(DPF_EINVAL, "sub_offset must start at 0 and end at n_bus");
+        for (int32_t s = 0; s < n_sub; ++s)
+            if (sub_offset[s + 1] < sub_offset[s]) return fail(DPF_EINVAL, "sub_offset must not decrease");
+    }
+    for (int32_t e = 0; e < n_branch; ++e)
+        if (from[e] < 0 || from[e] >= n_bus || to[e] < 0 || to[e] >= n_bus)
+            return fail(DPF_EINVAL, "branch end out of range");
+    try {
+        std::vector<int32_t> sub_of(n_bus, 0);
+        for (int32_t s = 0; s < n_sub; ++s)
+            for (int32_t i = sub_offset ? sub_offset[s] : 0; i < (sub_offset ? sub_offset[s + 1] : n_bus); ++i)
+                sub_of[i] = s;
+        // adjacency within each range, duplicates and self loops removed
+        std::vector<int32_t> deg(n_bus + 1, 0);
+        for (int32_t e = 0; e < n_branch; ++e)
+            if (from[e] != to[e] && sub_of[from[e]] == sub_of[to[e]]) {
+                ++deg[from[e]];
+                ++deg[to[e]];
+            }
+        std::vector<int32_t> ptr(n_bus + 1, 0);
+        for (int32_t i = 0; i < n_bus; ++i) ptr[i + 1] = ptr[i] + deg[i];
+        std::vector<int32_t> adj(ptr[n_bus]), fill(ptr.begin(), ptr.end() - 1);
+        for (int32_t e = 0; e < n_branch; ++e)
+            if (from[e] != to[e] && sub_of[from[e]] == sub_of[to[e]]) {
+                adj[fill[from[e]]++] = to[e];
+                adj[fill[to[e]]++] = from[e];
+            }
+        for (int32_t i = 0; i < n_bus; ++i) {
+            auto b = adj.begin() + ptr[i], en = adj.begin() + ptr[i + 1];
+            std::sort(b, en);
+            deg[i] = (int32_t)(std::unique(b, en) - b);
+        }
+        std::vector<int32_t> level(n_bus, -1), order, queue;
+        std::vector<char> done(n_bus, 0);
+        order.reserve(n_bus);
+        queue.reserve(n_bus);
+        // breadth-first levels from r inside its component; returns the last level's nodes
+        auto bfs_last = [&](int32_t r, int32_t &depth) {
+            queue.clear();
+            queue.push_back(r);
+            level[r] = 0;
+            for (size_t h = 0; h < queue.size(); ++h) {
+                int32_t u = queue[h];
+                for (int32_t p = ptr[u]; p < ptr[u] + deg[u]; ++p)
+                    if (level[adj[p]] < 0) {
+                        level[adj[p]] = level[u] + 1;
+                        queue.push_back(adj[p]);
+                    }
+            }
+            depth = level[queue.back()];
+            std::vector<int32_t> last;
+            for (int32_t u : queue)
+                if (level[u] == depth) last.push_back(u);
+            for (int32_t u : queue) level[u] = -1;
+            return last;
+        };
+        for (int32_t s = 0; s < n_sub; ++s) {
+            const int32_t lo = sub_offset ? sub_offset[s] : 0, hi = sub_offset ? sub_offset[s + 1] : n_bus;
+            const size_t first = order.size();
+            for (;;) {
+                // start of the next component: unvisited bus of least degree
+                int32_t r = -1;
+                for (int32_t i = lo; i < hi; ++i)
+                    if (!done[i] && (r < 0 || deg[i] < deg[r])) r = i;
+                if (r < 0) break;
+                // pseudo-peripheral start: move to a least-degree bus of the last
+                // level while the depth grows
+                int32_t depth = 0;
+                std::vector<int32_t> last = bfs_last(r, depth);
+                for (int guard = 0; guard < 32; ++guard) {
+                    int32_t c = last[0];
+                    for (int32_t u : last)
+                        if (deg[u] < deg[c]) c = u;
+                    int32_t d2 = 0;
+                    std::vector<int32_t> l2 = bfs_last(c, d2);
+                    if (d2 <= depth) break;
+                    r = c;
+                    depth = d2;
+                    last.swap(l2);
+                }
+                // Cuthill-McKee: breadth first, neighbours by increasing degree
+                size_t head = order.size();
+                order.push_back(r);
+                done[r] = 1;
+                std::vector<int32_t> nb;
+                while (head < order.size()) {
+                    int32_t u = order[head++];
+                    nb.clear();
+                    for (int32_t p = ptr[u]; p < ptr[u] + deg[u]; ++p)
+                        if (!done[adj[p]]) nb.push_back(adj[p]);
+                    std::stable_sort(nb.begin(), nb.end(), [&](int32_t x, int32_t y) { return deg[x] < deg[y]; });
+                    for (int32_t v : nb) {
+                        done[v] = 1;
+                        order.push_back(v);
+                    }
+                }
+            }
+            std::reverse(order.begin() + first, order.end());
+            if (group > 1)
+                for (size_t w = first; w < order.size(); w += (size_t)group) {
+                    auto we = order.begin() + std::min(order.size(), w + (size_t)group);
+                    std::stable_sort(order.begin() + w, we, [&](int32_t x, int32_t y) { return deg[x] < deg[y]; });
+                }
+        }
+        for (int32_t k = 0; k < n_bus; ++k) perm[k] = order[k];
+        if (bandwidth_out) {
+            std::vector<int32_t> inv(n_bus);
+            for (int32_t k = 0; k < n_bus; ++k) inv[order[k]] = k;
+            int32_t bw = 0;
+            for (int32_t e = 0; e < n_branch; ++e)
+                if (sub_of[from[e]] == sub_of[to[e]]) bw = std::max(bw, std::abs(inv[from[e]] - inv[to[e]]));
+            *bandwidth_out = bw;
+        }
+    } catch (const std::bad_alloc &) {
+        return fail(DPF_ENOMEM, "host allocation failed");
+    }
+    return DPF_OK;
+}
+
 int32_t dpf_solve_max_sub_buses(void) {
     DeviceInfo d;
     if (device_info(d) != DPF_OK) return 0;
@@ -518,7 +660,7 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
     }
     const int32_t cap = max_sub_buses_for(dev);
     const Variant *v = pick_variant(std::max(1, max_small_sub(g->n_bus, n_sub, sub_offset, cap)));
-    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode == dpf::kGlobal, cap).total;
+    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode != dpf::kReg, cap).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -561,7 +703,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                                       : g->n_bus <= cap;
     const Variant *v = pick_variant(std::max(1, n_max));
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
-    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode == dpf::kGlobal, cap);
+    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap);
     const bool has_wide = L.w_total > 0;
     (void)n_max_all;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
@@ -574,12 +716,13 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     int32_t *start = (int32_t *)(ws + L.off_start);
     int32_t *scol = (int32_t *)(ws + L.off_col);
     double2 *sval = (double2 *)(ws + L.off_val);
+    int32_t *sub_bw = (int32_t *)(ws + L.off_bw);
     const int32_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
     if (done_ns) hipLaunchKernelGGL(dpf::stamp_kernel, dim3(1), dim3(64), 0, st, (int64_t *)(ws + 8));
     // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
     // so that the whole call can be captured in a graph)
     hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
-                       g->n_bus, nslice, bad);
+                       g->n_bus, nslice, sub_bw, bad);
     hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
     if (L.n_slices > 0) {
         hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
@@ -587,7 +730,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, L.n_slices, width, 0, start);
         hipLaunchKernelGGL(dpf::sell_fill_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
                            g->n_bus, slice_off, g->row_ptr, g->col_idx, (const double2 *)g->val, width, start, scol,
-                           sval);
+                           sval, sub_bw);
     }
     DPF_HIP(hipGetLastError());
 
@@ -604,9 +747,11 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.ld = ld;
     a.st_stride = (int64_t)B * ld;
     a.sell = dpf::SellView{slice_off, width, start, scol, sval};
+    a.sub_bw = sub_bw;
+    a.band_nt = 0;
     a.bad_grid = bad;
     a.team_cap = cap;
-    if (v->mode == dpf::kGlobal || has_wide) {
+    if (v->mode != dpf::kReg || has_wide) {
         double *mom = (double *)(ws + L.off_mom);
         a.scratch = (double2 *)(ws + L.off_scr);
         a.st = adam_state ? adam_state : mom;
@@ -656,6 +801,17 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
         DPF_HIP(hipGetLastError());
+        if (v->mode == dpf::kBand) {
+            // items whose bandwidth exceeds the banded block go to the general variant
+            int cnt = 0;
+            const Variant *f = &variant_table(&cnt)[default_variant_index(std::max(1, n_max))];
+            dpf::SolveArgs b = a;
+            b.band_nt = v->nt * v->k;
+            DPF_HIP(hipFuncSetAttribute((const void *)f->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                        (int)lds_bytes));
+            hipLaunchKernelGGL(f->fn, dim3(items), dim3(f->nt), lds_bytes, st, b);
+            DPF_HIP(hipGetLastError());
+        }
     }
     if (has_wide) {
         int rc2 = run_wide(a, L, ws, n_sub, sub_offset_dev, B, ld, cap, dev);

@@ -25,16 +25,17 @@ struct SellView {
     const double2 *val;        // [entries]
 };
 
-// slices per sub-grid: ceil(n_s / 64)
+// slices per sub-grid: ceil(n_s / 64); clears the per-sub-grid bandwidth
 // (thread 0 also clears the bad-grid flag)
 __global__ void sell_count_kernel(int32_t n_sub, const int32_t *__restrict__ sub_off, int32_t n_bus,
-                                  int32_t *__restrict__ nslice, int32_t *__restrict__ bad) {
+                                  int32_t *__restrict__ nslice, int32_t *__restrict__ bw, int32_t *__restrict__ bad) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) *bad = 0;
     if (s >= n_sub) return;
     int32_t lo = sub_off ? sub_off[s] : 0;
     int32_t hi = sub_off ? sub_off[s + 1] : n_bus;
     nslice[s] = (hi - lo + kWave - 1) / kWave;
+    bw[s] = 0;
 }
 
 __device__ __forceinline__ int32_t find_sub(int32_t g, int32_t n_sub, const int32_t *__restrict__ slice_off) {
@@ -77,7 +78,8 @@ __global__ __launch_bounds__(kWave) void sell_fill_kernel(int32_t n_sub, const i
                                                           const double2 *__restrict__ yv,
                                                           const int32_t *__restrict__ width,
                                                           const int32_t *__restrict__ start,
-                                                          int32_t *__restrict__ col, double2 *__restrict__ val) {
+                                                          int32_t *__restrict__ col, double2 *__restrict__ val,
+                                                          int32_t *__restrict__ bw) {
     int32_t g = blockIdx.x;
     int32_t s = find_sub(g, n_sub, slice_off);
     int32_t lo = sub_off ? sub_off[s] : 0;
@@ -88,6 +90,7 @@ __global__ __launch_bounds__(kWave) void sell_fill_kernel(int32_t n_sub, const i
     int32_t q0 = r < hi ? rp[r] : 0;
     int32_t len = r < hi ? rp[r + 1] - q0 : 0;
     int32_t own = r < hi ? r - lo : 0;
+    int32_t far = 0;  // largest |row - col| of the kept entries
     for (int32_t k = 0; k < w; ++k) {
         int32_t c = own;
         double2 v = make_double2(0.0, 0.0);
@@ -96,11 +99,15 @@ __global__ __launch_bounds__(kWave) void sell_fill_kernel(int32_t n_sub, const i
             if (j >= lo && j < hi) {
                 c = j - lo;
                 v = yv[q0 + k];
+                far = max(far, abs(c - own));
             }
         }
         col[base + k * kWave] = c;
         val[base + k * kWave] = v;
     }
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) far = max(far, __shfl_xor(far, o, kWave));
+    if (threadIdx.x == 0) atomicMax(&bw[s], far);
 }
 
 }  // namespace dpf

@@ -33,7 +33,7 @@
 
 namespace dpf {
 
-enum StoreMode { kReg = 0, kGlobal = 1 };
+enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2 };
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched
 
@@ -55,6 +55,8 @@ struct SolveArgs {
     double *sched;       // [items][6] (t, lr, best, bad + cooldown * 2^20, b1^t, b2^t) or null
     const int32_t *sub_off;  // device [n_sub + 1] or null
     SellView sell;           // sliced-ELL copy of Y (local columns)
+    const int32_t *sub_bw;   // [n_sub] largest |row - col| of the sub-grid's matrix (local indices)
+    int32_t band_nt;         // > 0: sub-grids with sub_bw <= band_nt belong to the banded kernel
     int32_t team_cap;        // items above this size belong to the multi-workgroup path
     const int32_t *bad_grid; // set when a row exceeded the declared width bound
     int32_t n_bus;
@@ -99,6 +101,8 @@ __device__ __forceinline__ void block_reduce2_finish(double &s, double &m, doubl
         s += red[0][k];
         m = fmax(m, red[1][k]);
     }
+    s = uniform(s);  // every lane read the same partials
+    m = uniform(m);
 }
 
 template <int NT, int K, int MODE>
@@ -116,6 +120,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
     if (n > a.team_cap) return;  // handled by the multi-workgroup path
+    if (a.band_nt > 0 && a.sub_bw[sidx] <= a.band_nt) return;  // handled by the banded kernel
     if (n < 0 || n > NT * K || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
         if (tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;
@@ -486,6 +491,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     const int n = hi - lo;
     const int out_idx = c * a.n_sub + sidx;
     if (n > a.team_cap) return;  // handled by the multi-workgroup path
+    if (a.band_nt > 0 && a.sub_bw[sidx] <= a.band_nt) return;  // handled by the banded kernel
     if (n < 0 || (HOLD && n > NT * K) || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
         if (tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;
@@ -745,6 +751,309 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     }
 #undef DPF_BUS_LOOP_BEGIN
 #undef DPF_BUS_LOOP_END
+
+    if (tid == 0) {
+        a.iters[out_idx] = it;
+        a.status[out_idx] = stat;
+        a.mu_out[out_idx] = mu;
+        a.loss_out[out_idx] = loss;
+        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
+        if (a.sched) {
+            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+            ss[0] = t_step;
+            ss[1] = lr;
+            ss[2] = best;
+            ss[3] = (double)(bad + (cool << 20));
+            ss[4] = b1t;
+            ss[5] = b2t;
+        }
+    }
+}
+
+// Banded variant, for sub-grids numbered with a small bandwidth: every entry of
+// the matrix has |row - col| <= NT*J in local indices (a reverse Cuthill-McKee
+// numbering gives ~80 on a 9241-bus meshed grid).  Buses are processed in blocks
+// of BLK = NT*J consecutive buses, thread tid owning buses s*BLK + j*NT + tid of
+// block s.  The rows of block s then read the exchange vector only in blocks
+// s-1, s and s+1, so the single LDS array X can go from V to w to the new V
+// block by block, with one block of values held in registers instead of the
+// whole sub-grid:
+//   A/W sweep, step s: rows of block s gather V, form dS, the loss terms and
+//       w = a conj(V); I goes to scratch for the second sweep.  After a barrier
+//       the w of block s-1 replaces V there (its readers, blocks s-2..s, are done).
+//   stop test on the reduced max|r|
+//   B/U sweep, step s: rows of block s gather w, rebuild dS and a*I from I and V,
+//       form the gradient, apply Adam and compute the new V.  After a barrier the
+//       new V of block s-1 replaces w there.
+// Per bus and iteration this moves |V|, theta and the four moments once each way
+// plus I (16 B written, 16 B read), and evaluates one polar conversion per sweep;
+// there is no V or w round trip through memory.
+template <int NT, int J>
+__global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
+    constexpr int BLK = NT * J;
+    extern __shared__ double2 X[];
+    __shared__ double red[2][NT / kWave];
+
+    const int tid = threadIdx.x;
+    const int item = blockIdx.x;
+    const int sidx = item / a.B;
+    const int c = item - sidx * a.B;
+    const int lo = a.sub_off ? a.sub_off[sidx] : 0;
+    const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
+    const int n = hi - lo;
+    const int out_idx = c * a.n_sub + sidx;
+    if (n > a.team_cap) return;        // handled by the multi-workgroup path
+    if (a.sub_bw[sidx] > BLK) return;  // bandwidth too large: the general kernel takes it
+    if (n < 0 || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
+        if (tid == 0) {
+            a.status[out_idx] = DPF_BAD_GRID;
+            a.iters[out_idx] = 0;
+        }
+        return;
+    }
+    const int slice0 = a.sell.slice_off[sidx];
+    const int lane = tid & (kWave - 1);
+
+    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
+    int bad = 0, cool = 0;
+    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
+    if (a.sched) {
+        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+        t_step = ss[0];
+        lr = ss[1];
+        best = ss[2];
+        const int packed = (int)ss[3];
+        bad = packed & 0xFFFFF;
+        cool = packed >> 20;
+        b1t = ss[4];
+        b2t = ss[5];
+    }
+
+    double m_res;
+    {
+        double cnt = 0.0, dummy = 0.0;
+        for (int i = lo + tid; i < hi; i += NT) {
+            int8_t t = a.bt[i];
+            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
+        }
+        block_reduce2<NT>(cnt, dummy, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(cnt, dummy, red);
+        m_res = cnt;
+        __syncthreads();
+    }
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+
+    int of = -1, ot = -1;
+    double2 oy = make_double2(0.0, 0.0), oyd = oy;
+    if (a.ov.outage) {
+        int32_t k = a.ov.outage[c];
+        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
+            int32_t f = a.ov.from[k], t = a.ov.to[k];
+            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
+                of = f - lo;
+                ot = t - lo;
+                double2 ysh;
+                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
+                oyd = cadd(oy, ysh);
+            }
+        }
+    }
+
+    const int64_t cb = (int64_t)c * a.ld;
+    const int64_t sb = (int64_t)c * a.s_ld;
+    double *__restrict__ vm_c = a.vm + cb;
+    double *__restrict__ va_c = a.va + cb;
+    double *__restrict__ mv_c = a.st + cb;
+    double *__restrict__ ma_c = a.st + a.st_stride + cb;
+    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb;
+    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *__restrict__ Ig = a.scratch + cb;  // I of the A/W sweep
+    const double2 *__restrict__ Sc = a.s_spec + sb;
+    const int32_t *__restrict__ swidth = a.sell.width;
+    const int32_t *__restrict__ sstart = a.sell.start;
+    const int32_t *__restrict__ scol = a.sell.col;
+    const double2 *__restrict__ sval = a.sell.val;
+    const int8_t *__restrict__ btp = a.bt;
+
+    for (int i = lo + tid; i < hi; i += NT) {
+        double sn, cs;
+        const double vmi = vm_c[i];
+        fast_sincos(va_c[i], sn, cs);
+        X[i - lo] = make_double2(vmi * cs, vmi * sn);
+        if (a.st_fresh) {
+            mv_c[i] = 0.0;
+            ma_c[i] = 0.0;
+            sv_c[i] = 0.0;
+            sa_c[i] = 0.0;
+        }
+    }
+    __syncthreads();
+
+    const int nb = (n + BLK - 1) / BLK;
+    int it = 0, stat = DPF_MAX_ITER;
+    double mu = 0.0, loss = 0.0;
+    for (;; ++it) {
+        // ---------------- A/W sweep
+        double lsum = 0.0, lmax = 0.0;
+        double2 hold[J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) hold[j] = make_double2(0.0, 0.0);
+        for (int s = 0; s <= nb; ++s) {
+            double2 w[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                w[j] = make_double2(0.0, 0.0);
+                const int il = s * BLK + j * NT + tid;
+                if (s < nb && il < n) {
+                    const int i = lo + il;
+                    const int8_t tk = btp[i];
+                    const double2 sp = Sc[i];
+                    const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                    const int wdt = swidth[gsl];
+                    const int base = sstart[gsl] * kWave + lane;
+                    double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+                    for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], acc);
+                    if (il == of) acc = csub(acc, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
+                    else if (il == ot) acc = csub(acc, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
+                    const double2 v = X[il];
+                    const double2 d = csub(cmulc(v, acc), sp);
+                    const double rP = tk != kSlack ? d.x : 0.0;
+                    const double rQ = tk == kPQ ? d.y : 0.0;
+                    lsum += rP * rP + rQ * rQ;
+                    lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+                    const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
+                    Ig[i] = acc;
+                    w[j] = cmulc(av, v);
+                }
+            }
+            __syncthreads();
+            if (s > 0) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = (s - 1) * BLK + j * NT + tid;
+                    if (il < n) X[il] = hold[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) hold[j] = w[j];
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+
+        // ---------------- B/U sweep
+        t_step += 1.0;
+        b1t *= a.b1;
+        b2t *= a.b2;
+        const double bc1 = 1.0 - b1t;
+        const double bc2 = 1.0 - b2t;
+        for (int s = 0; s <= nb; ++s) {
+            double2 vn[J];
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                vn[j] = make_double2(0.0, 0.0);
+                const int il = s * BLK + j * NT + tid;
+                if (s < nb && il < n) {
+                    const int i = lo + il;
+                    // every global load of this bus first, so that they overlap the gather
+                    const int8_t tk = btp[i];
+                    const double2 I = Ig[i];
+                    const double2 sp = Sc[i];
+                    double vmi = vm_c[i], vai = va_c[i];
+                    const double mv0 = mv_c[i], sv0 = sv_c[i], ma0 = ma_c[i], sa0 = sa_c[i];
+                    const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+                    const int wdt = swidth[gsl];
+                    const int base = sstart[gsl] * kWave + lane;
+                    double2 h = make_double2(0.0, 0.0);
+#pragma unroll 4
+                    for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], h);
+                    if (il == of) h = csub(h, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
+                    else if (il == ot) h = csub(h, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
+                    double2 v;
+                    {
+                        double sn0, cs0;
+                        fast_sincos(vai, sn0, cs0);
+                        v = make_double2(vmi * cs0, vmi * sn0);
+                    }
+                    // the seed of the A/W sweep, rebuilt from I and the same V
+                    const double2 d = csub(cmulc(v, I), sp);
+                    const double rP = tk != kSlack ? d.x : 0.0;
+                    const double rQ = tk == kPQ ? d.y : 0.0;
+                    const double2 ai = cmul(make_double2(two_over_m * rP, two_over_m * rQ), I);
+                    const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+                    if (tk == kPQ) {
+                        const double g = (G.x * v.x + G.y * v.y) / vmi;
+                        const double mv = a.b1 * mv0 + (1.0 - a.b1) * g;
+                        const double sv = a.b2 * sv0 + (1.0 - a.b2) * (g * g);
+                        vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                        vm_c[i] = vmi;
+                        mv_c[i] = mv;
+                        sv_c[i] = sv;
+                    }
+                    if (tk != kSlack) {
+                        const double g = G.y * v.x - G.x * v.y;
+                        const double ma = a.b1 * ma0 + (1.0 - a.b1) * g;
+                        const double sa = a.b2 * sa0 + (1.0 - a.b2) * (g * g);
+                        vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                        va_c[i] = vai;
+                        ma_c[i] = ma;
+                        sa_c[i] = sa;
+                    }
+                    double sn, cs;
+                    fast_sincos(vai, sn, cs);
+                    vn[j] = make_double2(vmi * cs, vmi * sn);
+                }
+            }
+            __syncthreads();
+            if (s > 0) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = (s - 1) * BLK + j * NT + tid;
+                    if (il < n) X[il] = hold[j];
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < J; ++j) hold[j] = vn[j];
+        }
+        if (a.sch == DPF_SCHED_PLATEAU) {
+            if (loss < best * (1.0 - a.threshold)) {
+                best = loss;
+                bad = 0;
+            } else {
+                bad += 1;
+            }
+            if (cool > 0) {
+                cool -= 1;
+                bad = 0;
+            }
+            if (bad > a.patience) {
+                double nl = lr * a.factor;
+                if (nl < a.min_lr) nl = a.min_lr;
+                if (lr - nl > a.sched_eps) lr = nl;
+                cool = a.cooldown;
+                bad = 0;
+            }
+        } else if (a.sch == DPF_SCHED_STEP) {
+            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
+        }
+        __syncthreads();
+    }
 
     if (tid == 0) {
         a.iters[out_idx] = it;

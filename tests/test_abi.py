@@ -90,3 +90,76 @@ def test_variant_table_and_autotune_cache(lib):
     assert lib.dpf_autotune_set(9241, d) == 0
     lib.dpf_autotune_reset()
     assert lib.dpf_solve_variant_for(14) == 0
+
+
+# ---------------------------------------------------------------- bus ordering (host code)
+
+
+def _rcm(lib, n, f, t, sub=None, group=0):
+    import numpy as np
+    f = np.ascontiguousarray(f, dtype=np.int32)
+    t = np.ascontiguousarray(t, dtype=np.int32)
+    perm = np.full(n, -1, dtype=np.int32)
+    bw = ctypes.c_int32(-1)
+    so = None if sub is None else np.ascontiguousarray(sub, dtype=np.int32)
+    rc = lib.dpf_order_rcm(ctypes.c_int32(n), ctypes.c_int32(len(f)), f.ctypes.data_as(ctypes.c_void_p),
+                           t.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(1 if so is None else len(so) - 1),
+                           None if so is None else so.ctypes.data_as(ctypes.c_void_p), ctypes.c_int32(group),
+                           perm.ctypes.data_as(ctypes.c_void_p), ctypes.byref(bw))
+    return rc, perm, bw.value
+
+
+def test_rcm_order_is_a_small_bandwidth_permutation(lib):
+    import numpy as np
+
+    import synth
+    g = synth.config1(B=1)["grid"]
+    f, t = g.f, g.t
+    rc, perm, bw = _rcm(lib, g.n_bus, f, t)
+    assert rc == 0
+    assert np.array_equal(np.sort(perm), np.arange(g.n_bus))
+    inv = np.argsort(perm)
+    assert bw == np.abs(inv[f] - inv[t]).max()
+    assert bw < 60 < np.abs(f - t).max()  # the generator's numbering is far from banded
+    # grouping by degree: each bus moves within its window; degrees sorted per window
+    rc, perm2, bw2 = _rcm(lib, g.n_bus, f, t, group=128)
+    assert rc == 0 and np.array_equal(np.sort(perm2), np.arange(g.n_bus))
+    deg = np.bincount(np.concatenate([f, t]), minlength=g.n_bus)
+    for w in range(0, g.n_bus, 128):
+        d = deg[perm2[w:w + 128]]
+        assert np.all(np.diff(d) >= 0)
+    assert bw2 <= bw + 2 * 127
+
+
+def test_rcm_order_keeps_sub_grid_ranges_and_checks_input(lib):
+    import numpy as np
+    # two disjoint paths numbered in a scrambled way, as sub-grids [0, 50) and [50, 120)
+    rng = np.random.default_rng(0)
+    a = rng.permutation(50)
+    b = 50 + rng.permutation(70)
+    f = np.concatenate([a[:-1], b[:-1]])
+    t = np.concatenate([a[1:], b[1:]])
+    rc, perm, bw = _rcm(lib, 120, f, t, sub=[0, 50, 120])
+    assert rc == 0 and bw == 1
+    assert set(perm[:50].tolist()) == set(range(50)) and set(perm[50:].tolist()) == set(range(50, 120))
+    # errors: end out of range, bad sub_offset, negative group
+    assert _rcm(lib, 120, [0, 130], [1, 2])[0] == -1
+    assert _rcm(lib, 120, f, t, sub=[0, 60, 50, 120])[0] == -1
+    assert _rcm(lib, 120, f, t, group=-1)[0] == -1
+
+
+def test_two_over_pi_table_holds_the_binary_expansion():
+    """The Payne-Hanek table of the device sin/cos is 2/pi to 1280 bits
+    (checked with mpmath, independent of how the table was produced)."""
+    mpmath = pytest.importorskip("mpmath")
+    src = open(os.path.join(ROOT, "paper_2603_28203_amd", "csrc", "common.hpp")).read()
+    body = src[src.index("kTwoOverPiBits[20] = {"):]
+    body = body[:body.index("};")]
+    words = [int(w, 16) for w in re.findall(r"0x([0-9A-F]{16})ULL", body)]
+    assert len(words) == 20
+    table = 0
+    for w in words:
+        table = (table << 64) | w
+    mpmath.mp.prec = 1400
+    ref = int(mpmath.floor(2 / mpmath.pi * mpmath.mpf(2) ** 1280))
+    assert table == ref

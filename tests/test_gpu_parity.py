@@ -455,18 +455,29 @@ def test_solve_every_variant_tracks_oracle(dpf, n_bus):
 
 
 def test_large_angles_use_correct_reduction(dpf):
-    """Angles far outside [-pi, pi] (including the out-of-line wide path)
-    give the same mismatch as the oracle's libm sin/cos."""
+    """Angles far outside [-pi, pi] (the three-step reduction up to 2^19 pi/2,
+    the Payne-Hanek reduction above, up to the largest double) give the same
+    mismatch as the oracle's libm sin/cos."""
     g = synth.config0(2)["grid"]
     Yo = oracle.ybus_of(g)
     S = oracle.injections(Yo, g.vm, g.va)
     rng = np.random.default_rng(0)
-    B = 6
+    # 6381956970095103 * 2^797 is the double closest to a multiple of pi/2
+    # (J.-M. Muller, Elementary Functions, ch. 11): its reduced argument is
+    # ~2^-60, so a reduction short of ~120 bits of 2/pi gets it wrong
+    hardest = 6381956970095103.0 * 2.0 ** 797
+    shifts = [0.0, 2 * np.pi * 3, -2 * np.pi * 1000, 12345.678, -5.0e5, 3.0e6, 1.0e10, -3.3e15, 1.0e22,
+              -7.7e150, 1.7e308, hardest, -hardest]
+    B = len(shifts)
     vm = np.tile(g.vm, (B, 1))
     va = np.tile(g.va, (B, 1))
-    shifts = [0.0, 2 * np.pi * 3, -2 * np.pi * 1000, 12345.678, -5.0e5, 3.0e6]
     for c, sft in enumerate(shifts):
-        va[c] = va[c] + sft + rng.uniform(-4, 4, g.n_bus)
+        if abs(sft) < 1e9:
+            va[c] = va[c] + sft + rng.uniform(-4, 4, g.n_bus)
+        else:  # a different huge angle per bus (an added offset would be rounded away)
+            va[c] = sft * (1.0 + rng.uniform(-1e-3, 1e-3, g.n_bus))
+            va[c, :3] = sft
+    va = np.where(np.isfinite(va), va, 1.7e308)
     Yg = dgrid(dpf, g)
     r = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va))
     torch.cuda.synchronize()
@@ -660,3 +671,129 @@ def test_done_ns_orders_items_by_work(dpf):
     torch.cuda.synchronize()
     d = out["done_ns"].cpu().numpy()
     assert out["iters"].tolist()[1] == 0 and d[1] > 0 and d[0] > d[1]
+
+
+# ---------------------------------------------------------------- banded variants
+
+
+def renumber(g, perm):
+    """The same grid with bus k of the new numbering = bus perm[k] of the old."""
+    import dataclasses
+    inv = np.argsort(perm).astype(np.int32)
+    return dataclasses.replace(g, f=inv[g.f], t=inv[g.t], bus_type=g.bus_type[perm], vm=g.vm[perm],
+                               va=g.va[perm], name=g.name + "-renumbered")
+
+
+@pytest.fixture
+def tuned(dpf):
+    yield dpf
+    dpf.autotune_reset()
+
+
+@pytest.mark.parametrize("n_bus,group", [(3000, 0), (9241, 256)])
+def test_banded_variants_track_oracle(tuned, n_bus, group):
+    """Every variant, forced through the autotune cache, on a grid renumbered to
+    a small bandwidth (so that the banded kernels take the items), with N-1
+    outages; iterates after a few Adam steps equal the oracle's."""
+    dpf = tuned
+    base = synth.config1(B=1, seed=8000 + n_bus, n_bus=n_bus, n_branch=int(1.737 * n_bus),
+                         n_pv=n_bus // 6)["grid"]
+    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t, group=group)
+    assert bw < 1024
+    g = renumber(base, perm)
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    outage = np.sort(np.random.default_rng(1).choice(synth.non_bridge_branches(g.n_bus, g.f, g.t), 3,
+                                                     replace=False)).astype(np.int32)
+    B = 3
+    rng = np.random.default_rng(n_bus)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 6
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=steps)
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
+    Yg = dgrid(dpf, g)
+    for v in dpf.variants():
+        if v["kind"] != "banded" and not (v["buses_per_thread"] == 0
+                                          or v["threads"] * v["buses_per_thread"] >= g.n_bus):
+            continue
+        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+        print(f"banded parity n={g.n_bus} bw={bw} variant={v}", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        opts=opts)
+        torch.cuda.synchronize()
+        assert out["iters"].tolist() == [steps] * B
+        for c in range(B):
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, v
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, v
+            assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
+
+
+@pytest.mark.parametrize("chord", [(1023, 2047), (1023, 2048)])
+def test_banded_block_boundary(tuned, chord):
+    """A chain grid with one chord at bandwidth exactly one block (1024: the
+    banded 1024-thread kernel takes it) and one more (1025: it must leave the
+    item to the general kernel, since rows of block 0 would read block 2)."""
+    dpf = tuned
+    n = 3000
+    rng = np.random.default_rng(sum(chord))
+    f = np.concatenate([np.arange(n - 1), [chord[0]]]).astype(np.int32)
+    t = np.concatenate([np.arange(1, n), [chord[1]]]).astype(np.int32)
+    m = len(f)
+    bt = np.zeros(n, dtype=np.int8)
+    bt[0] = 2
+    bt[rng.choice(np.arange(1, n), n // 6, replace=False)] = 1
+    g = synth.Grid(n_bus=n, f=f, t=t, r=rng.uniform(0.01, 0.1, m), x=rng.uniform(0.05, 0.3, m),
+                   b=rng.uniform(0, 0.05, m), bus_type=bt, vm=rng.uniform(0.98, 1.02, n),
+                   va=np.concatenate([[0.0], rng.uniform(-0.05, 0.05, n - 1)]))
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    vm0 = g.vm + rng.normal(0, 1e-2, n) * (bt == 0)
+    va0 = g.va + rng.normal(0, 1e-2, n) * (bt != 2)
+    steps = 5
+    ref = oracle.solve_adam(Yo, bt, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+    Yg = dgrid(dpf, g)
+    for v in dpf.variants():
+        if not (v["kind"] == "banded" and v["threads"] == 1024 and v["buses_per_thread"] == 1):
+            continue
+        dpf.lib().dpf_autotune_set(n, v["index"])
+        vm = cu(vm0[None]); va = cu(va0[None])
+        dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+        torch.cuda.synchronize()
+        assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
+        assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
+
+
+def test_banded_and_general_sub_grids_in_one_call(tuned):
+    """Sub-grids of one call split between the banded kernel (renumbered) and the
+    general kernel (original numbering) give the separate solves' results."""
+    dpf = tuned
+    a = synth.config1(B=1, seed=41, n_bus=2500, n_branch=3700, n_pv=400)["grid"]
+    perm, _ = dpf.rcm_order(a.n_bus, a.f, a.t)
+    grids = [renumber(a, perm), synth.config1(B=1, seed=42, n_bus=2600, n_branch=3800, n_pv=400)["grid"]]
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    f = np.concatenate([gg.f + o for gg, o in zip(grids, off)])
+    t = np.concatenate([gg.t + o for gg, o in zip(grids, off)])
+    r = np.concatenate([gg.r for gg in grids]); x = np.concatenate([gg.x for gg in grids])
+    b = np.concatenate([gg.b for gg in grids]); bt = np.concatenate([gg.bus_type for gg in grids])
+    S = np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids])
+    rng = np.random.default_rng(3)
+    vm0 = np.concatenate([gg.vm for gg in grids]) + rng.normal(0, 1e-2, off[-1]) * (bt == 0)
+    va0 = np.concatenate([gg.va for gg in grids]) + rng.normal(0, 1e-2, off[-1]) * (bt != 2)
+    Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
+    band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
+    dpf.lib().dpf_autotune_set(2600, band)
+    steps = 8
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, bt, cu(S[None], torch.complex128), vm, va, sub_offset=off.tolist(),
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps, steps]
+    for k, gg in enumerate(grids):
+        sl = slice(off[k], off[k + 1])
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[sl], vm0[sl], va0[sl],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[0, sl].cpu().numpy() - ref["vm"]).max() < 1e-10
+        assert np.abs(va[0, sl].cpu().numpy() - ref["va"]).max() < 1e-10
