@@ -59,6 +59,11 @@ extern "C" {
 #define DPF_SCHED_PLATEAU 1  /* reduce-on-plateau, mode min, relative threshold */
 #define DPF_SCHED_STEP 2     /* lr *= factor every `patience` iterations */
 
+/* optimizers (Sec. 6.1 compares Adam, SGD and RMSprop) */
+#define DPF_OPT_ADAM 0
+#define DPF_OPT_SGD 1      /* momentum beta1 (0 = plain gradient descent) */
+#define DPF_OPT_RMSPROP 2  /* smoothing beta2, no momentum, not centred */
+
 /*
  * A bus admittance matrix in CSR form plus (optionally) the branch list it was
  * built from.  row_ptr/col_idx/val as produced by dpf_build_ybus: rows sorted
@@ -84,9 +89,13 @@ typedef struct dpf_grid {
 } dpf_grid_t;
 
 /*
- * Optimizer settings (Algorithm 1: optimizer + scheduler + tolerance).
- * Adam as in Kingma & Ba: m <- b1 m + (1-b1) g; s <- b2 s + (1-b2) g^2;
- * x <- x - lr * (m/(1-b1^t)) / (sqrt(s/(1-b2^t)) + eps), on learnable entries only.
+ * Optimizer settings (Algorithm 1: optimizer + scheduler + tolerance), applied
+ * on learnable entries only.  `optimizer` selects the update of a coordinate x
+ * with gradient g and per-coordinate state m, s (PyTorch's definitions):
+ *   DPF_OPT_ADAM (default), Kingma & Ba: m <- b1 m + (1-b1) g; s <- b2 s + (1-b2) g^2;
+ *       x <- x - lr * (m/(1-b1^t)) / (sqrt(s/(1-b2^t)) + eps)
+ *   DPF_OPT_SGD: m <- b1 m + g; x <- x - lr m (b1 = momentum, no dampening)
+ *   DPF_OPT_RMSPROP: s <- b2 s + (1-b2) g^2; x <- x - lr g / (sqrt(s) + eps)
  * Stop test: the largest absolute masked residual max|dS| (pu) < tol, tested
  * before each update.  Schedules:
  *   PLATEAU: after each step, with the iteration's loss L: if L < best*(1-threshold)
@@ -109,6 +118,7 @@ typedef struct dpf_opts {
     int32_t cooldown;
     double min_lr;
     double sched_eps;
+    int32_t optimizer; /* DPF_OPT_* */
 } dpf_opts_t;
 
 /* Text of the calling thread's last error ("" if none).  Host string owned by the library. */
@@ -297,8 +307,9 @@ int32_t dpf_solve_max_sub_buses(void);
  * The cache is process-wide and guarded by a mutex.
  *   dpf_solve_variant_count : number of variants
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
- *                             and the kind: register-resident (0), streaming (1)
- *                             or banded (2); host outs.  A banded variant (buses
+ *                             and the kind: register-resident (0), streaming (1),
+ *                             banded (2) or banded with a barrier-free gradient
+ *                             sweep (3); host outs.  A banded variant (buses
  *                             per thread = buses per thread per block) serves the
  *                             sub-grids whose bandwidth max|row - col| is at most
  *                             threads * buses_per_thread (see dpf_order_rcm); the

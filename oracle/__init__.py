@@ -204,10 +204,11 @@ class _Opts(ctypes.Structure):
                 ("sched", ctypes.c_int32), ("factor", ctypes.c_double),
                 ("patience", ctypes.c_int32), ("threshold", ctypes.c_double),
                 ("cooldown", ctypes.c_int32), ("min_lr", ctypes.c_double),
-                ("sched_eps", ctypes.c_double)]
+                ("sched_eps", ctypes.c_double), ("optimizer", ctypes.c_int32)]
 
 
 SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
+OPT_ADAM, OPT_SGD, OPT_RMSPROP = 0, 1, 2
 
 
 @dataclass
@@ -225,11 +226,12 @@ class AdamOptions:
     cooldown: int = 0
     min_lr: float = 0.0
     sched_eps: float = 1e-8
+    optimizer: int = 0  # OPT_ADAM, OPT_SGD (momentum beta1) or OPT_RMSPROP (smoothing beta2)
 
     def c(self) -> _Opts:
         return _Opts(self.lr, self.beta1, self.beta2, self.eps, self.tol, int(self.max_iter),
                      int(self.sched), self.factor, int(self.patience), self.threshold,
-                     int(self.cooldown), self.min_lr, self.sched_eps)
+                     int(self.cooldown), self.min_lr, self.sched_eps, int(self.optimizer))
 
 
 def solve_adam(Y: CSR, bus_type, s_spec, vm0, va0, opts: AdamOptions, state=None, t0: int = 0):

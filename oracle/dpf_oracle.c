@@ -272,7 +272,32 @@ typedef struct {
     int32_t cooldown;   /* plateau: iterations without counting after a decrease */
     double min_lr;      /* plateau: lower bound on lr                             */
     double sched_eps;   /* plateau: decreases smaller than this are skipped       */
+    /* optimizer (Sec. 6.1 compares Adam, SGD and RMSprop): 0 Adam, 1 SGD with
+       momentum beta1 (0 = plain), 2 RMSprop with smoothing beta2, no momentum */
+    int32_t optimizer;
 } orc_opts_t;
+
+/* One optimizer update of a learnable coordinate x with gradient g and state
+ * m (first moment / momentum buffer), s (second moment), written as the
+ * optimizers define them (PyTorch conventions: SGD without dampening, the
+ * buffer starting at the first gradient; RMSprop not centred, eps outside the
+ * root; Adam as in Kingma & Ba with bias corrections bc1 = 1-b1^t, bc2 = 1-b2^t). */
+static double orc_opt_update(const orc_opts_t *o, double lr, double bc1, double bc2, double x, double g,
+                             double *m, double *s)
+{
+    if (o->optimizer == 1) {
+        *m = o->beta1 * *m + g;
+        return x - lr * *m;
+    }
+    if (o->optimizer == 2) {
+        *s = o->beta2 * *s + (1.0 - o->beta2) * (g * g);
+        return x - lr * (g / (sqrt(*s) + o->eps));
+    }
+    *m = o->beta1 * *m + (1.0 - o->beta1) * g;
+    *s = o->beta2 * *s + (1.0 - o->beta2) * (g * g);
+    double mhat = *m / bc1, shat = *s / bc2;
+    return x - lr * mhat / (sqrt(shat) + o->eps);
+}
 
 /*
  * One DPF solve for one case (Algorithm 1 with Adam).  Iteration k:
@@ -282,7 +307,8 @@ typedef struct {
  *      number of updates applied.  Non-finite mu stops the case (status 2);
  *      reaching k == max_iter stops it unconverged (status 1);
  *   3. gradient (2/m) J_f^T f;
- *   4. Adam step t = k+1 on the learnable entries (Kingma & Ba):
+ *   4. optimizer step t = k+1 on the learnable entries (orc_opt_update), by
+ *      default Adam (Kingma & Ba):
  *        m <- b1 m + (1-b1) g;  s <- b2 s + (1-b2) g^2;
  *        mhat = m/(1-b1^t);     shat = s/(1-b2^t);
  *        x <- x - lr * mhat / (sqrt(shat) + eps);
@@ -317,18 +343,10 @@ int32_t orc_solve_adam(int32_t n, const int32_t *rp, const int32_t *ci,
         double bc1 = 1.0 - pow(o->beta1, t);
         double bc2 = 1.0 - pow(o->beta2, t);
         for (int32_t i = 0; i < n; ++i) {
-            if (bus_type[i] == BUS_PQ) {
-                m_vm[i] = o->beta1 * m_vm[i] + (1.0 - o->beta1) * g_vm[i];
-                s_vm[i] = o->beta2 * s_vm[i] + (1.0 - o->beta2) * (g_vm[i] * g_vm[i]);
-                double mhat = m_vm[i] / bc1, shat = s_vm[i] / bc2;
-                vm[i] = vm[i] - lr * mhat / (sqrt(shat) + o->eps);
-            }
-            if (bus_type[i] != BUS_SLACK) {
-                m_va[i] = o->beta1 * m_va[i] + (1.0 - o->beta1) * g_va[i];
-                s_va[i] = o->beta2 * s_va[i] + (1.0 - o->beta2) * (g_va[i] * g_va[i]);
-                double mhat = m_va[i] / bc1, shat = s_va[i] / bc2;
-                va[i] = va[i] - lr * mhat / (sqrt(shat) + o->eps);
-            }
+            if (bus_type[i] == BUS_PQ)
+                vm[i] = orc_opt_update(o, lr, bc1, bc2, vm[i], g_vm[i], &m_vm[i], &s_vm[i]);
+            if (bus_type[i] != BUS_SLACK)
+                va[i] = orc_opt_update(o, lr, bc1, bc2, va[i], g_va[i], &m_va[i], &s_va[i]);
         }
         if (o->sched == 1) {
             /* reduce-on-plateau, mode "min", relative threshold */

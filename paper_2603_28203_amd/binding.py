@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libdpf.so")
 DPF_OK, DPF_EINVAL, DPF_ECAP, DPF_EHIP, DPF_ENOMEM, DPF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
 CONVERGED, MAX_ITER, NONFINITE, BAD_GRID = 0, 1, 2, 3
 SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
+OPT_ADAM, OPT_SGD, OPT_RMSPROP = 0, 1, 2
 PQ, PV, SLACK = 0, 1, 2
 
 
@@ -42,7 +43,8 @@ class _Grid(ctypes.Structure):
 class _Opts(ctypes.Structure):
     _fields_ = [("lr", _f64), ("beta1", _f64), ("beta2", _f64), ("eps", _f64), ("tol", _f64),
                 ("max_iter", _i32), ("sched", _i32), ("factor", _f64), ("patience", _i32),
-                ("threshold", _f64), ("cooldown", _i32), ("min_lr", _f64), ("sched_eps", _f64)]
+                ("threshold", _f64), ("cooldown", _i32), ("min_lr", _f64), ("sched_eps", _f64),
+                ("optimizer", _i32)]
 
 
 _lib = None
@@ -185,7 +187,9 @@ def mismatch_grad(grid: DeviceGrid, bus_type, s_spec, vm, va, outage=None, want_
 
 @dataclass
 class Options:
-    """Optimizer settings of Algorithm 1 (Adam + schedule + tolerance)."""
+    """Optimizer settings of Algorithm 1 (optimizer + schedule + tolerance);
+    optimizer = OPT_ADAM (default), OPT_SGD (momentum beta1) or OPT_RMSPROP
+    (smoothing beta2)."""
     lr: float = 1e-2
     beta1: float = 0.9
     beta2: float = 0.999
@@ -199,11 +203,12 @@ class Options:
     cooldown: int = 0
     min_lr: float = 0.0
     sched_eps: float = 1e-8
+    optimizer: int = OPT_ADAM
 
     def c(self) -> _Opts:
         return _Opts(self.lr, self.beta1, self.beta2, self.eps, self.tol, int(self.max_iter), int(self.sched),
                      self.factor, int(self.patience), self.threshold, int(self.cooldown), self.min_lr,
-                     self.sched_eps)
+                     self.sched_eps, int(self.optimizer))
 
 
 class SolveWorkspace:
@@ -351,7 +356,7 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded")
+VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream")
 
 
 def variants():
@@ -413,7 +418,7 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
     times = {}
     for v in variants():
-        if not (v["kind"] == "banded" or v["buses_per_thread"] == 0
+        if not (v["kind"].startswith("banded") or v["buses_per_thread"] == 0
                 or v["threads"] * v["buses_per_thread"] >= n_max):
             continue
         _check(lib().dpf_autotune_set(n_max, v["index"]))

@@ -67,6 +67,26 @@ __device__ __forceinline__ void branch_admittance(double r, double x, double b, 
     ysh = make_double2(0.0, 0.5 * b);
 }
 
+// ---------------------------------------------------------------- optimizer
+// One optimizer update of a learnable coordinate x with gradient g and state
+// m (first moment / momentum buffer), s (second moment); kind = DPF_OPT_*
+// (0 Adam with bias corrections bc1 = 1 - b1^t, bc2 = 1 - b2^t; 1 SGD with
+// momentum b1; 2 RMSprop with smoothing b2).
+__device__ __forceinline__ double opt_update(int kind, double lr, double b1, double b2, double eps, double bc1,
+                                             double bc2, double x, double g, double &m, double &s) {
+    if (kind == 1) {
+        m = b1 * m + g;
+        return x - lr * m;
+    }
+    if (kind == 2) {
+        s = b2 * s + (1.0 - b2) * (g * g);
+        return x - lr * (g / (sqrt(s) + eps));
+    }
+    m = b1 * m + (1.0 - b1) * g;
+    s = b2 * s + (1.0 - b2) * (g * g);
+    return x - lr * (m / bc1) / (sqrt(s / bc2) + eps);
+}
+
 // ---------------------------------------------------------------- sin / cos
 // sincos for the voltage angles, after fdlibm (Sun Microsystems, 1993): a
 // three-step Cody-Waite reduction by pi/2 (valid for |x| < 2^19 pi/2) and the

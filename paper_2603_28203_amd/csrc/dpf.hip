@@ -106,9 +106,9 @@ template <int NT, int K>
 Variant make_stream_variant() {
     return Variant{NT, K, dpf::kGlobal, dpf::team_solve_stream_kernel<NT, K>};
 }
-template <int NT, int J>
+template <int NT, int J, bool PIPE = true>
 Variant make_band_variant() {
-    return Variant{NT, J, dpf::kBand, dpf::team_solve_band_kernel<NT, J>};
+    return Variant{NT, J, PIPE ? dpf::kBand : dpf::kBandStream, dpf::team_solve_band_kernel<NT, J, PIPE>};
 }
 
 // Register-resident variants up to 2048 buses per item, streaming above (512 threads
@@ -122,14 +122,15 @@ const Variant *variant_table(int *count) {
         make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<512, 8>(),
         make_stream_variant<512, 12>(), make_stream_variant<512, 16>(), make_stream_variant<512, 20>(),
         make_stream_variant<1024, 0>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
-        make_band_variant<512, 2>(),
+        make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
+        make_band_variant<512, 2, false>(),
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;
 }
 
 bool variant_fits(const Variant &v, int32_t n_max) {
-    return v.mode == dpf::kBand || v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k;
+    return dpf::is_banded(v.mode) || v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k;
 }
 
 // Autotune cache: size class (index of the default variant) -> chosen variant.
@@ -142,7 +143,7 @@ int default_variant_index(int32_t n_max) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     for (int i = 0; i < cnt; ++i)
-        if (t[i].mode != dpf::kBand && variant_fits(t[i], n_max)) return i;
+        if (!dpf::is_banded(t[i].mode) && variant_fits(t[i], n_max)) return i;
     return -1;
 }
 
@@ -162,6 +163,7 @@ bool valid_opts(const dpf_opts_t *o) {
         return false;
     if (!(o->eps >= 0.0) || !(o->tol >= 0.0) || o->max_iter < 0) return false;
     if (o->sched < DPF_SCHED_CONSTANT || o->sched > DPF_SCHED_STEP) return false;
+    if (o->optimizer < DPF_OPT_ADAM || o->optimizer > DPF_OPT_RMSPROP) return false;
     if (o->sched != DPF_SCHED_CONSTANT && (!(o->factor >= 0.0) || o->patience < 0 || o->cooldown < 0))
         return false;
     return true;
@@ -263,6 +265,7 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.m_res = (const double *)(ws + L.off_mres);
     w.sched = a.sched;
     w.lr = a.lr;
+    w.opt = a.opt;
     w.b1 = a.b1;
     w.b2 = a.b2;
     w.eps = a.eps;
@@ -766,6 +769,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.n_sub = n_sub;
     a.B = B;
     a.lr = opts->lr;
+    a.opt = opts->optimizer;
     a.b1 = opts->beta1;
     a.b2 = opts->beta2;
     a.eps = opts->eps;
@@ -801,7 +805,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
         hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
         DPF_HIP(hipGetLastError());
-        if (v->mode == dpf::kBand) {
+        if (dpf::is_banded(v->mode)) {
             // items whose bandwidth exceeds the banded block go to the general variant
             int cnt = 0;
             const Variant *f = &variant_table(&cnt)[default_variant_index(std::max(1, n_max))];

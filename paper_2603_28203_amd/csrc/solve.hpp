@@ -33,7 +33,8 @@
 
 namespace dpf {
 
-enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2 };
+enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3 };
+__host__ __device__ constexpr bool is_banded(int mode) { return mode == kBand || mode == kBandStream; }
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched
 
@@ -64,6 +65,7 @@ struct SolveArgs {
     int32_t B;
     int32_t lds_cap;     // complex entries available in dynamic LDS
     double lr, b1, b2, eps, tol;
+    int32_t opt;  // DPF_OPT_*
     int32_t max_iter;
     int32_t sch;
     double factor;
@@ -348,9 +350,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                         sv = sv_c[i];
                     }
                     const double g = (G.x * v.x + G.y * v.y) / vmi;
-                    mv = a.b1 * mv + (1.0 - a.b1) * g;
-                    sv = a.b2 * sv + (1.0 - a.b2) * (g * g);
-                    vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                    vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                     if (!REG) {
                         vm_c[i] = vmi;
                         mv_c[i] = mv;
@@ -363,9 +363,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                         sa = sa_c[i];
                     }
                     const double g = G.y * v.x - G.x * v.y;
-                    ma = a.b1 * ma + (1.0 - a.b1) * g;
-                    sa = a.b2 * sa + (1.0 - a.b2) * (g * g);
-                    vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                    vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                     if (!REG) {
                         va_c[i] = vai;
                         ma_c[i] = ma;
@@ -687,18 +685,16 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 }
                 if (tk == kPQ) {
                     const double g = (G.x * v.x + G.y * v.y) / vmi;
-                    const double mv = a.b1 * mv0 + (1.0 - a.b1) * g;
-                    const double sv = a.b2 * sv0 + (1.0 - a.b2) * (g * g);
-                    vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                    double mv = mv0, sv = sv0;
+                    vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                     vm_c[i] = vmi;
                     mv_c[i] = mv;
                     sv_c[i] = sv;
                 }
                 if (tk != kSlack) {
                     const double g = G.y * v.x - G.x * v.y;
-                    const double ma = a.b1 * ma0 + (1.0 - a.b1) * g;
-                    const double sa = a.b2 * sa0 + (1.0 - a.b2) * (g * g);
-                    vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                    double ma = ma0, sa = sa0;
+                    vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                     va_c[i] = vai;
                     ma_c[i] = ma;
                     sa_c[i] = sa;
@@ -788,7 +784,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 // Per bus and iteration this moves |V|, theta and the four moments once each way
 // plus I (16 B written, 16 B read), and evaluates one polar conversion per sweep;
 // there is no V or w round trip through memory.
-template <int NT, int J>
+template <int NT, int J, bool PIPE>
 __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
     constexpr int BLK = NT * J;
     extern __shared__ double2 X[];
@@ -963,7 +959,10 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
         b2t *= a.b2;
         const double bc1 = 1.0 - b1t;
         const double bc2 = 1.0 - b2t;
-        for (int s = 0; s <= nb; ++s) {
+        // PIPE: block steps with a barrier each, the new V held for one step.
+        // Otherwise: one barrier-free pass (w stays in X throughout), then the
+        // new V is rebuilt from |V| and theta in a refill pass.
+        for (int s = 0; s <= (PIPE ? nb : nb - 1); ++s) {
             double2 vn[J];
 #pragma unroll
             for (int j = 0; j < J; ++j) {
@@ -999,37 +998,48 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
                     if (tk == kPQ) {
                         const double g = (G.x * v.x + G.y * v.y) / vmi;
-                        const double mv = a.b1 * mv0 + (1.0 - a.b1) * g;
-                        const double sv = a.b2 * sv0 + (1.0 - a.b2) * (g * g);
-                        vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+                        double mv = mv0, sv = sv0;
+                        vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                         vm_c[i] = vmi;
                         mv_c[i] = mv;
                         sv_c[i] = sv;
                     }
                     if (tk != kSlack) {
                         const double g = G.y * v.x - G.x * v.y;
-                        const double ma = a.b1 * ma0 + (1.0 - a.b1) * g;
-                        const double sa = a.b2 * sa0 + (1.0 - a.b2) * (g * g);
-                        vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+                        double ma = ma0, sa = sa0;
+                        vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                         va_c[i] = vai;
                         ma_c[i] = ma;
                         sa_c[i] = sa;
                     }
-                    double sn, cs;
-                    fast_sincos(vai, sn, cs);
-                    vn[j] = make_double2(vmi * cs, vmi * sn);
+                    if (PIPE) {
+                        double sn, cs;
+                        fast_sincos(vai, sn, cs);
+                        vn[j] = make_double2(vmi * cs, vmi * sn);
+                    }
                 }
             }
+            if (PIPE) {
+                __syncthreads();
+                if (s > 0) {
+#pragma unroll
+                    for (int j = 0; j < J; ++j) {
+                        const int il = (s - 1) * BLK + j * NT + tid;
+                        if (il < n) X[il] = hold[j];
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < J; ++j) hold[j] = vn[j];
+            }
+        }
+        if (!PIPE) {
             __syncthreads();
-            if (s > 0) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const int il = (s - 1) * BLK + j * NT + tid;
-                    if (il < n) X[il] = hold[j];
-                }
+            for (int i = lo + tid; i < hi; i += NT) {
+                double sn, cs;
+                const double vmi = vm_c[i];
+                fast_sincos(va_c[i], sn, cs);
+                X[i - lo] = make_double2(vmi * cs, vmi * sn);
             }
-#pragma unroll
-            for (int j = 0; j < J; ++j) hold[j] = vn[j];
         }
         if (a.sch == DPF_SCHED_PLATEAU) {
             if (loss < best * (1.0 - a.threshold)) {

@@ -47,6 +47,7 @@ struct WideArgs {
     const double *m_res; // [n_sub] residual count per sub-grid
     double *sched;       // caller schedule state or null
     double lr, b1, b2, eps, tol;
+    int32_t opt;  // DPF_OPT_*
     int32_t max_iter, sch;
     double factor;
     int32_t patience;
@@ -286,18 +287,16 @@ __global__ __launch_bounds__(256) void wide_phase_b_kernel(WideArgs a) {
     double vmi = a.vm[o], vai = a.va[o];
     if (tk == kPQ) {
         const double g = (G.x * v.x + G.y * v.y) / vmi;
-        const double mv = a.b1 * a.st[o] + (1.0 - a.b1) * g;
-        const double sv = a.b2 * a.st[2 * a.st_stride + o] + (1.0 - a.b2) * (g * g);
-        vmi = vmi - lr * (mv / bc1) / (sqrt(sv / bc2) + a.eps);
+        double mv = a.st[o], sv = a.st[2 * a.st_stride + o];
+        vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
         a.vm[o] = vmi;
         a.st[o] = mv;
         a.st[2 * a.st_stride + o] = sv;
     }
     if (tk != kSlack) {
         const double g = G.y * v.x - G.x * v.y;
-        const double ma = a.b1 * a.st[a.st_stride + o] + (1.0 - a.b1) * g;
-        const double sa = a.b2 * a.st[3 * a.st_stride + o] + (1.0 - a.b2) * (g * g);
-        vai = vai - lr * (ma / bc1) / (sqrt(sa / bc2) + a.eps);
+        double ma = a.st[a.st_stride + o], sa = a.st[3 * a.st_stride + o];
+        vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
         a.va[o] = vai;
         a.st[a.st_stride + o] = ma;
         a.st[3 * a.st_stride + o] = sa;

@@ -715,7 +715,7 @@ def test_banded_variants_track_oracle(tuned, n_bus, group):
                               oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
     Yg = dgrid(dpf, g)
     for v in dpf.variants():
-        if v["kind"] != "banded" and not (v["buses_per_thread"] == 0
+        if not v["kind"].startswith("banded") and not (v["buses_per_thread"] == 0
                                           or v["threads"] * v["buses_per_thread"] >= g.n_bus):
             continue
         dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
@@ -756,7 +756,7 @@ def test_banded_block_boundary(tuned, chord):
     ref = oracle.solve_adam(Yo, bt, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
     Yg = dgrid(dpf, g)
     for v in dpf.variants():
-        if not (v["kind"] == "banded" and v["threads"] == 1024 and v["buses_per_thread"] == 1):
+        if not (v["kind"].startswith("banded") and v["threads"] == 1024 and v["buses_per_thread"] == 1):
             continue
         dpf.lib().dpf_autotune_set(n, v["index"])
         vm = cu(vm0[None]); va = cu(va0[None])
@@ -797,3 +797,44 @@ def test_banded_and_general_sub_grids_in_one_call(tuned):
                                 oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
         assert np.abs(vm[0, sl].cpu().numpy() - ref["vm"]).max() < 1e-10
         assert np.abs(va[0, sl].cpu().numpy() - ref["va"]).max() < 1e-10
+
+
+# ---------------------------------------------------------------- SGD and RMSprop
+
+
+@pytest.mark.parametrize("path", ["register", "streaming", "banded", "wide"])
+@pytest.mark.parametrize("kind", ["sgd", "rmsprop"])
+def test_other_optimizers_track_oracle(tuned, path, kind):
+    """SGD (with momentum) and RMSprop, the paper's alternatives to Adam, on
+    every solve path: iterates equal the oracle's after a few steps."""
+    dpf = tuned
+    n = 300 if path == "register" else 3000
+    g = synth.config1(B=1, seed=9100 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
+    if path == "banded":
+        g = renumber(g, dpf.rcm_order(g.n_bus, g.f, g.t)[0])
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(n + len(kind))
+    vm0 = g.vm + rng.normal(0, 1e-2, n) * (g.bus_type == 0)
+    va0 = g.va + rng.normal(0, 1e-2, n) * (g.bus_type != 2)
+    steps = 8
+    if kind == "sgd":
+        o = dict(lr=1e-3, beta1=0.9, optimizer=dpf.OPT_SGD)
+    else:
+        o = dict(lr=1e-3, beta2=0.99, eps=1e-8, optimizer=dpf.OPT_RMSPROP)
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
+    Yg = dgrid(dpf, g)
+    if path == "banded":
+        band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
+        dpf.lib().dpf_autotune_set(n, band)
+    if path == "wide":
+        dpf.set_team_cap(1000)
+    print(f"optimizer {kind} on the {path} path, n={n}", flush=True)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va,
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+    torch.cuda.synchronize()
+    assert out["iters"].item() == steps
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
+    assert np.abs(va[0].cpu().numpy() - va0).max() > 1e-4  # the update moved the iterate

@@ -318,6 +318,50 @@ def _torch_adam_reference(Y, bt, S, vm0, va0, steps, lr, betas, eps, plateau=Non
     return pv.detach().numpy(), pa.detach().numpy(), lrs
 
 
+def _torch_opt_reference(Y, bt, S, vm0, va0, steps, make_opt):
+    """The same iteration driven by a torch.optim optimizer on the oracle's gradients."""
+    torch = pytest.importorskip("torch")
+    pv = torch.nn.Parameter(torch.tensor(vm0, dtype=torch.float64))
+    pa = torch.nn.Parameter(torch.tensor(va0, dtype=torch.float64))
+    opt = make_opt([pv, pa])
+    for _ in range(steps):
+        _, _, gvm, gva = oracle.loss_grad(Y, bt, pv.detach().numpy(), pa.detach().numpy(), S)
+        pv.grad = torch.tensor(gvm)
+        pa.grad = torch.tensor(gva)
+        opt.step()
+    return pv.detach().numpy(), pa.detach().numpy()
+
+
+@pytest.mark.parametrize("kind", ["sgd", "sgd_momentum", "rmsprop"])
+def test_sgd_and_rmsprop_match_torch_optim(kind):
+    """The paper's other optimizers (Sec. 6.1: SGD and RMSprop) with PyTorch's
+    definitions: SGD with momentum beta1 (buffer = first gradient, no
+    dampening), RMSprop with smoothing beta2 and eps outside the root."""
+    torch = pytest.importorskip("torch")
+    g = synth.config0(1)["grid"]
+    Y = oracle.ybus_of(g)
+    S = oracle.injections(Y, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    # short enough that no coordinate has started to oscillate about its
+    # solution (there the sign-like steps amplify rounding differences)
+    steps = 50 if kind == "rmsprop" else 200
+    if kind == "rmsprop":
+        o = oracle.AdamOptions(lr=1e-3, beta2=0.99, eps=1e-8, tol=0.0, max_iter=steps,
+                               optimizer=oracle.OPT_RMSPROP)
+        make = lambda p: torch.optim.RMSprop(p, lr=1e-3, alpha=0.99, eps=1e-8)
+    else:
+        mom = 0.9 if kind == "sgd_momentum" else 0.0
+        o = oracle.AdamOptions(lr=3e-3, beta1=mom, tol=0.0, max_iter=steps, optimizer=oracle.OPT_SGD)
+        make = lambda p: torch.optim.SGD(p, lr=3e-3, momentum=mom)
+    ref_vm, ref_va = _torch_opt_reference(Y, g.bus_type, S, vm0, va0, steps, make)
+    res = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, o)
+    assert res["iters"] == steps
+    assert np.abs(res["vm"] - ref_vm).max() < 1e-12
+    assert np.abs(res["va"] - ref_va).max() < 1e-12
+    # the iteration moved: the pin is not satisfied by a no-op update
+    assert np.abs(res["va"] - va0).max() > 1e-3
+
+
 def test_adam_matches_torch_optim():
     g = synth.config0(1)["grid"]
     Y = oracle.ybus_of(g)
