@@ -185,6 +185,31 @@ int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *
 size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B);
 
 /*
+ * dpf_param_grad -- gradient of each case's loss with respect to the simulation
+ * parameters: every branch's r, x, b and the specified injections S_spec (Sec. 1
+ * and Sec. 2.3: the mismatch is differentiated end to end, so parameters can be
+ * identified by gradient descent).  Same forward pass as dpf_mismatch_grad; then,
+ * with the adjoint seed w_i = a_i conj(V_i), a_i = (2/m)(r^P_i + j r^Q_i), a branch
+ * (f, t) with y = 1/(r + jx) and D = (w_f - w_t)(V_f - V_t) has
+ *   dL/dr = -Re(y^2 D),  dL/dx = Im(y^2 D),  dL/db = -Im(w_f V_f + w_t V_t) / 2,
+ * and dL/dS_spec,i = -a_i (as d/dRe S + j d/dIm S).
+ * Arguments as in dpf_mismatch_grad, plus:
+ *   loss, max_mis : device [B] out, nullable (both or neither)
+ *   g_r, g_x, g_b : device double [B][bld] out (bld >= n_branch), nullable (all or
+ *                   none; need the grid's branch arrays).  A case's outaged branch
+ *                   is absent from its Y and gets 0.
+ *   g_s           : device complex [B][ld] out, nullable
+ *   workspace     : >= dpf_mismatch_grad_workspace_bytes(n_bus, B)
+ * Per case, not summed over cases (a shared S_spec or branch gets one gradient
+ * row per case).  Errors: DPF_EINVAL, DPF_ENOMEM, DPF_EHIP.
+ */
+int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus_type,
+                   const double *s_spec, int32_t s_ld, const int32_t *outage, const double *vm,
+                   const double *va, double *loss, double *max_mis, double *g_r, double *g_x,
+                   double *g_b, int32_t bld, double *g_s, void *workspace, size_t ws_bytes,
+                   void *stream);
+
+/*
  * dpf_solve_batch -- the DPF iteration (Algorithm 1 with Adam) run to
  * convergence for many independent problems in ONE kernel launch.
  *
@@ -292,6 +317,33 @@ size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int
  */
 int dpf_order_rcm(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, int32_t n_sub,
                   const int32_t *sub_offset, int32_t group, int32_t *perm, int32_t *bandwidth_out);
+
+/*
+ * dpf_dc_init -- DC power flow angles as a start point (Algorithm 2 initialises
+ * with the DC power flow; Sec. 3 lists the DC approximation as a screening
+ * method).  Solves  L theta = P  on the non-slack buses, with P = Re S_spec, the
+ * slack angle fixed at its input value and L the branch-susceptance Laplacian
+ * (weights 1/x): L_ij = -Im(Y_ij) of `g_dc`, the admittance matrix of the same
+ * branches built with r = 0 and b = 0 (dpf_build_ybus), whose branch arrays
+ * (r = 0, b = 0) give the N-1 corrections.  Jacobi-preconditioned conjugate
+ * gradients, one workgroup per case, until ||P - L theta||_2 <= tol ||P||_2 or
+ * max_iter iterations.  vm is not an argument: the DC model takes the start
+ * point's magnitudes (flat: 1 at PQ, setpoints at PV and slack).
+ *   B, ld, bus_type, s_spec, s_ld, outage : as in dpf_mismatch_grad
+ *   va        : device [B][ld] in: start angles (slack entry = slack angle;
+ *               others: the CG start, e.g. 0), out: DC angles (slack unchanged)
+ *   iters     : device int32 [B] out, nullable: CG iterations
+ *   residual  : device double [B] out, nullable: final ||r||_2 / ||P||_2
+ *   workspace : >= dpf_dc_init_workspace_bytes(n_bus, B)
+ * Errors: DPF_EINVAL, DPF_ENOMEM, DPF_EUNSUPPORTED (more buses than one
+ * workgroup's LDS holds at 8 B per bus), DPF_EHIP.
+ */
+int dpf_dc_init(const dpf_grid_t *g_dc, int32_t B, int32_t ld, const int8_t *bus_type,
+                const double *s_spec, int32_t s_ld, const int32_t *outage, double *va, double tol,
+                int32_t max_iter, int32_t *iters, double *residual, void *workspace, size_t ws_bytes,
+                void *stream);
+
+size_t dpf_dc_init_workspace_bytes(int32_t n_bus, int32_t B);
 
 /* Largest sub-grid (buses) one workgroup can hold on this device; larger sub-grids
  * are solved by several workgroups (see dpf_autotune_set_team_cap). */

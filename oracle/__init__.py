@@ -30,7 +30,7 @@ PQ, PV, SLACK = 0, 1, 2
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (always when force, else only if missing)."""
+    """Compile the C oracle with gcc (when forced, missing or older than its source)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
         tmp = LIB + ".tmp"
         subprocess.check_call(["gcc", *CFLAGS, SRC, "-o", tmp, "-lm"])
@@ -59,6 +59,7 @@ def _load():
         lib.orc_loss_from_mismatch.argtypes = [i32, P, P, P]
         lib.orc_loss_from_mismatch.restype = d
         lib.orc_dS_dV.argtypes = [i32, P, P, P, P, P, P, P]
+        lib.orc_param_grad.argtypes = [i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P]
         lib.orc_loss_grad.argtypes = [i32, P, P, P, P, P, P, P, P, P, P]
         lib.orc_loss_grad.restype = d
         lib.orc_solve_adam.argtypes = [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
@@ -195,6 +196,48 @@ def loss_grad(Y: CSR, bus_type, vm, va, s_spec):
     loss = lib.orc_loss_grad(Y.n, _p(Y.row_ptr), _p(Y.col), _p(Y.val), _p(bt), _p(vm), _p(va),
                              _p(s), _p(gvm), _p(gva), ctypes.byref(mu))
     return float(loss), float(mu.value), gvm, gva
+
+
+def param_grad(grid, bus_type, vm, va, s_spec, skip: int = -1):
+    """(g_r, g_x, g_b, g_s): gradient of one case's loss with respect to every
+    branch's r, x, b and to S_spec (complex: d/dRe S + j d/dIm S).  Branch `skip`
+    is outaged (absent from Y; zero gradient)."""
+    lib = _load()
+    Y = ybus_of(grid, skip=skip)
+    f, t = _i32(grid.f), _i32(grid.t)
+    r, x, b = _f64(grid.r), _f64(grid.x), _f64(grid.b)
+    bt, vm, va, s = _i8(bus_type), _f64(vm), _f64(va), _c128(s_spec)
+    nb = len(f)
+    g_r, g_x, g_b = np.zeros(nb), np.zeros(nb), np.zeros(nb)
+    g_s = np.zeros(Y.n, dtype=np.complex128)
+    lib.orc_param_grad(Y.n, nb, _p(f), _p(t), _p(r), _p(x), _p(b), int(skip), _p(Y.row_ptr), _p(Y.col),
+                       _p(Y.val), _p(bt), _p(vm), _p(va), _p(s), _p(g_r), _p(g_x), _p(g_b), _p(g_s))
+    return g_r, g_x, g_b, g_s
+
+
+def dc_power_flow(grid, bus_type, s_spec, va_slack: float = 0.0, skip: int = -1):
+    """DC power flow angles (the linear approximation used to start Newton-Raphson
+    in Algorithm 2): L theta = Re S_spec on the non-slack buses, L the Laplacian
+    of the branch susceptances 1/x (parallel branches add, branch `skip` left
+    out), the slack angle fixed at va_slack.  A library sparse solve does the
+    linear algebra."""
+    import scipy.sparse as sp
+    import scipy.sparse.linalg as spla
+    n = grid.n_bus
+    keep = np.ones(len(grid.f), dtype=bool)
+    if skip >= 0:
+        keep[skip] = False
+    f, t, w = grid.f[keep], grid.t[keep], 1.0 / grid.x[keep]
+    L = sp.coo_matrix((np.concatenate([w, w, -w, -w]),
+                       (np.concatenate([f, t, f, t]), np.concatenate([f, t, t, f]))), shape=(n, n)).tocsr()
+    bt = np.asarray(bus_type)
+    free = np.flatnonzero(bt != 2)
+    slack = np.flatnonzero(bt == 2)
+    theta = np.zeros(n)
+    theta[slack] = va_slack
+    rhs = np.asarray(s_spec).real[free] - L[free][:, slack] @ theta[slack]
+    theta[free] = spla.spsolve(L[free][:, free].tocsc(), rhs)
+    return theta
 
 
 class _Opts(ctypes.Structure):

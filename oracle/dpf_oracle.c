@@ -259,6 +259,75 @@ double orc_loss_grad(int32_t n, const int32_t *rp, const int32_t *ci, const doub
     return loss;
 }
 
+/* ------------------------------------------------------- parameter gradient */
+
+/*
+ * Gradient of the loss with respect to the simulation parameters (Sec. 1 and
+ * Sec. 2.3: gradients propagate from the power mismatch to the parameters of
+ * the simulation, which can then be identified by gradient descent).
+ * Parameters: each branch's r, x, b (pi model, Sec. 2.1 via Y) and the
+ * specified injections S_spec.  Forward mode, one parameter at a time: a branch
+ * parameter p changes only the four entries of Y that the branch stamps,
+ *   dY_ff = dY_tt = dy + j db/2,  dY_ft = dY_tf = -dy,  y = 1/(r + jx),
+ *   dy/dr = -y^2,  dy/dx = -j y^2,
+ * so dI = dY V is nonzero at f and t only, dS_i = V_i conj(dI_i) there, and
+ *   dL = (2/m) sum_{i in {f,t}} (r^P_i Re dS_i + r^Q_i Im dS_i).
+ * For S_spec: d dS_i / d S_i = -1, so dL/dRe S_i = -(2/m) r^P_i and
+ * dL/dIm S_i = -(2/m) r^Q_i (returned as one complex number per bus).
+ * Branch `skip` (an N-1 outage, or -1) is absent from Y: its gradients are 0.
+ * The residuals come from Y given in CSR (which must already exclude `skip`).
+ */
+void orc_param_grad(int32_t n, int32_t n_branch, const int32_t *from, const int32_t *to,
+                    const double *r, const double *x, const double *b, int32_t skip,
+                    const int32_t *rp, const int32_t *ci, const double complex *yv,
+                    const int8_t *bus_type, const double *vm, const double *va,
+                    const double complex *s_spec, double *g_r, double *g_x, double *g_b,
+                    double complex *g_s)
+{
+    double complex *V = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    double complex *dS = (double complex *)malloc(sizeof(double complex) * (size_t)n);
+    orc_polar(n, vm, va, V);
+    orc_mismatch(n, rp, ci, yv, vm, va, s_spec, dS);
+    int32_t m = orc_residual_count(n, bus_type);
+    double k = m > 0 ? 2.0 / (double)m : 0.0;
+    /* masked residuals r^P, r^Q per bus */
+    double *rP = (double *)calloc((size_t)n, sizeof(double));
+    double *rQ = (double *)calloc((size_t)n, sizeof(double));
+    for (int32_t i = 0; i < n; ++i) {
+        if (bus_type[i] != BUS_SLACK) rP[i] = creal(dS[i]);
+        if (bus_type[i] == BUS_PQ) rQ[i] = cimag(dS[i]);
+        if (g_s) g_s[i] = -k * rP[i] - I * (k * rQ[i]);
+    }
+    for (int32_t e = 0; e < n_branch; ++e) {
+        double gr = 0.0, gx = 0.0, gb = 0.0;
+        if (e != skip && from[e] != to[e]) {
+            int32_t f = from[e], t = to[e];
+            double complex y = 1.0 / (r[e] + I * x[e]);
+            /* dY stamps per unit change of r, x and b */
+            double complex dy_dp[3] = {-y * y, -I * y * y, 0.0};
+            double complex dsh_dp[3] = {0.0, 0.0, 0.5 * I};
+            double out3[3];
+            for (int p = 0; p < 3; ++p) {
+                double complex dI_f = (dy_dp[p] + dsh_dp[p]) * V[f] - dy_dp[p] * V[t];
+                double complex dI_t = (dy_dp[p] + dsh_dp[p]) * V[t] - dy_dp[p] * V[f];
+                double complex dS_f = V[f] * conj(dI_f), dS_t = V[t] * conj(dI_t);
+                out3[p] = k * (rP[f] * creal(dS_f) + rQ[f] * cimag(dS_f) +
+                               rP[t] * creal(dS_t) + rQ[t] * cimag(dS_t));
+            }
+            gr = out3[0];
+            gx = out3[1];
+            gb = out3[2];
+        }
+        if (g_r) g_r[e] = gr;
+        if (g_x) g_x[e] = gx;
+        if (g_b) g_b[e] = gb;
+    }
+    free(V);
+    free(dS);
+    free(rP);
+    free(rQ);
+}
+
 /* ------------------------------------------------------------- Adam solve */
 
 typedef struct {

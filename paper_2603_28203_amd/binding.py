@@ -64,6 +64,14 @@ def lib():
         L.dpf_mismatch_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P,
                                         _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.dpf_mismatch_grad.restype = ctypes.c_int
+        L.dpf_param_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P, _P, _P, _P,
+                                     _P, _i32, _P, _P, ctypes.c_size_t, _P]
+        L.dpf_param_grad.restype = ctypes.c_int
+        L.dpf_dc_init.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, ctypes.c_double, _i32,
+                                  _P, _P, _P, ctypes.c_size_t, _P]
+        L.dpf_dc_init.restype = ctypes.c_int
+        L.dpf_dc_init_workspace_bytes.argtypes = [_i32, _i32]
+        L.dpf_dc_init_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_mismatch_grad_workspace_bytes.argtypes = [_i32, _i32]
         L.dpf_mismatch_grad_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_solve_batch.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _P, _i32, _i32, _P, _P, _i32, _P,
@@ -183,6 +191,60 @@ def mismatch_grad(grid: DeviceGrid, bus_type, s_spec, vm, va, outage=None, want_
     _check(lib().dpf_mismatch_grad(ctypes.byref(g), B, ld, _ptr(bt), _ptr(s), s_ld, _ptr(out), _ptr(vm), _ptr(va),
                                    _ptr(dS), _ptr(loss), _ptr(mx), _ptr(gv), _ptr(ga), _ptr(ws), wsb, _stream()))
     return {"dS": dS, "loss": loss, "max_mis": mx, "g_vm": gv, "g_va": ga}
+
+
+def param_grad(grid: DeviceGrid, bus_type, s_spec, vm, va, outage=None, want_branch=True, want_s=True):
+    """dpf_param_grad: per-case gradient of the loss with respect to every
+    branch's r, x, b ([B, n_branch] each) and to S_spec ([B, n] complex,
+    d/dRe S + j d/dIm S).  Returns dict(loss, max_mis, g_r, g_x, g_b, g_s)."""
+    dev = vm.device
+    B, ld = vm.shape
+    bt = _dev(bus_type, torch.int8, dev)
+    s = _dev(s_spec, torch.complex128, dev)
+    s_ld = 0 if s.dim() == 1 else s.shape[1]
+    vm = vm.contiguous()
+    va = va.contiguous()
+    out = _dev(outage, torch.int32, dev) if outage is not None else None
+    nb = grid.n_branch
+    loss = torch.empty(B, dtype=torch.float64, device=dev)
+    mx = torch.empty(B, dtype=torch.float64, device=dev)
+    gr, gx, gb = ((torch.empty((B, nb), dtype=torch.float64, device=dev) for _ in range(3)) if want_branch
+                  else (None, None, None))
+    gs = torch.empty((B, ld), dtype=torch.complex128, device=dev) if want_s else None
+    wsb = lib().dpf_mismatch_grad_workspace_bytes(grid.n_bus, B)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    g = grid.c()
+    _check(lib().dpf_param_grad(ctypes.byref(g), B, ld, _ptr(bt), _ptr(s), s_ld, _ptr(out), _ptr(vm), _ptr(va),
+                                _ptr(loss), _ptr(mx), _ptr(gr), _ptr(gx), _ptr(gb), max(nb, 1), _ptr(gs), _ptr(ws),
+                                wsb, _stream()))
+    return {"loss": loss, "max_mis": mx, "g_r": gr, "g_x": gx, "g_b": gb, "g_s": gs}
+
+
+def build_dc_grid(n_bus: int, f, t, x, device="cuda") -> DeviceGrid:
+    """The admittance matrix of the branches with r = 0 and b = 0, whose
+    susceptance Laplacian L = -Im(Y) is the DC power flow matrix."""
+    z = np.zeros(len(np.asarray(f)))
+    return build_ybus(n_bus, f, t, z, x, z, device=device)
+
+
+def dc_init(dc_grid: DeviceGrid, bus_type, s_spec, va, outage=None, tol: float = 1e-12, max_iter: int = 20000):
+    """dpf_dc_init: DC power flow angles written into va ([B, n] float64, in
+    place; slack entries are kept).  Returns dict(iters, residual)."""
+    dev = va.device
+    B, ld = va.shape
+    assert va.is_contiguous() and va.dtype == torch.float64
+    bt = _dev(bus_type, torch.int8, dev)
+    s = _dev(s_spec, torch.complex128, dev)
+    s_ld = 0 if s.dim() == 1 else s.shape[1]
+    out = _dev(outage, torch.int32, dev) if outage is not None else None
+    it = torch.empty(B, dtype=torch.int32, device=dev)
+    res = torch.empty(B, dtype=torch.float64, device=dev)
+    wsb = int(lib().dpf_dc_init_workspace_bytes(dc_grid.n_bus, B))
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    g = dc_grid.c()
+    _check(lib().dpf_dc_init(ctypes.byref(g), B, ld, _ptr(bt), _ptr(s), s_ld, _ptr(out), _ptr(va), float(tol),
+                             int(max_iter), _ptr(it), _ptr(res), _ptr(ws), wsb, _stream()))
+    return {"iters": it, "residual": res}
 
 
 @dataclass

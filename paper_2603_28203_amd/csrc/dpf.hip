@@ -11,6 +11,7 @@
 
 #include "../../include/dpf.h"
 #include "common.hpp"
+#include "dc.hpp"
 #include "eval.hpp"
 #include "sell.hpp"
 #include "solve.hpp"
@@ -435,13 +436,112 @@ int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *
     hipLaunchKernelGGL(dpf::polar_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, (int64_t)ld, vm, va, Vw);
     hipLaunchKernelGGL(dpf::forward_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr, g->col_idx,
                        (const double2 *)g->val, bus_type, (const double2 *)s_spec, (int64_t)s_ld, ov, Vw, m_res,
-                       (int64_t)ld, (double2 *)dS, ww, aI, part);
+                       (int64_t)ld, (double2 *)dS, ww, aI, part, nullptr);
     if (g_vm)
         hipLaunchKernelGGL(dpf::adjoint_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr,
                            g->col_idx, (const double2 *)g->val, bus_type, ov, Vw, vm, (int64_t)ld, ww, aI, g_vm,
                            g_va);
     hipLaunchKernelGGL(dpf::finalize_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, nblk, part, m_res, loss,
                        max_mis);
+    DPF_HIP(hipGetLastError());
+    return DPF_OK;
+}
+
+int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec,
+                   int32_t s_ld, const int32_t *outage, const double *vm, const double *va, double *loss,
+                   double *max_mis, double *g_r, double *g_x, double *g_b, int32_t bld, double *g_s, void *workspace,
+                   size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
+    if (B <= 0 || ld < g->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
+    if (B > 65535) return fail(DPF_EINVAL, "B must be <= 65535 for one evaluation call");
+    if (s_ld != 0 && s_ld < g->n_bus) return fail(DPF_EINVAL, "s_ld must be 0 or >= n_bus");
+    if (!bus_type || !s_spec || !vm || !va) return fail(DPF_EINVAL, "null argument");
+    if ((loss == nullptr) != (max_mis == nullptr)) return fail(DPF_EINVAL, "loss and max_mis: both or neither");
+    const bool br = g_r || g_x || g_b;
+    if (br && !(g_r && g_x && g_b)) return fail(DPF_EINVAL, "g_r, g_x and g_b: all or none");
+    if ((br || outage) && (g->n_branch <= 0 || !g->from || !g->to || !g->r || !g->x || !g->b))
+        return fail(DPF_EINVAL, "branch gradients and outages need the grid's branch arrays");
+    if (br && bld < g->n_branch) return fail(DPF_EINVAL, "bld must be >= n_branch");
+    const int32_t n = g->n_bus;
+    size_t need = dpf_mismatch_grad_workspace_bytes(n, B);
+    if (!workspace || ws_bytes < need) return fail(DPF_ENOMEM, "workspace too small");
+    if ((int64_t)B * ld > ((int64_t)1 << 40) || (int64_t)B * bld > ((int64_t)1 << 40))
+        return fail(DPF_EINVAL, "batch too large");
+    hipStream_t st = (hipStream_t)stream;
+    size_t per = align_up(sizeof(double2) * (size_t)n * (size_t)B, 256);
+    char *ws = (char *)workspace;
+    double *m_res = (double *)ws;
+    double2 *Vw = (double2 *)(ws + 256);
+    double2 *ww = (double2 *)(ws + 256 + per);
+    double2 *aI = (double2 *)(ws + 256 + 2 * per);
+    double2 *part = (double2 *)(ws + 256 + 3 * per);
+    const int32_t nblk = (n + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
+    dpf::OutageView ov{outage, g->from, g->to, g->r, g->x, g->b, g->n_branch};
+    hipLaunchKernelGGL(dpf::residual_count_kernel, dim3(1), dim3(1024), 0, st, n, bus_type, m_res);
+    hipLaunchKernelGGL(dpf::polar_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, (int64_t)ld, vm, va, Vw);
+    hipLaunchKernelGGL(dpf::forward_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr, g->col_idx,
+                       (const double2 *)g->val, bus_type, (const double2 *)s_spec, (int64_t)s_ld, ov, Vw, m_res,
+                       (int64_t)ld, (double2 *)nullptr, ww, aI, part, (double2 *)g_s);
+    if (br) {
+        const int32_t eblk = (g->n_branch + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
+        hipLaunchKernelGGL(dpf::branch_grad_kernel, dim3(eblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->n_branch, ov,
+                           Vw, ww, (int64_t)bld, g_r, g_x, g_b);
+    }
+    if (loss)
+        hipLaunchKernelGGL(dpf::finalize_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, nblk, part, m_res,
+                           loss, max_mis);
+    DPF_HIP(hipGetLastError());
+    return DPF_OK;
+}
+
+size_t dpf_dc_init_workspace_bytes(int32_t n_bus, int32_t B) {
+    if (n_bus <= 0 || B <= 0) return 0;
+    return 3 * align_up(sizeof(double) * (size_t)n_bus * (size_t)B, 256);
+}
+
+int dpf_dc_init(const dpf_grid_t *g_dc, int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec,
+                int32_t s_ld, const int32_t *outage, double *va, double tol, int32_t max_iter, int32_t *iters,
+                double *residual, void *workspace, size_t ws_bytes, void *stream) {
+    g_err.clear();
+    if (!valid_grid(g_dc)) return fail(DPF_EINVAL, "invalid grid");
+    if (B <= 0 || ld < g_dc->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
+    if (s_ld != 0 && s_ld < g_dc->n_bus) return fail(DPF_EINVAL, "s_ld must be 0 or >= n_bus");
+    if (!bus_type || !s_spec || !va) return fail(DPF_EINVAL, "null argument");
+    if (!(tol >= 0.0) || max_iter < 0) return fail(DPF_EINVAL, "tol must be >= 0 and max_iter >= 0");
+    if (outage && (g_dc->n_branch <= 0 || !g_dc->from || !g_dc->to || !g_dc->r || !g_dc->x || !g_dc->b))
+        return fail(DPF_EINVAL, "outage needs the grid's branch arrays");
+    DeviceInfo dev;
+    int rc = device_info(dev);
+    if (rc != DPF_OK) return rc;
+    const int32_t n = g_dc->n_bus;
+    const size_t lds = sizeof(double) * (size_t)n;
+    if (lds + 1024 > (size_t)dev.lds_per_block) return fail(DPF_EUNSUPPORTED, "grid too large for one workgroup's LDS");
+    if (!workspace || ws_bytes < dpf_dc_init_workspace_bytes(n, B)) return fail(DPF_ENOMEM, "workspace too small");
+    const size_t per = align_up(sizeof(double) * (size_t)n * (size_t)B, 256);
+    char *ws = (char *)workspace;
+    dpf::DcArgs a{};
+    a.rp = g_dc->row_ptr;
+    a.ci = g_dc->col_idx;
+    a.yv = (const double2 *)g_dc->val;
+    a.bt = bus_type;
+    a.s_spec = (const double2 *)s_spec;
+    a.s_ld = s_ld;
+    a.ov = dpf::OutageView{outage, g_dc->from, g_dc->to, g_dc->r, g_dc->x, g_dc->b, g_dc->n_branch};
+    a.va = va;
+    a.ld = ld;
+    a.r = (double *)ws;
+    a.z = (double *)(ws + per);
+    a.dg = (double *)(ws + 2 * per);
+    a.n = n;
+    a.tol = tol;
+    a.max_iter = max_iter;
+    a.iters = iters;
+    a.res_out = residual;
+    hipStream_t st = (hipStream_t)stream;
+    DPF_HIP(hipFuncSetAttribute((const void *)dpf::dc_pcg_kernel<1024>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)lds));
+    hipLaunchKernelGGL(dpf::dc_pcg_kernel<1024>, dim3(B), dim3(1024), lds, st, a);
     DPF_HIP(hipGetLastError());
     return DPF_OK;
 }

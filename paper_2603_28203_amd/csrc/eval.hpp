@@ -73,7 +73,7 @@ __global__ __launch_bounds__(kEvalBlock) void forward_kernel(
     int32_t n, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci, const double2 *__restrict__ yv,
     const int8_t *__restrict__ bt, const double2 *__restrict__ s_spec, int64_t s_ld, OutageView ov,
     const double2 *__restrict__ V, const double *__restrict__ m_res, int64_t ld, double2 *__restrict__ dS,
-    double2 *__restrict__ w, double2 *__restrict__ aI, double2 *__restrict__ part) {
+    double2 *__restrict__ w, double2 *__restrict__ aI, double2 *__restrict__ part, double2 *__restrict__ g_s) {
     __shared__ double red[2][kEvalBlock / kWave];
     int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     int32_t c = blockIdx.y;
@@ -107,6 +107,7 @@ __global__ __launch_bounds__(kEvalBlock) void forward_kernel(
         w[o] = cmulc(a, v);
         aI[o] = cmul(a, acc);
         if (dS) dS[c * ld + i] = d;
+        if (g_s) g_s[c * ld + i] = make_double2(-a.x, -a.y);  // d loss / d S_spec
     }
     lsum = wave_sum(lsum);
     lmax = wave_max(lmax);
@@ -157,6 +158,41 @@ __global__ __launch_bounds__(kEvalBlock) void adjoint_kernel(
     double ga = ty != kSlack ? (G.y * v.x - G.x * v.y) : 0.0;
     g_vm[c * ld + i] = gv;
     g_va[c * ld + i] = ga;
+}
+
+// d loss / d(r, x, b) of every branch, from V and the adjoint seed w = a conj(V)
+// of the forward kernel.  With d loss = Re sum_i w_i dI_i and dI = dY V, a branch
+// (f, t) with y = 1/(r + jx) and charging b contributes
+//   dI_f = dy (V_f - V_t) + j (db/2) V_f,  dI_t = dy (V_t - V_f) + j (db/2) V_t,
+// so with D = (w_f - w_t)(V_f - V_t) and dy = -y^2 (dr + j dx):
+//   d/dr = -Re(y^2 D),  d/dx = Im(y^2 D),  d/db = -Im(w_f V_f + w_t V_t) / 2.
+// The outaged branch of a case is absent from its Y: gradient 0.
+__global__ __launch_bounds__(kEvalBlock) void branch_grad_kernel(int32_t n, int32_t n_branch, OutageView ov,
+                                                                  const double2 *__restrict__ V,
+                                                                  const double2 *__restrict__ w, int64_t bld,
+                                                                  double *__restrict__ g_r, double *__restrict__ g_x,
+                                                                  double *__restrict__ g_b) {
+    const int32_t e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int32_t c = blockIdx.y;
+    if (e >= n_branch) return;
+    const int32_t f = ov.from[e], t = ov.to[e];
+    double gr = 0.0, gx = 0.0, gb = 0.0;
+    const bool out = ov.outage && ov.outage[c] == e;
+    if (!out && f != t && (uint32_t)f < (uint32_t)n && (uint32_t)t < (uint32_t)n) {
+        const int64_t o = (int64_t)c * n;
+        const double2 vf = V[o + f], vt = V[o + t], wf = w[o + f], wt = w[o + t];
+        double2 y, ysh;
+        branch_admittance(ov.r[e], ov.x[e], ov.b[e], y, ysh);
+        const double2 D = cmul(csub(wf, wt), csub(vf, vt));
+        const double2 y2D = cmul(cmul(y, y), D);
+        gr = -y2D.x;
+        gx = y2D.y;
+        gb = -0.5 * (cmul(wf, vf).y + cmul(wt, vt).y);
+    }
+    const int64_t q = (int64_t)c * bld + e;
+    g_r[q] = gr;
+    g_x[q] = gx;
+    g_b[q] = gb;
 }
 
 __global__ void finalize_kernel(int32_t B, int32_t nblk, const double2 *__restrict__ part,

@@ -838,3 +838,70 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
     assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
     assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
     assert np.abs(va[0].cpu().numpy() - va0).max() > 1e-4  # the update moved the iterate
+
+
+# ---------------------------------------------------------------- parameter gradients
+
+
+@pytest.mark.parametrize("which", ["cfg0", "cfg2"])
+def test_param_grad_parity(dpf, which):
+    """dpf_param_grad (branch r, x, b and S_spec) against the oracle's
+    forward-mode derivatives, per case, with N-1 outages and a shared S_spec."""
+    if which == "cfg0":
+        g = synth.config0(4)["grid"]
+        outage = np.array([-1, 6, 11], dtype=np.int32)
+    else:
+        cfg = synth.config2(B=3)
+        g = cfg["grid"]
+        outage = cfg["outage"].copy()
+        outage[0] = -1
+    B = len(outage)
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm, va = perturbed_states(g, B, seed=21)
+    Yg = dgrid(dpf, g)
+    r = dpf.param_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm), cu(va), outage=cu(outage, torch.int32))
+    torch.cuda.synchronize()
+    for c in range(B):
+        g_r, g_x, g_b, g_s = oracle.param_grad(g, g.bus_type, vm[c], va[c], S, skip=int(outage[c]))
+        assert relerr(r["g_r"][c].cpu().numpy(), g_r) < REL
+        assert relerr(r["g_x"][c].cpu().numpy(), g_x) < REL
+        assert relerr(r["g_b"][c].cpu().numpy(), g_b) < REL
+        assert relerr(r["g_s"][c].cpu().numpy(), g_s) < REL
+        if outage[c] >= 0:
+            assert r["g_r"][c, outage[c]].item() == 0.0 and r["g_b"][c, outage[c]].item() == 0.0
+        Yc = oracle.ybus_of(g, skip=int(outage[c]))
+        loss, mu = oracle.loss_from_mismatch(g.bus_type, oracle.mismatch(Yc, vm[c], va[c], S))
+        assert abs(r["loss"][c].item() - loss) <= 1e-12 * loss
+
+
+# ---------------------------------------------------------------- DC power flow start
+
+
+@pytest.mark.parametrize("which", ["cfg1", "cfg2"])
+def test_dc_init_matches_oracle(dpf, which):
+    """dpf_dc_init (preconditioned CG on the susceptance Laplacian, per case,
+    with N-1 outages and per-case injections) against the oracle's sparse
+    direct solve."""
+    if which == "cfg1":
+        cfg = synth.config1(B=3)
+        g = cfg["grid"]
+        outage = np.array([-1, 5, 17], dtype=np.int32)
+        outage[1:] = synth.non_bridge_branches(g.n_bus, g.f, g.t)[[5, 17]]
+    else:
+        cfg = synth.config2(B=3)
+        g = cfg["grid"]
+        outage = cfg["outage"]
+    B = len(outage)
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    rng = np.random.default_rng(2)
+    S = S0[None, :] * rng.uniform(0.9, 1.1, (B, g.n_bus))
+    Gdc = dpf.build_dc_grid(g.n_bus, g.f, g.t, g.x)
+    va = np.zeros((B, g.n_bus))
+    va[:, g.bus_type == 2] = 0.05
+    va_d = cu(va)
+    r = dpf.dc_init(Gdc, g.bus_type, cu(S, torch.complex128), va_d, outage=cu(outage, torch.int32), tol=1e-13)
+    torch.cuda.synchronize()
+    assert np.all(r["residual"].cpu().numpy() <= 1e-13)
+    for c in range(B):
+        ref = oracle.dc_power_flow(g, g.bus_type, S[c], va_slack=0.05, skip=int(outage[c]))
+        assert relerr(va_d[c].cpu().numpy(), ref) < 1e-9

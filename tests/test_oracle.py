@@ -427,3 +427,108 @@ def test_batch_equals_single_solves():
     for c in range(3):
         one = oracle.solve_adam(Y, g.bus_type, Sb[c], vm0, va0, o)
         assert np.array_equal(one["vm"], res["vm"][c]) and one["iters"] == res["iters"][c]
+
+
+def _loss_of(g, bt, vm, va, S, skip=-1):
+    Y = oracle.ybus_of(g, skip=skip)
+    return oracle.loss_from_mismatch(bt, oracle.mismatch(Y, vm, va, S))[0]
+
+
+@pytest.mark.parametrize("skip", [-1, 6])
+def test_param_grad_matches_central_differences(skip):
+    """dL/d(r, x, b) of every branch and dL/dS_spec by central differences of
+    the loss (Y rebuilt from the perturbed branch data), with and without an
+    outaged branch."""
+    import dataclasses
+    g = synth.config0(4)["grid"]
+    Y = oracle.ybus_of(g, skip=skip)
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    rng = np.random.default_rng(11)
+    vm = g.vm + rng.normal(0, 0.02, g.n_bus)
+    va = g.va + rng.normal(0, 0.02, g.n_bus)
+    g_r, g_x, g_b, g_s = oracle.param_grad(g, g.bus_type, vm, va, S, skip=skip)
+    h = 1e-6
+    scale = max(np.abs(g_r).max(), np.abs(g_x).max(), np.abs(g_b).max())
+    for name, grad in (("r", g_r), ("x", g_x), ("b", g_b)):
+        for e in range(g.n_branch):
+            arr = getattr(g, name)
+            up, dn = arr.copy(), arr.copy()
+            up[e] += h
+            dn[e] -= h
+            fd = (_loss_of(dataclasses.replace(g, **{name: up}), g.bus_type, vm, va, S, skip)
+                  - _loss_of(dataclasses.replace(g, **{name: dn}), g.bus_type, vm, va, S, skip)) / (2 * h)
+            assert abs(grad[e] - fd) <= 1e-6 * scale, (name, e)
+    if skip >= 0:
+        assert g_r[skip] == 0.0 and g_x[skip] == 0.0 and g_b[skip] == 0.0
+    for i in range(g.n_bus):
+        for part in (1.0, 1.0j):
+            Su, Sd = S.copy(), S.copy()
+            Su[i] += part * h
+            Sd[i] -= part * h
+            fd = (_loss_of(g, g.bus_type, vm, va, Su, skip) - _loss_of(g, g.bus_type, vm, va, Sd, skip)) / (2 * h)
+            an = g_s[i].real if part == 1.0 else g_s[i].imag
+            assert abs(an - fd) <= 1e-6 * np.abs(g_s).max()
+    # closed form of the injection gradient: -(2/m) times the masked residual
+    dS = oracle.mismatch(Y, vm, va, S)
+    m = oracle.residual_count(g.bus_type)
+    rP = np.where(g.bus_type != SLACK, dS.real, 0.0)
+    rQ = np.where(g.bus_type == PQ, dS.imag, 0.0)
+    assert np.allclose(g_s, -(2.0 / m) * (rP + 1j * rQ), rtol=0, atol=1e-15)
+
+
+def test_param_grad_vanishes_at_the_planted_solution():
+    g = synth.config1(B=1)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    g_r, g_x, g_b, g_s = oracle.param_grad(g, g.bus_type, g.vm, g.va, S)
+    assert max(np.abs(g_r).max(), np.abs(g_x).max(), np.abs(g_b).max(), np.abs(g_s).max()) < 1e-12
+
+
+def test_dc_power_flow_two_bus_closed_form():
+    """Slack at bus 0, one branch of reactance x: theta_1 = P_1 x."""
+    g = synth.Grid(n_bus=2, f=np.array([0], np.int32), t=np.array([1], np.int32), r=np.array([0.02]),
+                   x=np.array([0.25]), b=np.array([0.0]), bus_type=np.array([2, 0], np.int8),
+                   vm=np.ones(2), va=np.zeros(2))
+    th = oracle.dc_power_flow(g, g.bus_type, np.array([0.0, -0.4 + 0.1j]), va_slack=0.1)
+    assert th[0] == 0.1 and abs(th[1] - (0.1 - 0.4 * 0.25)) < 1e-15
+
+
+def test_dc_power_flow_tree_flows_balance_subtree_injections():
+    """On a tree the DC branch flow (theta_f - theta_t)/x equals the injection
+    total of the subtree behind the branch (flow conservation, no solve)."""
+    g = synth.config0(7)["grid"]
+    rng = np.random.default_rng(4)
+    tree = synth.Grid(n_bus=g.n_bus, f=np.array([rng.integers(0, k) for k in range(1, g.n_bus)], np.int32),
+                      t=np.arange(1, g.n_bus, dtype=np.int32), r=np.full(g.n_bus - 1, 0.01),
+                      x=rng.uniform(0.05, 0.3, g.n_bus - 1), b=np.zeros(g.n_bus - 1),
+                      bus_type=np.where(np.arange(g.n_bus) == 0, 2, 0).astype(np.int8), vm=g.vm, va=g.va)
+    P = rng.normal(0, 0.3, g.n_bus)
+    th = oracle.dc_power_flow(tree, tree.bus_type, P + 0j)
+    children = {k: [] for k in range(g.n_bus)}
+    for f, t in zip(tree.f, tree.t):
+        children[int(f)].append(int(t))
+    def subtree(k):
+        return P[k] + sum(subtree(c) for c in children[k])
+    for e, (f, t) in enumerate(zip(tree.f, tree.t)):
+        flow_into_t = (th[f] - th[t]) / tree.x[e]  # from parent f towards child t
+        assert abs(flow_into_t + subtree(int(t))) < 1e-12
+
+
+def test_dc_power_flow_is_the_small_angle_limit_of_ac():
+    """Lossless branches, no charging, all non-slack buses PV at |V| = 1 and
+    tiny injections: Newton-Raphson's AC angles approach the DC angles with a
+    relative error of second order in the angles."""
+    g0 = synth.config0(3)["grid"]
+    g = synth.Grid(n_bus=g0.n_bus, f=g0.f, t=g0.t, r=np.zeros(g0.n_branch), x=g0.x, b=np.zeros(g0.n_branch),
+                   bus_type=np.where(g0.bus_type == 2, 2, 1).astype(np.int8), vm=np.ones(g0.n_bus),
+                   va=np.zeros(g0.n_bus))
+    rng = np.random.default_rng(9)
+    P = rng.normal(0, 1.0, g.n_bus)
+    P[g.bus_type == 2] = 0.0
+    P -= P.mean() * (g.bus_type != 2)
+    for eps in (1e-2, 1e-3):
+        th = oracle.dc_power_flow(g, g.bus_type, eps * P + 0j)
+        nr = oracle.newton(oracle.ybus_of(g), g.bus_type, eps * P + 0j, np.ones(g.n_bus), np.zeros(g.n_bus),
+                           tol=1e-14)
+        assert nr["converged"]
+        err = np.abs(nr["va"] - th).max() / np.abs(th).max()
+        assert err < 5 * eps ** 2
