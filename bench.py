@@ -77,9 +77,8 @@ def make_cfg2(B):
     g = cfg["grid"]
     # renumber the buses to a small bandwidth with rows of similar degree grouped
     # (the library's ordering; bus numbering does not change the power flow)
-    perm, bw = dpf.rcm_order(g.n_bus, g.f, g.t, group=BUS_ORDER_GROUP)
-    inv = np.argsort(perm).astype(np.int32)
-    g = dataclasses.replace(g, f=inv[g.f], t=inv[g.t], bus_type=g.bus_type[perm], vm=g.vm[perm], va=g.va[perm])
+    perm = dpf.rcm_order(g.n_bus, g.f, g.t, group=BUS_ORDER_GROUP)[0]
+    g, bw = renumbered(g)
     cfg["vm0"] = np.ascontiguousarray(cfg["vm0"][:, perm])
     cfg["va0"] = np.ascontiguousarray(cfg["va0"][:, perm])
     cfg["bandwidth"] = bw
@@ -177,7 +176,7 @@ def cpu_baseline_cfg2(g, out_idx, n_cases, iters, S_host, opts):
 def pmc_traffic(kernel_name):
     """HBM bytes per launch from a committed rocprofv3 counter summary of the
     current kernel source, else None."""
-    p = os.path.join(ROOT, "profiles", "solve_stream_cfg2_pmc.json")
+    p = os.path.join(ROOT, "profiles", "solve_nminus1_1024x9241_hbm.json")
     if not os.path.exists(p):
         return None
     with open(p) as fh:
@@ -197,6 +196,7 @@ def main():
     ap.add_argument("--quick", action="store_true", help="small cap, no baselines (smoke of the harness)")
     ap.add_argument("--no-autograd", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the time-series and uneven-batch lines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference for counter scaling)")
     args = ap.parse_args()
@@ -213,6 +213,7 @@ def main():
         args.cap = min(args.cap, 2000)
         args.no_autograd = True
         args.no_cpu = True
+        args.no_extras = True
 
     import torch
 
@@ -224,7 +225,7 @@ def main():
     log(f"building the N-1 batch: {B} outages of the 9241-bus grid")
     cfg, g, Yg, S, bt, out, vm0, va0 = make_cfg2(B)
     opts = solve_options(args.cap)
-    tune = dpf.autotune(Yg, bt, S, vm0, va0, outage=out, opts=opts, iters=50, reps=1)
+    tune = dpf.autotune(Yg, bt, S, vm0, va0, outage=out, opts=opts, iters=100, reps=2, tie=0.03)
     vinfo = dpf.variants()[tune["choice"]]
     log(f"autotune: variant {tune['choice']} {vinfo} ({ {k: round(v * 1e3, 2) for k, v in tune['seconds'].items()} } ms / 50 it)")
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
@@ -299,20 +300,152 @@ def main():
         log("cfg1 comparison: 64 cases x 1354 buses, fused vs autograd per iteration")
         line["cfg1"] = cfg1_comparison()
 
+    if not args.no_extras:
+        log("screening: the same N-1 batch at tol 1e-3 pu, 1000-iteration budget")
+        scr = solve_options(1000)
+        scr.tol = 1e-3
+        ts, _, rs, _, _ = run_fused(Yg, bt, S, out, vm0, va0, scr, 1, 1)
+        line["screening"] = {"tol": 1e-3, "iter_cap": 1000, "s": round(ts[0], 4),
+                             "converged": int((rs["status"] == 0).sum()),
+                             "solves_per_s": round(int((rs["status"] == 0).sum()) / ts[0], 1),
+                             "iters_median": float(np.median(rs["iters"]))}
+        log("cfg3: time series, sequential vs windows of 16")
+        line["cfg3"] = cfg3_series(1000)
+        log("cfg4: uneven batch of 129 grids")
+        line["cfg4"] = cfg4_uneven(2000)
+
     if not args.no_cpu:
         log("cpu baseline: oracle on a bounded sample")
         S_host = S.cpu().numpy()
         ncs = min(os.cpu_count() or 1, 16)
-        n_it = 600
+        n_it = 12000
         cb = cpu_baseline_cfg2(g, cfg["outage"], ncs, n_it, S_host, opts)
+        one = cpu_baseline_cfg2(g, cfg["outage"], 1, 1500, S_host, opts)
         cpu_value = conv / (case_iters / cb["case_iters_per_s"]) if conv else 0.0
         line["cpu_baseline"] = {"value": round(cpu_value, 5), "unit": "solves/s", "cores": cb["cores"],
                                 "kind": "oracle",
                                 "sample": f"{ncs} outage cases x {n_it} Adam iterations "
                                           f"({cb['seconds']:.1f} s); solves/s = converged cases / "
                                           f"(the batch's case-iterations / measured case-iterations/s)",
-                                "case_iters_per_s": round(cb["case_iters_per_s"], 1)}
+                                "case_iters_per_s": round(cb["case_iters_per_s"], 1),
+                                "single_thread_case_iters_per_s": round(one["case_iters_per_s"], 1)}
     print(json.dumps(line), flush=True)
+
+
+def renumbered(g, sub_offset=None):
+    """The grid with the library's small-bandwidth numbering (per sub-grid)."""
+    import paper_2603_28203_amd as dpf
+
+    perm, bw = dpf.rcm_order(g.n_bus, g.f, g.t, sub_offset=sub_offset, group=BUS_ORDER_GROUP)
+    inv = np.argsort(perm).astype(np.int32)
+    return dataclasses.replace(g, f=inv[g.f], t=inv[g.t], bus_type=g.bus_type[perm], vm=g.vm[perm],
+                               va=g.va[perm]), bw
+
+
+def base_injections(Yg, g):
+    """S = V conj(Y V) at the planted voltages (the library's own mismatch with S = 0)."""
+    import torch
+
+    import paper_2603_28203_amd as dpf
+
+    vm_p = torch.tensor(g.vm[None], dtype=torch.float64, device="cuda")
+    va_p = torch.tensor(g.va[None], dtype=torch.float64, device="cuda")
+    zero = torch.zeros(g.n_bus, dtype=torch.complex128, device="cuda")
+    return dpf.mismatch_grad(Yg, g.bus_type, zero, vm_p, va_p, want_grad=False)["dS"][0].contiguous()
+
+
+def cfg3_series(cap):
+    """Time series on the 9241-bus grid: 96 quarter-hour steps, sequential
+    warm-started solves (window 1) against windows of 16 steps solved as one
+    batch, each step capped at `cap` Adam iterations."""
+    import torch
+
+    import paper_2603_28203_amd as dpf
+    import synth
+
+    cfg = synth.config3()
+    g, _ = renumbered(cfg["grid"])
+    # the load model is per bus of the generator's numbering: renumber it too
+    perm = dpf.rcm_order(cfg["grid"].n_bus, cfg["grid"].f, cfg["grid"].t, group=BUS_ORDER_GROUP)[0]
+    Yg = dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
+    S0 = base_injections(Yg, g)
+    ls = torch.tensor(cfg["load_scale"][:, perm], device="cuda")
+    sp = torch.tensor(cfg["solar_p"][:, perm], device="cuda")
+    S = (S0[None, :] * ls + sp).contiguous()
+    opts = solve_options(cap)
+    vm0 = torch.tensor(g.vm, device="cuda")
+    va0 = torch.tensor(g.va, device="cuda")
+    out = {"workload": f"96-step time series on the 9241-bus grid, cap {cap} iterations per step",
+           "iter_cap": cap}
+    for name, window in (("sequential", 1), ("windows_of_16", 16)):
+        dpf.solve_series(Yg, g.bus_type, S[:window], vm0, va0, window=window, opts=solve_options(10))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = dpf.solve_series(Yg, g.bus_type, S, vm0, va0, window=window, opts=opts)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it = r["iters"].cpu().numpy()
+        st = r["status"].cpu().numpy()
+        out[name] = {"s": round(dt, 3), "steps_per_s": round(96 / dt, 2), "converged_steps": int((st == 0).sum()),
+                     "iters_median": float(np.median(it)), "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
+                     "bus_iters_per_s": round(float(it.sum()) * g.n_bus / dt, 1)}
+        log(f"cfg3 {name}: {dt:.2f} s, converged {int((st == 0).sum())}/96")
+    return out
+
+
+def cfg4_uneven(cap):
+    """Uneven batch: 128 grids of log-uniform size in [100, 80000] buses plus one
+    of 80000, concatenated as sub-grids of one call (the ones above one CU's LDS
+    take the multi-workgroup path).  Each grid's PQ loads are scaled by
+    U(0.98, 1.02) from its planted state, which is also the start point."""
+    import torch
+
+    import paper_2603_28203_amd as dpf
+    import synth
+
+    t0 = time.perf_counter()
+    cfg = synth.config4()
+    grids = cfg["grids"]
+    off = np.concatenate([[0], np.cumsum([gg.n_bus for gg in grids])]).astype(np.int64)
+    cat = synth.Grid(n_bus=int(off[-1]), f=np.concatenate([gg.f + off[k] for k, gg in enumerate(grids)]),
+                     t=np.concatenate([gg.t + off[k] for k, gg in enumerate(grids)]),
+                     r=np.concatenate([gg.r for gg in grids]), x=np.concatenate([gg.x for gg in grids]),
+                     b=np.concatenate([gg.b for gg in grids]), bus_type=np.concatenate([gg.bus_type for gg in grids]),
+                     vm=np.concatenate([gg.vm for gg in grids]), va=np.concatenate([gg.va for gg in grids]))
+    g, _ = renumbered(cat, sub_offset=off)
+    Yg = dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
+    S0 = base_injections(Yg, g)
+    rng = np.random.default_rng(np.random.SeedSequence(cfg["seed"]).spawn(1)[0])
+    fac = np.where(g.bus_type == 0, rng.uniform(0.98, 1.02, g.n_bus), 1.0)
+    S = (S0 * torch.tensor(fac, device="cuda")).contiguous()
+    log(f"cfg4: {len(grids)} grids, {g.n_bus} buses, built in {time.perf_counter() - t0:.1f} s")
+    opts = solve_options(cap)
+    vm0 = torch.tensor(g.vm[None], device="cuda")
+    va0 = torch.tensor(g.va[None], device="cuda")
+    dpf.solve(Yg, g.bus_type, S, vm0.clone(), va0.clone(), opts=solve_options(20), sub_offset=off.tolist())
+    torch.cuda.synchronize()
+    vm, va = vm0.clone(), va0.clone()
+    t0 = time.perf_counter()
+    r = dpf.solve(Yg, g.bus_type, S, vm, va, opts=opts, sub_offset=off.tolist())
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    it = r["iters"].cpu().numpy().astype(np.int64)
+    st = r["status"].cpu().numpy()
+    done = r["done_ns"].cpu().numpy() * 1e-6
+    sizes = np.diff(off)
+    bus_iters = float((it * sizes).sum())
+    conv = int((st == 0).sum())
+    nnz_rows = int(Yg.nnz)
+    alg = bus_iters * 96 + int(it.max()) * 2 * (20 * nnz_rows + 4 * (g.n_bus + len(grids)))
+    return {"workload": f"{len(grids)} grids, {g.n_bus} buses (log-uniform 100..80000 + one 80000), "
+                        f"PQ loads x U(0.98, 1.02), planted start, cap {cap}",
+            "iter_cap": cap, "s": round(dt, 3), "converged": conv, "solves_per_s": round(conv / dt, 3),
+            "bus_iters_per_s": round(bus_iters / dt, 1),
+            "alg_GBps": round(alg / dt / 1e9, 1),
+            "time_to_stop_ms_p50": round(float(np.percentile(done, 50)), 2),
+            "time_to_stop_ms_p99": round(float(np.percentile(done, 99)), 2),
+            "grids_above_one_cu": int((sizes > dpf.max_sub_buses()).sum()),
+            "max_mis_median": float(np.median(r["max_mis"].cpu().numpy()))}
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):

@@ -471,10 +471,12 @@ def set_team_cap(buses: int):
 
 
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,
-             iters: int = 40, reps: int = 2):
+             iters: int = 40, reps: int = 2, tie: float = 0.0):
     """Time every kernel variant that can hold the largest sub-grid on copies of
     the real inputs (``iters`` Adam iterations, no stop test) and record the
-    fastest in the library's autotune cache.  Returns {variant: seconds}."""
+    fastest in the library's autotune cache.  Variants within a fraction ``tie``
+    of the fastest count as equal and the first of them in the table is taken,
+    which keeps the choice stable under timing noise.  Returns {variant: seconds}."""
     opts = opts or Options()
     n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
@@ -497,6 +499,7 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
             dt = st.elapsed_time(en) * 1e-3
             best = dt if best is None else min(best, dt)
         times[v["index"]] = best
-    pick = min(times, key=times.get)
+    best = min(times.values())
+    pick = min(i for i, t in times.items() if t <= best * (1.0 + tie))
     _check(lib().dpf_autotune_set(n_max, pick))
     return {"choice": pick, "seconds": times, "n_max": n_max, "iters": iters}
