@@ -246,11 +246,20 @@ def main():
              "banded": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, true>",
              "banded-stream": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, false>",
              }[vinfo["kind"]]
+    # the same kernel with every item active (fixed 200 iterations, no stop test):
+    # the rate of the full-chip phase, before early retirement thins the batch out
+    fixed = dpf.Options(**{**opts.__dict__, "tol": 0.0, "max_iter": 200})
+    tf, kf, _, _, _ = run_fused(Yg, bt, S, out, vm0, va0, fixed, 1, 1)
+    steady_bytes = B * 200 * n * 96 + 200 * 2 * (20 * nnz + 4 * (n + 1))
     traffic = pmc_traffic(kname)
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": None if traffic is None else round(traffic / t_kern / 1e9, 1),
-                "alg_bytes_per_launch": alg_bytes, "launch_s": round(t_kern, 4)}
+                "alg_bytes_per_launch": alg_bytes, "launch_s": round(t_kern, 4),
+                "steady_state": {"what": "200 iterations, all 1024 items active", "launch_s": round(kf[0], 5),
+                                 "achieved": round(steady_bytes / kf[0] / 1e9, 1),
+                                 "frac": round(steady_bytes / kf[0] / 1e9 / HBM_PEAK_GBS, 4),
+                                 "ms_per_iter": round(kf[0] / 200 * 1e3, 4)}}
 
     line = {
         "metric": "converged PF solves/s at max|dS| < 1e-6 pu (fused adjoint)",
@@ -309,6 +318,8 @@ def main():
                              "converged": int((rs["status"] == 0).sum()),
                              "solves_per_s": round(int((rs["status"] == 0).sum()) / ts[0], 1),
                              "iters_median": float(np.median(rs["iters"]))}
+        log("graph: small solves issued eagerly vs replayed from a captured graph")
+        line["graph"] = graph_replay()
         log("cfg3: time series, sequential vs windows of 16")
         line["cfg3"] = cfg3_series(1000)
         log("cfg4: uneven batch of 129 grids")
@@ -446,6 +457,54 @@ def cfg4_uneven(cap):
             "time_to_stop_ms_p99": round(float(np.percentile(done, 99)), 2),
             "grids_above_one_cu": int((sizes > dpf.max_sub_buses()).sum()),
             "max_mis_median": float(np.median(r["max_mis"].cpu().numpy()))}
+
+
+def graph_replay(calls=200):
+    """Small repeated solves (the 14-bus grid, 200 iterations per call): one
+    dpf_solve_batch call issued eagerly (seven launches) against the same call
+    captured once in a HIP graph and replayed."""
+    import torch
+
+    import paper_2603_28203_amd as dpf
+    import synth
+
+    g = synth.config0(0)["grid"]
+    Yg = dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
+    S = base_injections(Yg, g)
+    bt = torch.tensor(g.bus_type, dtype=torch.int8, device="cuda")
+    vm0, va0 = synth.flat_start(g)
+    vm = torch.tensor(vm0[None], device="cuda")
+    va = torch.tensor(va0[None], device="cuda")
+    opts = dpf.Options(lr=1e-2, tol=0.0, max_iter=200)
+    ws = dpf.SolveWorkspace()
+    outs = {k: torch.empty(1, dtype=dt, device="cuda") for k, dt in
+            (("iters", torch.int32), ("status", torch.int32), ("max_mis", torch.float64), ("loss", torch.float64))}
+
+    def call():
+        dpf.solve(Yg, bt, S, vm, va, opts=opts, workspace=ws, outputs=outs)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        call()
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        call()
+    torch.cuda.synchronize()
+    eager = (time.perf_counter() - t0) / calls
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        call()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        graph.replay()
+    torch.cuda.synchronize()
+    replay = (time.perf_counter() - t0) / calls
+    return {"workload": "14-bus grid, one case, 200 iterations per call", "calls": calls,
+            "eager_us_per_call": round(eager * 1e6, 1), "graph_us_per_call": round(replay * 1e6, 1)}
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):

@@ -905,3 +905,58 @@ def test_dc_init_matches_oracle(dpf, which):
     for c in range(B):
         ref = oracle.dc_power_flow(g, g.bus_type, S[c], va_slack=0.05, skip=int(outage[c]))
         assert relerr(va_d[c].cpu().numpy(), ref) < 1e-9
+
+
+# ---------------------------------------------------------------- graph capture
+
+
+@pytest.mark.parametrize("which", ["cfg0", "cfg2"])
+def test_solve_call_replays_from_a_captured_graph(dpf, which):
+    """A whole dpf_solve_batch call (sliced-ELL build + solve kernel; no memset,
+    no host synchronisation on this path) captured in a HIP graph; every replay,
+    with eager resets and synchronisations between replays, equals the eager call
+    bit for bit."""
+    if which == "cfg0":
+        g = synth.config0(5)["grid"]
+        B, out_idx = 4, None
+    else:
+        cfg = synth.config2(B=8)
+        g = cfg["grid"]
+        B, out_idx = 8, cfg["outage"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm0, va0 = perturbed_states(g, B, seed=31, sd=0.01)
+    vm0[:, g.bus_type != 0] = g.vm[g.bus_type != 0]
+    Yg = dgrid(dpf, g)
+    opts = dpf.Options(lr=1e-3, tol=1e-9, max_iter=25)
+    Sd = cu(S, torch.complex128)
+    bt = cu(g.bus_type, torch.int8)
+    od = None if out_idx is None else cu(out_idx, torch.int32)
+    ws = dpf.SolveWorkspace()
+    items = B
+    outs = {"iters": torch.empty(items, dtype=torch.int32, device="cuda"),
+            "status": torch.empty(items, dtype=torch.int32, device="cuda"),
+            "max_mis": torch.empty(items, dtype=torch.float64, device="cuda"),
+            "loss": torch.empty(items, dtype=torch.float64, device="cuda")}
+    vm_e = cu(vm0); va_e = cu(va0)
+    ref = dpf.solve(Yg, bt, Sd, vm_e, va_e, opts=opts, outage=od, workspace=ws, outputs=outs)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    vm = cu(vm0); va = cu(va0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream kind
+        dpf.solve(Yg, bt, Sd, vm, va, opts=opts, outage=od, workspace=ws, outputs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dpf.solve(Yg, bt, Sd, vm, va, opts=opts, outage=od, workspace=ws, outputs=outs)
+    for rep in range(3):
+        vm.copy_(cu(vm0)); va.copy_(cu(va0))
+        outs["iters"].fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(vm, vm_e) and torch.equal(va, va_e), rep
+        for k in ("iters", "status", "max_mis", "loss"):
+            assert torch.equal(outs[k], ref[k]), (rep, k)
