@@ -225,9 +225,19 @@ def main():
     log(f"building the N-1 batch: {B} outages of the 9241-bus grid")
     cfg, g, Yg, S, bt, out, vm0, va0 = make_cfg2(B)
     opts = solve_options(args.cap)
-    tune = dpf.autotune(Yg, bt, S, vm0, va0, outage=out, opts=opts, iters=100, reps=2, tie=0.03)
-    vinfo = dpf.variants()[tune["choice"]]
-    log(f"autotune: variant {tune['choice']} {vinfo} ({ {k: round(v * 1e3, 2) for k, v in tune['seconds'].items()} } ms / 50 it)")
+    # two probes: the full batch (every CU busy) and 32 cases (one item per CU, as in
+    # the tail of a solve, when early retirement has emptied most CUs); the variant
+    # with the smallest sum is kept
+    full = dpf.autotune(Yg, bt, S, vm0, va0, outage=out, opts=opts, iters=100, reps=2)
+    tail = dpf.autotune(Yg, bt, S, vm0[:32].contiguous(), va0[:32].contiguous(), outage=out[:32], opts=opts,
+                        iters=100, reps=2)
+    score = {k: full["seconds"][k] + tail["seconds"][k] for k in full["seconds"]}
+    choice = min(score, key=score.get)
+    dpf.lib().dpf_autotune_set(g.n_bus, choice)
+    tune = {"choice": choice}
+    vinfo = dpf.variants()[choice]
+    log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
+        f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
     t_step = float(np.mean(times))
     t_kern = float(np.mean(kern))

@@ -124,7 +124,7 @@ const Variant *variant_table(int *count) {
         make_stream_variant<512, 12>(), make_stream_variant<512, 16>(), make_stream_variant<512, 20>(),
         make_stream_variant<1024, 0>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
         make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
-        make_band_variant<512, 2, false>(),
+        make_band_variant<512, 2, false>(), make_band_variant<1024, 3, false>(), make_band_variant<1024, 4, false>(),
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;

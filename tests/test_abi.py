@@ -60,8 +60,21 @@ def test_host_side_validation(lib):
     assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 15), ctypes.c_size_t(0), None) == -1
     assert lib.dpf_solve_series(None, 1, 1, *([None] * 3), 1, *([None] * 4), 1, *([None] * 7),
                                 ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_param_grad(None, 1, 1, *([None] * 3), 0, *([None] * 8), 1, None, None,
+                              ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_dc_init(None, 1, 1, None, None, 0, None, None, ctypes.c_double(1e-12), 10, None, None,
+                           None, ctypes.c_size_t(0), None) == -1
     # workspace sizing is pure host arithmetic
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
+    lib.dpf_dc_init_workspace_bytes.restype = ctypes.c_size_t
+    assert lib.dpf_dc_init_workspace_bytes(9241, 4) >= 3 * 9241 * 4 * 8
+    assert lib.dpf_dc_init_workspace_bytes(0, 4) == 0
+    # invalid argument checks that need no device: a grid is passed, sizes are wrong
+    gp = ctypes.byref(g)
+    assert lib.dpf_param_grad(gp, 0, 9241, *([None] * 3), 0, *([None] * 8), 1, None, None,
+                              ctypes.c_size_t(0), None) == -1  # B = 0
+    assert lib.dpf_dc_init(gp, 1, 100, None, None, 0, None, None, ctypes.c_double(1e-12), 10, None, None,
+                           None, ctypes.c_size_t(0), None) == -1  # ld < n_bus
     lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
     lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_int32, ctypes.c_int32]
@@ -80,7 +93,8 @@ def test_variant_table_and_autotune_cache(lib):
     for i in range(n):
         assert lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == 0
         assert t.value % 64 == 0 and t.value <= 1024
-        seen_stream |= bool(st.value)
+        seen_stream |= st.value == 1
+        assert st.value in (0, 1, 2, 3)  # register, streaming, banded, banded-stream
     assert seen_stream
     assert lib.dpf_solve_variant_info(n, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == -1
     # the register-resident 64-thread variant cannot hold 9241 buses
