@@ -232,8 +232,14 @@ def main():
     tail = dpf.autotune(Yg, bt, S, vm0[:32].contiguous(), va0[:32].contiguous(), outage=out[:32], opts=opts,
                         iters=100, reps=2)
     score = {k: full["seconds"][k] + tail["seconds"][k] for k in full["seconds"]}
-    choice = min(score, key=score.get)
-    dpf.lib().dpf_autotune_set(g.n_bus, choice)
+    # within 3% of the best, prefer a banded kernel: it moves fewer HBM bytes per
+    # bus-iteration (the timing difference is then noise)
+    best = min(score.values())
+    near = [k for k, v in score.items() if v <= 1.03 * best]
+    kinds = {v["index"]: v["kind"] for v in dpf.variants()}
+    banded = [k for k in near if kinds[k].startswith("banded")]
+    choice = min(banded, key=score.get) if banded else min(near, key=score.get)
+    dpf.lib().dpf_autotune_set_items(g.n_bus, B, choice)  # the batch's own item bucket
     tune = {"choice": choice}
     vinfo = dpf.variants()[choice]
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
@@ -469,8 +475,8 @@ def cfg4_uneven(cap):
             "max_mis_median": float(np.median(r["max_mis"].cpu().numpy()))}
 
 
-def graph_replay(calls=200):
-    """Small repeated solves (the 14-bus grid, 200 iterations per call): one
+def graph_replay(calls=200, iters=10):
+    """Small repeated solves (the 14-bus grid, 10 iterations per call): one
     dpf_solve_batch call issued eagerly (seven launches) against the same call
     captured once in a HIP graph and replayed."""
     import torch
@@ -485,7 +491,7 @@ def graph_replay(calls=200):
     vm0, va0 = synth.flat_start(g)
     vm = torch.tensor(vm0[None], device="cuda")
     va = torch.tensor(va0[None], device="cuda")
-    opts = dpf.Options(lr=1e-2, tol=0.0, max_iter=200)
+    opts = dpf.Options(lr=1e-2, tol=0.0, max_iter=iters)
     ws = dpf.SolveWorkspace()
     outs = {k: torch.empty(1, dtype=dt, device="cuda") for k, dt in
             (("iters", torch.int32), ("status", torch.int32), ("max_mis", torch.float64), ("loss", torch.float64))}
@@ -513,7 +519,7 @@ def graph_replay(calls=200):
         graph.replay()
     torch.cuda.synchronize()
     replay = (time.perf_counter() - t0) / calls
-    return {"workload": "14-bus grid, one case, 200 iterations per call", "calls": calls,
+    return {"workload": f"14-bus grid, one case, {iters} iterations per call", "calls": calls,
             "eager_us_per_call": round(eager * 1e6, 1), "graph_us_per_call": round(replay * 1e6, 1)}
 
 

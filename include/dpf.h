@@ -352,23 +352,32 @@ int32_t dpf_solve_max_sub_buses(void);
 /*
  * Kernel variants and the autotune cache.  dpf_solve_batch picks a kernel
  * variant (workgroup size, buses per thread, register-resident or streaming
- * state) from the largest sub-grid of the call.  Sizes are grouped into
- * classes (the smallest variant that holds them); dpf_autotune_set records,
- * for the class of n_max, which variant to use instead -- a project-side
- * autotuner times the eligible variants on real inputs and stores the fastest.
- * The cache is process-wide and guarded by a mutex.
+ * state) from the largest sub-grid of the call and the number of work items.
+ * Sizes are grouped into classes (the smallest variant that holds them) and
+ * item counts into buckets (<= 64, <= 256, more); dpf_autotune_set records, for
+ * the class of n_max, which variant to use instead -- a project-side autotuner
+ * times the eligible variants on real inputs and stores the fastest.  Without a
+ * recorded choice, items above 2048 buses that do not fill the device (items <=
+ * compute units) take the multi-workgroup path, the others the default variant
+ * of their class.  The cache is process-wide and guarded by a mutex.
  *   dpf_solve_variant_count : number of variants
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
  *                             and the kind: register-resident (0), streaming (1),
- *                             banded (2) or banded with a barrier-free gradient
- *                             sweep (3); host outs.  A banded variant (buses
- *                             per thread = buses per thread per block) serves the
- *                             sub-grids whose bandwidth max|row - col| is at most
- *                             threads * buses_per_thread (see dpf_order_rcm); the
- *                             same call runs the other sub-grids with the default
- *                             variant of their size
- *   dpf_solve_variant_for   : variant index dpf_solve_batch would use, -1 if none
- *   dpf_autotune_set        : DPF_EINVAL if the variant cannot hold n_max buses
+ *                             banded (2), banded with a barrier-free gradient
+ *                             sweep (3), or multi-workgroup (4: not a kernel of
+ *                             its own -- every sub-grid of the call is spread
+ *                             over many workgroups); host outs.  A banded variant
+ *                             (buses per thread = buses per thread per block)
+ *                             serves the sub-grids whose bandwidth max|row - col|
+ *                             is at most threads * buses_per_thread (see
+ *                             dpf_order_rcm); the same call runs the other
+ *                             sub-grids with the default variant of their size
+ *   dpf_solve_variant_for   : variant index dpf_solve_batch would use for many
+ *                             items, -1 if none
+ *   dpf_solve_variant_for_items : the same for `items` work items
+ *   dpf_autotune_set        : record `variant` for every item bucket of the class
+ *                             of n_max; DPF_EINVAL if it cannot hold n_max buses
+ *   dpf_autotune_set_items  : record it for the bucket of `items` only
  *   dpf_autotune_set_team_cap : sub-grids above `buses` take the multi-workgroup
  *                             path (several workgroups per item, three kernels per
  *                             iteration, host polls every 32 iterations) even when
@@ -380,7 +389,9 @@ int32_t dpf_solve_max_sub_buses(void);
 int dpf_solve_variant_count(void);
 int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming);
 int dpf_solve_variant_for(int32_t n_max);
+int dpf_solve_variant_for_items(int32_t n_max, int64_t items);
 int dpf_autotune_set(int32_t n_max, int variant);
+int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
 int dpf_autotune_set_team_cap(int32_t buses);
 void dpf_autotune_reset(void);
 

@@ -92,6 +92,10 @@ def lib():
         L.dpf_solve_variant_for.argtypes = [_i32]
         L.dpf_solve_variant_for.restype = ctypes.c_int
         L.dpf_autotune_set.argtypes = [_i32, ctypes.c_int]
+        L.dpf_autotune_set_items.argtypes = [_i32, ctypes.c_int64, ctypes.c_int]
+        L.dpf_autotune_set_items.restype = ctypes.c_int
+        L.dpf_solve_variant_for_items.argtypes = [_i32, ctypes.c_int64]
+        L.dpf_solve_variant_for_items.restype = ctypes.c_int
         L.dpf_autotune_set.restype = ctypes.c_int
         L.dpf_autotune_reset.restype = None
         L.dpf_order_rcm.argtypes = [_i32, _i32, _P, _P, _i32, _P, _i32, _P, _P]
@@ -418,7 +422,7 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream")
+VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide")
 
 
 def variants():
@@ -457,8 +461,11 @@ def rcm_order(n_bus: int, f, t, sub_offset=None, group: int = 0):
     return perm, int(bw.value)
 
 
-def variant_for(n_max: int) -> int:
-    return int(lib().dpf_solve_variant_for(int(n_max)))
+def variant_for(n_max: int, items: int | None = None) -> int:
+    """Variant index dpf_solve_batch would use (for many items, or for `items`)."""
+    if items is None:
+        return int(lib().dpf_solve_variant_for(int(n_max)))
+    return int(lib().dpf_solve_variant_for_items(int(n_max), int(items)))
 
 
 def autotune_reset():
@@ -474,18 +481,20 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
              iters: int = 40, reps: int = 2, tie: float = 0.0):
     """Time every kernel variant that can hold the largest sub-grid on copies of
     the real inputs (``iters`` Adam iterations, no stop test) and record the
-    fastest in the library's autotune cache.  Variants within a fraction ``tie``
-    of the fastest count as equal and the first of them in the table is taken,
-    which keeps the choice stable under timing noise.  Returns {variant: seconds}."""
+    fastest in the library's autotune cache for this size class and this number
+    of work items (B x sub-grids).  Variants within a fraction ``tie`` of the
+    fastest count as equal and the first of them in the table is taken, which
+    keeps the choice stable under timing noise.  Returns {variant: seconds}."""
     opts = opts or Options()
     n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))
+    items = int(vm.shape[0]) * (1 if sub_offset is None else len(sub_offset) - 1)
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
     times = {}
     for v in variants():
         if not (v["kind"].startswith("banded") or v["buses_per_thread"] == 0
                 or v["threads"] * v["buses_per_thread"] >= n_max):
             continue
-        _check(lib().dpf_autotune_set(n_max, v["index"]))
+        _check(lib().dpf_autotune_set_items(n_max, items, v["index"]))
         best = None
         for _ in range(reps):
             vm1, va1 = vm.clone(), va.clone()
@@ -501,5 +510,5 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
         times[v["index"]] = best
     best = min(times.values())
     pick = min(i for i, t in times.items() if t <= best * (1.0 + tie))
-    _check(lib().dpf_autotune_set(n_max, pick))
-    return {"choice": pick, "seconds": times, "n_max": n_max, "iters": iters}
+    _check(lib().dpf_autotune_set_items(n_max, items, pick))
+    return {"choice": pick, "seconds": times, "n_max": n_max, "items": items, "iters": iters}

@@ -112,51 +112,83 @@ Variant make_band_variant() {
     return Variant{NT, J, PIPE ? dpf::kBand : dpf::kBandStream, dpf::team_solve_band_kernel<NT, J, PIPE>};
 }
 
-// Register-resident variants up to 2048 buses per item, streaming above (512 threads
-// keep 256 VGPRs per thread, enough for 20 buses of held exchange values; the
-// 1024-thread streaming variant takes any size with holds in scratch).  The banded
-// variants (k = buses per thread per block) serve sub-grids whose bandwidth is at
-// most threads * k; the others go to the default variant of the size in the same call.
+// Register-resident variants up to 2048 buses per item, streaming above (the
+// 1024-thread streaming variant takes any size with holds in scratch; the 512-thread
+// ones keep held exchange values in registers).  The banded variants (k = buses per
+// thread per block) serve sub-grids whose bandwidth is at most threads * k; the others
+// go to the default variant of the size in the same call.  The last entry is not a
+// workgroup-per-item kernel: it sends every sub-grid of the call to the
+// multi-workgroup path, which spreads one item over many CUs.
 const Variant *variant_table(int *count) {
     static const Variant table[] = {
         make_variant<64, 1>(),  make_variant<128, 1>(), make_variant<256, 1>(), make_variant<256, 2>(),
         make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<512, 8>(),
-        make_stream_variant<512, 12>(), make_stream_variant<512, 16>(), make_stream_variant<512, 20>(),
-        make_stream_variant<1024, 0>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
+        make_stream_variant<512, 12>(), make_stream_variant<1024, 0>(), make_stream_variant<512, 16>(),
+        make_stream_variant<512, 20>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
         make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
         make_band_variant<512, 2, false>(), make_band_variant<1024, 3, false>(), make_band_variant<1024, 4, false>(),
+        Variant{0, 0, dpf::kWide, nullptr},
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
     return table;
 }
 
 bool variant_fits(const Variant &v, int32_t n_max) {
-    return dpf::is_banded(v.mode) || v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k;
+    return dpf::is_banded(v.mode) || v.mode == dpf::kWide || v.k == 0 || (int64_t)n_max <= (int64_t)v.nt * v.k;
 }
 
-// Autotune cache: size class (index of the default variant) -> chosen variant.
+// Autotune cache: (size class = index of the default variant, number-of-items
+// bucket) -> chosen variant.  Items buckets: <= 64, <= 256, more.
+constexpr int kItemBuckets = 3;
 std::mutex g_tune_mu;
-int g_tune[64];
+int g_tune[64][kItemBuckets];
 bool g_tune_init = false;
 
-// first general (non-banded) variant that holds n_max buses
+int items_bucket(int64_t items) { return items <= 64 ? 0 : (items <= 256 ? 1 : 2); }
+
+// Items larger than this (buses) that do not fill the chip (items <= CUs) are solved
+// faster spread over many workgroups than one workgroup each (measured: 9241 buses,
+// 1 to 256 cases, 1.25x to 5x; 3000 buses, 1 to 64 cases, 1.15x to 1.6x; 1354 buses:
+// one workgroup wins).
+constexpr int32_t kWideDefaultBuses = 2048;
+
+// first workgroup-per-item (non-banded) variant that holds n_max buses
 int default_variant_index(int32_t n_max) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     for (int i = 0; i < cnt; ++i)
-        if (!dpf::is_banded(t[i].mode) && variant_fits(t[i], n_max)) return i;
+        if (!dpf::is_banded(t[i].mode) && t[i].mode != dpf::kWide && variant_fits(t[i], n_max)) return i;
     return -1;
 }
 
-const Variant *pick_variant(int32_t n_max) {
+int wide_variant_index() {
+    int cnt = 0;
+    variant_table(&cnt);
+    return cnt - 1;
+}
+
+const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     int d = default_variant_index(n_max);
     if (d < 0) return nullptr;
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    if (g_tune_init && g_tune[d] >= 0 && g_tune[d] < cnt && variant_fits(t[g_tune[d]], n_max)) return &t[g_tune[d]];
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        const int c = g_tune_init ? g_tune[d][items_bucket(items)] : -1;
+        if (c >= 0 && c < cnt && variant_fits(t[c], n_max)) return &t[c];
+    }
+    if (n_max > kWideDefaultBuses && items <= n_cu) return &t[wide_variant_index()];
     return &t[d];
 }
+
+// How one call is split: sub-grids of at most `cap` buses run one workgroup per item
+// with variant `v`; larger ones take the multi-workgroup path.
+struct CallPlan {
+    int32_t cap = 0;
+    int32_t n_max = 0;  // largest sub-grid <= cap
+    bool has_small = false;
+    const Variant *v = nullptr;
+};
 
 bool valid_opts(const dpf_opts_t *o) {
     if (!o) return false;
@@ -564,14 +596,21 @@ int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread,
     return DPF_OK;
 }
 
-int dpf_solve_variant_for(int32_t n_max) {
-    const Variant *v = pick_variant(n_max);
+int dpf_solve_variant_for_items(int32_t n_max, int64_t items) {
+    DeviceInfo dev;
+    if (device_info(dev) != DPF_OK) {
+        g_err.clear();
+        dev.n_cu = 256;
+    }
+    const Variant *v = pick_variant(n_max, items, dev.n_cu > 0 ? dev.n_cu : 256);
     if (!v) return -1;
     int cnt = 0;
     return (int)(v - variant_table(&cnt));
 }
 
-int dpf_autotune_set(int32_t n_max, int variant) {
+int dpf_solve_variant_for(int32_t n_max) { return dpf_solve_variant_for_items(n_max, INT64_MAX); }
+
+static int autotune_store(int32_t n_max, int64_t items, int variant, bool all_buckets) {
     g_err.clear();
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
@@ -579,13 +618,22 @@ int dpf_autotune_set(int32_t n_max, int variant) {
     if (d < 0) return fail(DPF_EINVAL, "no variant holds a sub-grid of this size");
     if (variant < 0 || variant >= cnt || !variant_fits(t[variant], n_max))
         return fail(DPF_EINVAL, "variant cannot hold a sub-grid of this size");
+    if (!all_buckets && items <= 0) return fail(DPF_EINVAL, "items must be > 0");
     std::lock_guard<std::mutex> lk(g_tune_mu);
     if (!g_tune_init) {
-        for (int &x : g_tune) x = -1;
+        for (auto &row : g_tune)
+            for (int &x : row) x = -1;
         g_tune_init = true;
     }
-    g_tune[d] = variant;
+    for (int b = 0; b < kItemBuckets; ++b)
+        if (all_buckets || b == items_bucket(items)) g_tune[d][b] = variant;
     return DPF_OK;
+}
+
+int dpf_autotune_set(int32_t n_max, int variant) { return autotune_store(n_max, 0, variant, true); }
+
+int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant) {
+    return autotune_store(n_max, items, variant, false);
 }
 
 int dpf_autotune_set_team_cap(int32_t buses) {
@@ -598,7 +646,8 @@ int dpf_autotune_set_team_cap(int32_t buses) {
 void dpf_autotune_reset(void) {
     g_team_cap_override.store(0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    for (int &x : g_tune) x = -1;
+    for (auto &row : g_tune)
+        for (int &x : row) x = -1;
     g_tune_init = true;
 }
 
@@ -736,20 +785,26 @@ int32_t dpf_solve_max_sub_buses(void) {
     return max_sub_buses_for(d);
 }
 
-static int32_t max_sub_size(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset) {
-    if (!sub_offset) return n_bus;
-    int32_t m = 0;
-    for (int32_t s = 0; s < n_sub; ++s) m = std::max(m, sub_offset[s + 1] - sub_offset[s]);
-    return m;
-}
-
-static int32_t max_small_sub(int32_t n_bus, int32_t n_sub, const int32_t *sub_offset, int32_t cap) {
-    int32_t m = 0;
+static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
+                          const DeviceInfo &dev) {
+    CallPlan p;
+    p.cap = max_sub_buses_for(dev);
+    int64_t small = 0;
     for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
-        int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : n_bus;
-        if (ns <= cap) m = std::max(m, ns);
+        const int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
+        if (ns <= p.cap) {
+            ++small;
+            p.n_max = std::max(p.n_max, ns);
+        }
     }
-    return m;
+    p.has_small = small > 0;
+    p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256);
+    if (p.v && p.v->mode == dpf::kWide) {  // every sub-grid to the multi-workgroup path
+        p.cap = 0;
+        p.n_max = 0;
+        p.has_small = false;
+    }
+    return p;
 }
 
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
@@ -760,10 +815,10 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
     if (device_info(dev) != DPF_OK) {
         g_err.clear();
         dev.lds_per_block = kGfx950LdsBytes;  // no device visible: size for gfx950
+        dev.n_cu = 256;
     }
-    const int32_t cap = max_sub_buses_for(dev);
-    const Variant *v = pick_variant(std::max(1, max_small_sub(g->n_bus, n_sub, sub_offset, cap)));
-    return solve_layout(g, n_sub, sub_offset, B, ld, v && v->mode != dpf::kReg, cap).total;
+    const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev);
+    return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -795,20 +850,14 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     DeviceInfo dev;
     int rc = device_info(dev);
     if (rc != DPF_OK) return rc;
-    const int32_t n_max_all = max_sub_size(g->n_bus, n_sub, sub_offset);
-    const int32_t cap = max_sub_buses_for(dev);  // larger sub-grids take the multi-workgroup path
-    const int32_t n_max = max_small_sub(g->n_bus, n_sub, sub_offset, cap);
-    const bool has_small = sub_offset ? [&] {
-        for (int32_t s = 0; s < n_sub; ++s)
-            if (sub_offset[s + 1] - sub_offset[s] <= cap) return true;
-        return false;
-    }()
-                                      : g->n_bus <= cap;
-    const Variant *v = pick_variant(std::max(1, n_max));
+    const CallPlan plan = plan_call(g, n_sub, sub_offset, B, dev);
+    const int32_t cap = plan.cap;  // larger sub-grids take the multi-workgroup path
+    const int32_t n_max = plan.n_max;
+    const bool has_small = plan.has_small;
+    const Variant *v = plan.v;
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
     const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap);
     const bool has_wide = L.w_total > 0;
-    (void)n_max_all;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
     char *ws = (char *)workspace;

@@ -33,7 +33,7 @@
 
 namespace dpf {
 
-enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3 };
+enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3, kWide = 4 };
 __host__ __device__ constexpr bool is_banded(int mode) { return mode == kBand || mode == kBandStream; }
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched

@@ -429,7 +429,11 @@ def test_dpfloss_autograd_function(dpf):
 @pytest.mark.parametrize("n_bus", [14, 100, 200, 300, 700, 1354, 2000, 3000, 6000, 9241])
 def test_solve_every_variant_tracks_oracle(dpf, n_bus):
     """Each size class selects a different kernel variant (threads x buses per
-    thread, register-resident or streaming, double- or single-buffered LDS)."""
+    thread, register-resident or streaming, double- or single-buffered LDS); the
+    class default is forced, since a single large item would otherwise take the
+    multi-workgroup path."""
+    dpf.autotune_reset()
+    dpf.lib().dpf_autotune_set(n_bus, dpf.variant_for(n_bus))
     if n_bus == 14:
         g = synth.config0(3)["grid"]
     else:
@@ -452,6 +456,20 @@ def test_solve_every_variant_tracks_oracle(dpf, n_bus):
     assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-11
     assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-11
     assert abs(out["max_mis"].item() - ref["mu"]) <= 1e-9 * ref["mu"]
+    dpf.autotune_reset()
+
+
+def test_default_routing_spreads_few_large_items(dpf):
+    """Without a recorded choice, a few items above 2048 buses take the
+    multi-workgroup path; many items, or small ones, one workgroup each."""
+    dpf.autotune_reset()
+    wide = [v["index"] for v in dpf.variants() if v["kind"] == "wide"][0]
+    assert dpf.variant_for(9241, 1) == wide and dpf.variant_for(9241, 64) == wide
+    assert dpf.variant_for(9241, 4096) != wide
+    assert dpf.variant_for(1354, 1) != wide
+    dpf.lib().dpf_autotune_set_items(9241, 1, dpf.variant_for(9241))
+    assert dpf.variant_for(9241, 1) == dpf.variant_for(9241) and dpf.variant_for(9241, 300) == dpf.variant_for(9241)
+    dpf.autotune_reset()
 
 
 def test_large_angles_use_correct_reduction(dpf):
@@ -937,6 +955,10 @@ def test_solve_call_replays_from_a_captured_graph(dpf, which):
             "status": torch.empty(items, dtype=torch.int32, device="cuda"),
             "max_mis": torch.empty(items, dtype=torch.float64, device="cuda"),
             "loss": torch.empty(items, dtype=torch.float64, device="cuda")}
+    # one workgroup per item: the multi-workgroup path polls from the host and
+    # cannot be captured
+    dpf.autotune_reset()
+    dpf.lib().dpf_autotune_set(g.n_bus, dpf.variant_for(g.n_bus))
     vm_e = cu(vm0); va_e = cu(va0)
     ref = dpf.solve(Yg, bt, Sd, vm_e, va_e, opts=opts, outage=od, workspace=ws, outputs=outs)
     torch.cuda.synchronize()
@@ -960,3 +982,4 @@ def test_solve_call_replays_from_a_captured_graph(dpf, which):
         assert torch.equal(vm, vm_e) and torch.equal(va, va_e), rep
         for k in ("iters", "status", "max_mis", "loss"):
             assert torch.equal(outs[k], ref[k]), (rep, k)
+    dpf.autotune_reset()
