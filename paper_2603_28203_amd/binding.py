@@ -236,7 +236,8 @@ def dc_init(dc_grid: DeviceGrid, bus_type, s_spec, va, outage=None, tol: float =
     place; slack entries are kept).  Returns dict(iters, residual)."""
     dev = va.device
     B, ld = va.shape
-    assert va.is_contiguous() and va.dtype == torch.float64
+    if not (va.is_contiguous() and va.dtype == torch.float64):
+        raise ValueError("va must be a contiguous float64 tensor (updated in place)")
     bt = _dev(bus_type, torch.int8, dev)
     s = _dev(s_spec, torch.complex128, dev)
     s_ld = 0 if s.dim() == 1 else s.shape[1]
@@ -311,7 +312,8 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
     opts = opts or Options()
     dev = vm.device
     B, ld = vm.shape
-    assert vm.is_contiguous() and va.is_contiguous() and vm.dtype == torch.float64
+    if not (vm.is_contiguous() and va.is_contiguous() and vm.dtype == torch.float64 and va.dtype == torch.float64):
+        raise ValueError("vm and va must be contiguous float64 tensors (updated in place)")
     bt = bus_type if (torch.is_tensor(bus_type) and bus_type.dtype == torch.int8 and bus_type.device == dev) \
         else _dev(bus_type, torch.int8, dev)
     s = s_spec if (torch.is_tensor(s_spec) and s_spec.dtype == torch.complex128 and s_spec.device == dev

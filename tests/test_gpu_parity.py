@@ -983,3 +983,66 @@ def test_solve_call_replays_from_a_captured_graph(dpf, which):
         for k in ("iters", "status", "max_mis", "loss"):
             assert torch.equal(outs[k], ref[k]), (rep, k)
     dpf.autotune_reset()
+
+
+# ---------------------------------------------------------------- edge cases
+
+
+def test_solve_edge_cases(dpf):
+    """Degenerate inputs: a lone slack bus (nothing to learn: m = 0, converged
+    at once), a grid without PQ buses (only angles learnable), an empty batch
+    (rejected), and a start that is already a solution."""
+    one = synth.Grid(n_bus=1, f=np.zeros(0, np.int32), t=np.zeros(0, np.int32), r=np.zeros(0), x=np.zeros(0),
+                     b=np.zeros(0), bus_type=np.array([2], np.int8), vm=np.ones(1), va=np.zeros(1))
+    Y1 = dgrid(dpf, one)
+    vm = cu(np.ones((2, 1))); va = cu(np.zeros((2, 1)))
+    out = dpf.solve(Y1, one.bus_type, cu(np.zeros(1), torch.complex128), vm, va, opts=dpf.Options(max_iter=50))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [0, 0] and out["iters"].tolist() == [0, 0]
+    assert out["loss"].tolist() == [0.0, 0.0] and out["max_mis"].tolist() == [0.0, 0.0]
+    # no PQ bus: |V| is never touched, angles follow the oracle
+    g = synth.config0(6)["grid"]
+    g = synth.Grid(n_bus=g.n_bus, f=g.f, t=g.t, r=g.r, x=g.x, b=g.b,
+                   bus_type=np.where(g.bus_type == 2, 2, 1).astype(np.int8), vm=g.vm, va=g.va)
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(6)
+    va0 = g.va + rng.normal(0, 1e-2, g.n_bus) * (g.bus_type != 2)
+    ref = oracle.solve_adam(Yo, g.bus_type, S, g.vm, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=30))
+    vm = cu(g.vm[None]); va = cu(va0[None])
+    dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va,
+              opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=30))
+    torch.cuda.synchronize()
+    assert torch.equal(vm, cu(g.vm[None]))
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-11
+    # empty batch
+    with pytest.raises(dpf.DPFError):
+        dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), cu(np.ones((0, g.n_bus))),
+                  cu(np.zeros((0, g.n_bus))))
+
+
+@pytest.mark.parametrize("extra", [0, 1])
+def test_solve_at_the_lds_limit(tuned, extra):
+    """A sub-grid of exactly the largest size one workgroup holds, and one bus
+    more (which must take the multi-workgroup path), against the oracle."""
+    dpf = tuned
+    cap = dpf.max_sub_buses()
+    n = cap + extra
+    g = synth.config1(B=1, seed=77, n_bus=n, n_branch=int(1.6 * n), n_pv=n // 6)["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    rng = np.random.default_rng(n)
+    vm0 = g.vm + rng.normal(0, 1e-2, n) * (g.bus_type == 0)
+    va0 = g.va + rng.normal(0, 1e-2, n) * (g.bus_type != 2)
+    steps = 5
+    ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+    if extra == 0:  # force one workgroup per item (a single item would otherwise be spread out)
+        dpf.lib().dpf_autotune_set(n, dpf.variant_for(n))
+    print(f"LDS limit test n={n} (cap {cap})", flush=True)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va,
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["iters"].item() == steps and out["status"].item() == 1
+    assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
+    assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
