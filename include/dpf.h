@@ -124,7 +124,8 @@ typedef struct dpf_opts {
 /* Text of the calling thread's last error ("" if none).  Host string owned by the library. */
 const char *dpf_last_error(void);
 
-/* Library version string (host, static). */
+/* Library version string (host, static); ends with "src <hash>", a hash of the
+ * sources the library was built from. */
 const char *dpf_version(void);
 
 /*

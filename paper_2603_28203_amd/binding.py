@@ -59,6 +59,11 @@ def lib():
         L = ctypes.CDLL(LIB_PATH)
         L.dpf_last_error.restype = ctypes.c_char_p
         L.dpf_version.restype = ctypes.c_char_p
+        from . import build as _build
+        want = "src " + _build.source_hash()
+        if not L.dpf_version().decode().endswith(want):
+            raise ImportError(f"{LIB_PATH} was built from other sources ({L.dpf_version().decode()}, "
+                              f"expected {want}): rebuild it with `python -m paper_2603_28203_amd.build`")
         L.dpf_build_ybus.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]
         L.dpf_build_ybus.restype = ctypes.c_int
         L.dpf_mismatch_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P,

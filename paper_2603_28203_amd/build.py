@@ -2,6 +2,7 @@
 
 from __future__ import annotations
 
+import hashlib
 import os
 import subprocess
 import sys
@@ -33,10 +34,19 @@ def hipcc() -> str:
     return "hipcc"
 
 
+def source_hash() -> str:
+    """Hash of the library's sources (embedded in the build, checked at load)."""
+    h = hashlib.sha256()
+    for p in sorted(SOURCES + HEADERS):
+        with open(p, "rb") as fh:
+            h.update(os.path.basename(p).encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
 def build(verbose: bool = False) -> str:
     """Compile the library unconditionally and return its path."""
     tmp = LIB + ".tmp"
-    cmd = [hipcc(), *HIPCC_FLAGS, *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *HIPCC_FLAGS, f'-DDPF_SOURCE_HASH="{source_hash()}"', *SOURCES, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -48,10 +58,13 @@ def build(verbose: bool = False) -> str:
 
 
 def stale() -> bool:
+    """True when the library is missing or was built from other sources."""
     if not os.path.exists(LIB):
         return True
-    t = os.path.getmtime(LIB)
-    return any(os.path.getmtime(p) > t for p in SOURCES + HEADERS)
+    import ctypes
+    lib = ctypes.CDLL(LIB)
+    lib.dpf_version.restype = ctypes.c_char_p
+    return not lib.dpf_version().decode().endswith("src " + source_hash())
 
 
 if __name__ == "__main__":

@@ -357,7 +357,10 @@ extern "C" {
 
 const char *dpf_last_error(void) { return g_err.c_str(); }
 
-const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64)"; }
+#ifndef DPF_SOURCE_HASH
+#define DPF_SOURCE_HASH "unknown"
+#endif
+const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64) src " DPF_SOURCE_HASH; }
 
 int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
                    const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
