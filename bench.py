@@ -45,11 +45,14 @@ def log(msg):
 
 
 def kernel_source_hash() -> str:
+    """Hash of the device-code headers (the kernels; host code and the launch
+    table live in dpf.hip, and the launch shape is part of the kernel name)."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_28203_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
-        with open(os.path.join(csrc, f), "rb") as fh:
-            h.update(fh.read())
+        if f.endswith(".hpp"):
+            with open(os.path.join(csrc, f), "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
