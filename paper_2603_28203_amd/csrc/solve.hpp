@@ -107,6 +107,115 @@ __device__ __forceinline__ void block_reduce2_finish(double &s, double &m, doubl
     m = uniform(m);
 }
 
+// Per-item step count and learning-rate schedule, kept across calls in
+// SolveArgs::sched as {t, lr, best, bad + cooldown * 2^20, b1^t, b2^t}.
+struct ItemSched {
+    double t_step, lr, best, b1t, b2t;
+    int bad, cool;
+};
+
+__device__ __forceinline__ ItemSched load_item_sched(const SolveArgs &a, int out_idx) {
+    ItemSched s{0.0, a.lr, __longlong_as_double(0x7ff0000000000000LL), 1.0, 1.0, 0, 0};
+    if (a.sched) {
+        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+        s.t_step = ss[0];
+        s.lr = ss[1];
+        s.best = ss[2];
+        const int packed = (int)ss[3];
+        s.bad = packed & 0xFFFFF;
+        s.cool = packed >> 20;
+        s.b1t = ss[4];
+        s.b2t = ss[5];
+    }
+    return s;
+}
+
+// scheduler step after the optimizer step of iteration `it` (uniform across the
+// workgroup): PyTorch's reduce-on-plateau (mode min, relative threshold) or StepLR
+__device__ __forceinline__ void sched_step(const SolveArgs &a, ItemSched &s, double loss, int it) {
+    if (a.sch == DPF_SCHED_PLATEAU) {
+        if (loss < s.best * (1.0 - a.threshold)) {
+            s.best = loss;
+            s.bad = 0;
+        } else {
+            s.bad += 1;
+        }
+        if (s.cool > 0) {
+            s.cool -= 1;
+            s.bad = 0;
+        }
+        if (s.bad > a.patience) {
+            double nl = s.lr * a.factor;
+            if (nl < a.min_lr) nl = a.min_lr;
+            if (s.lr - nl > a.sched_eps) s.lr = nl;
+            s.cool = a.cooldown;
+            s.bad = 0;
+        }
+    } else if (a.sch == DPF_SCHED_STEP) {
+        if (a.patience > 0 && ((it + 1) % a.patience) == 0) s.lr = s.lr * a.factor;
+    }
+}
+
+// per-item results and the schedule state, written by one thread
+__device__ __forceinline__ void finish_item(const SolveArgs &a, int out_idx, int it, int stat, double mu, double loss,
+                                            const ItemSched &s) {
+    a.iters[out_idx] = it;
+    a.status[out_idx] = stat;
+    a.mu_out[out_idx] = mu;
+    a.loss_out[out_idx] = loss;
+    if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
+    if (a.sched) {
+        double *ss = a.sched + kSchedWords * (int64_t)out_idx;
+        ss[0] = s.t_step;
+        ss[1] = s.lr;
+        ss[2] = s.best;
+        ss[3] = (double)(s.bad + (s.cool << 20));
+        ss[4] = s.b1t;
+        ss[5] = s.b2t;
+    }
+}
+
+// residual count m = n_pv + 2 n_pq of buses [lo, hi) (workgroup reduction)
+template <int NT>
+__device__ __forceinline__ double residual_count(const int8_t *__restrict__ bt, int lo, int hi,
+                                                 double (*red)[NT / kWave]) {
+    double cnt = 0.0, dummy = 0.0;
+    for (int i = lo + (int)threadIdx.x; i < hi; i += NT) {
+        const int8_t t = bt[i];
+        cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
+    }
+    block_reduce2<NT>(cnt, dummy, red);
+    __syncthreads();
+    block_reduce2_finish<NT>(cnt, dummy, red);
+    __syncthreads();
+    return cnt;
+}
+
+// the N-1 branch of case c as local bus indices and its pi-model blocks
+// (of = ot = -1 when the case has no outage inside [lo, hi))
+struct Rank2 {
+    int of, ot;
+    double2 oy, oyd;
+};
+
+__device__ __forceinline__ Rank2 outage_of_case(const OutageView &ov, int c, int lo, int hi) {
+    Rank2 r{-1, -1, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    if (ov.outage) {
+        const int32_t k = ov.outage[c];
+        if ((uint32_t)k < (uint32_t)ov.n_branch) {
+            const int32_t f = ov.from[k], t = ov.to[k];
+            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
+                r.of = f - lo;
+                r.ot = t - lo;
+                double2 ysh;
+                branch_admittance(ov.r[k], ov.x[k], ov.b[k], r.oy, ysh);
+                r.oyd = cadd(r.oy, ysh);
+            }
+        }
+    }
+    return r;
+}
+
 template <int NT, int K, int MODE>
 __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     extern __shared__ double2 X[];
@@ -136,54 +245,16 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     double2 *Xv = X;
     double2 *Xw = dbl ? X + n : X;
 
-    // schedule state and Adam step count (a resumed solve continues them)
-    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
-    int bad = 0, cool = 0;
-    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
-    if (a.sched) {
-        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-        t_step = ss[0];
-        lr = ss[1];
-        best = ss[2];
-        const int packed = (int)ss[3];
-        bad = packed & 0xFFFFF;
-        cool = packed >> 20;
-        b1t = ss[4];
-        b2t = ss[5];
-    }
+    // step count and schedule (a resumed solve continues them)
+    ItemSched sc = load_item_sched(a, out_idx);
 
-    // residual count m of this sub-grid
-    double m_res;
-    {
-        double cnt = 0.0, dummy = 0.0;
-        for (int i = lo + tid; i < hi; i += NT) {
-            int8_t t = a.bt[i];
-            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
-        }
-        block_reduce2<NT>(cnt, dummy, red);
-        __syncthreads();
-        block_reduce2_finish<NT>(cnt, dummy, red);
-        m_res = cnt;
-        __syncthreads();
-    }
+    const double m_res = residual_count<NT>(a.bt, lo, hi, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
 
     // N-1 outage of this case (only meaningful for a single sub-grid)
-    int of = -1, ot = -1;
-    double2 oy = make_double2(0.0, 0.0), oyd = oy;
-    if (a.ov.outage) {
-        int32_t k = a.ov.outage[c];
-        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
-            int32_t f = a.ov.from[k], t = a.ov.to[k];
-            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
-                of = f - lo;
-                ot = t - lo;
-                double2 ysh;
-                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
-                oyd = cadd(oy, ysh);
-            }
-        }
-    }
+    const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
 
     const int64_t cb = (int64_t)c * a.ld;
     const int64_t sb = (int64_t)c * a.s_ld;
@@ -306,11 +377,11 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         }
 
         // ---------------- phase B: adjoint product, gradient, Adam
-        t_step += 1.0;
-        b1t *= a.b1;
-        b2t *= a.b2;
-        const double bc1 = 1.0 - b1t;
-        const double bc2 = 1.0 - b2t;
+        sc.t_step += 1.0;
+        sc.b1t *= a.b1;
+        sc.b2t *= a.b2;
+        const double bc1 = 1.0 - sc.b1t;
+        const double bc2 = 1.0 - sc.b2t;
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const int i = lo + tid + k * NT;
@@ -350,7 +421,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                         sv = sv_c[i];
                     }
                     const double g = (G.x * v.x + G.y * v.y) / vmi;
-                    vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                    vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                     if (!REG) {
                         vm_c[i] = vmi;
                         mv_c[i] = mv;
@@ -363,7 +434,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                         sa = sa_c[i];
                     }
                     const double g = G.y * v.x - G.x * v.y;
-                    vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                    vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                     if (!REG) {
                         va_c[i] = vai;
                         ma_c[i] = ma;
@@ -389,27 +460,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
             }
         }
         // ---------------- schedule step (uniform across the workgroup)
-        if (a.sch == DPF_SCHED_PLATEAU) {
-            if (loss < best * (1.0 - a.threshold)) {
-                best = loss;
-                bad = 0;
-            } else {
-                bad += 1;
-            }
-            if (cool > 0) {
-                cool -= 1;
-                bad = 0;
-            }
-            if (bad > a.patience) {
-                double nl = lr * a.factor;
-                if (nl < a.min_lr) nl = a.min_lr;
-                if (lr - nl > a.sched_eps) lr = nl;
-                cool = a.cooldown;
-                bad = 0;
-            }
-        } else if (a.sch == DPF_SCHED_STEP) {
-            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
-        }
+        sched_step(a, sc, loss, it);
         if (!dbl) {
             __syncthreads();
 #pragma unroll
@@ -438,22 +489,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
             }
         }
     }
-    if (tid == 0) {
-        a.iters[out_idx] = it;
-        a.status[out_idx] = stat;
-        a.mu_out[out_idx] = mu;
-        a.loss_out[out_idx] = loss;
-        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
-        if (a.sched) {
-            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-            ss[0] = t_step;
-            ss[1] = lr;
-            ss[2] = best;
-            ss[3] = (double)(bad + (cool << 20));
-            ss[4] = b1t;
-            ss[5] = b2t;
-        }
-    }
+    if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
 }
 
 // Streaming variant for large sub-grids.  Every per-bus value lives in global
@@ -503,51 +539,16 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     double2 *Xv = X;
     double2 *Xw = dbl ? X + n : X;
 
-    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
-    int bad = 0, cool = 0;
-    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
-    if (a.sched) {
-        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-        t_step = ss[0];
-        lr = ss[1];
-        best = ss[2];
-        const int packed = (int)ss[3];
-        bad = packed & 0xFFFFF;
-        cool = packed >> 20;
-        b1t = ss[4];
-        b2t = ss[5];
-    }
+    // step count and schedule (a resumed solve continues them)
+    ItemSched sc = load_item_sched(a, out_idx);
 
-    double m_res;
-    {
-        double cnt = 0.0, dummy = 0.0;
-        for (int i = lo + tid; i < hi; i += NT) {
-            int8_t t = a.bt[i];
-            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
-        }
-        block_reduce2<NT>(cnt, dummy, red);
-        __syncthreads();
-        block_reduce2_finish<NT>(cnt, dummy, red);
-        m_res = cnt;
-        __syncthreads();
-    }
+    const double m_res = residual_count<NT>(a.bt, lo, hi, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
 
-    int of = -1, ot = -1;
-    double2 oy = make_double2(0.0, 0.0), oyd = oy;
-    if (a.ov.outage) {
-        int32_t k = a.ov.outage[c];
-        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
-            int32_t f = a.ov.from[k], t = a.ov.to[k];
-            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
-                of = f - lo;
-                ot = t - lo;
-                double2 ysh;
-                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
-                oyd = cadd(oy, ysh);
-            }
-        }
-    }
+    // N-1 outage of this case (only meaningful for a single sub-grid)
+    const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
 
     const int64_t cb = (int64_t)c * a.ld;
     const int64_t sb = (int64_t)c * a.s_ld;
@@ -656,11 +657,11 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
         }
 
         // ---------------- phase B
-        t_step += 1.0;
-        b1t *= a.b1;
-        b2t *= a.b2;
-        const double bc1 = 1.0 - b1t;
-        const double bc2 = 1.0 - b2t;
+        sc.t_step += 1.0;
+        sc.b1t *= a.b1;
+        sc.b2t *= a.b2;
+        const double bc1 = 1.0 - sc.b1t;
+        const double bc2 = 1.0 - sc.b2t;
         DPF_BUS_LOOP_BEGIN
                 const int il = (int)i - lo;
                 // every global load of this bus first, so that they overlap the gather
@@ -686,7 +687,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 if (tk == kPQ) {
                     const double g = (G.x * v.x + G.y * v.y) / vmi;
                     double mv = mv0, sv = sv0;
-                    vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                    vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                     vm_c[i] = vmi;
                     mv_c[i] = mv;
                     sv_c[i] = sv;
@@ -694,7 +695,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 if (tk != kSlack) {
                     const double g = G.y * v.x - G.x * v.y;
                     double ma = ma0, sa = sa0;
-                    vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                    vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                     va_c[i] = vai;
                     ma_c[i] = ma;
                     sa_c[i] = sa;
@@ -705,27 +706,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 if (dbl) Xv[il] = v;
                 else if (HOLD) hold[kk % KH] = v;
         DPF_BUS_LOOP_END
-        if (a.sch == DPF_SCHED_PLATEAU) {
-            if (loss < best * (1.0 - a.threshold)) {
-                best = loss;
-                bad = 0;
-            } else {
-                bad += 1;
-            }
-            if (cool > 0) {
-                cool -= 1;
-                bad = 0;
-            }
-            if (bad > a.patience) {
-                double nl = lr * a.factor;
-                if (nl < a.min_lr) nl = a.min_lr;
-                if (lr - nl > a.sched_eps) lr = nl;
-                cool = a.cooldown;
-                bad = 0;
-            }
-        } else if (a.sch == DPF_SCHED_STEP) {
-            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
-        }
+        sched_step(a, sc, loss, it);
         if (!dbl) {
             __syncthreads();
             if (HOLD) {
@@ -748,22 +729,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 #undef DPF_BUS_LOOP_BEGIN
 #undef DPF_BUS_LOOP_END
 
-    if (tid == 0) {
-        a.iters[out_idx] = it;
-        a.status[out_idx] = stat;
-        a.mu_out[out_idx] = mu;
-        a.loss_out[out_idx] = loss;
-        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
-        if (a.sched) {
-            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-            ss[0] = t_step;
-            ss[1] = lr;
-            ss[2] = best;
-            ss[3] = (double)(bad + (cool << 20));
-            ss[4] = b1t;
-            ss[5] = b2t;
-        }
-    }
+    if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
 }
 
 // Banded variant, for sub-grids numbered with a small bandwidth: every entry of
@@ -810,51 +776,16 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
     const int slice0 = a.sell.slice_off[sidx];
     const int lane = tid & (kWave - 1);
 
-    double t_step = 0.0, lr = a.lr, best = __longlong_as_double(0x7ff0000000000000LL);
-    int bad = 0, cool = 0;
-    double b1t = 1.0, b2t = 1.0;  // b1^t, b2^t of the bias corrections
-    if (a.sched) {
-        const double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-        t_step = ss[0];
-        lr = ss[1];
-        best = ss[2];
-        const int packed = (int)ss[3];
-        bad = packed & 0xFFFFF;
-        cool = packed >> 20;
-        b1t = ss[4];
-        b2t = ss[5];
-    }
+    // step count and schedule (a resumed solve continues them)
+    ItemSched sc = load_item_sched(a, out_idx);
 
-    double m_res;
-    {
-        double cnt = 0.0, dummy = 0.0;
-        for (int i = lo + tid; i < hi; i += NT) {
-            int8_t t = a.bt[i];
-            cnt += t == kPQ ? 2.0 : (t == kPV ? 1.0 : 0.0);
-        }
-        block_reduce2<NT>(cnt, dummy, red);
-        __syncthreads();
-        block_reduce2_finish<NT>(cnt, dummy, red);
-        m_res = cnt;
-        __syncthreads();
-    }
+    const double m_res = residual_count<NT>(a.bt, lo, hi, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
 
-    int of = -1, ot = -1;
-    double2 oy = make_double2(0.0, 0.0), oyd = oy;
-    if (a.ov.outage) {
-        int32_t k = a.ov.outage[c];
-        if ((uint32_t)k < (uint32_t)a.ov.n_branch) {
-            int32_t f = a.ov.from[k], t = a.ov.to[k];
-            if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
-                of = f - lo;
-                ot = t - lo;
-                double2 ysh;
-                branch_admittance(a.ov.r[k], a.ov.x[k], a.ov.b[k], oy, ysh);
-                oyd = cadd(oy, ysh);
-            }
-        }
-    }
+    // N-1 outage of this case (only meaningful for a single sub-grid)
+    const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
 
     const int64_t cb = (int64_t)c * a.ld;
     const int64_t sb = (int64_t)c * a.s_ld;
@@ -954,11 +885,11 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
         }
 
         // ---------------- B/U sweep
-        t_step += 1.0;
-        b1t *= a.b1;
-        b2t *= a.b2;
-        const double bc1 = 1.0 - b1t;
-        const double bc2 = 1.0 - b2t;
+        sc.t_step += 1.0;
+        sc.b1t *= a.b1;
+        sc.b2t *= a.b2;
+        const double bc1 = 1.0 - sc.b1t;
+        const double bc2 = 1.0 - sc.b2t;
         // PIPE: block steps with a barrier each, the new V held for one step.
         // Otherwise: one barrier-free pass (w stays in X throughout), then the
         // new V is rebuilt from |V| and theta in a refill pass.
@@ -999,7 +930,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     if (tk == kPQ) {
                         const double g = (G.x * v.x + G.y * v.y) / vmi;
                         double mv = mv0, sv = sv0;
-                        vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                        vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
                         vm_c[i] = vmi;
                         mv_c[i] = mv;
                         sv_c[i] = sv;
@@ -1007,7 +938,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     if (tk != kSlack) {
                         const double g = G.y * v.x - G.x * v.y;
                         double ma = ma0, sa = sa0;
-                        vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                        vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
                         va_c[i] = vai;
                         ma_c[i] = ma;
                         sa_c[i] = sa;
@@ -1041,46 +972,11 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                 X[i - lo] = make_double2(vmi * cs, vmi * sn);
             }
         }
-        if (a.sch == DPF_SCHED_PLATEAU) {
-            if (loss < best * (1.0 - a.threshold)) {
-                best = loss;
-                bad = 0;
-            } else {
-                bad += 1;
-            }
-            if (cool > 0) {
-                cool -= 1;
-                bad = 0;
-            }
-            if (bad > a.patience) {
-                double nl = lr * a.factor;
-                if (nl < a.min_lr) nl = a.min_lr;
-                if (lr - nl > a.sched_eps) lr = nl;
-                cool = a.cooldown;
-                bad = 0;
-            }
-        } else if (a.sch == DPF_SCHED_STEP) {
-            if (a.patience > 0 && ((it + 1) % a.patience) == 0) lr = lr * a.factor;
-        }
+        sched_step(a, sc, loss, it);
         __syncthreads();
     }
 
-    if (tid == 0) {
-        a.iters[out_idx] = it;
-        a.status[out_idx] = stat;
-        a.mu_out[out_idx] = mu;
-        a.loss_out[out_idx] = loss;
-        if (a.done_ns) a.done_ns[out_idx] = (int64_t)((double)(wall_clock64() - *a.stamp) * a.ns_per_tick);
-        if (a.sched) {
-            double *ss = a.sched + kSchedWords * (int64_t)out_idx;
-            ss[0] = t_step;
-            ss[1] = lr;
-            ss[2] = best;
-            ss[3] = (double)(bad + (cool << 20));
-            ss[4] = b1t;
-            ss[5] = b2t;
-        }
-    }
+    if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
 }
 
 // start point of every step of a time-series window: rows [0, gridDim.y) of dst
