@@ -365,9 +365,11 @@ int32_t dpf_solve_max_sub_buses(void);
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
  *                             and the kind: register-resident (0), streaming (1),
  *                             banded (2), banded with a barrier-free gradient
- *                             sweep (3), or multi-workgroup (4: not a kernel of
+ *                             sweep (3), multi-workgroup (4: not a kernel of
  *                             its own -- every sub-grid of the call is spread
- *                             over many workgroups); host outs.  A banded variant
+ *                             over many workgroups), or banded with a window of
+ *                             12 blocks in LDS and one pipelined sweep per
+ *                             iteration (5); host outs.  A banded variant
  *                             (buses per thread = buses per thread per block)
  *                             serves the sub-grids whose bandwidth max|row - col|
  *                             is at most threads * buses_per_thread (see

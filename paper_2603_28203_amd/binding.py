@@ -429,7 +429,7 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide")
+VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window")
 
 
 def variants():

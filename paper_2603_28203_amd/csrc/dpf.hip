@@ -111,12 +111,18 @@ template <int NT, int J, bool PIPE = true>
 Variant make_band_variant() {
     return Variant{NT, J, PIPE ? dpf::kBand : dpf::kBandStream, dpf::team_solve_band_kernel<NT, J, PIPE>};
 }
+template <int NT, int J>
+Variant make_window_variant() {
+    return Variant{NT, J, dpf::kWindow, dpf::team_solve_window_kernel<NT, J>};
+}
 
 // Register-resident variants up to 2048 buses per item, streaming above (the
 // 1024-thread streaming variant takes any size with holds in scratch; the 512-thread
 // ones keep held exchange values in registers).  The banded variants (k = buses per
 // thread per block) serve sub-grids whose bandwidth is at most threads * k; the others
-// go to the default variant of the size in the same call.  The last entry is not a
+// go to the default variant of the size in the same call.  The windowed ones keep
+// 12 blocks of threads * k buses in LDS whatever the sub-grid size, so that several
+// items share a compute unit.  The last entry is not a
 // workgroup-per-item kernel: it sends every sub-grid of the call to the
 // multi-workgroup path, which spreads one item over many CUs.
 const Variant *variant_table(int *count) {
@@ -127,6 +133,8 @@ const Variant *variant_table(int *count) {
         make_stream_variant<512, 20>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
         make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
         make_band_variant<512, 2, false>(), make_band_variant<1024, 3, false>(), make_band_variant<1024, 4, false>(),
+        make_window_variant<256, 1>(),      make_window_variant<128, 2>(),        make_window_variant<128, 1>(),
+        make_window_variant<512, 1>(),      make_window_variant<256, 2>(),
         Variant{0, 0, dpf::kWide, nullptr},
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
@@ -954,8 +962,15 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
     }
     if (has_small) {
-        DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes));
-        hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
+        // the windowed kernel's LDS is a fixed ring of 12 blocks
+        dpf::SolveArgs aw = a;
+        size_t v_lds = lds_bytes;
+        if (v->mode == dpf::kWindow) {
+            aw.lds_cap = 12 * v->nt * v->k;
+            v_lds = (size_t)aw.lds_cap * 16;
+        }
+        DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)v_lds));
+        hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), v_lds, st, aw);
         DPF_HIP(hipGetLastError());
         if (dpf::is_banded(v->mode)) {
             // items whose bandwidth exceeds the banded block go to the general variant

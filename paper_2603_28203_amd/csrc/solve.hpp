@@ -33,8 +33,8 @@
 
 namespace dpf {
 
-enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3, kWide = 4 };
-__host__ __device__ constexpr bool is_banded(int mode) { return mode == kBand || mode == kBandStream; }
+enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3, kWide = 4, kWindow = 5 };
+__host__ __device__ constexpr bool is_banded(int mode) { return mode == kBand || mode == kBandStream || mode == kWindow; }
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched
 
@@ -974,6 +974,276 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
         }
         sched_step(a, sc, loss, it);
         __syncthreads();
+    }
+
+    if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
+}
+
+// Windowed variant for banded sub-grids of any size: one sweep per iteration
+// over blocks of BLK = NT*J consecutive buses, with the LDS holding only a few
+// blocks of each exchange vector.  A sweep runs four stages as a pipeline, each
+// one block behind the block it needs complete (rows of block b read blocks
+// b-1..b+1 when the bandwidth is at most BLK), one barrier per step:
+//   S1, block s  : load |V|, theta; V_k = polar -> V ring
+//   S2, block s-2: I = Y V_k, dS, a = (2/m)(r^P + j r^Q); w = a conj(V_k) -> w ring
+//   S3, block s-4: h = Y^T w; G = a I + conj(h); optimizer step on |V|, theta and
+//                  the moments (written back); V_k+1 -> V ring
+//   S4, block s-6: I = Y V_k+1, dS at the new point -> loss and max|r| for the
+//                  stop test that decides whether the next sweep updates
+// The V ring holds 8 blocks (V_k ahead of S3, V_k+1 behind it), the w ring 4.
+// Per bus and iteration this moves |V|, theta and the four moments once each way
+// (the 96-byte floor) and no other per-bus array; the cost is a third product
+// with Y (S4) and a pipeline fill of six steps per sweep.  The first sweep of a
+// call only measures the start point (S2 and S3 idle, S4 reads V_k).
+// HBM loads are issued one step ahead (|V|, theta of block s+1 and the moments
+// of block s-3), so that their latency overlaps the barrier and the LDS work.
+template <int NT, int J>
+__global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
+    constexpr int BLK = NT * J;
+    constexpr int VM = 8 * BLK - 1;  // V ring index mask
+    constexpr int WM = 4 * BLK - 1;  // w ring index mask
+    extern __shared__ double2 X[];
+    double2 *__restrict__ RV = X;
+    double2 *__restrict__ RW = X + 8 * BLK;
+    __shared__ double red[2][NT / kWave];
+
+    const int tid = threadIdx.x;
+    const int item = blockIdx.x;
+    const int sidx = item / a.B;
+    const int c = item - sidx * a.B;
+    const int lo = a.sub_off ? a.sub_off[sidx] : 0;
+    const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
+    const int n = hi - lo;
+    const int out_idx = c * a.n_sub + sidx;
+    if (n > a.team_cap) return;        // handled by the multi-workgroup path
+    if (a.sub_bw[sidx] > BLK) return;  // bandwidth too large: the general kernel takes it
+    if (n < 0 || a.lds_cap < 12 * BLK || *a.bad_grid) {  // see DPF_BAD_GRID
+        if (tid == 0) {
+            a.status[out_idx] = DPF_BAD_GRID;
+            a.iters[out_idx] = 0;
+        }
+        return;
+    }
+    const int slice0 = a.sell.slice_off[sidx];
+    const int lane = tid & (kWave - 1);
+
+    ItemSched sc = load_item_sched(a, out_idx);
+    const double m_res = residual_count<NT>(a.bt, lo, hi, red);
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+    const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
+
+    const int64_t cb = (int64_t)c * a.ld;
+    const int64_t sb = (int64_t)c * a.s_ld;
+    double *__restrict__ vm_c = a.vm + cb + lo;
+    double *__restrict__ va_c = a.va + cb + lo;
+    double *__restrict__ mv_c = a.st + cb + lo;
+    double *__restrict__ ma_c = a.st + a.st_stride + cb + lo;
+    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb + lo;
+    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb + lo;
+    const double2 *__restrict__ Sc = a.s_spec + sb + lo;
+    const int8_t *__restrict__ btp = a.bt + lo;
+    const int32_t *__restrict__ swidth = a.sell.width;
+    const int32_t *__restrict__ sstart = a.sell.start;
+    const int32_t *__restrict__ scol = a.sell.col;
+    const double2 *__restrict__ sval = a.sell.val;
+
+    if (a.st_fresh) {
+        for (int il = tid; il < n; il += NT) {
+            mv_c[il] = 0.0;
+            ma_c[il] = 0.0;
+            sv_c[il] = 0.0;
+            sa_c[il] = 0.0;
+        }
+    }
+
+    // I_i = (Y R)_i for local row il of ring R (mask M), with the outage block removed
+    auto row_product = [&](const double2 *__restrict__ R, int M, int il) -> double2 {
+        const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+        const int wdt = swidth[gsl];
+        const int base = sstart[gsl] * kWave + lane;
+        double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+        for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], R[scol[base + q * kWave] & M], acc);
+        if (il == of) acc = csub(acc, csub(cmul(oyd, R[of & M]), cmul(oy, R[ot & M])));
+        else if (il == ot) acc = csub(acc, csub(cmul(oyd, R[ot & M]), cmul(oy, R[of & M])));
+        return acc;
+    };
+
+    const int nb = (n + BLK - 1) / BLK;
+    int it = 0, stat = DPF_MAX_ITER;
+    double mu = 0.0, loss = 0.0;
+    bool upd = false;  // the first sweep only measures the start point
+    for (;;) {
+        double bc1 = 1.0, bc2 = 1.0;
+        if (upd) {
+            sc.t_step += 1.0;
+            sc.b1t *= a.b1;
+            sc.b2t *= a.b2;
+            bc1 = 1.0 - sc.b1t;
+            bc2 = 1.0 - sc.b2t;
+        }
+        const double lr = sc.lr;
+        // register pipelines: |V|, theta from S1 to S3 (qm/qa[d] = block s-d at step s,
+        // [0] is the prefetch for block s+1 ... see the shifts), a*I from S2 to S3,
+        // moments prefetched one step before S3
+        double qm[6][J], qa[6][J];
+        double2 pI[3][J];
+        double pm[4][J];
+#pragma unroll
+        for (int j = 0; j < J; ++j) {
+#pragma unroll
+            for (int d = 0; d < 6; ++d) qm[d][j] = qa[d][j] = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; ++d) pI[d][j] = make_double2(0.0, 0.0);
+#pragma unroll
+            for (int d = 0; d < 4; ++d) pm[d][j] = 0.0;
+            const int il = j * NT + tid;  // prefetch of block 0
+            if (il < n) {
+                qm[0][j] = vm_c[il];
+                qa[0][j] = va_c[il];
+            }
+        }
+        double lsum = 0.0, lmax = 0.0;
+        for (int s = 0; s < nb + 6; ++s) {
+            // shift: the prefetched block s becomes qm[1]
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+#pragma unroll
+                for (int d = 5; d > 0; --d) {
+                    qm[d][j] = qm[d - 1][j];
+                    qa[d][j] = qa[d - 1][j];
+                }
+            }
+            // S1: block s
+            if (s < nb) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = s * BLK + j * NT + tid;
+                    if (il < n) {
+                        double sn, cs;
+                        fast_sincos(qa[1][j], sn, cs);
+                        RV[il & VM] = make_double2(qm[1][j] * cs, qm[1][j] * sn);
+                    }
+                }
+            }
+            // S2: block s-2
+            if (upd && s >= 2 && s - 2 < nb) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = (s - 2) * BLK + j * NT + tid;
+                    double2 ai = make_double2(0.0, 0.0);
+                    if (il < n) {
+                        const int8_t tk = btp[il];
+                        const double2 sp = Sc[il];
+                        const double2 I = row_product(RV, VM, il);
+                        const double2 v = RV[il & VM];
+                        const double2 d = csub(cmulc(v, I), sp);
+                        const double rP = tk != kSlack ? d.x : 0.0;
+                        const double rQ = tk == kPQ ? d.y : 0.0;
+                        const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
+                        ai = cmul(av, I);
+                        RW[il & WM] = cmulc(av, v);
+                    }
+                    pI[0][j] = ai;
+                }
+            }
+            // S3: block s-4
+            if (upd && s >= 4 && s - 4 < nb) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = (s - 4) * BLK + j * NT + tid;
+                    if (il < n) {
+                        const int8_t tk = btp[il];
+                        const double2 h = row_product(RW, WM, il);
+                        const double2 v = RV[il & VM];
+                        const double2 ai = pI[2][j];
+                        const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+                        double vmi = qm[5][j], vai = qa[5][j];
+                        if (tk == kPQ) {
+                            const double g = (G.x * v.x + G.y * v.y) / vmi;
+                            double mv = pm[0][j], sv = pm[1][j];
+                            vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                            vm_c[il] = vmi;
+                            mv_c[il] = mv;
+                            sv_c[il] = sv;
+                        }
+                        if (tk != kSlack) {
+                            const double g = G.y * v.x - G.x * v.y;
+                            double ma = pm[2][j], sa = pm[3][j];
+                            vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                            va_c[il] = vai;
+                            ma_c[il] = ma;
+                            sa_c[il] = sa;
+                        }
+                        double sn, cs;
+                        fast_sincos(vai, sn, cs);
+                        RV[il & VM] = make_double2(vmi * cs, vmi * sn);
+                    }
+                }
+            }
+            // S4: block s-6, the loss at the point this sweep leaves behind
+            if (s >= 6) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) {
+                    const int il = (s - 6) * BLK + j * NT + tid;
+                    if (il < n) {
+                        const int8_t tk = btp[il];
+                        const double2 sp = Sc[il];
+                        const double2 I = row_product(RV, VM, il);
+                        const double2 v = RV[il & VM];
+                        const double2 d = csub(cmulc(v, I), sp);
+                        const double rP = tk != kSlack ? d.x : 0.0;
+                        const double rQ = tk == kPQ ? d.y : 0.0;
+                        lsum += rP * rP + rQ * rQ;
+                        lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+                    }
+                }
+            }
+            // prefetch for the next step: |V|, theta of block s+1, moments of block s-3
+#pragma unroll
+            for (int j = 0; j < J; ++j) {
+                const int il = (s + 1) * BLK + j * NT + tid;
+                if (s + 1 < nb && il < n) {
+                    qm[0][j] = vm_c[il];
+                    qa[0][j] = va_c[il];
+                }
+                const int im = (s - 3) * BLK + j * NT + tid;
+                if (upd && s >= 3 && s - 3 < nb && im < n) {
+                    pm[0][j] = mv_c[im];
+                    pm[1][j] = sv_c[im];
+                    pm[2][j] = ma_c[im];
+                    pm[3][j] = sa_c[im];
+                }
+#pragma unroll
+                for (int d = 2; d > 0; --d) pI[d][j] = pI[d - 1][j];
+            }
+            __syncthreads();
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        __syncthreads();  // red is rewritten by the next sweep's reduction
+        if (upd) {
+            sched_step(a, sc, loss, it);  // with the loss of the point just updated
+            ++it;
+        }
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+        upd = true;
     }
 
     if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);

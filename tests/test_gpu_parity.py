@@ -1046,3 +1046,166 @@ def test_solve_at_the_lds_limit(tuned, extra):
     assert out["iters"].item() == steps and out["status"].item() == 1
     assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
     assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
+
+
+# ---------------------------------------------------------------- windowed banded kernel
+
+
+def window_variants(dpf, blk=None):
+    return [v for v in dpf.variants() if v["kind"] == "banded-window"
+            and (blk is None or v["threads"] * v["buses_per_thread"] == blk)]
+
+
+@pytest.mark.parametrize("n_bus", [14, 100, 257, 700, 3000])
+def test_window_variants_track_oracle(tuned, n_bus):
+    """The windowed kernel on sub-grids of one to a dozen blocks (ragged last
+    block included), with N-1 outages and a plateau schedule that lowers the
+    learning rate inside the run: iterates, max|dS| and the schedule state equal
+    the oracle's."""
+    dpf = tuned
+    if n_bus == 14:
+        base = synth.config0(3)["grid"]
+    else:
+        base = synth.config1(B=1, seed=9300 + n_bus, n_bus=n_bus, n_branch=int(1.6 * n_bus),
+                             n_pv=max(1, n_bus // 6))["grid"]
+    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t)
+    g = renumber(base, perm)
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    nb = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.array([-1] + sorted(np.random.default_rng(2).choice(nb, 2, replace=False).tolist()), np.int32)
+    B = 3
+    rng = np.random.default_rng(n_bus + 1)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 9
+    pl = dict(sched=oracle.SCHED_PLATEAU, factor=0.5, patience=1, threshold=0.5, cooldown=1)
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps, **pl)) for c in range(B)]
+    assert min(r["lr"] for r in refs) < 1e-3  # the schedule acted
+    Yg = dgrid(dpf, g)
+    vs = window_variants(dpf)
+    assert vs
+    for v in vs:
+        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+        print(f"window parity n={g.n_bus} bw={bw} variant={v}", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        sch = torch.tensor([[0.0, 1e-3, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        sched_state=sch, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps, **pl))
+        torch.cuda.synchronize()
+        assert out["iters"].tolist() == [steps] * B and out["status"].tolist() == [1] * B
+        for c in range(B):
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, v
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-11, v
+            assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
+            assert sch[c, 1].item() == pytest.approx(refs[c]["lr"], rel=1e-15)
+
+
+@pytest.mark.parametrize("far", [256, 257])
+def test_window_block_boundary(tuned, far):
+    """A chain with one chord of bandwidth exactly one 256-bus block (the
+    windowed kernel takes it) or one more (rows would read two blocks ahead: the
+    general kernel must take the item); both equal the oracle."""
+    dpf = tuned
+    n = 700
+    rng = np.random.default_rng(far)
+    f = np.concatenate([np.arange(n - 1), [300]]).astype(np.int32)
+    t = np.concatenate([np.arange(1, n), [300 + far]]).astype(np.int32)
+    m = len(f)
+    bt = np.zeros(n, dtype=np.int8)
+    bt[0] = 2
+    bt[rng.choice(np.arange(1, n), n // 6, replace=False)] = 1
+    g = synth.Grid(n_bus=n, f=f, t=t, r=rng.uniform(0.01, 0.1, m), x=rng.uniform(0.05, 0.3, m),
+                   b=rng.uniform(0, 0.05, m), bus_type=bt, vm=rng.uniform(0.98, 1.02, n),
+                   va=np.concatenate([[0.0], rng.uniform(-0.05, 0.05, n - 1)]))
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm0 = g.vm + rng.normal(0, 1e-2, n) * (bt == 0)
+    va0 = g.va + rng.normal(0, 1e-2, n) * (bt != 2)
+    steps = 8
+    outage = np.array([m - 1], np.int32)  # the chord itself (the chain stays connected)
+    ref = oracle.solve_adam(oracle.ybus_of(g, skip=m - 1), bt, S, vm0, va0,
+                            oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+    Yg = dgrid(dpf, g)
+    for v in window_variants(dpf, blk=256):
+        dpf.lib().dpf_autotune_set(n, v["index"])
+        vm = cu(vm0[None]); va = cu(va0[None])
+        dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                  opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+        torch.cuda.synchronize()
+        assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-11, v
+        assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-11, v
+
+
+def test_window_resume_and_convergence(tuned):
+    """Two half-length calls with the moments and schedule passed through equal
+    one call (bit for bit), and a solve to tolerance from the flat start ends
+    on the planted solution at about the oracle's iteration count."""
+    dpf = tuned
+    g = synth.config0(2)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    vm0, va0 = synth.flat_start(g)
+    v = window_variants(dpf, blk=128)[0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    opts = dpf.Options(tol=0.0, max_iter=120, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05,
+                       cooldown=3)
+    vmA = cu(vm0[None]); vaA = cu(va0[None])
+    dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=opts)
+    vmB = cu(vm0[None]); vaB = cu(va0[None])
+    st = torch.zeros((4, 1, g.n_bus), dtype=torch.float64, device="cuda")
+    sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]], dtype=torch.float64, device="cuda")
+    half = dpf.Options(**{**opts.__dict__, "max_iter": 60})
+    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+    torch.cuda.synchronize()
+    assert torch.equal(vmA, vmB) and torch.equal(vaA, vaB)
+    assert sch[0, 0].item() == 120
+    # to tolerance
+    g = synth.config0(0)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0, va0, oracle.AdamOptions(max_iter=20000))
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(max_iter=20000))
+    torch.cuda.synchronize()
+    assert out["status"].item() == ref["status"] == 0
+    assert abs(out["iters"].item() - ref["iters"]) <= max(3, ref["iters"] // 20)
+    assert out["max_mis"].item() < 1e-6
+    assert np.abs(vm[0].cpu().numpy() - g.vm).max() < 1e-5
+
+
+def test_window_edge_cases(tuned):
+    """max_iter = 0 (only the start point is measured), a start that is already
+    a solution, a NaN injection, and a lone slack bus, on the windowed kernel."""
+    dpf = tuned
+    g = synth.config0(0)["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    v = window_variants(dpf, blk=256)[0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    vm0, va0 = synth.flat_start(g)
+    B = 3
+    Sb = np.tile(S, (B, 1))
+    Sb[1, 4] = np.nan
+    vm = cu(np.tile(vm0, (B, 1))); va = cu(np.tile(va0, (B, 1)))
+    vm[2] = cu(g.vm); va[2] = cu(g.va)  # case 2 starts at the solution
+    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(Sb, torch.complex128), vm, va, opts=dpf.Options(max_iter=7))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [1, 2, 0] and out["iters"].tolist() == [7, 0, 0]
+    ref0 = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(tol=0.0, max_iter=0))
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va,
+                    opts=dpf.Options(tol=0.0, max_iter=0))
+    torch.cuda.synchronize()
+    assert out["iters"].item() == 0 and out["status"].item() == 1
+    assert abs(out["max_mis"].item() - ref0["mu"]) <= 1e-12 * ref0["mu"]
+    assert torch.equal(vm, cu(vm0[None])) and torch.equal(va, cu(va0[None]))
+    one = synth.Grid(n_bus=1, f=np.zeros(0, np.int32), t=np.zeros(0, np.int32), r=np.zeros(0), x=np.zeros(0),
+                     b=np.zeros(0), bus_type=np.array([2], np.int8), vm=np.ones(1), va=np.zeros(1))
+    dpf.lib().dpf_autotune_set(1, v["index"])
+    vm = cu(np.ones((2, 1))); va = cu(np.zeros((2, 1)))
+    out = dpf.solve(dgrid(dpf, one), one.bus_type, cu(np.zeros(1), torch.complex128), vm, va,
+                    opts=dpf.Options(max_iter=50))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [0, 0] and out["iters"].tolist() == [0, 0]
