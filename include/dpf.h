@@ -367,14 +367,19 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             banded (2), banded with a barrier-free gradient
  *                             sweep (3), multi-workgroup (4: not a kernel of
  *                             its own -- every sub-grid of the call is spread
- *                             over many workgroups), or banded with a window of
- *                             12 blocks in LDS and one pipelined sweep per
- *                             iteration (5); host outs.  A banded variant
+ *                             over many workgroups), banded with a window of
+ *                             8 blocks in LDS and one pipelined sweep per
+ *                             iteration (5), or the same for several cases of
+ *                             a single-grid call per workgroup, sharing the
+ *                             matrix loads (6: buses_per_thread is 1, see
+ *                             dpf_solve_variant_cases); host outs.  A banded variant
  *                             (buses per thread = buses per thread per block)
  *                             serves the sub-grids whose bandwidth max|row - col|
  *                             is at most threads * buses_per_thread (see
  *                             dpf_order_rcm); the same call runs the other
  *                             sub-grids with the default variant of their size
+ *   dpf_solve_variant_cases : cases per workgroup of a variant (1 except kind 6),
+ *                             DPF_EINVAL for a bad index
  *   dpf_solve_variant_for   : variant index dpf_solve_batch would use for many
  *                             items, -1 if none
  *   dpf_solve_variant_for_items : the same for `items` work items
@@ -391,6 +396,7 @@ int32_t dpf_solve_max_sub_buses(void);
  */
 int dpf_solve_variant_count(void);
 int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming);
+int dpf_solve_variant_cases(int idx);
 int dpf_solve_variant_for(int32_t n_max);
 int dpf_solve_variant_for_items(int32_t n_max, int64_t items);
 int dpf_autotune_set(int32_t n_max, int variant);

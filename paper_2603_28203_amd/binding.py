@@ -94,6 +94,8 @@ def lib():
         L.dpf_solve_variant_count.restype = ctypes.c_int
         L.dpf_solve_variant_info.argtypes = [ctypes.c_int, _P, _P, _P]
         L.dpf_solve_variant_info.restype = ctypes.c_int
+        L.dpf_solve_variant_cases.argtypes = [ctypes.c_int]
+        L.dpf_solve_variant_cases.restype = ctypes.c_int
         L.dpf_solve_variant_for.argtypes = [_i32]
         L.dpf_solve_variant_for.restype = ctypes.c_int
         L.dpf_autotune_set.argtypes = [_i32, ctypes.c_int]
@@ -429,20 +431,24 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window")
+VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window", "banded-batched")
 
 
 def variants():
     """The solve kernel variants: list of dicts (index, threads, buses_per_thread,
-    kind, streaming).  For a banded variant buses_per_thread counts the buses of
-    one block; it serves sub-grids of bandwidth <= threads * buses_per_thread."""
+    kind, streaming, cases).  For a banded variant buses_per_thread counts the buses
+    of one block; it serves sub-grids of bandwidth <= threads * buses_per_thread.
+    `cases` is the number of cases one workgroup solves at a time."""
     L = lib()
     out = []
     for i in range(L.dpf_solve_variant_count()):
         t, k, st = ctypes.c_int32(0), ctypes.c_int32(0), ctypes.c_int32(0)
         _check(L.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)))
+        cases = L.dpf_solve_variant_cases(i)
+        if cases < 0:
+            _check(cases)
         out.append({"index": i, "threads": t.value, "buses_per_thread": k.value, "kind": VARIANT_KINDS[st.value],
-                    "streaming": st.value != 0})
+                    "streaming": st.value != 0, "cases": cases})
     return out
 
 

@@ -115,14 +115,20 @@ template <int NT, int J>
 Variant make_window_variant() {
     return Variant{NT, J, dpf::kWindow, dpf::team_solve_window_kernel<NT, J>};
 }
+// k = cases per workgroup (one bus per thread per block)
+template <int NT, int C>
+Variant make_multi_variant() {
+    return Variant{NT, C, dpf::kMulti, dpf::team_solve_multi_kernel<NT, C>};
+}
 
 // Register-resident variants up to 2048 buses per item, streaming above (the
 // 1024-thread streaming variant takes any size with holds in scratch; the 512-thread
 // ones keep held exchange values in registers).  The banded variants (k = buses per
 // thread per block) serve sub-grids whose bandwidth is at most threads * k; the others
 // go to the default variant of the size in the same call.  The windowed ones keep
-// 12 blocks of threads * k buses in LDS whatever the sub-grid size, so that several
-// items share a compute unit.  The last entry is not a
+// 8 blocks of threads * k buses in LDS whatever the sub-grid size, so that several
+// items share a compute unit; the batched windowed ones (k = cases per workgroup)
+// run k cases of a single-grid call per workgroup on one stream of matrix loads.  The last entry is not a
 // workgroup-per-item kernel: it sends every sub-grid of the call to the
 // multi-workgroup path, which spreads one item over many CUs.
 const Variant *variant_table(int *count) {
@@ -134,7 +140,9 @@ const Variant *variant_table(int *count) {
         make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
         make_band_variant<512, 2, false>(), make_band_variant<1024, 3, false>(), make_band_variant<1024, 4, false>(),
         make_window_variant<256, 1>(),      make_window_variant<128, 2>(),        make_window_variant<128, 1>(),
-        make_window_variant<512, 1>(),      make_window_variant<256, 2>(),
+        make_window_variant<512, 1>(),      make_window_variant<256, 2>(),        make_multi_variant<256, 2>(),
+        make_multi_variant<256, 3>(),       make_multi_variant<256, 4>(),         make_multi_variant<512, 2>(),
+        make_multi_variant<128, 4>(),
         Variant{0, 0, dpf::kWide, nullptr},
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
@@ -602,9 +610,17 @@ int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread,
     if (idx < 0 || idx >= cnt || !threads || !buses_per_thread || !streaming)
         return fail(DPF_EINVAL, "variant index out of range or null output");
     *threads = t[idx].nt;
-    *buses_per_thread = t[idx].k;
+    *buses_per_thread = t[idx].mode == dpf::kMulti ? 1 : t[idx].k;
     *streaming = t[idx].mode;
     return DPF_OK;
+}
+
+int dpf_solve_variant_cases(int idx) {
+    g_err.clear();
+    int cnt = 0;
+    const Variant *t = variant_table(&cnt);
+    if (idx < 0 || idx >= cnt) return fail(DPF_EINVAL, "variant index out of range");
+    return t[idx].mode == dpf::kMulti ? t[idx].k : 1;
 }
 
 int dpf_solve_variant_for_items(int32_t n_max, int64_t items) {
@@ -810,6 +826,11 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
     }
     p.has_small = small > 0;
     p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256);
+    if (p.v && p.v->mode == dpf::kMulti && sub_offset && n_sub != 1) {  // batched kernel: one grid only
+        int cnt = 0;
+        const int d = default_variant_index(std::max(1, p.n_max));
+        p.v = d >= 0 ? &variant_table(&cnt)[d] : nullptr;
+    }
     if (p.v && p.v->mode == dpf::kWide) {  // every sub-grid to the multi-workgroup path
         p.cap = 0;
         p.n_max = 0;
@@ -885,7 +906,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
     // so that the whole call can be captured in a graph)
     hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
-                       g->n_bus, nslice, sub_bw, bad);
+                       g->n_bus, nslice, sub_bw, bad, bad + 4);
     hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
     if (L.n_slices > 0) {
         hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
@@ -913,6 +934,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.sub_bw = sub_bw;
     a.band_nt = 0;
     a.bad_grid = bad;
+    a.queue = bad + 4;  // header word 4: the batched kernel's case queue
     a.team_cap = cap;
     if (v->mode != dpf::kReg || has_wide) {
         double *mom = (double *)(ws + L.off_mom);
@@ -962,22 +984,27 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
     }
     if (has_small) {
-        // the windowed kernel's LDS is a fixed ring of 12 blocks
+        // the windowed kernel's LDS is a fixed pair of 4-block rings
         dpf::SolveArgs aw = a;
         size_t v_lds = lds_bytes;
+        int grid = items;
         if (v->mode == dpf::kWindow) {
-            aw.lds_cap = 12 * v->nt * v->k;
+            aw.lds_cap = 8 * v->nt * v->k;
             v_lds = (size_t)aw.lds_cap * 16;
+        } else if (v->mode == dpf::kMulti) {  // k cases per workgroup, more from the queue
+            aw.lds_cap = 8 * v->nt * v->k;
+            v_lds = (size_t)aw.lds_cap * 16;
+            grid = (items + v->k - 1) / v->k;
         }
         DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)v_lds));
-        hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), v_lds, st, aw);
+        hipLaunchKernelGGL(v->fn, dim3(grid), dim3(v->nt), v_lds, st, aw);
         DPF_HIP(hipGetLastError());
         if (dpf::is_banded(v->mode)) {
             // items whose bandwidth exceeds the banded block go to the general variant
             int cnt = 0;
             const Variant *f = &variant_table(&cnt)[default_variant_index(std::max(1, n_max))];
             dpf::SolveArgs b = a;
-            b.band_nt = v->nt * v->k;
+            b.band_nt = v->mode == dpf::kMulti ? v->nt : v->nt * v->k;  // the banded block
             DPF_HIP(hipFuncSetAttribute((const void *)f->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds_bytes));
             hipLaunchKernelGGL(f->fn, dim3(items), dim3(f->nt), lds_bytes, st, b);

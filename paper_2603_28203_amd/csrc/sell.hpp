@@ -26,11 +26,15 @@ struct SellView {
 };
 
 // slices per sub-grid: ceil(n_s / 64); clears the per-sub-grid bandwidth
-// (thread 0 also clears the bad-grid flag)
+// (thread 0 also clears the bad-grid flag and the case queue)
 __global__ void sell_count_kernel(int32_t n_sub, const int32_t *__restrict__ sub_off, int32_t n_bus,
-                                  int32_t *__restrict__ nslice, int32_t *__restrict__ bw, int32_t *__restrict__ bad) {
+                                  int32_t *__restrict__ nslice, int32_t *__restrict__ bw, int32_t *__restrict__ bad,
+                                  int32_t *__restrict__ queue) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s == 0) *bad = 0;
+    if (s == 0) {
+        *bad = 0;
+        *queue = 0;
+    }
     if (s >= n_sub) return;
     int32_t lo = sub_off ? sub_off[s] : 0;
     int32_t hi = sub_off ? sub_off[s + 1] : n_bus;

@@ -1209,3 +1209,190 @@ def test_window_edge_cases(tuned):
                     opts=dpf.Options(max_iter=50))
     torch.cuda.synchronize()
     assert out["status"].tolist() == [0, 0] and out["iters"].tolist() == [0, 0]
+
+
+# ---------------------------------------------------------------- batched windowed kernel
+
+
+def batched_variants(dpf):
+    return [v for v in dpf.variants() if v["kind"] == "banded-batched"]
+
+
+@pytest.mark.parametrize("shared_s", [True, False])
+def test_batched_variants_track_oracle(tuned, shared_s):
+    """Several cases per workgroup with cases taken from a queue: 9 cases with
+    N-1 outages, two non-finite injections and one start at the solution (all
+    three stop at once and their slots take new cases), shared or per-case
+    S_spec; every case equals its own oracle solve."""
+    dpf = tuned
+    base = synth.config1(B=1, seed=9500, n_bus=700, n_branch=1120, n_pv=110)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 9
+    rng = np.random.default_rng(95)
+    S = np.tile(S0, (B, 1))
+    if not shared_s:
+        S = S * rng.uniform(0.97, 1.03, (B, 1))
+    S[1, 5] = np.nan
+    S[6, 9] = np.nan
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.where(np.arange(B) % 3 == 0, -1, rng.choice(nbr, B)).astype(np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm0[4], va0[4] = g.vm, g.va  # case 4 starts at the solution of the base case
+    outage[4] = -1
+    if not shared_s:
+        S[4] = S0
+    steps = 9
+    tol = 1e-9
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=tol, max_iter=steps)) for c in range(B)]
+    assert [r["status"] for r in refs] == [1, 2, 1, 1, 0, 1, 2, 1, 1]
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    vs = batched_variants(dpf)
+    assert vs
+    for v in vs:
+        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+        print(f"batched parity variant={v} shared={shared_s}", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=cu(outage, torch.int32),
+                        opts=dpf.Options(lr=1e-3, tol=tol, max_iter=steps))
+        torch.cuda.synchronize()
+        assert out["status"].tolist() == [r["status"] for r in refs], v
+        assert out["iters"].tolist() == [r["iters"] for r in refs], v
+        for c in range(B):
+            if refs[c]["status"] == 2:
+                continue
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, (v, c)
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-11, (v, c)
+            if refs[c]["status"] == 0:
+                assert out["max_mis"][c].item() < tol
+            else:
+                assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
+
+
+def test_batched_shared_spec_row(tuned):
+    """A single S_spec row shared by every case (leading dimension 0) gives the
+    per-case results of the same row repeated."""
+    dpf = tuned
+    base = synth.config1(B=1, seed=9501, n_bus=600, n_branch=960, n_pv=100)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 5
+    rng = np.random.default_rng(96)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = rng.choice(nbr, B).astype(np.int32)
+    vm0 = np.tile(g.vm, (B, 1)); va0 = np.tile(g.va, (B, 1))
+    Yg = dgrid(dpf, g)
+    steps = 12
+    res = {}
+    for v in [dpf.variant_for(g.n_bus)] + [x["index"] for x in batched_variants(dpf)]:
+        dpf.lib().dpf_autotune_set(g.n_bus, v)
+        for rows in ("shared", "tiled"):
+            Sd = cu(S, torch.complex128) if rows == "shared" else cu(np.tile(S, (B, 1)), torch.complex128)
+            vm = cu(vm0); va = cu(va0)
+            dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=cu(outage, torch.int32),
+                      opts=dpf.Options(lr=1e-4, eps=1e-14, tol=0.0, max_iter=steps))
+            torch.cuda.synchronize()
+            res[(v, rows)] = (vm.cpu().numpy(), va.cpu().numpy())
+        assert np.array_equal(res[(v, "shared")][0], res[(v, "tiled")][0])
+        assert np.array_equal(res[(v, "shared")][1], res[(v, "tiled")][1])
+        assert np.abs(res[(v, "shared")][1] - va0).max() > 0  # the iterates moved
+
+
+def test_batched_resume_convergence_and_bad_grid(tuned):
+    """Two half-length calls (moments and schedule passed through) equal one
+    call bit for bit; solves to tolerance from the flat start end on the planted
+    solution near the oracle's iteration count; a bad grid marks every case."""
+    dpf = tuned
+    g = synth.config0(0)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    vm0, va0 = synth.flat_start(g)
+    B = 5
+    rng = np.random.default_rng(97)
+    vmB0 = np.tile(vm0, (B, 1)) + rng.normal(0, 1e-3, (B, g.n_bus)) * (g.bus_type == 0)
+    vaB0 = np.tile(va0, (B, 1)) + rng.normal(0, 1e-3, (B, g.n_bus)) * (g.bus_type != 2)
+    opts = dpf.Options(tol=0.0, max_iter=120, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05,
+                       cooldown=3)
+    half = dpf.Options(**{**opts.__dict__, "max_iter": 60})
+    for v in batched_variants(dpf):
+        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+        vmA = cu(vmB0); vaA = cu(vaB0)
+        dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=opts)
+        vmB = cu(vmB0); vaB = cu(vaB0)
+        st = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
+        sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+        dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+        dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
+        torch.cuda.synchronize()
+        assert torch.equal(vmA, vmB) and torch.equal(vaA, vaB), v
+        assert sch[:, 0].tolist() == [120.0] * B
+    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0, va0, oracle.AdamOptions(max_iter=20000))
+    v = batched_variants(dpf)[0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    vm = cu(np.tile(vm0, (3, 1))); va = cu(np.tile(va0, (3, 1)))
+    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=dpf.Options(max_iter=20000))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [0, 0, 0] and ref["status"] == 0
+    assert len(set(out["iters"].tolist())) == 1
+    assert abs(out["iters"][0].item() - ref["iters"]) <= max(3, ref["iters"] // 20)
+    assert np.abs(vm.cpu().numpy() - g.vm[None]).max() < 1e-5
+    Yb = dgrid(dpf, g)
+    Yb.max_row_nnz = 2
+    Yb._c = None
+    vm = cu(np.tile(vm0, (B, 1))); va = cu(np.tile(va0, (B, 1)))
+    out = dpf.solve(Yb, g.bus_type, Sd, vm, va, opts=dpf.Options(max_iter=5))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [dpf.BAD_GRID] * B and out["iters"].tolist() == [0] * B
+    assert np.array_equal(vm.cpu().numpy(), np.tile(vm0, (B, 1)))
+
+
+def test_batched_falls_back_for_sub_grids_and_wide_band(tuned):
+    """The batched kernel only takes single-grid calls of small bandwidth: a
+    call with sub-grids, and a grid whose bandwidth exceeds the block, still
+    equal the oracle (the general kernel takes them)."""
+    dpf = tuned
+    n = 700
+    rng = np.random.default_rng(98)
+    f = np.concatenate([np.arange(n - 1), [50]]).astype(np.int32)
+    t = np.concatenate([np.arange(1, n), [650]]).astype(np.int32)  # bandwidth 600 > 512
+    m = len(f)
+    bt = np.zeros(n, dtype=np.int8)
+    bt[0] = 2
+    bt[rng.choice(np.arange(1, n), n // 6, replace=False)] = 1
+    g = synth.Grid(n_bus=n, f=f, t=t, r=rng.uniform(0.01, 0.1, m), x=rng.uniform(0.05, 0.3, m),
+                   b=rng.uniform(0, 0.05, m), bus_type=bt, vm=rng.uniform(0.98, 1.02, n),
+                   va=np.concatenate([[0.0], rng.uniform(-0.05, 0.05, n - 1)]))
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 3
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (bt == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (bt != 2)
+    steps = 6
+    refs = [oracle.solve_adam(oracle.ybus_of(g), bt, S, vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
+    Yg = dgrid(dpf, g)
+    for v in batched_variants(dpf):
+        dpf.lib().dpf_autotune_set(n, v["index"])
+        vm = cu(vm0); va = cu(va0)
+        dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+        torch.cuda.synchronize()
+        for c in range(B):
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, v
+    # two sub-grids in one call (each the chain grid): the default kernel takes the call
+    off = [0, n, 2 * n]
+    g2 = (np.concatenate([f, f + n]), np.concatenate([t, t + n]))
+    Y2 = dpf.build_ybus(2 * n, g2[0], g2[1], np.tile(g.r, 2), np.tile(g.x, 2), np.tile(g.b, 2))
+    bt2 = np.tile(bt, 2)
+    S2 = np.tile(S, 2)
+    for v in batched_variants(dpf):
+        dpf.lib().dpf_autotune_set(n, v["index"])
+        vm = cu(np.tile(vm0[:1], (1, 2))); va = cu(np.tile(va0[:1], (1, 2)))
+        out = dpf.solve(Y2, bt2, cu(S2[None], torch.complex128), vm, va, sub_offset=off,
+                        opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+        torch.cuda.synchronize()
+        assert out["iters"].tolist() == [steps, steps]
+        assert np.abs(vm[0, :n].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
+        assert np.abs(vm[0, n:].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
