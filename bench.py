@@ -335,10 +335,13 @@ def main():
 
     if not args.no_extras:
         log("screening: the same N-1 batch at tol 1e-3 pu, 1000-iteration budget")
+        # a loose tolerance is reached in the first few hundred steps, where fast
+        # moment decay rates (PyTorch's defaults) move faster than the tuned ones
         scr = solve_options(1000)
         scr.tol = 1e-3
+        scr.beta1, scr.beta2, scr.patience = 0.9, 0.999, 1000
         ts, _, rs, _, _ = run_fused(Yg, bt, S, out, vm0, va0, scr, 1, 1)
-        line["screening"] = {"tol": 1e-3, "iter_cap": 1000, "s": round(ts[0], 4),
+        line["screening"] = {"tol": 1e-3, "iter_cap": 1000, "betas": [scr.beta1, scr.beta2], "s": round(ts[0], 4),
                              "converged": int((rs["status"] == 0).sum()),
                              "solves_per_s": round(int((rs["status"] == 0).sum()) / ts[0], 1),
                              "iters_median": float(np.median(rs["iters"]))}
