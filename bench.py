@@ -37,6 +37,9 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BUS_ORDER_GROUP = 256
+# the last 192 unfinished cases of the N-1 batch finish on the multi-workgroup path
+# (dpf_autotune_set_tail_handoff); measured 128..192 best, 0 = off
+TAIL_HANDOFF = 192
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -198,6 +201,8 @@ def main():
     ap.add_argument("--steps", type=int, default=1)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cap", type=int, default=60000, help="Adam iteration cap per case")
+    ap.add_argument("--handoff", type=int, default=TAIL_HANDOFF,
+                    help="unfinished cases handed to the multi-workgroup path (0 = off)")
     ap.add_argument("--cases", type=int, default=1024)
     ap.add_argument("--quick", action="store_true", help="small cap, no baselines (smoke of the harness)")
     ap.add_argument("--no-autograd", action="store_true")
@@ -250,6 +255,7 @@ def main():
     vinfo = dpf.variants()[choice]
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
         f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
+    dpf.set_tail_handoff(args.handoff)
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
     t_step = float(np.mean(times))
     t_kern = float(np.mean(kern))
@@ -257,8 +263,8 @@ def main():
     iters = res["iters"].astype(np.int64)
     value = conv / t_step
 
-    # ---- roofline of the solve kernel: state floor 96 B per bus-iteration (vm, va and
-    # four Adam moments read and written; S_spec shared) + the shared CSR twice per iteration
+    # ---- algorithmic bytes: state floor 96 B per bus-iteration (vm, va and four Adam
+    # moments read and written; S_spec shared) + the shared CSR twice per iteration
     n, nnz = g.n_bus, Yg.nnz
     case_iters = int(iters.sum())
     alg_bytes = case_iters * n * 96 + int(iters.max()) * 2 * (20 * nnz + 4 * (n + 1))
@@ -270,20 +276,25 @@ def main():
              "banded-window": f"team_solve_window_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
              "banded-batched": f"team_solve_multi_kernel<{vinfo['threads']}, {vinfo['cases']}>",
              }[vinfo["kind"]]
-    # the same kernel with every item active (fixed 200 iterations, no stop test):
-    # the rate of the full-chip phase, before early retirement thins the batch out
+    # roofline of the dominant kernel on one launch of it alone: every item active for
+    # 200 iterations (no stop test, no handoff), timed with HIP events on its stream
+    dpf.set_tail_handoff(0)
     fixed = dpf.Options(**{**opts.__dict__, "tol": 0.0, "max_iter": 200})
     tf, kf, _, _, _ = run_fused(Yg, bt, S, out, vm0, va0, fixed, 1, 1)
     steady_bytes = B * 200 * n * 96 + 200 * 2 * (20 * nnz + 4 * (n + 1))
+    steady = steady_bytes / kf[0] / 1e9
     traffic = pmc_traffic(kname)
-    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic / t_kern / 1e9, 1),
-                "alg_bytes_per_launch": alg_bytes, "launch_s": round(t_kern, 4),
-                "steady_state": {"what": "200 iterations, all 1024 items active", "launch_s": round(kf[0], 5),
-                                 "achieved": round(steady_bytes / kf[0] / 1e9, 1),
-                                 "frac": round(steady_bytes / kf[0] / 1e9 / HBM_PEAK_GBS, 4),
-                                 "ms_per_iter": round(kf[0] / 200 * 1e3, 4)}}
+    roofline = {"bound": "hbm", "kernel": kname,
+                "what": f"one launch of the kernel: all {B} cases active for 200 iterations",
+                "achieved": round(steady, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(steady / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / kf[0] / 1e9, 1),
+                "alg_bytes_per_launch": steady_bytes, "launch_s": round(kf[0], 5),
+                "ms_per_iter": round(kf[0] / 200 * 1e3, 4)}
+    solve_rate = {"what": "the timed solve call: per-item kernel, early retirement, then the last "
+                          f"{args.handoff} cases on the multi-workgroup path",
+                  "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                  "alg_bytes": alg_bytes, "call_s": round(t_kern, 4), "tail_handoff": args.handoff}
 
     line = {
         "metric": "converged PF solves/s at max|dS| < 1e-6 pu (fused adjoint)",
@@ -304,6 +315,7 @@ def main():
                    "bus_order": f"reverse Cuthill-McKee, degree-grouped in windows of {BUS_ORDER_GROUP} "
                                 f"(dpf_order_rcm; bandwidth {cfg['bandwidth']})",
                    "kernel_variant": vinfo,
+                   "tail_handoff": args.handoff,
                    "optimizer": {"lr": opts.lr, "betas": [opts.beta1, opts.beta2], "eps": opts.eps,
                                  "schedule": "plateau", "factor": opts.factor, "patience": opts.patience,
                                  "threshold": opts.threshold}},
@@ -316,6 +328,7 @@ def main():
                                       if conv else None),
         "max_mis_p50": float(np.percentile(res["max_mis"], 50)),
         "roofline": roofline,
+        "solve_rate": solve_rate,
     }
 
     if not args.no_autograd:
@@ -340,7 +353,9 @@ def main():
         scr = solve_options(1000)
         scr.tol = 1e-3
         scr.beta1, scr.beta2, scr.patience = 0.9, 0.999, 1000
+        dpf.set_tail_handoff(args.handoff)
         ts, _, rs, _, _ = run_fused(Yg, bt, S, out, vm0, va0, scr, 1, 1)
+        dpf.set_tail_handoff(0)
         line["screening"] = {"tol": 1e-3, "iter_cap": 1000, "betas": [scr.beta1, scr.beta2], "s": round(ts[0], 4),
                              "converged": int((rs["status"] == 0).sum()),
                              "solves_per_s": round(int((rs["status"] == 0).sum()) / ts[0], 1),

@@ -390,7 +390,20 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             path (several workgroups per item, three kernels per
  *                             iteration, host polls every 32 iterations) even when
  *                             they would fit one workgroup's LDS; 0 = the LDS limit
- *   dpf_autotune_reset      : forget every choice (and the team cap)
+ *   dpf_autotune_set_tail_handoff : tail handoff for single-grid calls: once at
+ *                             most `items` of a call's items are unfinished, the
+ *                             per-item kernels pause them (every 32 iterations they
+ *                             read a finished-items counter) and the call finishes
+ *                             them on the multi-workgroup path, which spreads each
+ *                             item over many CUs; iteration counts, optimizer and
+ *                             schedule state carry over, so results equal a call
+ *                             without handoff up to the rounding of the other path.
+ *                             The call then returns only when every item has
+ *                             finished (it cannot be captured in a graph).  Applies
+ *                             to the streaming, banded and windowed kernels; 0 (the
+ *                             default) turns it off.  Set it before sizing the
+ *                             workspace: a handoff call needs a larger one
+ *   dpf_autotune_reset      : forget every choice (and the team cap and handoff)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
  */
@@ -402,6 +415,7 @@ int dpf_solve_variant_for_items(int32_t n_max, int64_t items);
 int dpf_autotune_set(int32_t n_max, int variant);
 int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
 int dpf_autotune_set_team_cap(int32_t buses);
+int dpf_autotune_set_tail_handoff(int32_t items);
 void dpf_autotune_reset(void);
 
 #ifdef __cplusplus

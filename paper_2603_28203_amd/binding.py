@@ -109,6 +109,8 @@ def lib():
         L.dpf_order_rcm.restype = ctypes.c_int
         L.dpf_autotune_set_team_cap.argtypes = [_i32]
         L.dpf_autotune_set_team_cap.restype = ctypes.c_int
+        L.dpf_autotune_set_tail_handoff.argtypes = [_i32]
+        L.dpf_autotune_set_tail_handoff.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -488,6 +490,12 @@ def autotune_reset():
 def set_team_cap(buses: int):
     """Route sub-grids above `buses` to the multi-workgroup path (0 = LDS limit)."""
     _check(lib().dpf_autotune_set_team_cap(int(buses)))
+
+
+def set_tail_handoff(items: int):
+    """dpf_autotune_set_tail_handoff: finish the last `items` unfinished items of a
+    single-grid call on the multi-workgroup path (0 = off)."""
+    _check(lib().dpf_autotune_set_tail_handoff(int(items)))
 
 
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,

@@ -6,6 +6,10 @@
 
 namespace dpf {
 
+// status of an item handed over from a per-item solve kernel to the multi-workgroup
+// path (internal: that path finishes the item and overwrites the status)
+constexpr int kPaused = 4;
+
 constexpr int kWave = 64;
 constexpr int8_t kPQ = 0;
 constexpr int8_t kPV = 1;

@@ -80,6 +80,7 @@ constexpr int kGfx950LdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kSolveStaticLds = 2 * (1024 / dpf::kWave) * 8 + 256;
 
 std::atomic<int32_t> g_team_cap_override{0};
+std::atomic<int32_t> g_tail_handoff{0};  // unfinished items at which per-item kernels hand over (0 = never)
 
 int32_t max_sub_buses_for(const DeviceInfo &d) {
     int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
@@ -204,6 +205,7 @@ struct CallPlan {
     int32_t n_max = 0;  // largest sub-grid <= cap
     bool has_small = false;
     const Variant *v = nullptr;
+    int32_t handoff = 0;  // tail handoff threshold for this call (0 = none)
 };
 
 bool valid_opts(const dpf_opts_t *o) {
@@ -228,19 +230,22 @@ struct SolveLayout {
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
-           off_items = 0;
+           off_items = 0, off_list = 0, off_sched = 0;
+    int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
 
 static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
-                                int32_t ld, bool streaming, int32_t team_cap) {
+                                int32_t ld, bool streaming, int32_t team_cap, bool handoff = false) {
     SolveLayout L;
     for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
         int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
         L.n_slices += (ns + 63) / 64;
         if (ns > team_cap) L.w_total += (ns + 63) / 64;
     }
-    const bool wide = L.w_total > 0;
+    if (handoff) L.h_total = L.n_slices;
+    const bool wide = L.w_total > 0 || handoff;
+    const int32_t part_slices = std::max(L.w_total, L.h_total);
     streaming = streaming || wide;
     int64_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
     L.entries = std::min<int64_t>((int64_t)L.n_slices * 64 * wmax, (int64_t)64 * std::max<int32_t>(g->nnz, 1));
@@ -273,9 +278,15 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         L.off_mres = o;
         o += align_up(sizeof(double) * (size_t)n_sub, 256);
         L.off_part = o;
-        o += align_up(sizeof(double2) * (size_t)B * L.w_total, 256);
+        o += align_up(sizeof(double2) * (size_t)B * part_slices, 256);
         L.off_items = o;
         o += align_up(sizeof(dpf::WideItem) * (size_t)B * n_sub, 256);
+    }
+    if (handoff) {
+        L.off_list = o;  // paused items
+        o += align_up(sizeof(int32_t) * (size_t)B, 256);
+        L.off_sched = o;  // schedule state when the caller passes none [B][6]
+        o += align_up(sizeof(double) * dpf::kSchedWords * (size_t)B, 256);
     }
     L.total = o;
     return L;
@@ -285,7 +296,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
 // Runs on the device's side stream; the host enqueues chunks of iterations and
 // polls the number of active items, so this part of the call blocks the host.
 int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_sub, const int32_t *sub_offset_dev,
-             int32_t B, int32_t ld, int32_t cap, const DeviceInfo &dev) {
+             int32_t B, int32_t ld, int32_t cap, const DeviceInfo &dev, const int32_t *list = nullptr,
+             int32_t n_list = 0) {
     hipStream_t sd = dev.side;
     dpf::WideArgs w{};
     w.sell = a.sell;
@@ -295,7 +307,9 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.n_sub = n_sub;
     w.B = B;
     w.n_bus = a.n_bus;
-    w.w_total = L.w_total;
+    w.w_total = list ? L.h_total : L.w_total;
+    w.list = list;
+    w.resume = list ? 1 : 0;
     w.bt = a.bt;
     w.s_spec = a.s_spec;
     w.s_ld = a.s_ld;
@@ -305,7 +319,7 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.ld = ld;
     w.st = a.st;
     w.st_stride = a.st_stride;
-    w.st_fresh = a.st_fresh;
+    w.st_fresh = list ? 0 : a.st_fresh;  // paused items bring their moments
     w.Vg = a.scratch;
     w.aIg = a.scratch + a.st_stride;
     w.Wg = a.scratch + 2 * a.st_stride;
@@ -344,15 +358,16 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     hipLaunchKernelGGL(dpf::sub_residual_count_kernel, dim3(n_sub), dim3(256), 0, sd, n_sub, sub_offset_dev, a.n_bus,
                        a.bt, (double *)w.m_res);
     hipLaunchKernelGGL(dpf::wide_item_init_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
-    const int units = B * L.w_total;
+    const int units = (list ? n_list : B) * w.w_total;
     const int ublocks = (units + 3) / 4;
+    const int rblocks = list ? n_list : items;
     hipLaunchKernelGGL(dpf::wide_init_rows_kernel, dim3(ublocks), dim3(256), 0, sd, w);
     DPF_HIP(hipGetLastError());
     const int chunk = 32;
     for (int64_t done = 0; done <= (int64_t)a.max_iter; done += chunk) {
         for (int k = 0; k < chunk && done + k <= (int64_t)a.max_iter; ++k) {
             hipLaunchKernelGGL(dpf::wide_phase_a_kernel, dim3(ublocks), dim3(256), 0, sd, w);
-            hipLaunchKernelGGL(dpf::wide_reduce_kernel, dim3(items), dim3(dpf::kWave), 0, sd, w);
+            hipLaunchKernelGGL(dpf::wide_reduce_kernel, dim3(rblocks), dim3(dpf::kWave), 0, sd, w);
             hipLaunchKernelGGL(dpf::wide_phase_b_kernel, dim3(ublocks), dim3(256), 0, sd, w);
         }
         hipLaunchKernelGGL(dpf::wide_active_count_kernel, dim3(1), dim3(256), 0, sd, w);
@@ -670,8 +685,16 @@ int dpf_autotune_set_team_cap(int32_t buses) {
     return DPF_OK;
 }
 
+int dpf_autotune_set_tail_handoff(int32_t items) {
+    g_err.clear();
+    if (items < 0) return fail(DPF_EINVAL, "handoff threshold must be >= 0");
+    g_tail_handoff.store(items);
+    return DPF_OK;
+}
+
 void dpf_autotune_reset(void) {
     g_team_cap_override.store(0);
+    g_tail_handoff.store(0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &row : g_tune)
         for (int &x : row) x = -1;
@@ -836,6 +859,12 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
         p.n_max = 0;
         p.has_small = false;
     }
+    // tail handoff: single-grid calls whose per-item kernel keeps the state in global memory
+    const int32_t h = g_tail_handoff.load();
+    if (h > 0 && p.v && p.has_small && small == 1 && (!sub_offset || n_sub == 1) &&
+        (p.v->mode == dpf::kGlobal || p.v->mode == dpf::kBand || p.v->mode == dpf::kBandStream ||
+         p.v->mode == dpf::kWindow))
+        p.handoff = h;
     return p;
 }
 
@@ -850,7 +879,7 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
         dev.n_cu = 256;
     }
     const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev);
-    return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap).total;
+    return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap, p.handoff > 0).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -888,7 +917,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     const bool has_small = plan.has_small;
     const Variant *v = plan.v;
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
-    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap);
+    const bool handoff = plan.handoff > 0;
+    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff);
     const bool has_wide = L.w_total > 0;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -906,7 +936,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
     // so that the whole call can be captured in a graph)
     hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
-                       g->n_bus, nslice, sub_bw, bad, bad + 4);
+                       g->n_bus, nslice, sub_bw, bad, bad + 4);  // clears header words 0, 4 and 5
     hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
     if (L.n_slices > 0) {
         hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
@@ -935,6 +965,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.band_nt = 0;
     a.bad_grid = bad;
     a.queue = bad + 4;  // header word 4: the batched kernel's case queue
+    a.done_count = bad + 5;  // header word 5: finished items (tail handoff)
+    a.handoff = handoff ? plan.handoff : 0;
+    a.total_items = B * n_sub;
     a.team_cap = cap;
     if (v->mode != dpf::kReg || has_wide) {
         double *mom = (double *)(ws + L.off_mom);
@@ -946,6 +979,10 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     }
     a.st_fresh = adam_state ? 0 : 1;
     a.sched = sched_state;
+    if (handoff && !sched_state) {  // paused items carry their schedule to the multi-workgroup path
+        a.sched = (double *)(ws + L.off_sched);
+        hipLaunchKernelGGL(dpf::sched_init_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, opts->lr, a.sched);
+    }
     a.sub_off = sub_offset_dev;
     a.n_bus = g->n_bus;
     a.n_sub = n_sub;
@@ -1016,6 +1053,25 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         if (rc2 != DPF_OK) return rc2;
         DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
         DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+    }
+    if (handoff) {
+        // the items the per-item kernels paused finish on the multi-workgroup path
+        int32_t *list = (int32_t *)(ws + L.off_list);
+        int32_t *n_paused = bad + 6;  // header word 6
+        hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, st, B, a.status, list, n_paused);
+        DPF_HIP(hipGetLastError());
+        DPF_HIP(hipMemcpyAsync(dev.pinned_count, n_paused, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        DPF_HIP(hipEventRecord(dev.ev_poll, st));
+        DPF_HIP(hipEventSynchronize(dev.ev_poll));
+        const int32_t paused = *dev.pinned_count;
+        if (paused > 0) {
+            DPF_HIP(hipEventRecord(dev.ev_in, st));
+            DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
+            int rc2 = run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, list, paused);
+            if (rc2 != DPF_OK) return rc2;
+            DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
+            DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+        }
     }
     return DPF_OK;
 }

@@ -26,14 +26,16 @@ struct SellView {
 };
 
 // slices per sub-grid: ceil(n_s / 64); clears the per-sub-grid bandwidth
-// (thread 0 also clears the bad-grid flag and the case queue)
+// (thread 0 also clears the bad-grid flag and the two counters that follow
+// `queue`: the case queue and the finished-item count)
 __global__ void sell_count_kernel(int32_t n_sub, const int32_t *__restrict__ sub_off, int32_t n_bus,
                                   int32_t *__restrict__ nslice, int32_t *__restrict__ bw, int32_t *__restrict__ bad,
                                   int32_t *__restrict__ queue) {
     int32_t s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s == 0) {
         *bad = 0;
-        *queue = 0;
+        queue[0] = 0;
+        queue[1] = 0;
     }
     if (s >= n_sub) return;
     int32_t lo = sub_off ? sub_off[s] : 0;

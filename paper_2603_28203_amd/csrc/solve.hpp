@@ -63,6 +63,9 @@ struct SolveArgs {
     int32_t team_cap;        // items above this size belong to the multi-workgroup path
     const int32_t *bad_grid; // set when a row exceeded the declared width bound
     int32_t *queue;          // next unstarted case (batched windowed kernel), cleared per call
+    int32_t handoff;         // > 0: tail handoff threshold in unfinished items (see handoff_due)
+    int32_t total_items;     // items of the call
+    int32_t *done_count;     // items finished so far (handoff only), cleared per call
     int32_t n_bus;
     int32_t n_sub;
     int32_t B;
@@ -159,9 +162,25 @@ __device__ __forceinline__ void sched_step(const SolveArgs &a, ItemSched &s, dou
     }
 }
 
+// Tail handoff.  Early retirement leaves the last items of a batch alone on
+// their CUs, one workgroup each; once at most a.handoff items of the call are
+// unfinished, the per-item kernels stop them (status kPaused, state in global
+// memory, schedule in a.sched) and the host finishes them on the multi-workgroup
+// path, which spreads every item over many CUs.  Checked every 32 iterations;
+// thread 0 reads the counter and the decision reaches the workgroup through LDS.
+__device__ __forceinline__ bool handoff_due(const SolveArgs &a, int it, int *flag) {
+    if (a.handoff <= 0 || it == 0 || (it & 31) != 0) return false;
+    if (threadIdx.x == 0)
+        *flag = a.total_items - __hip_atomic_load(a.done_count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <=
+                a.handoff;
+    __syncthreads();
+    return *flag != 0;
+}
+
 // per-item results and the schedule state, written by one thread
 __device__ __forceinline__ void finish_item(const SolveArgs &a, int out_idx, int it, int stat, double mu, double loss,
                                             const ItemSched &s) {
+    if (a.handoff > 0 && stat != kPaused) atomicAdd(a.done_count, 1);
     a.iters[out_idx] = it;
     a.status[out_idx] = stat;
     a.mu_out[out_idx] = mu;
@@ -320,7 +339,12 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
 
     int it = 0, stat = DPF_MAX_ITER;
     double mu = 0.0, loss = 0.0;
+    __shared__ int pause_flag;
     for (;; ++it) {
+        if (!REG && handoff_due(a, it, &pause_flag)) {
+            stat = kPaused;
+            break;
+        }
         // ---------------- phase A: forward product, residual, loss, seed
         double lsum = 0.0, lmax = 0.0;
 #pragma unroll
@@ -600,7 +624,12 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 
     int it = 0, stat = DPF_MAX_ITER;
     double mu = 0.0, loss = 0.0;
+    __shared__ int pause_flag;
     for (;; ++it) {
+        if (handoff_due(a, it, &pause_flag)) {
+            stat = kPaused;
+            break;
+        }
         // ---------------- phase A
         double lsum = 0.0, lmax = 0.0;
         DPF_BUS_LOOP_BEGIN
@@ -823,7 +852,12 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
     const int nb = (n + BLK - 1) / BLK;
     int it = 0, stat = DPF_MAX_ITER;
     double mu = 0.0, loss = 0.0;
+    __shared__ int pause_flag;
     for (;; ++it) {
+        if (handoff_due(a, it, &pause_flag)) {
+            stat = kPaused;
+            break;
+        }
         // ---------------- A/W sweep
         double lsum = 0.0, lmax = 0.0;
         double2 hold[J];
@@ -1079,7 +1113,12 @@ __global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
     const int nb = (n + BLK - 1) / BLK;
     int it = 0, stat = DPF_MAX_ITER;
     double mu = 0.0, loss = 0.0;
+    __shared__ int pause_flag;
     for (;; ++it) {
+        if (handoff_due(a, it, &pause_flag)) {  // the point reached sits in copy it mod 2
+            stat = kPaused;
+            break;
+        }
         const int rd = it & 1;
         const double *__restrict__ vm_r = state[rd][0];
         const double *__restrict__ va_r = state[rd][1];
@@ -1597,6 +1636,31 @@ __global__ void row_broadcast_kernel(int32_t n, const double *__restrict__ src_m
     const double m = src_m[i], v = src_a[i];
     dst_m[blockIdx.y * ld + i] = m;
     dst_a[blockIdx.y * ld + i] = v;
+}
+
+// default schedule state {t, lr, best, bad + cooldown * 2^20, b1^t, b2^t} of B items
+__global__ void sched_init_kernel(int32_t B, double lr, double *__restrict__ sched) {
+    const int32_t c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B) return;
+    double *ss = sched + kSchedWords * (int64_t)c;
+    ss[0] = 0.0;
+    ss[1] = lr;
+    ss[2] = __longlong_as_double(0x7ff0000000000000LL);
+    ss[3] = 0.0;
+    ss[4] = 1.0;
+    ss[5] = 1.0;
+}
+
+// indices of the paused items (one workgroup; the order of the list is free)
+__global__ __launch_bounds__(1024) void collect_paused_kernel(int32_t n_items, const int32_t *__restrict__ status,
+                                                              int32_t *__restrict__ list, int32_t *__restrict__ count) {
+    __shared__ int n;
+    if (threadIdx.x == 0) n = 0;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n_items; i += blockDim.x)
+        if (status[i] == kPaused) list[atomicAdd(&n, 1)] = i;
+    __syncthreads();
+    if (threadIdx.x == 0) *count = n;
 }
 
 // wall-clock stamp at the start of a solve call (for per-item completion times)

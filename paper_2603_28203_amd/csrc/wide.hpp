@@ -23,7 +23,7 @@ namespace dpf {
 struct WideItem {
     double t, lr, best, b1t, b2t, loss, mu, lr_use;
     int64_t done;  // wall clock when the item stopped
-    int32_t bad, cool, iters, status, active, pad0;
+    int32_t bad, cool, iters, status, active, owned;  // owned: run (and reported) by this path
 };
 
 struct WideArgs {
@@ -60,6 +60,10 @@ struct WideArgs {
     int64_t *done_ns;
     const int64_t *stamp;
     double ns_per_tick;
+    // tail handoff (single grid): the items listed here were paused by the per-item
+    // kernels (status kPaused) and continue from their state and iteration count
+    const int32_t *list;  // [n_list] item indices, or null: every wide item
+    int32_t resume;
 };
 
 struct WideUnit {
@@ -68,8 +72,9 @@ struct WideUnit {
 
 __device__ __forceinline__ WideUnit wide_unit(const WideArgs &a, int u) {
     WideUnit w;
-    w.c = u / a.w_total;
-    w.ws = u - w.c * a.w_total;
+    const int k = u / a.w_total;
+    w.ws = u - k * a.w_total;
+    w.c = a.list ? a.list[k] : k;  // with a list the call has one sub-grid: item index = case
     w.s = find_sub(w.ws, a.n_sub, a.wide_off);
     w.lo = a.sub_off ? a.sub_off[w.s] : 0;
     w.hi = a.sub_off ? a.sub_off[w.s + 1] : a.n_bus;
@@ -111,6 +116,9 @@ __global__ void wide_item_init_kernel(WideArgs a, int32_t cap) {
     int lo = a.sub_off ? a.sub_off[s] : 0, hi = a.sub_off ? a.sub_off[s + 1] : a.n_bus;
     WideItem it{};
     it.active = (hi - lo) > cap ? 1 : 0;  // only wide items are run here
+    if (a.resume) it.active = a.status[idx] == kPaused ? 1 : 0;
+    it.owned = it.active;
+    it.iters = a.resume && it.active ? a.iters[idx] : 0;
     it.t = 0.0;
     it.lr = a.lr;
     it.best = __longlong_as_double(0x7ff0000000000000LL);
@@ -197,9 +205,9 @@ __global__ __launch_bounds__(256) void wide_phase_a_kernel(WideArgs a) {
     if (lane == 0) a.part[(int64_t)w.c * a.w_total + w.ws] = make_double2(lsum, lmax);
 }
 
-// one wave per item
+// one wave per item (per listed item)
 __global__ __launch_bounds__(kWave) void wide_reduce_kernel(WideArgs a) {
-    const int idx = blockIdx.x;
+    const int idx = a.list ? a.list[blockIdx.x] : blockIdx.x;
     WideItem it = a.items[idx];
     if (!it.active) return;
     const int c = idx / a.n_sub, s = idx - c * a.n_sub;
@@ -321,10 +329,8 @@ __global__ __launch_bounds__(256) void wide_active_count_kernel(WideArgs a) {
 __global__ void wide_finish_kernel(WideArgs a, int32_t cap) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= a.B * a.n_sub) return;
-    int s = idx % a.n_sub;
-    int lo = a.sub_off ? a.sub_off[s] : 0, hi = a.sub_off ? a.sub_off[s + 1] : a.n_bus;
-    if ((hi - lo) <= cap) return;
     WideItem it = a.items[idx];
+    if (!it.owned) return;
     a.iters[idx] = it.iters;
     a.status[idx] = it.status;
     a.mu_out[idx] = it.mu;

@@ -1396,3 +1396,102 @@ def test_batched_falls_back_for_sub_grids_and_wide_band(tuned):
         assert out["iters"].tolist() == [steps, steps]
         assert np.abs(vm[0, :n].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
         assert np.abs(vm[0, n:].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
+
+
+# ---------------------------------------------------------------- tail handoff
+
+
+@pytest.fixture
+def handoff(dpf):
+    yield dpf
+    dpf.set_tail_handoff(0)
+    dpf.autotune_reset()
+
+
+@pytest.mark.parametrize("kind", ["banded-stream", "streaming", "banded-window"])
+@pytest.mark.parametrize("threshold", [5, 64])
+def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold):
+    """Items paused by the per-item kernel (every item when the threshold is at
+    least the batch, else once enough items have stopped) finish on the
+    multi-workgroup path: iterates, statuses, iteration counts and the plateau
+    schedule equal the oracle's and the results of the same call without
+    handoff."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9700, n_bus=700, n_branch=1120, n_pv=110)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 8
+    rng = np.random.default_rng(97)
+    S = np.tile(S0, (B, 1))
+    S[1, 7] = np.nan
+    S[5, 3] = np.nan
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.where(np.arange(B) % 2 == 0, -1, rng.choice(nbr, B)).astype(np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm0[3], va0[3] = g.vm, g.va
+    outage[3] = -1
+    steps = 100
+    pl = dict(sched=oracle.SCHED_PLATEAU, factor=0.5, patience=3, threshold=0.2, cooldown=2)
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=1e-9, max_iter=steps, **pl)) for c in range(B)]
+    assert [r["status"] for r in refs] == [1, 2, 1, 0, 1, 2, 1, 1]
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == kind and
+         (x["buses_per_thread"] == 0 or x["threads"] * x["buses_per_thread"] >= 256)][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    opts = dpf.Options(lr=1e-3, tol=1e-9, max_iter=steps, **pl)
+    res = {}
+    for h in (0, threshold):
+        dpf.set_tail_handoff(h)
+        print(f"handoff {h} variant {v}", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        sch = torch.tensor([[0.0, 1e-3, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        sched_state=sch, opts=opts)
+        torch.cuda.synchronize()
+        assert out["status"].tolist() == [r["status"] for r in refs], h
+        assert out["iters"].tolist() == [r["iters"] for r in refs], h
+        for c in range(B):
+            if refs[c]["status"] == 2:
+                continue
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, (h, c)
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, (h, c)
+            assert sch[c, 1].item() == pytest.approx(refs[c]["lr"], rel=1e-15)
+            assert sch[c, 0].item() == refs[c]["iters"]
+        res[h] = (vm.cpu().numpy(), va.cpu().numpy(), out["max_mis"].cpu().numpy(), out["done_ns"].cpu().numpy())
+    d = max(np.abs(res[0][0] - res[threshold][0]).max(), np.abs(res[0][1] - res[threshold][1]).max())
+    print(f"handoff vs plain: max |diff| {d:.3e}", flush=True)
+    assert d < 1e-12
+    assert (res[threshold][3][[0, 2, 4, 6, 7]] > 0).all()
+
+
+def test_tail_handoff_with_caller_moments_and_resume(handoff):
+    """With the caller's optimizer state, a handed-over call continues exactly
+    like a call without handoff when resumed (two half calls)."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9701, n_bus=600, n_branch=960, n_pv=100)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 4
+    rng = np.random.default_rng(98)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=70, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=4,
+                       threshold=0.1)
+    out = {}
+    for h in (0, 8):
+        dpf.set_tail_handoff(h)
+        vm = cu(vm0); va = cu(va0)
+        st = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
+        sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+        dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=opts, adam_state=st, sched_state=sch)
+        dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=opts, adam_state=st, sched_state=sch)
+        torch.cuda.synchronize()
+        assert sch[:, 0].tolist() == [140.0] * B
+        out[h] = (vm.cpu().numpy(), va.cpu().numpy(), st.cpu().numpy(), sch.cpu().numpy())
+    for k in range(4):
+        assert np.abs(out[0][k] - out[8][k]).max() <= 1e-12 * max(1.0, np.abs(out[0][k]).max())
