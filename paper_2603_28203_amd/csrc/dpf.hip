@@ -359,6 +359,7 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
                        a.bt, (double *)w.m_res);
     hipLaunchKernelGGL(dpf::wide_item_init_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
     const int units = (list ? n_list : B) * w.w_total;
+    w.n_units = units;  // the spare waves of the last block must not read past the list
     const int ublocks = (units + 3) / 4;
     const int rblocks = list ? n_list : items;
     hipLaunchKernelGGL(dpf::wide_init_rows_kernel, dim3(ublocks), dim3(256), 0, sd, w);

@@ -64,6 +64,7 @@ struct WideArgs {
     // kernels (status kPaused) and continue from their state and iteration count
     const int32_t *list;  // [n_list] item indices, or null: every wide item
     int32_t resume;
+    int32_t n_units;      // (n_list, or B) * w_total: one wave per unit
 };
 
 struct WideUnit {
@@ -143,7 +144,7 @@ __global__ void wide_item_init_kernel(WideArgs a, int32_t cap) {
 // V = vm e^{j va} for every row of the wide items; fresh moments cleared
 __global__ __launch_bounds__(256) void wide_init_rows_kernel(WideArgs a) {
     int u = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (u >= a.B * a.w_total) return;
+    if (u >= a.n_units) return;
     WideUnit w = wide_unit(a, u);
     int r = w.lo + (w.ws - a.wide_off[w.s]) * kWave + (threadIdx.x & (kWave - 1));
     if (r >= w.hi) return;
@@ -172,7 +173,7 @@ __device__ __forceinline__ double2 wide_outage_term(const WideArgs &a, int c, in
 
 __global__ __launch_bounds__(256) void wide_phase_a_kernel(WideArgs a) {
     int u = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (u >= a.B * a.w_total) return;
+    if (u >= a.n_units) return;
     WideUnit w = wide_unit(a, u);
     const int idx = w.c * a.n_sub + w.s;
     if (!a.items[idx].active) return;
@@ -271,7 +272,7 @@ __global__ __launch_bounds__(kWave) void wide_reduce_kernel(WideArgs a) {
 
 __global__ __launch_bounds__(256) void wide_phase_b_kernel(WideArgs a) {
     int u = blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-    if (u >= a.B * a.w_total) return;
+    if (u >= a.n_units) return;
     WideUnit w = wide_unit(a, u);
     const int idx = w.c * a.n_sub + w.s;
     const WideItem &it = a.items[idx];
