@@ -107,6 +107,47 @@ def test_variant_table_and_autotune_cache(lib):
     assert lib.dpf_autotune_set(9241, d) == 0
     lib.dpf_autotune_reset()
     assert lib.dpf_solve_variant_for(14) == 0
+    # cases per workgroup: 1 except for the batched kind, whose info reports 1 bus per thread
+    kinds = []
+    for i in range(n):
+        lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st))
+        kinds.append((st.value, k.value, lib.dpf_solve_variant_cases(i)))
+    assert any(c > 1 for s, _, c in kinds if s == 6)
+    assert all(c == 1 for s, _, c in kinds if s != 6) and all(b == 1 for s, b, _ in kinds if s == 6)
+    assert lib.dpf_solve_variant_cases(n) == -1 and lib.dpf_solve_variant_cases(-1) == -1
+
+
+def test_tail_handoff_setting_and_workspace(lib):
+    """dpf_autotune_set_tail_handoff validates its argument, is undone by the
+    reset, and a call that may hand over needs the larger workspace (the paused
+    item list, a schedule buffer and the multi-workgroup arrays)."""
+    lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
+    lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_int32]
+    g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
+    lib.dpf_autotune_reset()
+    band = [i for i in range(lib.dpf_solve_variant_count()) if _kind(lib, i) == 3][0]
+    assert lib.dpf_autotune_set(9241, band) == 0
+    plain = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
+    assert lib.dpf_autotune_set_tail_handoff(-1) == -1
+    assert lib.dpf_autotune_set_tail_handoff(192) == 0
+    handed = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
+    slices = (9241 + 63) // 64
+    assert handed - plain >= 1024 * (4 + 6 * 8 + slices * 16)
+    # sub-grids never hand over: same size with and without the setting
+    sub = (ctypes.c_int32 * 3)(0, 5000, 9241)
+    with_sub = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241)
+    lib.dpf_autotune_reset()  # also clears the handoff
+    assert lib.dpf_autotune_set(9241, band) == 0
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == plain
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241) == with_sub
+    lib.dpf_autotune_reset()
+
+
+def _kind(lib, i):
+    t, k, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st))
+    return st.value
 
 
 # ---------------------------------------------------------------- bus ordering (host code)
