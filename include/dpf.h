@@ -403,6 +403,7 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             to the streaming, banded and windowed kernels; 0 (the
  *                             default) turns it off.  Set it before sizing the
  *                             workspace: a handoff call needs a larger one
+ *   dpf_tail_handoff        : the current handoff threshold (0 = off)
  *   dpf_autotune_reset      : forget every choice (and the team cap and handoff)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
@@ -416,6 +417,7 @@ int dpf_autotune_set(int32_t n_max, int variant);
 int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
 int dpf_autotune_set_team_cap(int32_t buses);
 int dpf_autotune_set_tail_handoff(int32_t items);
+int32_t dpf_tail_handoff(void);
 void dpf_autotune_reset(void);
 
 #ifdef __cplusplus

@@ -111,6 +111,7 @@ def lib():
         L.dpf_autotune_set_team_cap.restype = ctypes.c_int
         L.dpf_autotune_set_tail_handoff.argtypes = [_i32]
         L.dpf_autotune_set_tail_handoff.restype = ctypes.c_int
+        L.dpf_tail_handoff.restype = _i32
         _lib = L
     return _lib
 
@@ -498,6 +499,11 @@ def set_tail_handoff(items: int):
     _check(lib().dpf_autotune_set_tail_handoff(int(items)))
 
 
+def tail_handoff() -> int:
+    """The current tail handoff threshold (0 = off)."""
+    return int(lib().dpf_tail_handoff())
+
+
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,
              iters: int = 40, reps: int = 2, tie: float = 0.0):
     """Time every kernel variant that can hold the largest sub-grid on copies of
@@ -511,6 +517,19 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     items = int(vm.shape[0]) * (1 if sub_offset is None else len(sub_offset) - 1)
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
     times = {}
+    handoff = tail_handoff()  # timed without it: fixed-length launches would hand every item over
+    set_tail_handoff(0)
+    try:
+        _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, items, reps, times)
+    finally:
+        set_tail_handoff(handoff)
+    best = min(times.values())
+    pick = min(i for i, t in times.items() if t <= best * (1.0 + tie))
+    _check(lib().dpf_autotune_set_items(n_max, items, pick))
+    return {"choice": pick, "seconds": times, "n_max": n_max, "items": items, "iters": iters}
+
+
+def _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, items, reps, times):
     for v in variants():
         if not (v["kind"].startswith("banded") or v["buses_per_thread"] == 0
                 or v["threads"] * v["buses_per_thread"] >= n_max):
@@ -529,7 +548,3 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
             dt = st.elapsed_time(en) * 1e-3
             best = dt if best is None else min(best, dt)
         times[v["index"]] = best
-    best = min(times.values())
-    pick = min(i for i, t in times.items() if t <= best * (1.0 + tie))
-    _check(lib().dpf_autotune_set_items(n_max, items, pick))
-    return {"choice": pick, "seconds": times, "n_max": n_max, "items": items, "iters": iters}

@@ -686,6 +686,8 @@ int dpf_autotune_set_team_cap(int32_t buses) {
     return DPF_OK;
 }
 
+int32_t dpf_tail_handoff(void) { return g_tail_handoff.load(); }
+
 int dpf_autotune_set_tail_handoff(int32_t items) {
     g_err.clear();
     if (items < 0) return fail(DPF_EINVAL, "handoff threshold must be >= 0");

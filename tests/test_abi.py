@@ -131,6 +131,7 @@ def test_tail_handoff_setting_and_workspace(lib):
     plain = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
     assert lib.dpf_autotune_set_tail_handoff(-1) == -1
     assert lib.dpf_autotune_set_tail_handoff(192) == 0
+    assert lib.dpf_tail_handoff() == 192
     handed = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
     slices = (9241 + 63) // 64
     assert handed - plain >= 1024 * (4 + 6 * 8 + slices * 16)
@@ -138,6 +139,7 @@ def test_tail_handoff_setting_and_workspace(lib):
     sub = (ctypes.c_int32 * 3)(0, 5000, 9241)
     with_sub = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241)
     lib.dpf_autotune_reset()  # also clears the handoff
+    assert lib.dpf_tail_handoff() == 0
     assert lib.dpf_autotune_set(9241, band) == 0
     assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == plain
     assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241) == with_sub
