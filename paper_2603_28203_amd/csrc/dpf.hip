@@ -230,7 +230,7 @@ struct SolveLayout {
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
-           off_items = 0, off_list = 0, off_sched = 0;
+           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0;
     int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
@@ -283,7 +283,9 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(dpf::WideItem) * (size_t)B * n_sub, 256);
     }
     if (handoff) {
-        L.off_list = o;  // paused items
+        L.off_list = o;  // paused items, and the list compacted as they finish
+        o += align_up(sizeof(int32_t) * (size_t)B, 256);
+        L.off_list2 = o;
         o += align_up(sizeof(int32_t) * (size_t)B, 256);
         L.off_sched = o;  // schedule state when the caller passes none [B][6]
         o += align_up(sizeof(double) * dpf::kSchedWords * (size_t)B, 256);
@@ -358,10 +360,10 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     hipLaunchKernelGGL(dpf::sub_residual_count_kernel, dim3(n_sub), dim3(256), 0, sd, n_sub, sub_offset_dev, a.n_bus,
                        a.bt, (double *)w.m_res);
     hipLaunchKernelGGL(dpf::wide_item_init_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
-    const int units = (list ? n_list : B) * w.w_total;
+    int units = (list ? n_list : B) * w.w_total;
     w.n_units = units;  // the spare waves of the last block must not read past the list
-    const int ublocks = (units + 3) / 4;
-    const int rblocks = list ? n_list : items;
+    int ublocks = (units + 3) / 4;
+    int rblocks = list ? n_list : items;
     hipLaunchKernelGGL(dpf::wide_init_rows_kernel, dim3(ublocks), dim3(256), 0, sd, w);
     DPF_HIP(hipGetLastError());
     const int chunk = 32;
@@ -371,12 +373,29 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
             hipLaunchKernelGGL(dpf::wide_reduce_kernel, dim3(rblocks), dim3(dpf::kWave), 0, sd, w);
             hipLaunchKernelGGL(dpf::wide_phase_b_kernel, dim3(ublocks), dim3(256), 0, sd, w);
         }
-        hipLaunchKernelGGL(dpf::wide_active_count_kernel, dim3(1), dim3(256), 0, sd, w);
+        // with a list, the poll also drops the finished items from it (into the other
+        // list buffer), so that the launches shrink as items finish
+        int32_t *next = nullptr;
+        if (list) {
+            next = (int32_t *)(list == (const int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
+            hipLaunchKernelGGL(dpf::wide_compact_kernel, dim3(1), dim3(1024), 0, sd, w, rblocks, next);
+        } else {
+            hipLaunchKernelGGL(dpf::wide_active_count_kernel, dim3(1), dim3(256), 0, sd, w);
+        }
         DPF_HIP(hipGetLastError());
         DPF_HIP(hipMemcpyAsync(dev.pinned_count, w.active_count, sizeof(int32_t), hipMemcpyDeviceToHost, sd));
         DPF_HIP(hipEventRecord(dev.ev_poll, sd));
         DPF_HIP(hipEventSynchronize(dev.ev_poll));
-        if (*dev.pinned_count == 0) break;
+        const int32_t active = *dev.pinned_count;
+        if (active == 0) break;
+        if (list) {
+            list = next;
+            w.list = next;
+            rblocks = active;
+            units = active * w.w_total;
+            w.n_units = units;
+            ublocks = (units + 3) / 4;
+        }
     }
     hipLaunchKernelGGL(dpf::wide_finish_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
     DPF_HIP(hipGetLastError());

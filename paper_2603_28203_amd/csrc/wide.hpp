@@ -326,6 +326,20 @@ __global__ __launch_bounds__(256) void wide_active_count_kernel(WideArgs a) {
     if (threadIdx.x == 0) *a.active_count = part[0] + part[1] + part[2] + part[3];
 }
 
+// the still active entries of a list of n items (one workgroup), written to out;
+// their number goes to *a.active_count
+__global__ __launch_bounds__(1024) void wide_compact_kernel(WideArgs a, int32_t n, int32_t *__restrict__ out) {
+    __shared__ int cnt;
+    if (threadIdx.x == 0) cnt = 0;
+    __syncthreads();
+    for (int32_t i = threadIdx.x; i < n; i += blockDim.x) {
+        const int32_t idx = a.list[i];
+        if (a.items[idx].active) out[atomicAdd(&cnt, 1)] = idx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) *a.active_count = cnt;
+}
+
 // outputs of the wide items
 __global__ void wide_finish_kernel(WideArgs a, int32_t cap) {
     int idx = blockIdx.x * blockDim.x + threadIdx.x;
