@@ -27,6 +27,7 @@ import dataclasses
 import hashlib
 import json
 import os
+import re
 import sys
 import time
 
@@ -49,13 +50,16 @@ def log(msg):
 
 def kernel_source_hash() -> str:
     """Hash of the device-code headers (the kernels; host code and the launch
-    table live in dpf.hip, and the launch shape is part of the kernel name)."""
+    table live in dpf.hip, and the launch shape is part of the kernel name),
+    with comments and blank space removed: edits to comments leave it alone."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_28203_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         if f.endswith(".hpp"):
-            with open(os.path.join(csrc, f), "rb") as fh:
-                h.update(fh.read())
+            with open(os.path.join(csrc, f)) as fh:
+                text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
+            text = re.sub(r"//[^\n]*", "", text)
+            h.update(re.sub(r"\s+", " ", text).strip().encode())
     return h.hexdigest()[:16]
 
 
