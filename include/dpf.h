@@ -401,8 +401,10 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             The call then returns only when every item has
  *                             finished (it cannot be captured in a graph).  Applies
  *                             to the streaming, banded and windowed kernels; 0 (the
- *                             default) turns it off.  Set it before sizing the
- *                             workspace: a handoff call needs a larger one
+ *                             default) turns it off.  A call of at most `items`
+ *                             items is handed over after its first 32 iterations.
+ *                             Set it before sizing the workspace: a handoff call
+ *                             needs a larger one
  *   dpf_tail_handoff        : the current handoff threshold (0 = off)
  *   dpf_autotune_reset      : forget every choice (and the team cap and handoff)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
