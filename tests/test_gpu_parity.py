@@ -1495,3 +1495,51 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff):
         out[h] = (vm.cpu().numpy(), va.cpu().numpy(), st.cpu().numpy(), sch.cpu().numpy())
     for k in range(4):
         assert np.abs(out[0][k] - out[8][k]).max() <= 1e-12 * max(1.0, np.abs(out[0][k]).max())
+
+
+def test_bench_configuration_at_full_size_with_handoff(handoff):
+    """The bench's launch configuration at its full size: 1024 outage cases of
+    the 9241-bus grid (degree-grouped RCM numbering), the 1024 x 4 banded-stream
+    kernel, the bench's optimizer settings and a tail handoff at 192 cases.  900
+    cases carry a non-finite injection and stop at once, so the other 124 are
+    handed over after 32 iterations; sampled cases equal their oracle solves."""
+    dpf = handoff
+    cfg = synth.config2(B=1024)
+    base = cfg["grid"]
+    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t, group=256)
+    g = renumber(base, perm)
+    B, n = 1024, g.n_bus
+    rng = np.random.default_rng(2024)
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    S = np.tile(S0, (B, 1))
+    finite = np.sort(rng.choice(B, 124, replace=False))
+    nonfinite = np.setdiff1d(np.arange(B), finite)
+    S[nonfinite, 11] = np.nan
+    vm0 = g.vm[None] + rng.normal(0, 1e-3, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-3, (B, n)) * (g.bus_type != 2)
+    # the outages as the bench draws them, in the renumbered indices (branch order is kept)
+    outage = cfg["outage"].astype(np.int32)
+    steps = 40
+    o = dict(lr=1e-4, beta1=0.995, beta2=0.995, eps=1e-14, sched=oracle.SCHED_PLATEAU, factor=0.5,
+             patience=300, threshold=1e-3)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024
+         and x["buses_per_thread"] == 4][0]
+    assert bw <= 4096
+    dpf.lib().dpf_autotune_set(n, v["index"])
+    dpf.set_tail_handoff(192)
+    Yg = dgrid(dpf, g)
+    print(f"full-size handoff test: n={n} bw={bw} variant={v}", flush=True)
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+    torch.cuda.synchronize()
+    st = out["status"].cpu().numpy()
+    it = out["iters"].cpu().numpy()
+    assert (st[nonfinite] == 2).all() and (it[nonfinite] == 0).all()
+    assert (st[finite] == 1).all() and (it[finite] == steps).all()
+    for c in finite[::25]:
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+        assert abs(out["max_mis"][c].item() - ref["mu"]) <= 1e-8 * ref["mu"], c
