@@ -169,7 +169,7 @@ def cpu_baseline_cfg2(g, out_idx, n_cases, iters, S_host, opts):
 
     import oracle
 
-    cores = min(os.cpu_count() or 1, 16)  # the host share of one GPU machine
+    cores = min(os.cpu_count() or 1, 16)  # at most 16 worker threads
     Ys = [oracle.ybus_of(g, skip=int(k)) for k in out_idx[:n_cases]]
     o = oracle.AdamOptions(lr=opts.lr, beta1=opts.beta1, beta2=opts.beta2, eps=opts.eps, tol=0.0,
                            max_iter=iters, sched=oracle.SCHED_PLATEAU, factor=opts.factor,
