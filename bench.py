@@ -295,6 +295,10 @@ def main():
                 "traffic": None if traffic is None else round(traffic / kf[0] / 1e9, 1),
                 "alg_bytes_per_launch": steady_bytes, "launch_s": round(kf[0], 5),
                 "ms_per_iter": round(kf[0] / 200 * 1e3, 4)}
+    copy_gbs = copy_bandwidth()
+    roofline["copy_peak"] = {"what": "plain 1 GiB device copy on this GPU (read + write)",
+                             "GBps": round(copy_gbs, 1), "frac_achieved": round(steady / copy_gbs, 4),
+                             "frac_traffic": None if traffic is None else round(traffic / kf[0] / 1e9 / copy_gbs, 4)}
     solve_rate = {"what": "the timed solve call: per-item kernel, early retirement, then the last "
                           f"{args.handoff} cases on the multi-workgroup path",
                   "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
@@ -564,6 +568,28 @@ def copy_calibration(nbytes=1 << 30, reps=3):
         dst.copy_(src)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes, "reps": reps}), flush=True)
+
+
+def copy_bandwidth(nbytes=1 << 30, reps=5):
+    """Bandwidth of a plain 1 GiB device-to-device copy (bytes read + written over
+    the best of `reps` copies timed with HIP events): the achievable HBM rate."""
+    import torch
+
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = None
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        t = e0.elapsed_time(e1) * 1e-3
+        best = t if best is None else min(best, t)
+    del src, dst
+    return 2 * nbytes / best / 1e9
 
 
 def cfg1_comparison(iters=2000):
