@@ -18,7 +18,10 @@
  *    2 = slack (V specified, angle 0) -- the three bus kinds of Sec. 2.1.
  *    Exactly one slack per grid (per sub-grid for concatenated grids).
  *  - Every call is ordered on `stream` (a hipStream_t; NULL = default stream)
- *    and returns after enqueueing, unless documented as synchronising.
+ *    and returns after enqueueing, unless documented as synchronising.  The
+ *    synchronising parts of dpf_solve_batch (multi-workgroup items, tail
+ *    handoff) use one side stream per device; concurrent such calls on one
+ *    device take turns.
  *  - Return value: DPF_OK (0) or a negative error code; dpf_last_error()
  *    returns a text for the calling thread's last error.  On error nothing
  *    has been enqueued, except for DPF_EHIP, which reports a HIP runtime

@@ -45,9 +45,13 @@ struct DeviceInfo {
     hipStream_t side = nullptr;      // stream of the multi-workgroup path
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
     int32_t *pinned_count = nullptr; // host-pinned poll target
+    int index = 0;
 };
 std::mutex g_dev_mu;
 DeviceInfo g_dev[64];
+// the side stream, its events and the poll word are per device: calls that use them
+// (multi-workgroup items, tail handoff) hold this lock while they do
+std::mutex g_side_mu[64];
 
 int device_info(DeviceInfo &out) {
     int dev = 0;
@@ -68,6 +72,7 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_out, hipEventDisableTiming));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_poll, hipEventDisableTiming));
         DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, sizeof(int32_t), hipHostMallocDefault));
+        g_dev[dev].index = dev;
         g_dev[dev].ok = true;
     }
     out = g_dev[dev];
@@ -1038,6 +1043,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.lds_cap = entries;
     const size_t lds_bytes = (size_t)entries * 16;
     const int32_t items = B * n_sub;
+    std::unique_lock<std::mutex> side_lock;  // concurrent blocking calls on one device take turns
+    if (has_wide || handoff) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
     if (has_wide) {
         DPF_HIP(hipEventRecord(dev.ev_in, st));
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
