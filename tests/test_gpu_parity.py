@@ -1543,3 +1543,49 @@ def test_bench_configuration_at_full_size_with_handoff(handoff):
         assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
         assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
         assert abs(out["max_mis"][c].item() - ref["mu"]) <= 1e-8 * ref["mu"], c
+
+
+def test_concurrent_handoff_calls_on_two_streams(handoff):
+    """Two host threads, each with its own stream and workspace, run solves that
+    hand their tail over at the same time; each result equals the same call run
+    alone (the side stream of the device is shared and taken in turns)."""
+    import threading
+    dpf = handoff
+    base = synth.config1(B=1, seed=9800, n_bus=700, n_branch=1120, n_pv=110)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    dpf.set_tail_handoff(64)
+    B = 6
+    starts = []
+    for seed in (1, 2):
+        rng = np.random.default_rng(9800 + seed)
+        starts.append((g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0),
+                       g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)))
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=300)
+    Sd = cu(S, torch.complex128)
+
+    def run(k, out):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            vm = cu(starts[k][0]); va = cu(starts[k][1])
+            r = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=opts, workspace=dpf.SolveWorkspace())
+            stream.synchronize()
+            out[k] = (vm.cpu().numpy(), va.cpu().numpy(), r["iters"].cpu().numpy())
+
+    alone = {}
+    for k in (0, 1):
+        run(k, alone)
+    together = {}
+    th = [threading.Thread(target=run, args=(k, together)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert sorted(together) == [0, 1]
+    for k in (0, 1):
+        assert together[k][2].tolist() == [300] * B
+        assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12
+        assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12
