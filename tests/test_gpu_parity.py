@@ -1589,3 +1589,46 @@ def test_concurrent_handoff_calls_on_two_streams(handoff):
         assert together[k][2].tolist() == [300] * B
         assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12
         assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_grids_on_default_and_banded_paths(tuned, seed):
+    """Seeded random grids (20 to 2500 buses, branch ratio 1.3 to 1.9, 5% to 40%
+    PV buses), 1 to 5 cases with random outages and per-case S_spec: the default
+    routing and one randomly drawn banded, windowed or batched variant (on the
+    small-bandwidth numbering) both follow the oracle for a few steps."""
+    dpf = tuned
+    rng = np.random.default_rng(31000 + seed)
+    n = int(rng.integers(20, 2500))
+    m = int(n * rng.uniform(1.3, 1.9))
+    n_pv = max(1, int(n * rng.uniform(0.05, 0.4)))
+    base = synth.config1(B=1, seed=32000 + seed, n_bus=n, n_branch=m, n_pv=n_pv)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    B = int(rng.integers(1, 6))
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    S = S0[None] * rng.uniform(0.97, 1.03, (B, 1))
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.where(rng.random(B) < 0.7, rng.choice(nbr, B), -1).astype(np.int32) if len(nbr) else \
+        np.full(B, -1, np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type != 2)
+    steps = int(rng.integers(3, 12))
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
+    Yg = dgrid(dpf, g)
+    banded = [v for v in dpf.variants() if v["kind"] in ("banded", "banded-stream", "banded-window",
+                                                          "banded-batched")]
+    pick = banded[int(rng.integers(len(banded)))]
+    for choice in (None, pick):
+        dpf.autotune_reset()
+        if choice is not None:
+            dpf.lib().dpf_autotune_set(n, choice["index"])
+        print(f"random grid seed {seed}: n={n} m={m} pv={n_pv} B={B} steps={steps} variant={choice}", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+        torch.cuda.synchronize()
+        assert out["iters"].tolist() == [steps] * B
+        for c in range(B):
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, (choice, c)
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, (choice, c)
