@@ -1499,14 +1499,14 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff):
 
 def test_bench_configuration_at_full_size_with_handoff(handoff):
     """The bench's launch configuration at its full size: 1024 outage cases of
-    the 9241-bus grid (degree-grouped RCM numbering), the 1024 x 4 banded-stream
+    the 9241-bus grid (RCM numbering degree-grouped in windows of 2560), the 1024 x 4 banded-stream
     kernel, the bench's optimizer settings and a tail handoff at 192 cases.  900
     cases carry a non-finite injection and stop at once, so the other 124 are
     handed over after 32 iterations; sampled cases equal their oracle solves."""
     dpf = handoff
     cfg = synth.config2(B=1024)
     base = cfg["grid"]
-    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t, group=256)
+    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t, group=2560)
     g = renumber(base, perm)
     B, n = 1024, g.n_bus
     rng = np.random.default_rng(2024)
