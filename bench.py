@@ -42,9 +42,13 @@ HBM_PEAK_GBS = 8000.0
 # sliced-ELL padding to 1.04x the nonzeros; measured 0.34 ms per batch iteration against
 # 0.41 at a window of 256 (padding 1.25x)
 BUS_ORDER_GROUP = 2560
-# the last 192 unfinished cases of the N-1 batch finish on the multi-workgroup path
-# (dpf_autotune_set_tail_handoff); measured 128..192 best, 0 = off
+# the last 192 unfinished cases of the N-1 batch leave the per-item kernel
+# (dpf_autotune_set_tail_handoff); measured 128..256 best, 0 = off
 TAIL_HANDOFF = 192
+# ... and finish on the split kernel in teams of up to 8 workgroups, relaunched every
+# 128 iterations, until 32 are left, then on the multi-workgroup path, whose latency
+# per iteration is lower for a few cases (dpf_autotune_set_tail_team)
+TAIL_TEAM = (8, 128, 32)
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -210,7 +214,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--cap", type=int, default=60000, help="Adam iteration cap per case")
     ap.add_argument("--handoff", type=int, default=TAIL_HANDOFF,
-                    help="unfinished cases handed to the multi-workgroup path (0 = off)")
+                    help="unfinished cases handed over by the per-item kernel (0 = off)")
+    ap.add_argument("--tail-team", type=str, default=":".join(map(str, TAIL_TEAM)),
+                    help="max_team:chunk:min_items of the split kernel for handed-over cases (0:1:0 = off)")
     ap.add_argument("--cases", type=int, default=1024)
     ap.add_argument("--quick", action="store_true", help="small cap, no baselines (smoke of the harness)")
     ap.add_argument("--no-autograd", action="store_true")
@@ -264,6 +270,8 @@ def main():
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
         f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
     dpf.set_tail_handoff(args.handoff)
+    tail_team = [int(x) for x in args.tail_team.split(":")]
+    dpf.set_tail_team(*tail_team)
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
     t_step = float(np.mean(times))
     t_kern = float(np.mean(kern))
@@ -328,6 +336,7 @@ def main():
                                 f"(dpf_order_rcm; bandwidth {cfg['bandwidth']})",
                    "kernel_variant": vinfo,
                    "tail_handoff": args.handoff,
+                   "tail_team": {"max_team": tail_team[0], "chunk": tail_team[1], "min_items": tail_team[2]},
                    "optimizer": {"lr": opts.lr, "betas": [opts.beta1, opts.beta2], "eps": opts.eps,
                                  "schedule": "plateau", "factor": opts.factor, "patience": opts.patience,
                                  "threshold": opts.threshold}},

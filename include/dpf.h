@@ -409,7 +409,28 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             Set it before sizing the workspace: a handoff call
  *                             needs a larger one
  *   dpf_tail_handoff        : the current handoff threshold (0 = off)
- *   dpf_autotune_reset      : forget every choice (and the team cap and handoff)
+ *   dpf_autotune_set_tail_team : how handed-over items finish.  max_team > 0: the
+ *                             split kernel, which gives each item a team of
+ *                             T = min(max_team, W / items left, slices of the grid)
+ *                             workgroups (W = workgroups of it the device holds at
+ *                             once; each member keeps the exchange vector in LDS
+ *                             and the team synchronises through global memory
+ *                             twice per iteration), relaunched every `chunk`
+ *                             iterations (1..65536) with larger teams as items
+ *                             finish, while more than min_items (>= 0) items are
+ *                             left; the multi-workgroup path finishes the rest
+ *                             (its few-item latency is lower).  A team member that waits at a barrier longer
+ *                             than 1 s (first barrier of a launch: other work may
+ *                             hold the CUs) or 5 s abandons it; the items not yet
+ *                             finished then continue on the multi-workgroup path.
+ *                             max_team = 0 (the default): the multi-workgroup path
+ *                             only.  Returns DPF_EINVAL for arguments out of range
+ *   dpf_tail_team           : the current max_team (0 = multi-workgroup path)
+ *   dpf_tail_split_stats    : split-kernel launches, and launches in which a team
+ *                             abandoned a barrier, since the library was loaded
+ *                             (either pointer may be null)
+ *   dpf_autotune_reset      : forget every choice (and the team cap, handoff and
+ *                             tail team settings)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
  */
@@ -423,6 +444,9 @@ int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
 int dpf_autotune_set_team_cap(int32_t buses);
 int dpf_autotune_set_tail_handoff(int32_t items);
 int32_t dpf_tail_handoff(void);
+int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items);
+int32_t dpf_tail_team(void);
+void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned);
 void dpf_autotune_reset(void);
 
 #ifdef __cplusplus

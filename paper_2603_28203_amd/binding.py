@@ -112,6 +112,11 @@ def lib():
         L.dpf_autotune_set_tail_handoff.argtypes = [_i32]
         L.dpf_autotune_set_tail_handoff.restype = ctypes.c_int
         L.dpf_tail_handoff.restype = _i32
+        L.dpf_autotune_set_tail_team.argtypes = [_i32, _i32, _i32]
+        L.dpf_autotune_set_tail_team.restype = ctypes.c_int
+        L.dpf_tail_team.restype = _i32
+        L.dpf_tail_split_stats.argtypes = [_P, _P]
+        L.dpf_tail_split_stats.restype = None
         _lib = L
     return _lib
 
@@ -502,6 +507,26 @@ def set_tail_handoff(items: int):
 def tail_handoff() -> int:
     """The current tail handoff threshold (0 = off)."""
     return int(lib().dpf_tail_handoff())
+
+
+def set_tail_team(max_team: int, chunk: int = 128, min_items: int = 0):
+    """dpf_autotune_set_tail_team: finish handed-over items on the split kernel,
+    with at most ``max_team`` workgroups per item, relaunched every ``chunk``
+    iterations while more than ``min_items`` items are left; the
+    multi-workgroup path takes the rest (max_team 0 = that path only)."""
+    _check(lib().dpf_autotune_set_tail_team(int(max_team), int(chunk), int(min_items)))
+
+
+def tail_team() -> int:
+    """The current most workgroups per handed-over item (0 = multi-workgroup path)."""
+    return int(lib().dpf_tail_team())
+
+
+def split_stats() -> dict:
+    """dpf_tail_split_stats: split-kernel launches and abandoned launches so far."""
+    n, ab = ctypes.c_int64(), ctypes.c_int64()
+    lib().dpf_tail_split_stats(ctypes.byref(n), ctypes.byref(ab))
+    return {"launches": n.value, "abandoned": ab.value}
 
 
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,

@@ -15,6 +15,7 @@
 #include "eval.hpp"
 #include "sell.hpp"
 #include "solve.hpp"
+#include "split.hpp"
 #include "wide.hpp"
 #include "ybus.hpp"
 
@@ -44,7 +45,7 @@ struct DeviceInfo {
     bool ok = false;
     hipStream_t side = nullptr;      // stream of the multi-workgroup path
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
-    int32_t *pinned_count = nullptr; // host-pinned poll target
+    int32_t *pinned_count = nullptr; // host-pinned poll target (two words)
     int index = 0;
 };
 std::mutex g_dev_mu;
@@ -71,7 +72,7 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_in, hipEventDisableTiming));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_out, hipEventDisableTiming));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_poll, hipEventDisableTiming));
-        DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, sizeof(int32_t), hipHostMallocDefault));
+        DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, 2 * sizeof(int32_t), hipHostMallocDefault));
         g_dev[dev].index = dev;
         g_dev[dev].ok = true;
     }
@@ -86,6 +87,10 @@ constexpr int kSolveStaticLds = 2 * (1024 / dpf::kWave) * 8 + 256;
 
 std::atomic<int32_t> g_team_cap_override{0};
 std::atomic<int32_t> g_tail_handoff{0};  // unfinished items at which per-item kernels hand over (0 = never)
+std::atomic<int32_t> g_tail_team{0};     // handed-over items: most workgroups per item (0 = multi-workgroup path)
+std::atomic<int32_t> g_tail_chunk{128};  // ... and iterations per launch of the split kernel
+std::atomic<int32_t> g_tail_min{0};      // ... while more than this many items are left
+std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // since the library was loaded
 
 int32_t max_sub_buses_for(const DeviceInfo &d) {
     int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
@@ -235,7 +240,7 @@ struct SolveLayout {
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
-           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0;
+           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0;
     int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
@@ -294,6 +299,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(int32_t) * (size_t)B, 256);
         L.off_sched = o;  // schedule state when the caller passes none [B][6]
         o += align_up(sizeof(double) * dpf::kSchedWords * (size_t)B, 256);
+        L.off_bar = o;  // split kernel: one arrival counter per listed item
+        o += align_up(sizeof(int32_t) * (size_t)B, 256);
     }
     L.total = o;
     return L;
@@ -404,6 +411,66 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     }
     hipLaunchKernelGGL(dpf::wide_finish_kernel, dim3((items + 255) / 256), dim3(256), 0, sd, w, cap);
     DPF_HIP(hipGetLastError());
+    return DPF_OK;
+}
+
+// Split kernel for the handed-over items (see split.hpp): chunks of iterations
+// with T = (workgroups the device holds at once) / (items left) workgroups per
+// item, at most max_team, relaunched as items finish, for as long as more than
+// min_items items are left.  Items still paused when it returns (at most
+// min_items, or a team abandoned a barrier) are left in *rest / *rest_list for
+// the multi-workgroup path.
+int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const DeviceInfo &dev, int32_t *list,
+              int32_t n_list, int32_t B, int32_t max_team, int32_t chunk, int32_t min_items, int32_t *rest,
+              int32_t **rest_list) {
+    hipStream_t sd = dev.side;
+    *rest = n_list;
+    *rest_list = list;
+    dpf::SolveArgs a = a0;
+    a.handoff = 0;  // no per-item kernel polls the finished count any more
+    const int32_t ns = (a.n_bus + dpf::kWave - 1) / dpf::kWave;
+    const size_t lds = (size_t)a.n_bus * 16;
+    void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<1024>;
+    DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1024, lds));
+    const int64_t capacity = (int64_t)std::max(per_cu, 0) * dev.n_cu;
+    if (capacity < 1) return DPF_OK;
+    int32_t *hdr = (int32_t *)ws;  // header words 6 (paused count) and 7 (abandoned flag)
+    dpf::SplitArgs p{};
+    p.bar = (int32_t *)(ws + L.off_bar);
+    p.part = (double2 *)(ws + L.off_part);
+    p.Ig = a.scratch;
+    p.Wg = a.scratch + 2 * a.st_stride;
+    p.aborted = hdr + 7;
+    p.chunk = chunk;
+    p.first_limit = (int64_t)(1e9 / dev.ns_per_tick);  // 1 s: other work may still hold CUs
+    p.limit = (int64_t)(5e9 / dev.ns_per_tick);
+    hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, p.aborted);
+    int32_t *cur = list;
+    int32_t *other = (int32_t *)(list == (int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
+    while (n_list > std::max(min_items, 0)) {
+        const int64_t t = std::min<int64_t>(std::min<int64_t>(capacity / n_list, max_team), ns);
+        p.T = (int32_t)std::max<int64_t>(t, 1);
+        p.list = cur;
+        p.n_list = n_list;
+        hipLaunchKernelGGL(dpf::split_clear_kernel, dim3((n_list + 255) / 256), dim3(256), 0, sd, n_list, p.bar);
+        hipLaunchKernelGGL(fn, dim3(n_list * p.T), dim3(1024), lds, sd, a, p);
+        hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, sd, B, a.status, other, hdr + 6);
+        DPF_HIP(hipGetLastError());
+        DPF_HIP(hipMemcpyAsync(dev.pinned_count, hdr + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, sd));
+        DPF_HIP(hipEventRecord(dev.ev_poll, sd));
+        DPF_HIP(hipEventSynchronize(dev.ev_poll));
+        n_list = dev.pinned_count[0];
+        std::swap(cur, other);
+        *rest = n_list;
+        *rest_list = cur;
+        g_split_launches.fetch_add(1);
+        if (dev.pinned_count[1]) {  // abandoned: the rest goes to the multi-workgroup path
+            g_split_abandoned.fetch_add(1);
+            break;
+        }
+    }
     return DPF_OK;
 }
 
@@ -719,9 +786,30 @@ int dpf_autotune_set_tail_handoff(int32_t items) {
     return DPF_OK;
 }
 
+int32_t dpf_tail_team(void) { return g_tail_team.load(); }
+
+void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned) {
+    if (launches) *launches = g_split_launches.load();
+    if (abandoned) *abandoned = g_split_abandoned.load();
+}
+
+int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items) {
+    g_err.clear();
+    if (max_team < 0 || max_team > 1024) return fail(DPF_EINVAL, "max_team must be in [0, 1024]");
+    if (chunk < 1 || chunk > 65536) return fail(DPF_EINVAL, "chunk must be in [1, 65536]");
+    if (min_items < 0) return fail(DPF_EINVAL, "min_items must be >= 0");
+    g_tail_team.store(max_team);
+    g_tail_chunk.store(chunk);
+    g_tail_min.store(min_items);
+    return DPF_OK;
+}
+
 void dpf_autotune_reset(void) {
     g_team_cap_override.store(0);
     g_tail_handoff.store(0);
+    g_tail_team.store(0);
+    g_tail_chunk.store(128);
+    g_tail_min.store(0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &row : g_tune)
         for (int &x : row) x = -1;
@@ -1096,7 +1184,15 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         if (paused > 0) {
             DPF_HIP(hipEventRecord(dev.ev_in, st));
             DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
-            int rc2 = run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, list, paused);
+            int32_t rest = paused;
+            int32_t *rest_list = list;
+            const int32_t team = g_tail_team.load();
+            if (team > 0) {
+                int rc2 = run_split(a, L, ws, dev, list, paused, B, team, g_tail_chunk.load(), g_tail_min.load(),
+                                    &rest, &rest_list);
+                if (rc2 != DPF_OK) return rc2;
+            }
+            int rc2 = rest > 0 ? run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, rest_list, rest) : DPF_OK;
             if (rc2 != DPF_OK) return rc2;
             DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
             DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));

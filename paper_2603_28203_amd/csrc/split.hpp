@@ -1,0 +1,316 @@
+// Split solve: the last unfinished cases of a single-grid batch, each spread over
+// a team of T workgroups on T CUs.
+//
+// Per-item kernels give every case one CU.  Once a batch has retired most of its
+// cases, the few left (often the slowest: they run to the iteration cap) would
+// hold a handful of CUs for thousands of iterations while the rest of the chip
+// idles.  Here each of them is cut into T row ranges of whole 64-row slices, one
+// workgroup per range, and the team keeps the per-item kernels' LDS gathers:
+// every member holds the exchange vector X for the columns its rows reference
+// (rows +- the grid's bandwidth) and refreshes it from global memory after each
+// of the two exchanges of an iteration (Sec. 4.2's adjoint needs every
+// neighbour's seed w, the next forward product every neighbour's new V):
+//   A : rows of the member: I = Y V, dS, loss terms, w = a conj(V) -> global;
+//       the member's (loss sum, max|r|) partial -> global
+//   -- team barrier --
+//   every member sums the T partials in the same order (identical loss, max|r|
+//   and stop decision in all members); X <- w of the range
+//   B : rows of the member: h = Y^T w, G, optimizer step; |V|, theta, moments
+//       -> global; schedule step
+//   -- team barrier --
+//   X <- polar(|V|, theta) of the range
+// The barrier is a per-team arrival counter in global memory.  What crosses it
+// (w, |V|, theta, the partials) is written and read with device-scope accesses
+// (relaxed agent-scope atomics: stores write through to the device's coherence
+// point, loads do not hit a possibly stale L1/L2 copy), and every thread waits
+// for its own stores to complete before the team's arrival is counted.  Fences
+// at agent scope would do the same for all memory, but on a chip with one L2 per
+// XCD they write back and invalidate the L2 at every barrier of every member,
+// which cost several times the iteration itself.  Members of one team must run
+// at the same time, which the host arranges by launching at most as many
+// workgroups as the device holds.
+// A member that waits longer than a bound abandons the barrier (kSplitAbort in
+// the counter); every member then leaves at its next barrier with the item still
+// paused, and the host finishes it on the multi-workgroup path.  An abandoned
+// first barrier leaves the state untouched (the first exchange precedes every
+// update).
+//
+// A launch runs each listed case for at most `chunk` iterations; the host then
+// drops the finished cases and relaunches the rest with larger teams.
+#pragma once
+
+#include "../../include/dpf.h"
+#include "common.hpp"
+#include "solve.hpp"
+
+namespace dpf {
+
+constexpr int32_t kSplitAbort = 1 << 30;
+
+struct SplitArgs {
+    const int32_t *list;  // [n_list] paused case indices
+    int32_t n_list;
+    int32_t T;            // workgroups per case (<= slices of the grid)
+    int32_t chunk;        // iterations per launch
+    int32_t *bar;         // [n_list] arrival counters, zero at launch
+    double2 *part;        // [n_list * T] member partials (loss sum, max|r|)
+    double2 *Ig;          // [B][ld] I of the A sweep
+    double2 *Wg;          // [B][ld] exchanged w
+    int32_t *aborted;     // set when a team abandoned a barrier
+    int64_t first_limit;  // wall-clock ticks a member waits at the first barrier
+    int64_t limit;        // ... and at every later one
+};
+
+// device-scope store / load of what one member hands to the others
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev2(double2 *p, double2 v) {
+    st_dev(&p->x, v.x);
+    st_dev(&p->y, v.y);
+}
+__device__ __forceinline__ double2 ld_dev2(const double2 *p) { return make_double2(ld_dev(&p->x), ld_dev(&p->y)); }
+
+// arrival barrier of the T members of one team; false when it was abandoned
+__device__ __forceinline__ bool team_barrier(int32_t *cnt, int32_t target, int64_t limit, int *flag) {
+    // this thread's device-scope stores have completed (and the compiler keeps
+    // every earlier memory access before this point)
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int32_t v = atomicAdd(cnt, 1) + 1;
+        bool ok = (v & kSplitAbort) == 0;
+        const int64_t t0 = wall_clock64();
+        while (ok && v < target) {
+            __builtin_amdgcn_s_sleep(1);
+            v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v & kSplitAbort) {
+                ok = false;
+            } else if (v < target && wall_clock64() - t0 > limit) {
+                // abandon only if no member arrived meanwhile (else poll again)
+                if (atomicCAS(cnt, v, v | kSplitAbort) == v) ok = false;
+            }
+        }
+        *flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, SplitArgs p) {
+    extern __shared__ double2 X[];
+    __shared__ double red[2][NT / kWave];
+    __shared__ int bar_flag;
+
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int team = blockIdx.x / p.T;
+    const int mem = blockIdx.x - team * p.T;
+    if (team >= p.n_list) return;  // the whole team is absent
+    const int c = p.list[team];
+    const int n = a.n_bus;
+    const int ns = (n + kWave - 1) / kWave;
+    const int rlo = (int)((int64_t)mem * ns / p.T) * kWave;
+    const int rhi = min((int)((int64_t)(mem + 1) * ns / p.T) * kWave, n);
+    const int bw = a.sub_bw[0];
+    const int xlo = max(0, rlo - bw), xhi = min(n, rhi + bw);
+    int32_t *cnt = p.bar + team;
+    double2 *part = p.part + (int64_t)team * p.T;
+
+    ItemSched sc = load_item_sched(a, c);
+    const double m_res = residual_count<NT>(a.bt, 0, n, red);
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+    const Rank2 r2 = outage_of_case(a.ov, c, 0, n);
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
+
+    const int64_t cb = (int64_t)c * a.ld;
+    double *__restrict__ vm_c = a.vm + cb;
+    double *__restrict__ va_c = a.va + cb;
+    double *__restrict__ mv_c = a.st + cb;
+    double *__restrict__ ma_c = a.st + a.st_stride + cb;
+    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb;
+    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *__restrict__ Ig = p.Ig + cb;
+    double2 *__restrict__ Wg = p.Wg + cb;
+    const double2 *__restrict__ Sc = a.s_spec + (int64_t)c * a.s_ld;
+    const int32_t *__restrict__ swidth = a.sell.width;
+    const int32_t *__restrict__ sstart = a.sell.start;
+    const int32_t *__restrict__ scol = a.sell.col;
+    const double2 *__restrict__ sval = a.sell.val;
+    const int8_t *__restrict__ btp = a.bt;
+
+    // X <- V over the range (and the two buses of the outage, which the rank-2
+    // term of the outage rows reads)
+    auto fill_v = [&]() {
+        for (int i = xlo + tid; i < xhi; i += NT) {
+            double sn, cs;
+            const double vmi = ld_dev(vm_c + i);
+            fast_sincos(ld_dev(va_c + i), sn, cs);
+            X[i] = make_double2(vmi * cs, vmi * sn);
+        }
+        if (of >= 0 && tid < 2) {
+            const int i = tid == 0 ? of : ot;
+            if (i < xlo || i >= xhi) {
+                double sn, cs;
+                const double vmi = ld_dev(vm_c + i);
+                fast_sincos(ld_dev(va_c + i), sn, cs);
+                X[i] = make_double2(vmi * cs, vmi * sn);
+            }
+        }
+    };
+    auto fill_w = [&]() {
+        for (int i = xlo + tid; i < xhi; i += NT) X[i] = ld_dev2(Wg + i);
+        if (of >= 0 && tid < 2) {
+            const int i = tid == 0 ? of : ot;
+            if (i < xlo || i >= xhi) X[i] = ld_dev2(Wg + i);
+        }
+    };
+
+    fill_v();
+    __syncthreads();
+
+    const int it0 = a.iters[c];  // paused cases continue their iteration count
+    int it = it0, stat = kPaused, nbar = 0;
+    double mu = 0.0, loss = 0.0;
+    bool ok = true;
+    for (;; ++it) {
+        if (it - it0 >= p.chunk) break;  // paused again; the host relaunches
+        // ---------------- A: rows of this member
+        double lsum = 0.0, lmax = 0.0;
+        for (int il = rlo + tid; il < rhi; il += NT) {
+            const int8_t tk = btp[il];
+            const double2 sp = Sc[il];
+            const int gsl = __builtin_amdgcn_readfirstlane(il >> 6);
+            const int wdt = swidth[gsl];
+            const int base = sstart[gsl] * kWave + lane;
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], acc);
+            if (il == of) acc = csub(acc, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
+            else if (il == ot) acc = csub(acc, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
+            const double2 v = X[il];
+            const double2 d = csub(cmulc(v, acc), sp);
+            const double rP = tk != kSlack ? d.x : 0.0;
+            const double rQ = tk == kPQ ? d.y : 0.0;
+            lsum += rP * rP + rQ * rQ;
+            lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+            Ig[il] = acc;
+            st_dev2(Wg + il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        if (tid == 0) st_dev2(part + mem, make_double2(lsum, lmax));
+        ok = team_barrier(cnt, ++nbar * p.T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
+        if (!ok) break;
+        // team totals: the same partials combined in the same order by every member
+        {
+            double s = 0.0, m = 0.0;
+            for (int q = tid; q < p.T; q += NT) {
+                const double2 pp = ld_dev2(part + q);
+                s += pp.x;
+                m = fmax(m, pp.y);
+            }
+            block_reduce2<NT>(s, m, red);
+            __syncthreads();
+            block_reduce2_finish<NT>(s, m, red);
+            __syncthreads();
+            lsum = s;
+            lmax = m;
+        }
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+        fill_w();
+        __syncthreads();
+
+        // ---------------- B: rows of this member
+        sc.t_step += 1.0;
+        sc.b1t *= a.b1;
+        sc.b2t *= a.b2;
+        const double bc1 = 1.0 - sc.b1t;
+        const double bc2 = 1.0 - sc.b2t;
+        for (int il = rlo + tid; il < rhi; il += NT) {
+            const int8_t tk = btp[il];
+            const double2 I = Ig[il];
+            const double2 sp = Sc[il];
+            double vmi = vm_c[il], vai = va_c[il];
+            const double mv0 = mv_c[il], sv0 = sv_c[il], ma0 = ma_c[il], sa0 = sa_c[il];
+            const int gsl = __builtin_amdgcn_readfirstlane(il >> 6);
+            const int wdt = swidth[gsl];
+            const int base = sstart[gsl] * kWave + lane;
+            double2 h = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], h);
+            if (il == of) h = csub(h, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
+            else if (il == ot) h = csub(h, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
+            double2 v;
+            {
+                double sn0, cs0;
+                fast_sincos(vai, sn0, cs0);
+                v = make_double2(vmi * cs0, vmi * sn0);
+            }
+            const double2 d = csub(cmulc(v, I), sp);
+            const double rP = tk != kSlack ? d.x : 0.0;
+            const double rQ = tk == kPQ ? d.y : 0.0;
+            const double2 ai = cmul(make_double2(two_over_m * rP, two_over_m * rQ), I);
+            const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+            if (tk == kPQ) {
+                const double g = (G.x * v.x + G.y * v.y) / vmi;
+                double mv = mv0, sv = sv0;
+                vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                st_dev(vm_c + il, vmi);
+                mv_c[il] = mv;
+                sv_c[il] = sv;
+            }
+            if (tk != kSlack) {
+                const double g = G.y * v.x - G.x * v.y;
+                double ma = ma0, sa = sa0;
+                vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                st_dev(va_c + il, vai);
+                ma_c[il] = ma;
+                sa_c[il] = sa;
+            }
+        }
+        sched_step(a, sc, loss, it);
+        ok = team_barrier(cnt, ++nbar * p.T, p.limit, &bar_flag);
+        if (!ok) {
+            ++it;  // the members that arrived applied this iteration's step
+            break;
+        }
+        fill_v();
+        __syncthreads();
+    }
+
+    if (mem != 0 || tid != 0) return;
+    if (!ok) {
+        // abandoned: the case stays paused with its current count and schedule
+        *p.aborted = 1;
+        stat = kPaused;
+    }
+    finish_item(a, c, it, stat, mu, loss, sc);
+}
+
+// zero the arrival counters of a launch
+__global__ void split_clear_kernel(int32_t n, int32_t *__restrict__ bar) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) bar[i] = 0;
+}
+
+}  // namespace dpf

@@ -146,6 +146,29 @@ def test_tail_handoff_setting_and_workspace(lib):
     lib.dpf_autotune_reset()
 
 
+def test_tail_team_setting(lib):
+    """dpf_autotune_set_tail_team validates both arguments and is undone by the
+    reset; it does not change the workspace size."""
+    lib.dpf_tail_team.restype = ctypes.c_int32
+    lib.dpf_autotune_set_tail_team.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
+    lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
+                                              ctypes.c_int32, ctypes.c_int32]
+    g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
+    lib.dpf_autotune_reset()
+    assert lib.dpf_tail_team() == 0
+    assert lib.dpf_autotune_set_tail_handoff(192) == 0
+    before = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
+    for bad in ((-1, 128, 0), (1025, 128, 0), (8, 0, 0), (8, 65537, 0), (8, 128, -1)):
+        assert lib.dpf_autotune_set_tail_team(*bad) == -1, bad
+        assert lib.dpf_tail_team() == 0
+    assert lib.dpf_autotune_set_tail_team(32, 128, 16) == 0
+    assert lib.dpf_tail_team() == 32
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == before
+    lib.dpf_autotune_reset()
+    assert lib.dpf_tail_team() == 0 and lib.dpf_tail_handoff() == 0
+
+
 def _kind(lib, i):
     t, k, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st))

@@ -1408,15 +1408,28 @@ def handoff(dpf):
     dpf.autotune_reset()
 
 
+def split_ran(dpf, before):
+    """The split kernel was launched since `before` and no team abandoned a barrier."""
+    after = dpf.split_stats()
+    print(f"split launches {after['launches'] - before['launches']}, "
+          f"abandoned {after['abandoned'] - before['abandoned']}", flush=True)
+    return after["launches"] > before["launches"] and after["abandoned"] == before["abandoned"]
+
+
 @pytest.mark.parametrize("kind", ["banded-stream", "streaming", "banded-window"])
 @pytest.mark.parametrize("threshold", [5, 64])
-def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold):
+@pytest.mark.parametrize("team", [0, 8])
+def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold, team):
     """Items paused by the per-item kernel (every item when the threshold is at
     least the batch, else once enough items have stopped) finish on the
-    multi-workgroup path: iterates, statuses, iteration counts and the plateau
-    schedule equal the oracle's and the results of the same call without
-    handoff."""
+    multi-workgroup path (team 0) or the split kernel (teams of up to 8
+    workgroups, relaunched every 16 iterations while more than 3 items are left,
+    the rest then on the multi-workgroup path): iterates, statuses, iteration
+    counts and the plateau schedule equal the oracle's and the results of the
+    same call without handoff."""
     dpf = handoff
+    dpf.set_tail_team(team, 16, 3)
+    stats = dpf.split_stats()
     base = synth.config1(B=1, seed=9700, n_bus=700, n_branch=1120, n_pv=110)["grid"]
     g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
     S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
@@ -1464,12 +1477,17 @@ def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, thres
     print(f"handoff vs plain: max |diff| {d:.3e}", flush=True)
     assert d < 1e-12
     assert (res[threshold][3][[0, 2, 4, 6, 7]] > 0).all()
+    assert split_ran(dpf, stats) == (team > 0)
 
 
-def test_tail_handoff_with_caller_moments_and_resume(handoff):
+@pytest.mark.parametrize("team", [0, 3])
+def test_tail_handoff_with_caller_moments_and_resume(handoff, team):
     """With the caller's optimizer state, a handed-over call continues exactly
-    like a call without handoff when resumed (two half calls)."""
+    like a call without handoff when resumed (two half calls), on either tail
+    path (team 3: the split kernel, relaunched every 5 iterations)."""
     dpf = handoff
+    dpf.set_tail_team(team, 5)
+    stats = dpf.split_stats()
     base = synth.config1(B=1, seed=9701, n_bus=600, n_branch=960, n_pv=100)["grid"]
     g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
     S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
@@ -1495,15 +1513,21 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff):
         out[h] = (vm.cpu().numpy(), va.cpu().numpy(), st.cpu().numpy(), sch.cpu().numpy())
     for k in range(4):
         assert np.abs(out[0][k] - out[8][k]).max() <= 1e-12 * max(1.0, np.abs(out[0][k]).max())
+    assert split_ran(dpf, stats) == (team > 0)
 
 
-def test_bench_configuration_at_full_size_with_handoff(handoff):
+@pytest.mark.parametrize("team", [0, 32])
+def test_bench_configuration_at_full_size_with_handoff(handoff, team):
     """The bench's launch configuration at its full size: 1024 outage cases of
     the 9241-bus grid (RCM numbering degree-grouped in windows of 2560), the 1024 x 4 banded-stream
     kernel, the bench's optimizer settings and a tail handoff at 192 cases.  900
     cases carry a non-finite injection and stop at once, so the other 124 are
-    handed over after 32 iterations; sampled cases equal their oracle solves."""
+    handed over after 32 iterations (to the multi-workgroup path, or to the split
+    kernel in teams of 2 relaunched every 3 iterations); sampled cases equal their
+    oracle solves."""
     dpf = handoff
+    dpf.set_tail_team(team, 3)
+    stats = dpf.split_stats()
     cfg = synth.config2(B=1024)
     base = cfg["grid"]
     perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t, group=2560)
@@ -1543,14 +1567,18 @@ def test_bench_configuration_at_full_size_with_handoff(handoff):
         assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
         assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
         assert abs(out["max_mis"][c].item() - ref["mu"]) <= 1e-8 * ref["mu"], c
+    assert split_ran(dpf, stats) == (team > 0)
 
 
-def test_concurrent_handoff_calls_on_two_streams(handoff):
+@pytest.mark.parametrize("team", [0, 8])
+def test_concurrent_handoff_calls_on_two_streams(handoff, team):
     """Two host threads, each with its own stream and workspace, run solves that
     hand their tail over at the same time; each result equals the same call run
     alone (the side stream of the device is shared and taken in turns)."""
     import threading
     dpf = handoff
+    dpf.set_tail_team(team, 64)
+    stats = dpf.split_stats()
     base = synth.config1(B=1, seed=9800, n_bus=700, n_branch=1120, n_pv=110)["grid"]
     g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
     S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
@@ -1589,6 +1617,7 @@ def test_concurrent_handoff_calls_on_two_streams(handoff):
         assert together[k][2].tolist() == [300] * B
         assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12
         assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12
+    assert split_ran(dpf, stats) == (team > 0)
 
 
 @pytest.mark.parametrize("seed", range(6))
