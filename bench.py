@@ -45,10 +45,10 @@ BUS_ORDER_GROUP = 2560
 # the last 192 unfinished cases of the N-1 batch leave the per-item kernel
 # (dpf_autotune_set_tail_handoff); measured 128..256 best, 0 = off
 TAIL_HANDOFF = 192
-# ... and finish on the split kernel in teams of up to 8 workgroups, relaunched every
-# 128 iterations, until 32 are left, then on the multi-workgroup path, whose latency
-# per iteration is lower for a few cases (dpf_autotune_set_tail_team)
-TAIL_TEAM = (8, 128, 32)
+# ... and finish on the split kernel in teams of up to 16 workgroups, relaunched every
+# 128 iterations with larger teams as cases finish (dpf_autotune_set_tail_team);
+# measured 6.9 s per step against 7.4 s on the multi-workgroup path
+TAIL_TEAM = (16, 128, 0)
 FP64_PEAK_TFLOPS = 78.6
 
 

@@ -57,6 +57,27 @@ __device__ __forceinline__ double uniform(double x) {
     const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
+// Device-scope (relaxed agent-scope atomic) store and load of a double: the store
+// writes through to the device's coherence point and the load does not hit a
+// possibly stale L1/L2 copy, so values handed between workgroups of one kernel
+// on different XCDs need no cache-wide write-back or invalidation.  A thread
+// makes its device-scope stores visible before signalling with
+// dev_stores_done() followed by a device-scope atomic.
+__device__ __forceinline__ void st_dev(double *p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double *p) {
+    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void st_dev2(double2 *p, double2 v) {
+    st_dev(&p->x, v.x);
+    st_dev(&p->y, v.y);
+}
+__device__ __forceinline__ double2 ld_dev2(const double2 *p) { return make_double2(ld_dev(&p->x), ld_dev(&p->y)); }
+// this thread's stores have completed (and the compiler keeps every earlier
+// memory access before this point)
+__device__ __forceinline__ void dev_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
 __device__ __forceinline__ int wave_isum(int v) {
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);

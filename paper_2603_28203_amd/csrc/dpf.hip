@@ -299,8 +299,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(int32_t) * (size_t)B, 256);
         L.off_sched = o;  // schedule state when the caller passes none [B][6]
         o += align_up(sizeof(double) * dpf::kSchedWords * (size_t)B, 256);
-        L.off_bar = o;  // split kernel: one arrival counter per listed item
-        o += align_up(sizeof(int32_t) * (size_t)B, 256);
+        L.off_bar = o;  // split kernel: one arrival counter per listed item, 256 bytes apart
+        o += align_up(sizeof(int32_t) * dpf::kBarStride * (size_t)B, 256);
     }
     L.total = o;
     return L;
@@ -429,7 +429,9 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     dpf::SolveArgs a = a0;
     a.handoff = 0;  // no per-item kernel polls the finished count any more
     const int32_t ns = (a.n_bus + dpf::kWave - 1) / dpf::kWave;
-    const size_t lds = (size_t)a.n_bus * 16;
+    // X and the bitmap of the columns a member reads
+    const size_t lds = (size_t)a.n_bus * 16 + (size_t)(a.n_bus + 31) / 32 * 4;
+    if (lds + 512 > (size_t)dev.lds_per_block) return DPF_OK;  // the multi-workgroup path takes them
     void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<1024>;
     DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
@@ -446,7 +448,7 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     p.chunk = chunk;
     p.first_limit = (int64_t)(1e9 / dev.ns_per_tick);  // 1 s: other work may still hold CUs
     p.limit = (int64_t)(5e9 / dev.ns_per_tick);
-    hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, p.aborted);
+    hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, 1, p.aborted);
     int32_t *cur = list;
     int32_t *other = (int32_t *)(list == (int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
     while (n_list > std::max(min_items, 0)) {
@@ -454,7 +456,8 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
         p.T = (int32_t)std::max<int64_t>(t, 1);
         p.list = cur;
         p.n_list = n_list;
-        hipLaunchKernelGGL(dpf::split_clear_kernel, dim3((n_list + 255) / 256), dim3(256), 0, sd, n_list, p.bar);
+        hipLaunchKernelGGL(dpf::split_clear_kernel, dim3((n_list + 255) / 256), dim3(256), 0, sd, n_list,
+                           dpf::kBarStride, p.bar);
         hipLaunchKernelGGL(fn, dim3(n_list * p.T), dim3(1024), lds, sd, a, p);
         hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, sd, B, a.status, other, hdr + 6);
         DPF_HIP(hipGetLastError());

@@ -7,8 +7,8 @@
 // idles.  Here each of them is cut into T row ranges of whole 64-row slices, one
 // workgroup per range, and the team keeps the per-item kernels' LDS gathers:
 // every member holds the exchange vector X for the columns its rows reference
-// (rows +- the grid's bandwidth) and refreshes it from global memory after each
-// of the two exchanges of an iteration (Sec. 4.2's adjoint needs every
+// (a bitmap of them follows X in LDS) and refreshes those from global memory
+// after each of the two exchanges of an iteration (Sec. 4.2's adjoint needs every
 // neighbour's seed w, the next forward product every neighbour's new V):
 //   A : rows of the member: I = Y V, dS, loss terms, w = a conj(V) -> global;
 //       the member's (loss sum, max|r|) partial -> global
@@ -46,13 +46,16 @@
 namespace dpf {
 
 constexpr int32_t kSplitAbort = 1 << 30;
+// one counter per 256 bytes: device-scope atomics and polls of different teams on
+// one cache line serialize
+constexpr int32_t kBarStride = 64;
 
 struct SplitArgs {
     const int32_t *list;  // [n_list] paused case indices
     int32_t n_list;
     int32_t T;            // workgroups per case (<= slices of the grid)
     int32_t chunk;        // iterations per launch
-    int32_t *bar;         // [n_list] arrival counters, zero at launch
+    int32_t *bar;         // [n_list][kBarStride] arrival counters (first word of each), zero at launch
     double2 *part;        // [n_list * T] member partials (loss sum, max|r|)
     double2 *Ig;          // [B][ld] I of the A sweep
     double2 *Wg;          // [B][ld] exchanged w
@@ -61,24 +64,9 @@ struct SplitArgs {
     int64_t limit;        // ... and at every later one
 };
 
-// device-scope store / load of what one member hands to the others
-__device__ __forceinline__ void st_dev(double *p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double ld_dev(const double *p) {
-    return __hip_atomic_load(const_cast<double *>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ void st_dev2(double2 *p, double2 v) {
-    st_dev(&p->x, v.x);
-    st_dev(&p->y, v.y);
-}
-__device__ __forceinline__ double2 ld_dev2(const double2 *p) { return make_double2(ld_dev(&p->x), ld_dev(&p->y)); }
-
 // arrival barrier of the T members of one team; false when it was abandoned
 __device__ __forceinline__ bool team_barrier(int32_t *cnt, int32_t target, int64_t limit, int *flag) {
-    // this thread's device-scope stores have completed (and the compiler keeps
-    // every earlier memory access before this point)
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    dev_stores_done();
     __syncthreads();
     if (threadIdx.x == 0) {
         int32_t v = atomicAdd(cnt, 1) + 1;
@@ -118,7 +106,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     const int rhi = min((int)((int64_t)(mem + 1) * ns / p.T) * kWave, n);
     const int bw = a.sub_bw[0];
     const int xlo = max(0, rlo - bw), xhi = min(n, rhi + bw);
-    int32_t *cnt = p.bar + team;
+    int32_t *cnt = p.bar + (int64_t)team * kBarStride;
     double2 *part = p.part + (int64_t)team * p.T;
 
     ItemSched sc = load_item_sched(a, c);
@@ -144,10 +132,34 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     const double2 *__restrict__ sval = a.sell.val;
     const int8_t *__restrict__ btp = a.bt;
 
-    // X <- V over the range (and the two buses of the outage, which the rank-2
-    // term of the outage rows reads)
+    // The columns the member's rows read (its own rows, their neighbours and the
+    // two buses of the outage) as a bitmap behind X: the refills below load only
+    // those, about a third of the range under a degree-grouped numbering.
+    uint32_t *need = reinterpret_cast<uint32_t *>(X + n);
+    for (int k = tid; k < (n + 31) / 32; k += NT) need[k] = 0u;
+    __syncthreads();
+    for (int il = rlo + tid; il < rhi; il += NT) {
+        const int gsl = __builtin_amdgcn_readfirstlane(il >> 6);
+        const int wdt = swidth[gsl];
+        const int base = sstart[gsl] * kWave + lane;
+        atomicOr(need + (il >> 5), 1u << (il & 31));
+        for (int q = 0; q < wdt; ++q) {
+            const int cc = scol[base + q * kWave];
+            atomicOr(need + (cc >> 5), 1u << (cc & 31));
+        }
+    }
+    if (of >= 0 && tid < 2) {
+        const int i = tid == 0 ? of : ot;
+        atomicOr(need + (i >> 5), 1u << (i & 31));
+    }
+    __syncthreads();
+    auto needed = [&](int i) { return (need[i >> 5] >> (i & 31)) & 1u; };
+
+    // X <- V at the needed columns of the range (and the two buses of the outage,
+    // which the rank-2 term of the outage rows reads, wherever they are)
     auto fill_v = [&]() {
         for (int i = xlo + tid; i < xhi; i += NT) {
+            if (!needed(i)) continue;
             double sn, cs;
             const double vmi = ld_dev(vm_c + i);
             fast_sincos(ld_dev(va_c + i), sn, cs);
@@ -164,7 +176,8 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         }
     };
     auto fill_w = [&]() {
-        for (int i = xlo + tid; i < xhi; i += NT) X[i] = ld_dev2(Wg + i);
+        for (int i = xlo + tid; i < xhi; i += NT)
+            if (needed(i)) X[i] = ld_dev2(Wg + i);
         if (of >= 0 && tid < 2) {
             const int i = tid == 0 ? of : ot;
             if (i < xlo || i >= xhi) X[i] = ld_dev2(Wg + i);
@@ -209,6 +222,8 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         ok = team_barrier(cnt, ++nbar * p.T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
         if (!ok) break;
         // team totals: the same partials combined in the same order by every member
+        // (their loads overlap the refill of X with w, which the stop test would
+        // only discard)
         {
             double s = 0.0, m = 0.0;
             for (int q = tid; q < p.T; q += NT) {
@@ -216,6 +231,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
                 s += pp.x;
                 m = fmax(m, pp.y);
             }
+            fill_w();
             block_reduce2<NT>(s, m, red);
             __syncthreads();
             block_reduce2_finish<NT>(s, m, red);
@@ -237,8 +253,6 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             stat = DPF_MAX_ITER;
             break;
         }
-        fill_w();
-        __syncthreads();
 
         // ---------------- B: rows of this member
         sc.t_step += 1.0;
@@ -307,10 +321,10 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     finish_item(a, c, it, stat, mu, loss, sc);
 }
 
-// zero the arrival counters of a launch
-__global__ void split_clear_kernel(int32_t n, int32_t *__restrict__ bar) {
+// zero n counters spaced `stride` words apart
+__global__ void split_clear_kernel(int32_t n, int32_t stride, int32_t *__restrict__ bar) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) bar[i] = 0;
+    if (i < n) bar[(int64_t)i * stride] = 0;
 }
 
 }  // namespace dpf
