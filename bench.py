@@ -312,6 +312,9 @@ def main():
                              "GBps": round(copy_gbs, 1), "frac_achieved": round(steady / copy_gbs, 4),
                              "frac_traffic": None if traffic is None else round(traffic / kf[0] / 1e9 / copy_gbs, 4)}
     solve_rate = {"what": "the timed solve call: per-item kernel, early retirement, then the last "
+                          f"{args.handoff} cases on the split kernel (teams of up to {tail_team[0]} workgroups)"
+                          if tail_team[0] > 0 else
+                          "the timed solve call: per-item kernel, early retirement, then the last "
                           f"{args.handoff} cases on the multi-workgroup path",
                   "achieved": round(achieved, 1), "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                   "alg_bytes": alg_bytes, "call_s": round(t_kern, 4), "tail_handoff": args.handoff}
