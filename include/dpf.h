@@ -425,12 +425,20 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             finished then continue on the multi-workgroup path.
  *                             max_team = 0 (the default): the multi-workgroup path
  *                             only.  Returns DPF_EINVAL for arguments out of range
+ *   dpf_autotune_set_tail_waits : the split kernel's barrier wait bounds in seconds,
+ *                             [0, 60] each (defaults 1 s at a launch's first barrier,
+ *                             5 s after it).  Every member finishes its part of an
+ *                             iteration before it arrives, so an abandoned barrier
+ *                             leaves the state of a whole iteration; a bound of 0
+ *                             makes nearly every team abandon its first barrier and
+ *                             hand its items to the multi-workgroup path (a way to
+ *                             exercise that path).  Returns DPF_EINVAL out of range
  *   dpf_tail_team           : the current max_team (0 = multi-workgroup path)
  *   dpf_tail_split_stats    : split-kernel launches, and launches in which a team
  *                             abandoned a barrier, since the library was loaded
  *                             (either pointer may be null)
- *   dpf_autotune_reset      : forget every choice (and the team cap, handoff and
- *                             tail team settings)
+ *   dpf_autotune_reset      : forget every choice (and the team cap, handoff, tail
+ *                             team and wait settings)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
  */
@@ -446,6 +454,7 @@ int dpf_autotune_set_tail_handoff(int32_t items);
 int32_t dpf_tail_handoff(void);
 int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items);
 int32_t dpf_tail_team(void);
+int dpf_autotune_set_tail_waits(double first_s, double later_s);
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned);
 void dpf_autotune_reset(void);
 

@@ -115,6 +115,8 @@ def lib():
         L.dpf_autotune_set_tail_team.argtypes = [_i32, _i32, _i32]
         L.dpf_autotune_set_tail_team.restype = ctypes.c_int
         L.dpf_tail_team.restype = _i32
+        L.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
+        L.dpf_autotune_set_tail_waits.restype = ctypes.c_int
         L.dpf_tail_split_stats.argtypes = [_P, _P]
         L.dpf_tail_split_stats.restype = None
         _lib = L
@@ -520,6 +522,11 @@ def set_tail_team(max_team: int, chunk: int = 128, min_items: int = 0):
 def tail_team() -> int:
     """The current most workgroups per handed-over item (0 = multi-workgroup path)."""
     return int(lib().dpf_tail_team())
+
+
+def set_tail_waits(first_s: float = 1.0, later_s: float = 5.0):
+    """dpf_autotune_set_tail_waits: the split kernel's barrier wait bounds (s)."""
+    _check(lib().dpf_autotune_set_tail_waits(float(first_s), float(later_s)))
 
 
 def split_stats() -> dict:

@@ -91,6 +91,7 @@ std::atomic<int32_t> g_tail_team{0};     // handed-over items: most workgroups p
 std::atomic<int32_t> g_tail_chunk{128};  // ... and iterations per launch of the split kernel
 std::atomic<int32_t> g_tail_min{0};      // ... while more than this many items are left
 std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // since the library was loaded
+std::atomic<double> g_split_first_wait{1.0}, g_split_wait{5.0};  // barrier wait bounds (s)
 
 int32_t max_sub_buses_for(const DeviceInfo &d) {
     int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
@@ -446,8 +447,8 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     p.Wg = a.scratch + 2 * a.st_stride;
     p.aborted = hdr + 7;
     p.chunk = chunk;
-    p.first_limit = (int64_t)(1e9 / dev.ns_per_tick);  // 1 s: other work may still hold CUs
-    p.limit = (int64_t)(5e9 / dev.ns_per_tick);
+    p.first_limit = (int64_t)(g_split_first_wait.load() * 1e9 / dev.ns_per_tick);  // other work may hold CUs
+    p.limit = (int64_t)(g_split_wait.load() * 1e9 / dev.ns_per_tick);
     hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, 1, p.aborted);
     int32_t *cur = list;
     int32_t *other = (int32_t *)(list == (int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
@@ -791,6 +792,15 @@ int dpf_autotune_set_tail_handoff(int32_t items) {
 
 int32_t dpf_tail_team(void) { return g_tail_team.load(); }
 
+int dpf_autotune_set_tail_waits(double first_s, double later_s) {
+    g_err.clear();
+    if (!(first_s >= 0.0 && first_s <= 60.0) || !(later_s >= 0.0 && later_s <= 60.0))
+        return fail(DPF_EINVAL, "wait bounds must be in [0, 60] s");
+    g_split_first_wait.store(first_s);
+    g_split_wait.store(later_s);
+    return DPF_OK;
+}
+
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned) {
     if (launches) *launches = g_split_launches.load();
     if (abandoned) *abandoned = g_split_abandoned.load();
@@ -813,6 +823,8 @@ void dpf_autotune_reset(void) {
     g_tail_team.store(0);
     g_tail_chunk.store(128);
     g_tail_min.store(0);
+    g_split_first_wait.store(1.0);
+    g_split_wait.store(5.0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &row : g_tune)
         for (int &x : row) x = -1;

@@ -30,10 +30,13 @@
 // at the same time, which the host arranges by launching at most as many
 // workgroups as the device holds.
 // A member that waits longer than a bound abandons the barrier (kSplitAbort in
-// the counter); every member then leaves at its next barrier with the item still
-// paused, and the host finishes it on the multi-workgroup path.  An abandoned
-// first barrier leaves the state untouched (the first exchange precedes every
-// update).
+// the counter, set by a compare-and-swap that fails if a member arrived
+// meanwhile); every member then leaves at its next barrier with the item still
+// paused, and the host finishes it on the multi-workgroup path.  Members finish
+// their part of an iteration before they arrive, so the state left behind is
+// that of a whole iteration: the start of iteration it (barrier after A, no
+// update yet) or of it + 1 (barrier after B, every member's rows updated), and
+// member 0 records that count with the schedule.
 //
 // A launch runs each listed case for at most `chunk` iterations; the host then
 // drops the finished cases and relaunches the rest with larger teams.

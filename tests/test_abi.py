@@ -164,6 +164,10 @@ def test_tail_team_setting(lib):
         assert lib.dpf_tail_team() == 0
     assert lib.dpf_autotune_set_tail_team(32, 128, 16) == 0
     assert lib.dpf_tail_team() == 32
+    lib.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
+    for bad in ((-1.0, 1.0), (1.0, -1.0), (61.0, 1.0), (float("nan"), 1.0)):
+        assert lib.dpf_autotune_set_tail_waits(*bad) == -1, bad
+    assert lib.dpf_autotune_set_tail_waits(0.0, 0.0) == 0
     assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == before
     lib.dpf_autotune_reset()
     assert lib.dpf_tail_team() == 0 and lib.dpf_tail_handoff() == 0

@@ -1516,15 +1516,15 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff, team):
     assert split_ran(dpf, stats) == (team > 0)
 
 
-@pytest.mark.parametrize("team", [0, 32])
-def test_bench_configuration_at_full_size_with_handoff(handoff, team):
+@pytest.mark.parametrize("team,n_finite", [(0, 124), (32, 124), (16, 8)])
+def test_bench_configuration_at_full_size_with_handoff(handoff, team, n_finite):
     """The bench's launch configuration at its full size: 1024 outage cases of
     the 9241-bus grid (RCM numbering degree-grouped in windows of 2560), the 1024 x 4 banded-stream
-    kernel, the bench's optimizer settings and a tail handoff at 192 cases.  900
-    cases carry a non-finite injection and stop at once, so the other 124 are
-    handed over after 32 iterations (to the multi-workgroup path, or to the split
-    kernel in teams of 2 relaunched every 3 iterations); sampled cases equal their
-    oracle solves."""
+    kernel, the bench's optimizer settings and a tail handoff at 192 cases.  All
+    but n_finite cases carry a non-finite injection and stop at once, so the
+    others are handed over after 32 iterations (to the multi-workgroup path, or to
+    the split kernel relaunched every 3 iterations: teams of 2 for 124 cases, of
+    16 for 8); sampled cases equal their oracle solves."""
     dpf = handoff
     dpf.set_tail_team(team, 3)
     stats = dpf.split_stats()
@@ -1536,7 +1536,7 @@ def test_bench_configuration_at_full_size_with_handoff(handoff, team):
     rng = np.random.default_rng(2024)
     S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
     S = np.tile(S0, (B, 1))
-    finite = np.sort(rng.choice(B, 124, replace=False))
+    finite = np.sort(rng.choice(B, n_finite, replace=False))
     nonfinite = np.setdiff1d(np.arange(B), finite)
     S[nonfinite, 11] = np.nan
     vm0 = g.vm[None] + rng.normal(0, 1e-3, (B, n)) * (g.bus_type == 0)
@@ -1561,7 +1561,7 @@ def test_bench_configuration_at_full_size_with_handoff(handoff, team):
     it = out["iters"].cpu().numpy()
     assert (st[nonfinite] == 2).all() and (it[nonfinite] == 0).all()
     assert (st[finite] == 1).all() and (it[finite] == steps).all()
-    for c in finite[::25]:
+    for c in finite[::25] if n_finite > 25 else finite[::3]:
         ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
                                 oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
         assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
@@ -1618,6 +1618,89 @@ def test_concurrent_handoff_calls_on_two_streams(handoff, team):
         assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12
         assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12
     assert split_ran(dpf, stats) == (team > 0)
+
+
+@pytest.mark.parametrize("opt", ["sgd", "rmsprop", "adam-constant"])
+def test_split_kernel_optimizers_and_shared_injections(handoff, opt):
+    """The split kernel (every case handed over after 32 iterations, teams of up
+    to 5 relaunched every 7 iterations) with SGD, RMSprop or Adam at a constant
+    rate, outages, and one injection row shared by all cases (s_ld = 0), follows
+    the oracle; iteration counts and statuses match."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9710, n_bus=900, n_branch=1400, n_pv=150)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 6
+    rng = np.random.default_rng(9711)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = rng.choice(nbr, B).astype(np.int32)
+    outage[0] = -1
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 90
+    o = {"sgd": dict(optimizer=oracle.OPT_SGD, lr=1e-3, beta1=0.9),
+         "rmsprop": dict(optimizer=oracle.OPT_RMSPROP, lr=1e-3, beta2=0.99, eps=1e-8),
+         "adam-constant": dict(lr=1e-3)}[opt]
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                              oracle.AdamOptions(tol=0.0, max_iter=steps, **o)) for c in range(B)]
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    dpf.set_tail_handoff(B)
+    dpf.set_tail_team(5, 7)
+    stats = dpf.split_stats()
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [r["iters"] for r in refs]
+    assert out["status"].tolist() == [r["status"] for r in refs]
+    for c in range(B):
+        assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - va0[c]).max() > 1e-5, c  # the updates moved the iterate
+    assert split_ran(dpf, stats)
+
+
+def test_split_kernel_abandoned_barriers_fall_back(handoff):
+    """With zero barrier wait bounds, teams abandon their barriers (forced from
+    the host; every wait still ends) and the items continue on the
+    multi-workgroup path from the state of a whole iteration: iterates equal the
+    same call with the tail on the multi-workgroup path, and the abandoned
+    launches are counted."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9720, n_bus=800, n_branch=1250, n_pv=120)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 8
+    rng = np.random.default_rng(9721)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    dpf.set_tail_handoff(B)
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=150, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5,
+                       threshold=0.05)
+    Sd = cu(S, torch.complex128)
+    res = {}
+    for mode in ("wide", "abandon"):
+        if mode == "wide":
+            dpf.set_tail_team(0, 128)
+        else:
+            dpf.set_tail_team(8, 16)
+            dpf.set_tail_waits(0.0, 0.0)
+        stats = dpf.split_stats()
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=opts)
+        torch.cuda.synchronize()
+        after = dpf.split_stats()
+        print(mode, after["launches"] - stats["launches"], after["abandoned"] - stats["abandoned"], flush=True)
+        assert out["iters"].tolist() == [150] * B
+        res[mode] = (vm.cpu().numpy(), va.cpu().numpy(), after["abandoned"] - stats["abandoned"])
+    assert res["abandon"][2] >= 1
+    assert np.abs(res["abandon"][0] - res["wide"][0]).max() < 1e-12
+    assert np.abs(res["abandon"][1] - res["wide"][1]).max() < 1e-12
 
 
 @pytest.mark.parametrize("seed", range(6))
