@@ -45,10 +45,11 @@ BUS_ORDER_GROUP = 2560
 # the last 192 unfinished cases of the N-1 batch leave the per-item kernel
 # (dpf_autotune_set_tail_handoff); measured 128..256 best, 0 = off
 TAIL_HANDOFF = 192
-# ... and finish on the split kernel in teams of up to 16 workgroups, relaunched every
-# 128 iterations with larger teams as cases finish (dpf_autotune_set_tail_team);
-# measured 6.9 s per step against 7.4 s on the multi-workgroup path
-TAIL_TEAM = (16, 128, 0)
+# ... and finish on the split kernel (dpf_autotune_set_tail_team): launches of 10 ms,
+# teams of up to 32 workgroups sized by each case's remaining iteration budget, so that
+# the cases that can still run longest get the most CUs; measured 6.56 s per step
+# against 7.0 s with equal teams and 7.4 s on the multi-workgroup path
+TAIL_TEAM = (32, 4096, 0, 10.0)
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -216,7 +217,8 @@ def main():
     ap.add_argument("--handoff", type=int, default=TAIL_HANDOFF,
                     help="unfinished cases handed over by the per-item kernel (0 = off)")
     ap.add_argument("--tail-team", type=str, default=":".join(map(str, TAIL_TEAM)),
-                    help="max_team:chunk:min_items of the split kernel for handed-over cases (0:1:0 = off)")
+                    help="max_team:chunk:min_items:slice_ms of the split kernel for handed-over cases "
+                         "(0:1:0:0 = off)")
     ap.add_argument("--cases", type=int, default=1024)
     ap.add_argument("--quick", action="store_true", help="small cap, no baselines (smoke of the harness)")
     ap.add_argument("--no-autograd", action="store_true")
@@ -270,7 +272,8 @@ def main():
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
         f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
     dpf.set_tail_handoff(args.handoff)
-    tail_team = [int(x) for x in args.tail_team.split(":")]
+    tt = args.tail_team.split(":")
+    tail_team = [int(x) for x in tt[:3]] + [float(tt[3]) if len(tt) > 3 else 0.0]
     dpf.set_tail_team(*tail_team)
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
     t_step = float(np.mean(times))
@@ -339,7 +342,8 @@ def main():
                                 f"(dpf_order_rcm; bandwidth {cfg['bandwidth']})",
                    "kernel_variant": vinfo,
                    "tail_handoff": args.handoff,
-                   "tail_team": {"max_team": tail_team[0], "chunk": tail_team[1], "min_items": tail_team[2]},
+                   "tail_team": {"max_team": tail_team[0], "chunk": tail_team[1], "min_items": tail_team[2],
+                                 "slice_ms": tail_team[3]},
                    "optimizer": {"lr": opts.lr, "betas": [opts.beta1, opts.beta2], "eps": opts.eps,
                                  "schedule": "plateau", "factor": opts.factor, "patience": opts.patience,
                                  "threshold": opts.threshold}},

@@ -418,8 +418,13 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             twice per iteration), relaunched every `chunk`
  *                             iterations (1..65536) with larger teams as items
  *                             finish, while more than min_items (>= 0) items are
- *                             left; the multi-workgroup path finishes the rest
- *                             (its few-item latency is lower).  A team member that waits at a barrier longer
+ *                             left; the multi-workgroup path finishes the rest.
+ *                             slice_ms in (0, 1000] also ends a launch after that
+ *                             much time and sizes the teams in proportion to each
+ *                             item's remaining budget max_iter - iters (at least 1
+ *                             workgroup, at most max_team, together at most W), so
+ *                             that the items that can run longest get the most CUs;
+ *                             0 = equal teams, launches of `chunk` iterations.  A team member that waits at a barrier longer
  *                             than 1 s (first barrier of a launch: other work may
  *                             hold the CUs) or 5 s abandons it; the items not yet
  *                             finished then continue on the multi-workgroup path.
@@ -452,7 +457,7 @@ int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
 int dpf_autotune_set_team_cap(int32_t buses);
 int dpf_autotune_set_tail_handoff(int32_t items);
 int32_t dpf_tail_handoff(void);
-int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items);
+int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms);
 int32_t dpf_tail_team(void);
 int dpf_autotune_set_tail_waits(double first_s, double later_s);
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned);

@@ -112,7 +112,7 @@ def lib():
         L.dpf_autotune_set_tail_handoff.argtypes = [_i32]
         L.dpf_autotune_set_tail_handoff.restype = ctypes.c_int
         L.dpf_tail_handoff.restype = _i32
-        L.dpf_autotune_set_tail_team.argtypes = [_i32, _i32, _i32]
+        L.dpf_autotune_set_tail_team.argtypes = [_i32, _i32, _i32, ctypes.c_double]
         L.dpf_autotune_set_tail_team.restype = ctypes.c_int
         L.dpf_tail_team.restype = _i32
         L.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
@@ -511,12 +511,14 @@ def tail_handoff() -> int:
     return int(lib().dpf_tail_handoff())
 
 
-def set_tail_team(max_team: int, chunk: int = 128, min_items: int = 0):
+def set_tail_team(max_team: int, chunk: int = 128, min_items: int = 0, slice_ms: float = 0.0):
     """dpf_autotune_set_tail_team: finish handed-over items on the split kernel,
     with at most ``max_team`` workgroups per item, relaunched every ``chunk``
-    iterations while more than ``min_items`` items are left; the
-    multi-workgroup path takes the rest (max_team 0 = that path only)."""
-    _check(lib().dpf_autotune_set_tail_team(int(max_team), int(chunk), int(min_items)))
+    iterations (and every ``slice_ms`` ms, with teams sized by each item's
+    remaining iteration budget, when > 0) while more than ``min_items`` items
+    are left; the multi-workgroup path takes the rest (max_team 0 = that path
+    only)."""
+    _check(lib().dpf_autotune_set_tail_team(int(max_team), int(chunk), int(min_items), float(slice_ms)))
 
 
 def tail_team() -> int:

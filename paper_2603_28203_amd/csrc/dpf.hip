@@ -90,6 +90,7 @@ std::atomic<int32_t> g_tail_handoff{0};  // unfinished items at which per-item k
 std::atomic<int32_t> g_tail_team{0};     // handed-over items: most workgroups per item (0 = multi-workgroup path)
 std::atomic<int32_t> g_tail_chunk{128};  // ... and iterations per launch of the split kernel
 std::atomic<int32_t> g_tail_min{0};      // ... while more than this many items are left
+std::atomic<double> g_tail_slice{0.0};   // ... and ms per launch (0 = iterations only)
 std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // since the library was loaded
 std::atomic<double> g_split_first_wait{1.0}, g_split_wait{5.0};  // barrier wait bounds (s)
 
@@ -241,7 +242,7 @@ struct SolveLayout {
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
-           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0;
+           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0, off_tfirst = 0;
     int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
@@ -302,6 +303,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(double) * dpf::kSchedWords * (size_t)B, 256);
         L.off_bar = o;  // split kernel: one arrival counter per listed item, 256 bytes apart
         o += align_up(sizeof(int32_t) * dpf::kBarStride * (size_t)B, 256);
+        L.off_tfirst = o;  // ... and its team table
+        o += align_up(sizeof(int32_t) * (size_t)(B + 1), 256);
     }
     L.total = o;
     return L;
@@ -421,9 +424,38 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
 // min_items items are left.  Items still paused when it returns (at most
 // min_items, or a team abandoned a barrier) are left in *rest / *rest_list for
 // the multi-workgroup path.
+// host-pinned staging of the split kernel's team table and the list / counts it
+// is computed from, per device; used under the device's side lock
+struct PinnedScratch {
+    int32_t *p = nullptr;
+    size_t n = 0;
+};
+PinnedScratch g_pinned[64];
+
+int pinned_scratch(int dev, size_t n, int32_t **out) {
+    PinnedScratch &ps = g_pinned[dev];
+    if (ps.n < n) {
+        if (ps.p) DPF_HIP(hipHostFree(ps.p));
+        ps.p = nullptr;
+        ps.n = 0;
+        DPF_HIP(hipHostMalloc((void **)&ps.p, n * sizeof(int32_t), hipHostMallocDefault));
+        ps.n = n;
+    }
+    *out = ps.p;
+    return DPF_OK;
+}
+
+// Split kernel for the handed-over items (see split.hpp), relaunched as items
+// finish for as long as more than min_items are left.  Team sizes per launch:
+// without a time slice T = (workgroups the device holds at once) / (items left)
+// for every item; with one, in proportion to each item's remaining iteration
+// budget (max_iter - iters), at least 1, and together at most what the device
+// holds.  Both are capped by max_team and the slices of the grid.  Items still
+// paused when it returns (at most min_items, or a team abandoned a barrier) are
+// left in *rest / *rest_list for the multi-workgroup path.
 int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const DeviceInfo &dev, int32_t *list,
-              int32_t n_list, int32_t B, int32_t max_team, int32_t chunk, int32_t min_items, int32_t *rest,
-              int32_t **rest_list) {
+              int32_t n_list, int32_t B, int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms,
+              int32_t *rest, int32_t **rest_list) {
     hipStream_t sd = dev.side;
     *rest = n_list;
     *rest_list = list;
@@ -439,30 +471,74 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1024, lds));
     const int64_t capacity = (int64_t)std::max(per_cu, 0) * dev.n_cu;
     if (capacity < 1) return DPF_OK;
+    const int64_t tmax = std::max<int64_t>(1, std::min<int64_t>(max_team, ns));
+    int32_t *hp = nullptr;  // [B] list, [B] iteration counts, [B + 1] team table
+    int rc = pinned_scratch(dev.index, 3 * (size_t)B + 1, &hp);
+    if (rc != DPF_OK) return rc;
+    int32_t *h_list = hp, *h_iters = hp + B, *h_first = hp + 2 * B;
     int32_t *hdr = (int32_t *)ws;  // header words 6 (paused count) and 7 (abandoned flag)
     dpf::SplitArgs p{};
     p.bar = (int32_t *)(ws + L.off_bar);
     p.part = (double2 *)(ws + L.off_part);
+    p.first = (const int32_t *)(ws + L.off_tfirst);
     p.Ig = a.scratch;
     p.Wg = a.scratch + 2 * a.st_stride;
     p.aborted = hdr + 7;
     p.chunk = chunk;
+    p.slice = slice_ms > 0.0 ? (int64_t)(slice_ms * 1e6 / dev.ns_per_tick) : 0;
     p.first_limit = (int64_t)(g_split_first_wait.load() * 1e9 / dev.ns_per_tick);  // other work may hold CUs
     p.limit = (int64_t)(g_split_wait.load() * 1e9 / dev.ns_per_tick);
+    const bool by_budget = p.slice > 0;
     hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, 1, p.aborted);
     int32_t *cur = list;
     int32_t *other = (int32_t *)(list == (int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
+    auto fetch_counts = [&](const int32_t *dlist, int32_t n) -> int {
+        DPF_HIP(hipMemcpyAsync(h_list, dlist, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, sd));
+        DPF_HIP(hipMemcpyAsync(h_iters, a.iters, sizeof(int32_t) * (size_t)B, hipMemcpyDeviceToHost, sd));
+        return DPF_OK;
+    };
+    if (by_budget) {
+        if ((rc = fetch_counts(cur, n_list)) != DPF_OK) return rc;
+        DPF_HIP(hipEventRecord(dev.ev_poll, sd));
+        DPF_HIP(hipEventSynchronize(dev.ev_poll));
+    }
+    std::vector<int64_t> T((size_t)B);
     while (n_list > std::max(min_items, 0)) {
-        const int64_t t = std::min<int64_t>(std::min<int64_t>(capacity / n_list, max_team), ns);
-        p.T = (int32_t)std::max<int64_t>(t, 1);
+        int64_t total = 0;
+        if (by_budget && n_list <= capacity) {
+            double wsum = 0.0;
+            for (int32_t k = 0; k < n_list; ++k) wsum += std::max(1, a.max_iter - h_iters[h_list[k]]);
+            for (int32_t k = 0; k < n_list; ++k) {
+                const double w = std::max(1, a.max_iter - h_iters[h_list[k]]);
+                T[k] = std::min<int64_t>(std::max<int64_t>((int64_t)(w / wsum * (double)capacity), 1), tmax);
+                total += T[k];
+            }
+            while (total > capacity) {  // the floor of 1 can overshoot: shrink the largest teams
+                int32_t big = 0;
+                for (int32_t k = 1; k < n_list; ++k)
+                    if (T[k] > T[big]) big = k;
+                if (T[big] <= 1) break;
+                --T[big];
+                --total;
+            }
+        } else {
+            const int64_t t = std::max<int64_t>(1, std::min<int64_t>(capacity / n_list, tmax));
+            for (int32_t k = 0; k < n_list; ++k) T[k] = t;
+        }
+        h_first[0] = 0;
+        for (int32_t k = 0; k < n_list; ++k) h_first[k + 1] = h_first[k] + (int32_t)T[k];
+        DPF_HIP(hipMemcpyAsync((void *)p.first, h_first, sizeof(int32_t) * (size_t)(n_list + 1),
+                               hipMemcpyHostToDevice, sd));
         p.list = cur;
         p.n_list = n_list;
         hipLaunchKernelGGL(dpf::split_clear_kernel, dim3((n_list + 255) / 256), dim3(256), 0, sd, n_list,
                            dpf::kBarStride, p.bar);
-        hipLaunchKernelGGL(fn, dim3(n_list * p.T), dim3(1024), lds, sd, a, p);
+        hipLaunchKernelGGL(fn, dim3(h_first[n_list]), dim3(1024), lds, sd, a, p);
         hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, sd, B, a.status, other, hdr + 6);
         DPF_HIP(hipGetLastError());
         DPF_HIP(hipMemcpyAsync(dev.pinned_count, hdr + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, sd));
+        // the next table needs the new list and counts (at most B entries are read)
+        if (by_budget && (rc = fetch_counts(other, B)) != DPF_OK) return rc;
         DPF_HIP(hipEventRecord(dev.ev_poll, sd));
         DPF_HIP(hipEventSynchronize(dev.ev_poll));
         n_list = dev.pinned_count[0];
@@ -806,14 +882,16 @@ void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned) {
     if (abandoned) *abandoned = g_split_abandoned.load();
 }
 
-int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items) {
+int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms) {
     g_err.clear();
     if (max_team < 0 || max_team > 1024) return fail(DPF_EINVAL, "max_team must be in [0, 1024]");
     if (chunk < 1 || chunk > 65536) return fail(DPF_EINVAL, "chunk must be in [1, 65536]");
     if (min_items < 0) return fail(DPF_EINVAL, "min_items must be >= 0");
+    if (!(slice_ms >= 0.0 && slice_ms <= 1000.0)) return fail(DPF_EINVAL, "slice_ms must be in [0, 1000]");
     g_tail_team.store(max_team);
     g_tail_chunk.store(chunk);
     g_tail_min.store(min_items);
+    g_tail_slice.store(slice_ms);
     return DPF_OK;
 }
 
@@ -823,6 +901,7 @@ void dpf_autotune_reset(void) {
     g_tail_team.store(0);
     g_tail_chunk.store(128);
     g_tail_min.store(0);
+    g_tail_slice.store(0.0);
     g_split_first_wait.store(1.0);
     g_split_wait.store(5.0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1204,7 +1283,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
             const int32_t team = g_tail_team.load();
             if (team > 0) {
                 int rc2 = run_split(a, L, ws, dev, list, paused, B, team, g_tail_chunk.load(), g_tail_min.load(),
-                                    &rest, &rest_list);
+                                    g_tail_slice.load(), &rest, &rest_list);
                 if (rc2 != DPF_OK) return rc2;
             }
             int rc2 = rest > 0 ? run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, rest_list, rest) : DPF_OK;

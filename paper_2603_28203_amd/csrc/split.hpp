@@ -38,8 +38,14 @@
 // update yet) or of it + 1 (barrier after B, every member's rows updated), and
 // member 0 records that count with the schedule.
 //
-// A launch runs each listed case for at most `chunk` iterations; the host then
-// drops the finished cases and relaunches the rest with larger teams.
+// A launch runs each listed case for at most `chunk` iterations and, when a time
+// slice is set, until member 0 of its team sees the slice used up (it publishes
+// that beside the team's counter before the first barrier of an iteration, so
+// that every member pauses at the same point); the host then drops the finished
+// cases and relaunches the rest.  Team sizes come from the host per launch
+// (`first`): equal, or -- with time slices -- in proportion to each case's
+// remaining iteration budget, so that the cases that can still run longest get
+// the most CUs.
 #pragma once
 
 #include "../../include/dpf.h"
@@ -56,8 +62,9 @@ constexpr int32_t kBarStride = 64;
 struct SplitArgs {
     const int32_t *list;  // [n_list] paused case indices
     int32_t n_list;
-    int32_t T;            // workgroups per case (<= slices of the grid)
+    const int32_t *first; // [n_list + 1] first workgroup of each team (sizes <= slices of the grid)
     int32_t chunk;        // iterations per launch
+    int64_t slice;        // wall-clock ticks per launch, 0 = no limit
     int32_t *bar;         // [n_list][kBarStride] arrival counters (first word of each), zero at launch
     double2 *part;        // [n_list * T] member partials (loss sum, max|r|)
     double2 *Ig;          // [B][ld] I of the A sweep
@@ -96,21 +103,29 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     extern __shared__ double2 X[];
     __shared__ double red[2][NT / kWave];
     __shared__ int bar_flag;
+    __shared__ int slice_flag;
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
-    const int team = blockIdx.x / p.T;
-    const int mem = blockIdx.x - team * p.T;
-    if (team >= p.n_list) return;  // the whole team is absent
+    int team = 0;  // largest k with first[k] <= blockIdx.x
+    for (int hi_k = p.n_list - 1; team < hi_k;) {
+        const int m = (team + hi_k + 1) >> 1;
+        if (p.first[m] <= (int)blockIdx.x) team = m;
+        else hi_k = m - 1;
+    }
+    const int T = p.first[team + 1] - p.first[team];
+    const int mem = blockIdx.x - p.first[team];
     const int c = p.list[team];
     const int n = a.n_bus;
     const int ns = (n + kWave - 1) / kWave;
-    const int rlo = (int)((int64_t)mem * ns / p.T) * kWave;
-    const int rhi = min((int)((int64_t)(mem + 1) * ns / p.T) * kWave, n);
+    const int rlo = (int)((int64_t)mem * ns / T) * kWave;
+    const int rhi = min((int)((int64_t)(mem + 1) * ns / T) * kWave, n);
     const int bw = a.sub_bw[0];
     const int xlo = max(0, rlo - bw), xhi = min(n, rhi + bw);
     int32_t *cnt = p.bar + (int64_t)team * kBarStride;
-    double2 *part = p.part + (int64_t)team * p.T;
+    int32_t *slice_up = cnt + 1;  // member 0: this launch's time slice is used up
+    double2 *part = p.part + p.first[team];
+    const int64_t t_start = wall_clock64();
 
     ItemSched sc = load_item_sched(a, c);
     const double m_res = residual_count<NT>(a.bt, 0, n, red);
@@ -221,19 +236,27 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         block_reduce2<NT>(lsum, lmax, red);
         __syncthreads();
         block_reduce2_finish<NT>(lsum, lmax, red);
-        if (tid == 0) st_dev2(part + mem, make_double2(lsum, lmax));
-        ok = team_barrier(cnt, ++nbar * p.T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
+        if (tid == 0) {
+            st_dev2(part + mem, make_double2(lsum, lmax));
+            if (mem == 0)
+                __hip_atomic_store(slice_up, p.slice > 0 && wall_clock64() - t_start >= p.slice ? 1 : 0,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        ok = team_barrier(cnt, ++nbar * T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
         if (!ok) break;
         // team totals: the same partials combined in the same order by every member
         // (their loads overlap the refill of X with w, which the stop test would
         // only discard)
         {
             double s = 0.0, m = 0.0;
-            for (int q = tid; q < p.T; q += NT) {
+            for (int q = tid; q < T; q += NT) {
                 const double2 pp = ld_dev2(part + q);
                 s += pp.x;
                 m = fmax(m, pp.y);
             }
+            // member 0 cannot rewrite the flag before every member has passed the
+            // next barrier; the barriers below hand it to the whole workgroup
+            if (tid == 0) slice_flag = __hip_atomic_load(slice_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             fill_w();
             block_reduce2<NT>(s, m, red);
             __syncthreads();
@@ -256,6 +279,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             stat = DPF_MAX_ITER;
             break;
         }
+        if (slice_flag) break;  // time slice used up: paused at the start of iteration it
 
         // ---------------- B: rows of this member
         sc.t_step += 1.0;
@@ -306,7 +330,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             }
         }
         sched_step(a, sc, loss, it);
-        ok = team_barrier(cnt, ++nbar * p.T, p.limit, &bar_flag);
+        ok = team_barrier(cnt, ++nbar * T, p.limit, &bar_flag);
         if (!ok) {
             ++it;  // the members that arrived applied this iteration's step
             break;

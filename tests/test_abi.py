@@ -147,10 +147,10 @@ def test_tail_handoff_setting_and_workspace(lib):
 
 
 def test_tail_team_setting(lib):
-    """dpf_autotune_set_tail_team validates both arguments and is undone by the
+    """dpf_autotune_set_tail_team validates its arguments and is undone by the
     reset; it does not change the workspace size."""
     lib.dpf_tail_team.restype = ctypes.c_int32
-    lib.dpf_autotune_set_tail_team.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+    lib.dpf_autotune_set_tail_team.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
     lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
     lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
                                               ctypes.c_int32, ctypes.c_int32]
@@ -159,10 +159,11 @@ def test_tail_team_setting(lib):
     assert lib.dpf_tail_team() == 0
     assert lib.dpf_autotune_set_tail_handoff(192) == 0
     before = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
-    for bad in ((-1, 128, 0), (1025, 128, 0), (8, 0, 0), (8, 65537, 0), (8, 128, -1)):
+    for bad in ((-1, 128, 0, 0.0), (1025, 128, 0, 0.0), (8, 0, 0, 0.0), (8, 65537, 0, 0.0), (8, 128, -1, 0.0),
+                (8, 128, 0, -1.0), (8, 128, 0, 1001.0), (8, 128, 0, float("nan"))):
         assert lib.dpf_autotune_set_tail_team(*bad) == -1, bad
         assert lib.dpf_tail_team() == 0
-    assert lib.dpf_autotune_set_tail_team(32, 128, 16) == 0
+    assert lib.dpf_autotune_set_tail_team(32, 128, 16, 2.5) == 0
     assert lib.dpf_tail_team() == 32
     lib.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
     for bad in ((-1.0, 1.0), (1.0, -1.0), (61.0, 1.0), (float("nan"), 1.0)):

@@ -1662,6 +1662,49 @@ def test_split_kernel_optimizers_and_shared_injections(handoff, opt):
     assert split_ran(dpf, stats)
 
 
+def test_split_kernel_budget_sized_teams(handoff):
+    """Time-sliced split launches (0.02 ms, so that cases pause at uneven
+    iteration counts) with teams sized by each case's remaining budget: iterates,
+    iteration counts and statuses equal the same call without handoff and, for
+    sampled cases, the oracle."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9730, n_bus=3000, n_branch=4500, n_pv=500)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 8
+    rng = np.random.default_rng(9731)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = rng.choice(nbr, B).astype(np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 120
+    o = dict(lr=1e-3, sched=oracle.SCHED_PLATEAU, factor=0.5, patience=4, threshold=0.05)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    res = {}
+    for mode in ("plain", "sliced"):
+        dpf.set_tail_handoff(0 if mode == "plain" else B)
+        dpf.set_tail_team(64, 4096, 0, 0.02)
+        stats = dpf.split_stats()
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+        torch.cuda.synchronize()
+        if mode == "sliced":
+            assert split_ran(dpf, stats)
+        res[mode] = (vm.cpu().numpy(), va.cpu().numpy(), out["iters"].tolist(), out["status"].tolist())
+    assert res["sliced"][2] == res["plain"][2] == [steps] * B
+    assert res["sliced"][3] == res["plain"][3]
+    assert np.abs(res["sliced"][0] - res["plain"][0]).max() < 1e-12
+    assert np.abs(res["sliced"][1] - res["plain"][1]).max() < 1e-12
+    for c in (0, 5):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
+        assert np.abs(res["sliced"][0][c] - ref["vm"]).max() < 1e-10, c
+        assert np.abs(res["sliced"][1][c] - ref["va"]).max() < 1e-10, c
+
+
 def test_split_kernel_abandoned_barriers_fall_back(handoff):
     """With zero barrier wait bounds, teams abandon their barriers (forced from
     the host; every wait still ends) and the items continue on the
