@@ -46,9 +46,9 @@ BUS_ORDER_GROUP = 2560
 # (dpf_autotune_set_tail_handoff); measured 128..256 best, 0 = off
 TAIL_HANDOFF = 192
 # ... and finish on the split kernel (dpf_autotune_set_tail_team): launches of 10 ms,
-# teams of up to 32 workgroups sized by each case's remaining iteration budget, so that
-# the cases that can still run longest get the most CUs; measured 6.56 s per step
-# against 7.0 s with equal teams and 7.4 s on the multi-workgroup path
+# teams of up to 32 workgroups sized by the square of each case's remaining iteration
+# budget, so that the cases that can still run longest get the most CUs; measured
+# 6.48 s per step against 7.0 s with equal teams and 7.4 s on the multi-workgroup path
 TAIL_TEAM = (32, 4096, 0, 10.0)
 FP64_PEAK_TFLOPS = 78.6
 

@@ -420,10 +420,11 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             finish, while more than min_items (>= 0) items are
  *                             left; the multi-workgroup path finishes the rest.
  *                             slice_ms in (0, 1000] also ends a launch after that
- *                             much time and sizes the teams in proportion to each
- *                             item's remaining budget max_iter - iters (at least 1
- *                             workgroup, at most max_team, together at most W), so
- *                             that the items that can run longest get the most CUs;
+ *                             much time and sizes the teams in proportion to the
+ *                             square of each item's remaining budget max_iter -
+ *                             iters (at least 1 workgroup, at most max_team,
+ *                             together at most W), so that the items that can run
+ *                             longest get the most CUs;
  *                             0 = equal teams, launches of `chunk` iterations.  A team member that waits at a barrier longer
  *                             than 1 s (first barrier of a launch: other work may
  *                             hold the CUs) or 5 s abandons it; the items not yet

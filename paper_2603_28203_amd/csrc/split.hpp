@@ -43,9 +43,9 @@
 // that beside the team's counter before the first barrier of an iteration, so
 // that every member pauses at the same point); the host then drops the finished
 // cases and relaunches the rest.  Team sizes come from the host per launch
-// (`first`): equal, or -- with time slices -- in proportion to each case's
-// remaining iteration budget, so that the cases that can still run longest get
-// the most CUs.
+// (`first`): equal, or -- with time slices -- in proportion to the square of
+// each case's remaining iteration budget, so that the cases that can still run
+// longest get the most CUs.
 #pragma once
 
 #include "../../include/dpf.h"
