@@ -463,9 +463,12 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     dpf::SolveArgs a = a0;
     a.handoff = 0;  // no per-item kernel polls the finished count any more
     const int32_t ns = (a.n_bus + dpf::kWave - 1) / dpf::kWave;
-    // X and the bitmap of the columns a member reads
-    const size_t lds = (size_t)a.n_bus * 16 + (size_t)(a.n_bus + 31) / 32 * 4;
-    if (lds + 512 > (size_t)dev.lds_per_block) return DPF_OK;  // the multi-workgroup path takes them
+    // X and the bitmap of the columns a member reads, then as much of the list of
+    // those columns (16-bit) as the rest of the LDS holds
+    const size_t lds_x = (size_t)a.n_bus * 16 + (size_t)(a.n_bus + 31) / 32 * 4;
+    if (lds_x + 512 > (size_t)dev.lds_per_block) return DPF_OK;  // the multi-workgroup path takes them
+    const int32_t list_cap = (int32_t)std::min<size_t>((size_t)a.n_bus, ((size_t)dev.lds_per_block - 512 - lds_x) / 2);
+    const size_t lds = lds_x + align_up((size_t)list_cap * 2, 4);
     void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<1024>;
     DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
@@ -489,6 +492,7 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     p.slice = slice_ms > 0.0 ? (int64_t)(slice_ms * 1e6 / dev.ns_per_tick) : 0;
     p.first_limit = (int64_t)(g_split_first_wait.load() * 1e9 / dev.ns_per_tick);  // other work may hold CUs
     p.limit = (int64_t)(g_split_wait.load() * 1e9 / dev.ns_per_tick);
+    p.list_cap = list_cap;
     const bool by_budget = p.slice > 0;
     hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, 1, p.aborted);
     int32_t *cur = list;

@@ -72,6 +72,7 @@ struct SplitArgs {
     int32_t *aborted;     // set when a team abandoned a barrier
     int64_t first_limit;  // wall-clock ticks a member waits at the first barrier
     int64_t limit;        // ... and at every later one
+    int32_t list_cap;     // needed-column list entries the dynamic LDS holds behind the bitmap
 };
 
 // arrival barrier of the T members of one team; false when it was abandoned
@@ -104,6 +105,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     __shared__ double red[2][NT / kWave];
     __shared__ int bar_flag;
     __shared__ int slice_flag;
+    __shared__ int scan_part[NT / kWave];
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
@@ -174,9 +176,53 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     __syncthreads();
     auto needed = [&](int i) { return (need[i >> 5] >> (i & 31)) & 1u; };
 
+    // The same columns in increasing order as a list behind the bitmap, when they
+    // fit: a refill then loads them directly instead of testing every column of
+    // the range (which is several times longer).  n_need = -1: no list.
+    const int nwords = (n + 31) / 32;
+    uint16_t *nlist = reinterpret_cast<uint16_t *>(need + nwords);
+    int n_need = -1;
+    {
+        const int per = (nwords + NT - 1) / NT;  // contiguous words per thread
+        const int w0 = min(tid * per, nwords), w1 = min(w0 + per, nwords);
+        int cnt_b = 0;
+        for (int w = w0; w < w1; ++w) cnt_b += __popc(need[w]);
+        int incl = cnt_b;  // inclusive scan over the wave, then over the waves
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) scan_part[tid / kWave] = incl;
+        __syncthreads();
+        int before = 0, total = 0;
+        for (int k = 0; k < NT / kWave; ++k) {
+            before += k < tid / kWave ? scan_part[k] : 0;
+            total += scan_part[k];
+        }
+        if (total <= p.list_cap) {
+            int pos = before + incl - cnt_b;
+            for (int w = w0; w < w1; ++w)
+                for (uint32_t bits = need[w]; bits != 0u; bits &= bits - 1u)
+                    nlist[pos++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
+            n_need = total;
+        }
+        __syncthreads();
+    }
+
     // X <- V at the needed columns of the range (and the two buses of the outage,
     // which the rank-2 term of the outage rows reads, wherever they are)
     auto fill_v = [&]() {
+        if (n_need >= 0) {
+            for (int k = tid; k < n_need; k += NT) {
+                const int i = nlist[k];
+                double sn, cs;
+                const double vmi = ld_dev(vm_c + i);
+                fast_sincos(ld_dev(va_c + i), sn, cs);
+                X[i] = make_double2(vmi * cs, vmi * sn);
+            }
+            return;
+        }
         for (int i = xlo + tid; i < xhi; i += NT) {
             if (!needed(i)) continue;
             double sn, cs;
@@ -195,6 +241,13 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         }
     };
     auto fill_w = [&]() {
+        if (n_need >= 0) {
+            for (int k = tid; k < n_need; k += NT) {
+                const int i = nlist[k];
+                X[i] = ld_dev2(Wg + i);
+            }
+            return;
+        }
         for (int i = xlo + tid; i < xhi; i += NT)
             if (needed(i)) X[i] = ld_dev2(Wg + i);
         if (of >= 0 && tid < 2) {
@@ -203,14 +256,13 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         }
     };
 
-    fill_v();
-    __syncthreads();
-
     const int it0 = a.iters[c];  // paused cases continue their iteration count
     int it = it0, stat = kPaused, nbar = 0;
     double mu = 0.0, loss = 0.0;
     bool ok = true;
     for (;; ++it) {
+        fill_v();  // X <- V (the state at the start of iteration it)
+        __syncthreads();
         if (it - it0 >= p.chunk) break;  // paused again; the host relaunches
         // ---------------- A: rows of this member
         double lsum = 0.0, lmax = 0.0;
@@ -336,8 +388,6 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             ++it;  // the members that arrived applied this iteration's step
             break;
         }
-        fill_v();
-        __syncthreads();
     }
 
     if (mem != 0 || tid != 0) return;
