@@ -469,10 +469,13 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     if (lds_x + 512 > (size_t)dev.lds_per_block) return DPF_OK;  // the multi-workgroup path takes them
     const int32_t list_cap = (int32_t)std::min<size_t>((size_t)a.n_bus, ((size_t)dev.lds_per_block - 512 - lds_x) / 2);
     const size_t lds = lds_x + align_up((size_t)list_cap * 2, 4);
-    void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<1024>;
+    // 512 threads: 168 VGPRs without spills (1024 threads spill ~37 at 128); one
+    // case alone 12.5 us per iteration against 16.4 (1024) and 16.5 (256)
+    constexpr int kSplitThreads = 512;
+    void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<kSplitThreads>;
     DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     int per_cu = 0;
-    DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 1024, lds));
+    DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSplitThreads, lds));
     const int64_t capacity = (int64_t)std::max(per_cu, 0) * dev.n_cu;
     if (capacity < 1) return DPF_OK;
     const int64_t tmax = std::max<int64_t>(1, std::min<int64_t>(max_team, ns));
@@ -542,7 +545,7 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
         p.n_list = n_list;
         hipLaunchKernelGGL(dpf::split_clear_kernel, dim3((n_list + 255) / 256), dim3(256), 0, sd, n_list,
                            dpf::kBarStride, p.bar);
-        hipLaunchKernelGGL(fn, dim3(h_first[n_list]), dim3(1024), lds, sd, a, p);
+        hipLaunchKernelGGL(fn, dim3(h_first[n_list]), dim3(kSplitThreads), lds, sd, a, p);
         hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, sd, B, a.status, other, hdr + 6);
         DPF_HIP(hipGetLastError());
         DPF_HIP(hipMemcpyAsync(dev.pinned_count, hdr + 6, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, sd));
