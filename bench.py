@@ -391,7 +391,7 @@ def main():
         log("graph: small solves issued eagerly vs replayed from a captured graph")
         line["graph"] = graph_replay()
         log("cfg3: time series, sequential vs windows of 16")
-        line["cfg3"] = cfg3_series(1000)
+        line["cfg3"] = cfg3_series(1000, tail_team)
         log("cfg4: uneven batch of 129 grids")
         line["cfg4"] = cfg4_uneven(2000)
 
@@ -435,7 +435,7 @@ def base_injections(Yg, g):
     return dpf.mismatch_grad(Yg, g.bus_type, zero, vm_p, va_p, want_grad=False)["dS"][0].contiguous()
 
 
-def cfg3_series(cap):
+def cfg3_series(cap, tail_team):
     """Time series on the 9241-bus grid: 96 quarter-hour steps, sequential
     warm-started solves (window 1) against windows of 16 steps solved as one
     batch, each step capped at `cap` Adam iterations."""
@@ -458,7 +458,16 @@ def cfg3_series(cap):
     va0 = torch.tensor(g.va, device="cuda")
     out = {"workload": f"96-step time series on the 9241-bus grid, cap {cap} iterations per step",
            "iter_cap": cap}
-    for name, window in (("sequential", 1), ("windows_of_16", 16)):
+    # few large items of one grid: the split kernel from the first iteration (the
+    # bench's tail settings, when on), and the multi-workgroup path (split kernel off)
+    runs = [("sequential_multi_workgroup", 1, False), ("windows_of_16_multi_workgroup", 16, False)]
+    if tail_team[0] > 0:
+        runs = [("sequential", 1, True), ("windows_of_16", 16, True)] + runs
+    for name, window, split in runs:
+        if split:
+            dpf.set_tail_team(*tail_team)
+        else:
+            dpf.set_tail_team(0)
         dpf.solve_series(Yg, g.bus_type, S[:window], vm0, va0, window=window, opts=solve_options(10))
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -471,6 +480,7 @@ def cfg3_series(cap):
                      "iters_median": float(np.median(it)), "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
                      "bus_iters_per_s": round(float(it.sum()) * g.n_bus / dt, 1)}
         log(f"cfg3 {name}: {dt:.2f} s, converged {int((st == 0).sum())}/96")
+    dpf.set_tail_team(*tail_team)
     return out
 
 

@@ -430,7 +430,13 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             hold the CUs) or 5 s abandons it; the items not yet
  *                             finished then continue on the multi-workgroup path.
  *                             max_team = 0 (the default): the multi-workgroup path
- *                             only.  Returns DPF_EINVAL for arguments out of range
+ *                             only.  With max_team > 0, a single-grid call of few
+ *                             large items (more than 2048 buses, at most one item
+ *                             per CU, no autotune choice for them) that the default
+ *                             routing would give to the multi-workgroup path runs
+ *                             them on the split kernel from their first iteration,
+ *                             without the per-item kernel or a handoff.  Returns
+ *                             DPF_EINVAL for arguments out of range
  *   dpf_autotune_set_tail_waits : the split kernel's barrier wait bounds in seconds,
  *                             [0, 60] each (defaults 1 s at a launch's first barrier,
  *                             5 s after it).  Every member finishes its part of an

@@ -196,17 +196,23 @@ int wide_variant_index() {
     return cnt - 1;
 }
 
-const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu) {
+// *few_large: the multi-workgroup path was chosen by default for few large items
+// (not from the autotune cache)
+const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu, bool *few_large = nullptr) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     int d = default_variant_index(n_max);
+    if (few_large) *few_large = false;
     if (d < 0) return nullptr;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const int c = g_tune_init ? g_tune[d][items_bucket(items)] : -1;
         if (c >= 0 && c < cnt && variant_fits(t[c], n_max)) return &t[c];
     }
-    if (n_max > kWideDefaultBuses && items <= n_cu) return &t[wide_variant_index()];
+    if (n_max > kWideDefaultBuses && items <= n_cu) {
+        if (few_large) *few_large = true;
+        return &t[wide_variant_index()];
+    }
     return &t[d];
 }
 
@@ -218,6 +224,7 @@ struct CallPlan {
     bool has_small = false;
     const Variant *v = nullptr;
     int32_t handoff = 0;  // tail handoff threshold for this call (0 = none)
+    bool split_direct = false;  // every item on the split kernel from its first iteration
 };
 
 bool valid_opts(const dpf_opts_t *o) {
@@ -343,6 +350,7 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.Wg = a.scratch + 2 * a.st_stride;
     w.part = (double2 *)(ws + L.off_part);
     w.items = (dpf::WideItem *)(ws + L.off_items);
+    w.bad_grid = a.bad_grid;
     w.m_res = (const double *)(ws + L.off_mres);
     w.sched = a.sched;
     w.lr = a.lr;
@@ -1069,7 +1077,14 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
         }
     }
     p.has_small = small > 0;
-    p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256);
+    bool few_large = false;
+    p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256, &few_large);
+    // few large items of one grid that the split kernel can hold, with the split
+    // kernel enabled: it runs them from the first iteration (the multi-workgroup
+    // path's iteration is launch-bound for a few items)
+    if (few_large && g_tail_team.load() > 0 && small == 1 && (!sub_offset || n_sub == 1) &&
+        (size_t)p.n_max * 16 + (size_t)(p.n_max + 31) / 32 * 4 + 512 <= (size_t)dev.lds_per_block)
+        p.split_direct = true;
     if (p.v && p.v->mode == dpf::kMulti && sub_offset && n_sub != 1) {  // batched kernel: one grid only
         int cnt = 0;
         const int d = default_variant_index(std::max(1, p.n_max));
@@ -1100,7 +1115,8 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
         dev.n_cu = 256;
     }
     const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev);
-    return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap, p.handoff > 0).total;
+    return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap,
+                        p.handoff > 0 || p.split_direct).total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -1139,7 +1155,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     const Variant *v = plan.v;
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
     const bool handoff = plan.handoff > 0;
-    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff);
+    const SolveLayout L =
+        solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff || plan.split_direct);
     const bool has_wide = L.w_total > 0;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -1200,7 +1217,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     }
     a.st_fresh = adam_state ? 0 : 1;
     a.sched = sched_state;
-    if (handoff && !sched_state) {  // paused items carry their schedule to the multi-workgroup path
+    if ((handoff || plan.split_direct) && !sched_state) {  // paused items carry their schedule
         a.sched = (double *)(ws + L.off_sched);
         hipLaunchKernelGGL(dpf::sched_init_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, opts->lr, a.sched);
     }
@@ -1238,7 +1255,32 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     const size_t lds_bytes = (size_t)entries * 16;
     const int32_t items = B * n_sub;
     std::unique_lock<std::mutex> side_lock;  // concurrent blocking calls on one device take turns
-    if (has_wide || handoff) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
+    if (has_wide || handoff || plan.split_direct) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
+    if (plan.split_direct) {
+        // every item starts paused at iteration 0; the split kernel runs them, and any
+        // it leaves (a team abandoned a barrier) finish on the multi-workgroup path
+        int32_t *list = (int32_t *)(ws + L.off_list);
+        hipLaunchKernelGGL(dpf::split_start_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, a.status, a.iters,
+                           list);
+        if (a.st_fresh) {
+            const int64_t words = 4 * (int64_t)B * ld;
+            hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, words,
+                               a.st);
+        }
+        DPF_HIP(hipGetLastError());
+        DPF_HIP(hipEventRecord(dev.ev_in, st));
+        DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
+        int32_t rest = B;
+        int32_t *rest_list = list;
+        int rc2 = run_split(a, L, ws, dev, list, B, B, g_tail_team.load(), g_tail_chunk.load(), g_tail_min.load(),
+                            g_tail_slice.load(), &rest, &rest_list);
+        if (rc2 != DPF_OK) return rc2;
+        rc2 = rest > 0 ? run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, rest_list, rest) : DPF_OK;
+        if (rc2 != DPF_OK) return rc2;
+        DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
+        DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+        return DPF_OK;
+    }
     if (has_wide) {
         DPF_HIP(hipEventRecord(dev.ev_in, st));
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));

@@ -129,6 +129,13 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     double2 *part = p.part + p.first[team];
     const int64_t t_start = wall_clock64();
 
+    if (*a.bad_grid) {  // a row longer than the declared bound (see DPF_BAD_GRID); every member leaves
+        if (mem == 0 && tid == 0) {
+            a.status[c] = DPF_BAD_GRID;
+            a.iters[c] = 0;
+        }
+        return;
+    }
     ItemSched sc = load_item_sched(a, c);
     const double m_res = residual_count<NT>(a.bt, 0, n, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
@@ -397,6 +404,23 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         stat = kPaused;
     }
     finish_item(a, c, it, stat, mu, loss, sc);
+}
+
+// a call that starts on the split kernel: every case paused at iteration 0 and
+// listed in order
+__global__ void split_start_kernel(int32_t B, int32_t *__restrict__ status, int32_t *__restrict__ iters,
+                                   int32_t *__restrict__ list) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B) return;
+    status[c] = kPaused;
+    iters[c] = 0;
+    list[c] = c;
+}
+
+// fresh optimizer moments
+__global__ void zero_f64_kernel(int64_t n, double *__restrict__ x) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.0;
 }
 
 // zero n counters spaced `stride` words apart

@@ -44,6 +44,7 @@ struct WideArgs {
     double2 *Vg, *Wg, *aIg;  // [B][ld] complex each
     double2 *part;       // [B][w_total] (loss partial, max partial)
     WideItem *items;     // [B * n_sub]
+    const int32_t *bad_grid;  // set when a row exceeded the declared width bound
     const double *m_res; // [n_sub] residual count per sub-grid
     double *sched;       // caller schedule state or null
     double lr, b1, b2, eps, tol;
@@ -136,6 +137,11 @@ __global__ void wide_item_init_kernel(WideArgs a, int32_t cap) {
         it.cool = packed >> 20;
         it.b1t = ss[4];
         it.b2t = ss[5];
+    }
+    if (it.active && *a.bad_grid) {  // see DPF_BAD_GRID (the schedule is written back unchanged)
+        it.active = 0;
+        it.status = DPF_BAD_GRID;
+        it.iters = 0;
     }
     it.lr_use = it.lr;
     a.items[idx] = it;

@@ -1705,6 +1705,90 @@ def test_split_kernel_budget_sized_teams(handoff):
         assert np.abs(res["sliced"][1][c] - ref["va"]).max() < 1e-10, c
 
 
+def test_split_kernel_runs_few_large_items_from_the_start(handoff):
+    """With the split kernel enabled, a single-grid call of few large items (which
+    the default routing gives to the multi-workgroup path) runs on the split
+    kernel from its first iteration: statuses, iteration counts and iterates
+    equal the oracle's and the multi-workgroup path's, and two resumed half
+    calls with the caller's optimizer and schedule state equal one whole call."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9740, n_bus=3000, n_branch=4500, n_pv=500)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 3
+    rng = np.random.default_rng(9741)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = rng.choice(nbr, B).astype(np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm0[1], va0[1] = g.vm, g.va  # planted: stops at iteration 0
+    outage[1] = -1
+    steps = 60
+    o = dict(lr=1e-3, sched=oracle.SCHED_PLATEAU, factor=0.5, patience=4, threshold=0.05)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    od = cu(outage, torch.int32)
+    res = {}
+    for team in (0, 32):
+        dpf.set_tail_team(team, 16)
+        stats = dpf.split_stats()
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=od, opts=dpf.Options(tol=1e-9, max_iter=steps, **o))
+        torch.cuda.synchronize()
+        assert split_ran(dpf, stats) == (team > 0)
+        res[team] = (vm.cpu().numpy(), va.cpu().numpy(), out["iters"].tolist(), out["status"].tolist())
+    assert res[32][2] == res[0][2] == [steps, 0, steps]
+    assert res[32][3] == res[0][3] == [1, 0, 1]
+    assert np.abs(res[32][0] - res[0][0]).max() < 1e-12
+    assert np.abs(res[32][1] - res[0][1]).max() < 1e-12
+    for c in (0, 2):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(tol=1e-9, max_iter=steps, **o))
+        assert np.abs(res[32][0][c] - ref["vm"]).max() < 1e-10, c
+        assert np.abs(res[32][1][c] - ref["va"]).max() < 1e-10, c
+    # resumed: two calls of 30 iterations with the caller's state equal one of 60
+    dpf.set_tail_team(32, 16)
+    half = dpf.Options(tol=0.0, max_iter=steps // 2, **o)
+    whole = dpf.Options(tol=0.0, max_iter=steps, **o)
+    out2 = {}
+    for name, calls in (("halves", (half, half)), ("whole", (whole,))):
+        vm = cu(vm0); va = cu(va0)
+        st = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
+        sch = dpf.fresh_sched_state(B, o["lr"])
+        for opts in calls:
+            dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=od, opts=opts, adam_state=st, sched_state=sch)
+        torch.cuda.synchronize()
+        out2[name] = (vm.cpu().numpy(), va.cpu().numpy(), st.cpu().numpy(), sch.cpu().numpy())
+    for k in range(4):
+        assert np.abs(out2["halves"][k] - out2["whole"][k]).max() <= 1e-12 * max(1.0, np.abs(out2["whole"][k]).max())
+
+
+@pytest.mark.parametrize("path", ["wide", "split"])
+def test_bad_grid_row_bound_on_the_shared_paths(handoff, path):
+    """A declared longest row that is too short is reported (status 3, iteration
+    count 0, iterate untouched) on the multi-workgroup path and on the split
+    kernel as on the per-item kernels."""
+    dpf = handoff
+    g = synth.config1(B=1, seed=9750, n_bus=2500, n_branch=3700, n_pv=400)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Yg.max_row_nnz = 2
+    Yg._c = None
+    dpf.set_tail_team(32 if path == "split" else 0, 16)
+    stats = dpf.split_stats()
+    B = 2
+    rng = np.random.default_rng(9751)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(max_iter=5))
+    torch.cuda.synchronize()
+    assert out["status"].tolist() == [dpf.BAD_GRID] * B and out["iters"].tolist() == [0] * B
+    assert np.array_equal(vm.cpu().numpy(), vm0) and np.array_equal(va.cpu().numpy(), va0)
+    after = dpf.split_stats()
+    assert (after["launches"] > stats["launches"]) == (path == "split")
+
+
 def test_split_kernel_abandoned_barriers_fall_back(handoff):
     """With zero barrier wait bounds, teams abandon their barriers (forced from
     the host; every wait still ends) and the items continue on the
