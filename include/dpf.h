@@ -397,8 +397,9 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             most `items` of a call's items are unfinished, the
  *                             per-item kernels pause them (every 32 iterations they
  *                             read a finished-items counter) and the call finishes
- *                             them on the multi-workgroup path, which spreads each
- *                             item over many CUs; iteration counts, optimizer and
+ *                             them on the split kernel (see below) or the
+ *                             multi-workgroup path, both of which spread each item
+ *                             over many CUs; iteration counts, optimizer and
  *                             schedule state carry over, so results equal a call
  *                             without handoff up to the rounding of the other path.
  *                             The call then returns only when every item has
@@ -409,34 +410,34 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             Set it before sizing the workspace: a handoff call
  *                             needs a larger one
  *   dpf_tail_handoff        : the current handoff threshold (0 = off)
- *   dpf_autotune_set_tail_team : how handed-over items finish.  max_team > 0: the
- *                             split kernel, which gives each item a team of
- *                             T = min(max_team, W / items left, slices of the grid)
- *                             workgroups (W = workgroups of it the device holds at
- *                             once; each member keeps the exchange vector in LDS
- *                             and the team synchronises through global memory
- *                             twice per iteration), relaunched every `chunk`
- *                             iterations (1..65536) with larger teams as items
- *                             finish, while more than min_items (>= 0) items are
+ *   dpf_autotune_set_tail_team : how handed-over items finish.  max_team = 0 (the
+ *                             default): on the multi-workgroup path.  max_team > 0:
+ *                             on the split kernel, which gives each item a team of
+ *                             workgroups (each member keeps the exchange vector in
+ *                             LDS; the team synchronises through global memory twice
+ *                             per iteration).  Launches run `chunk` iterations
+ *                             (1..65536) and are repeated with the finished items
+ *                             dropped while more than min_items (>= 0) items are
  *                             left; the multi-workgroup path finishes the rest.
- *                             slice_ms in (0, 1000] also ends a launch after that
- *                             much time and sizes the teams in proportion to the
- *                             square of each item's remaining budget max_iter -
- *                             iters (at least 1 workgroup, at most max_team,
- *                             together at most W), so that the items that can run
- *                             longest get the most CUs;
- *                             0 = equal teams, launches of `chunk` iterations.  A team member that waits at a barrier longer
- *                             than 1 s (first barrier of a launch: other work may
- *                             hold the CUs) or 5 s abandons it; the items not yet
- *                             finished then continue on the multi-workgroup path.
- *                             max_team = 0 (the default): the multi-workgroup path
- *                             only.  With max_team > 0, a single-grid call of few
- *                             large items (more than 2048 buses, at most one item
- *                             per CU, no autotune choice for them) that the default
- *                             routing would give to the multi-workgroup path runs
- *                             them on the split kernel from their first iteration,
- *                             without the per-item kernel or a handoff.  Returns
- *                             DPF_EINVAL for arguments out of range
+ *                             slice_ms = 0: equal teams, T = min(max_team, W / items
+ *                             left, slices of the grid), W = workgroups of the
+ *                             kernel the device holds at once.  slice_ms in
+ *                             (0, 1000]: a launch also ends after that much time,
+ *                             and the teams are sized in proportion to the square of
+ *                             each item's remaining budget max_iter - iters (at
+ *                             least 1 workgroup, at most max_team, together at most
+ *                             W), so that the items that can run longest get the
+ *                             most CUs.  A member that waits at a team barrier
+ *                             longer than a bound (dpf_autotune_set_tail_waits)
+ *                             abandons it; the items not yet finished then continue
+ *                             on the multi-workgroup path.  With max_team > 0, a
+ *                             single-grid call of few large items (more than 2048
+ *                             buses, at most one item per CU, no autotune choice for
+ *                             them) that the default routing would give to the
+ *                             multi-workgroup path runs them on the split kernel
+ *                             from their first iteration, without the per-item
+ *                             kernel or a handoff.  Returns DPF_EINVAL for
+ *                             arguments out of range
  *   dpf_autotune_set_tail_waits : the split kernel's barrier wait bounds in seconds,
  *                             [0, 60] each (defaults 1 s at a launch's first barrier,
  *                             5 s after it).  Every member finishes its part of an
