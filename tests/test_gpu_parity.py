@@ -1789,6 +1789,42 @@ def test_bad_grid_row_bound_on_the_shared_paths(handoff, path):
     assert (after["launches"] > stats["launches"]) == (path == "split")
 
 
+@pytest.mark.parametrize("n_bus", [64, 70, 130])
+def test_split_kernel_on_grids_of_one_to_three_slices(handoff, n_bus):
+    """Grids of 64, 70 and 130 buses (1 to 3 slices of 64 rows, the last one
+    ragged or full): the split kernel's teams shrink to the slice count and
+    the handed-over cases still follow the oracle."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9760 + n_bus, n_bus=n_bus, n_branch=int(1.4 * n_bus), n_pv=n_bus // 6)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 3
+    rng = np.random.default_rng(9770 + n_bus)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.array([-1] + list(rng.choice(nbr, B - 1)), dtype=np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 70
+    o = dict(lr=1e-3)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    dpf.set_tail_handoff(B)
+    dpf.set_tail_team(8, 9)
+    stats = dpf.split_stats()
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * B
+    for c in range(B):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+    assert split_ran(dpf, stats)
+
+
 def test_split_kernel_abandoned_barriers_fall_back(handoff):
     """With zero barrier wait bounds, teams abandon their barriers (forced from
     the host; every wait still ends) and the items continue on the
