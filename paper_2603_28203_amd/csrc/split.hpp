@@ -159,6 +159,16 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     const double2 *__restrict__ sval = a.sell.val;
     const int8_t *__restrict__ btp = a.bt;
 
+    // A team of one has no partners: plain accesses, workgroup barriers only, and
+    // its own sums are the totals.
+    const bool solo = T == 1;
+    auto ld = [&](const double *q) { return solo ? *q : ld_dev(q); };
+    auto ld2 = [&](const double2 *q) { return solo ? *q : ld_dev2(q); };
+    auto st = [&](double *q, double v) {
+        if (solo) *q = v;
+        else st_dev(q, v);
+    };
+
     // The columns the member's rows read (its own rows, their neighbours and the
     // two buses of the outage) as a bitmap behind X: the refills below load only
     // those (on the 9241-bus grid under the degree-grouped numbering, 32% of the
@@ -224,8 +234,8 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             for (int k = tid; k < n_need; k += NT) {
                 const int i = nlist[k];
                 double sn, cs;
-                const double vmi = ld_dev(vm_c + i);
-                fast_sincos(ld_dev(va_c + i), sn, cs);
+                const double vmi = ld(vm_c + i);
+                fast_sincos(ld(va_c + i), sn, cs);
                 X[i] = make_double2(vmi * cs, vmi * sn);
             }
             return;
@@ -233,16 +243,16 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         for (int i = xlo + tid; i < xhi; i += NT) {
             if (!needed(i)) continue;
             double sn, cs;
-            const double vmi = ld_dev(vm_c + i);
-            fast_sincos(ld_dev(va_c + i), sn, cs);
+            const double vmi = ld(vm_c + i);
+            fast_sincos(ld(va_c + i), sn, cs);
             X[i] = make_double2(vmi * cs, vmi * sn);
         }
         if (of >= 0 && tid < 2) {
             const int i = tid == 0 ? of : ot;
             if (i < xlo || i >= xhi) {
                 double sn, cs;
-                const double vmi = ld_dev(vm_c + i);
-                fast_sincos(ld_dev(va_c + i), sn, cs);
+                const double vmi = ld(vm_c + i);
+                fast_sincos(ld(va_c + i), sn, cs);
                 X[i] = make_double2(vmi * cs, vmi * sn);
             }
         }
@@ -251,15 +261,15 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         if (n_need >= 0) {
             for (int k = tid; k < n_need; k += NT) {
                 const int i = nlist[k];
-                X[i] = ld_dev2(Wg + i);
+                X[i] = ld2(Wg + i);
             }
             return;
         }
         for (int i = xlo + tid; i < xhi; i += NT)
-            if (needed(i)) X[i] = ld_dev2(Wg + i);
+            if (needed(i)) X[i] = ld2(Wg + i);
         if (of >= 0 && tid < 2) {
             const int i = tid == 0 ? of : ot;
-            if (i < xlo || i >= xhi) X[i] = ld_dev2(Wg + i);
+            if (i < xlo || i >= xhi) X[i] = ld2(Wg + i);
         }
     };
 
@@ -291,32 +301,46 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             lsum += rP * rP + rQ * rQ;
             lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
             Ig[il] = acc;
-            st_dev2(Wg + il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
+            const double2 w = cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v);
+            if (solo) Wg[il] = w;
+            else st_dev2(Wg + il, w);
         }
         block_reduce2<NT>(lsum, lmax, red);
         __syncthreads();
         block_reduce2_finish<NT>(lsum, lmax, red);
-        if (tid == 0) {
+        if (tid == 0 && !solo) {
             st_dev2(part + mem, make_double2(lsum, lmax));
             if (mem == 0)
                 __hip_atomic_store(slice_up, p.slice > 0 && wall_clock64() - t_start >= p.slice ? 1 : 0,
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        ok = team_barrier(cnt, ++nbar * T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
-        if (!ok) break;
+        if (!solo) {
+            ok = team_barrier(cnt, ++nbar * T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
+            if (!ok) break;
+        } else {
+            __syncthreads();
+        }
         // team totals: the same partials combined in the same order by every member
         // (their loads overlap the refill of X with w, which the stop test would
         // only discard)
         {
             double s = 0.0, m = 0.0;
-            for (int q = tid; q < T; q += NT) {
-                const double2 pp = ld_dev2(part + q);
-                s += pp.x;
-                m = fmax(m, pp.y);
+            if (solo) {
+                if (tid == 0) {  // the whole team's sums, spread over the first wave's lanes below
+                    s = lsum;
+                    m = lmax;
+                    slice_flag = p.slice > 0 && wall_clock64() - t_start >= p.slice ? 1 : 0;
+                }
+            } else {
+                for (int q = tid; q < T; q += NT) {
+                    const double2 pp = ld_dev2(part + q);
+                    s += pp.x;
+                    m = fmax(m, pp.y);
+                }
+                // member 0 cannot rewrite the flag before every member has passed the
+                // next barrier; the barriers below hand it to the whole workgroup
+                if (tid == 0) slice_flag = __hip_atomic_load(slice_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            // member 0 cannot rewrite the flag before every member has passed the
-            // next barrier; the barriers below hand it to the whole workgroup
-            if (tid == 0) slice_flag = __hip_atomic_load(slice_up, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             fill_w();
             block_reduce2<NT>(s, m, red);
             __syncthreads();
@@ -376,7 +400,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
                 const double g = (G.x * v.x + G.y * v.y) / vmi;
                 double mv = mv0, sv = sv0;
                 vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
-                st_dev(vm_c + il, vmi);
+                st(vm_c + il, vmi);
                 mv_c[il] = mv;
                 sv_c[il] = sv;
             }
@@ -384,13 +408,14 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
                 const double g = G.y * v.x - G.x * v.y;
                 double ma = ma0, sa = sa0;
                 vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
-                st_dev(va_c + il, vai);
+                st(va_c + il, vai);
                 ma_c[il] = ma;
                 sa_c[il] = sa;
             }
         }
         sched_step(a, sc, loss, it);
-        ok = team_barrier(cnt, ++nbar * T, p.limit, &bar_flag);
+        if (!solo) ok = team_barrier(cnt, ++nbar * T, p.limit, &bar_flag);
+        else __syncthreads();
         if (!ok) {
             ++it;  // the members that arrived applied this iteration's step
             break;
