@@ -446,12 +446,22 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             makes nearly every team abandon its first barrier and
  *                             hand its items to the multi-workgroup path (a way to
  *                             exercise that path).  Returns DPF_EINVAL out of range
+ *   dpf_autotune_set_case_order : mode 1: a call that may hand over its tail (see
+ *                             dpf_autotune_set_tail_handoff; one grid, at most 16384
+ *                             cases) first evaluates every case's max|r| at its start
+ *                             point and starts the cases in descending order of it
+ *                             (non-finite first, ties by index), so that the cases
+ *                             likely to run longest do not start last; results per
+ *                             case are those of the natural order up to the rounding
+ *                             of the tail path.  mode 0 (the default): cases start in
+ *                             index order.  Returns DPF_EINVAL for other modes
+ *   dpf_case_order          : the current case order mode
  *   dpf_tail_team           : the current max_team (0 = multi-workgroup path)
  *   dpf_tail_split_stats    : split-kernel launches, and launches in which a team
  *                             abandoned a barrier, since the library was loaded
  *                             (either pointer may be null)
  *   dpf_autotune_reset      : forget every choice (and the team cap, handoff, tail
- *                             team and wait settings)
+ *                             team, wait and case order settings)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
  */
@@ -467,6 +477,8 @@ int dpf_autotune_set_tail_handoff(int32_t items);
 int32_t dpf_tail_handoff(void);
 int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms);
 int32_t dpf_tail_team(void);
+int dpf_autotune_set_case_order(int32_t mode);
+int32_t dpf_case_order(void);
 int dpf_autotune_set_tail_waits(double first_s, double later_s);
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned);
 void dpf_autotune_reset(void);

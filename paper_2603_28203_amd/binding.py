@@ -117,6 +117,9 @@ def lib():
         L.dpf_tail_team.restype = _i32
         L.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
         L.dpf_autotune_set_tail_waits.restype = ctypes.c_int
+        L.dpf_autotune_set_case_order.argtypes = [_i32]
+        L.dpf_autotune_set_case_order.restype = ctypes.c_int
+        L.dpf_case_order.restype = _i32
         L.dpf_tail_split_stats.argtypes = [_P, _P]
         L.dpf_tail_split_stats.restype = None
         _lib = L
@@ -529,6 +532,17 @@ def tail_team() -> int:
 def set_tail_waits(first_s: float = 1.0, later_s: float = 5.0):
     """dpf_autotune_set_tail_waits: the split kernel's barrier wait bounds (s)."""
     _check(lib().dpf_autotune_set_tail_waits(float(first_s), float(later_s)))
+
+
+def set_case_order(mode: int):
+    """dpf_autotune_set_case_order: 1 = calls that may hand over their tail start
+    their cases by descending initial max|r|; 0 = index order."""
+    _check(lib().dpf_autotune_set_case_order(int(mode)))
+
+
+def case_order() -> int:
+    """The current case order mode."""
+    return int(lib().dpf_case_order())
 
 
 def split_stats() -> dict:

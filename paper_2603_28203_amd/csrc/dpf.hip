@@ -91,6 +91,7 @@ std::atomic<int32_t> g_tail_team{0};     // handed-over items: most workgroups p
 std::atomic<int32_t> g_tail_chunk{128};  // ... and iterations per launch of the split kernel
 std::atomic<int32_t> g_tail_min{0};      // ... while more than this many items are left
 std::atomic<double> g_tail_slice{0.0};   // ... and ms per launch (0 = iterations only)
+std::atomic<int32_t> g_case_order{0};    // handoff calls: 1 = start cases by descending initial max|r|
 std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // since the library was loaded
 std::atomic<double> g_split_first_wait{1.0}, g_split_wait{5.0};  // barrier wait bounds (s)
 
@@ -249,7 +250,8 @@ struct SolveLayout {
     int64_t entries = 0;  // sliced-ELL entries (multiple of 64)
     size_t off_nslice = 0, off_slice_off = 0, off_width = 0, off_start = 0, off_col = 0, off_val = 0;
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
-           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0, off_tfirst = 0;
+           off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0, off_tfirst = 0,
+           off_order = 0;
     int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
@@ -312,6 +314,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(int32_t) * dpf::kBarStride * (size_t)B, 256);
         L.off_tfirst = o;  // ... and its team table
         o += align_up(sizeof(int32_t) * (size_t)(B + 1), 256);
+        L.off_order = o;  // case order: [B] int32 order, [B] max|r|, [B] loss, residual count
+        o += align_up(sizeof(int32_t) * (size_t)B, 256) + 2 * align_up(sizeof(double) * (size_t)B, 256) + 256;
     }
     L.total = o;
     return L;
@@ -888,6 +892,15 @@ int dpf_autotune_set_tail_handoff(int32_t items) {
 
 int32_t dpf_tail_team(void) { return g_tail_team.load(); }
 
+int dpf_autotune_set_case_order(int32_t mode) {
+    g_err.clear();
+    if (mode < 0 || mode > 1) return fail(DPF_EINVAL, "case order mode must be 0 or 1");
+    g_case_order.store(mode);
+    return DPF_OK;
+}
+
+int32_t dpf_case_order(void) { return g_case_order.load(); }
+
 int dpf_autotune_set_tail_waits(double first_s, double later_s) {
     g_err.clear();
     if (!(first_s >= 0.0 && first_s <= 60.0) || !(later_s >= 0.0 && later_s <= 60.0))
@@ -922,6 +935,7 @@ void dpf_autotune_reset(void) {
     g_tail_chunk.store(128);
     g_tail_min.store(0);
     g_tail_slice.store(0.0);
+    g_case_order.store(0);
     g_split_first_wait.store(1.0);
     g_split_wait.store(5.0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1254,6 +1268,30 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.lds_cap = entries;
     const size_t lds_bytes = (size_t)entries * 16;
     const int32_t items = B * n_sub;
+    // handoff calls of one grid may start their cases by descending initial max|r|:
+    // the cases likely to run longest then do not start last (one evaluation of
+    // every case with the mismatch kernels, into the solve's scratch, then a rank)
+    if (handoff && !sub_offset && g_case_order.load() == 1 && B <= 16384) {
+        const int32_t n = g->n_bus;
+        const int32_t nblk = (n + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
+        int32_t *order = (int32_t *)(ws + L.off_order);
+        double *key = (double *)(ws + L.off_order + align_up(sizeof(int32_t) * (size_t)B, 256));
+        double *lossv = key + align_up(sizeof(double) * (size_t)B, 256) / sizeof(double);
+        double *m_res = lossv + align_up(sizeof(double) * (size_t)B, 256) / sizeof(double);
+        double2 *Vw = a.scratch, *ww = a.scratch + a.st_stride, *aIw = a.scratch + 2 * a.st_stride;
+        double2 *part = (double2 *)(ws + L.off_part);  // B x slices >= B x nblk entries
+        hipLaunchKernelGGL(dpf::residual_count_kernel, dim3(1), dim3(1024), 0, st, n, bus_type, m_res);
+        hipLaunchKernelGGL(dpf::polar_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, (int64_t)ld, vm, va,
+                           Vw);
+        hipLaunchKernelGGL(dpf::forward_kernel, dim3(nblk, B), dim3(dpf::kEvalBlock), 0, st, n, g->row_ptr,
+                           g->col_idx, (const double2 *)g->val, bus_type, (const double2 *)s_spec, (int64_t)s_ld,
+                           a.ov, Vw, m_res, (int64_t)ld, (double2 *)nullptr, ww, aIw, part, (double2 *)nullptr);
+        hipLaunchKernelGGL(dpf::finalize_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, nblk, part, m_res, lossv,
+                           key);
+        hipLaunchKernelGGL(dpf::rank_desc_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, key, order);
+        DPF_HIP(hipGetLastError());
+        a.order = order;
+    }
     std::unique_lock<std::mutex> side_lock;  // concurrent blocking calls on one device take turns
     if (has_wide || handoff || plan.split_direct) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
     if (plan.split_direct) {

@@ -66,6 +66,7 @@ struct SolveArgs {
     int32_t handoff;         // > 0: tail handoff threshold in unfinished items (see handoff_due)
     int32_t total_items;     // items of the call
     int32_t *done_count;     // items finished so far (handoff only), cleared per call
+    const int32_t *order;    // [items] item taken by workgroup k, or null: workgroup k takes item k
     int32_t n_bus;
     int32_t n_sub;
     int32_t B;
@@ -245,7 +246,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
     constexpr bool REG = MODE == kReg;
 
     const int tid = threadIdx.x;
-    const int item = blockIdx.x;
+    const int item = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
     const int sidx = item / a.B;
     const int c = item - sidx * a.B;
     const int lo = a.sub_off ? a.sub_off[sidx] : 0;
@@ -544,7 +545,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     __shared__ double red[2][NT / kWave];
 
     const int tid = threadIdx.x;
-    const int item = blockIdx.x;
+    const int item = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
     const int sidx = item / a.B;
     const int c = item - sidx * a.B;
     const int lo = a.sub_off ? a.sub_off[sidx] : 0;
@@ -789,7 +790,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
     __shared__ double red[2][NT / kWave];
 
     const int tid = threadIdx.x;
-    const int item = blockIdx.x;
+    const int item = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
     const int sidx = item / a.B;
     const int c = item - sidx * a.B;
     const int lo = a.sub_off ? a.sub_off[sidx] : 0;
@@ -1046,7 +1047,7 @@ __global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
     __shared__ double red[2][NT / kWave];
 
     const int tid = threadIdx.x;
-    const int item = blockIdx.x;
+    const int item = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
     const int sidx = item / a.B;
     const int c = item - sidx * a.B;
     const int lo = a.sub_off ? a.sub_off[sidx] : 0;
@@ -1662,6 +1663,25 @@ __global__ __launch_bounds__(1024) void collect_paused_kernel(int32_t n_items, c
         if (status[i] == kPaused) list[atomicAdd(&n, 1)] = i;
     __syncthreads();
     if (threadIdx.x == 0) *count = n;
+}
+
+// Case order of a call: descending initial max|r| (NaN first, ties by index), so
+// that the cases likely to run longest start first.  order[rank] = case; one
+// thread per case counts the cases ahead of it (B is small enough for O(B^2)).
+__global__ void rank_desc_kernel(int32_t B, const double *__restrict__ key, int32_t *__restrict__ order) {
+    const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= B) return;
+    auto k = [&](int32_t j) {
+        const double x = key[j];
+        return isnan(x) ? __longlong_as_double(0x7ff0000000000000LL) : x;
+    };
+    const double ki = k(i);
+    int32_t rank = 0;
+    for (int32_t j = 0; j < B; ++j) {
+        const double kj = k(j);
+        rank += (kj > ki || (kj == ki && j < i)) ? 1 : 0;
+    }
+    order[rank] = i;
 }
 
 // wall-clock stamp at the start of a solve call (for per-item completion times)

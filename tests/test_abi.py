@@ -174,6 +174,19 @@ def test_tail_team_setting(lib):
     assert lib.dpf_tail_team() == 0 and lib.dpf_tail_handoff() == 0
 
 
+def test_case_order_setting(lib):
+    """dpf_autotune_set_case_order accepts 0 and 1 only and is undone by the reset."""
+    lib.dpf_case_order.restype = ctypes.c_int32
+    lib.dpf_autotune_set_case_order.argtypes = [ctypes.c_int32]
+    lib.dpf_autotune_reset()
+    assert lib.dpf_case_order() == 0
+    for bad in (-1, 2):
+        assert lib.dpf_autotune_set_case_order(bad) == -1
+    assert lib.dpf_autotune_set_case_order(1) == 0 and lib.dpf_case_order() == 1
+    lib.dpf_autotune_reset()
+    assert lib.dpf_case_order() == 0
+
+
 def _kind(lib, i):
     t, k, st = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
     lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st))

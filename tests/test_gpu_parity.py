@@ -1825,6 +1825,55 @@ def test_split_kernel_on_grids_of_one_to_three_slices(handoff, n_bus):
     assert split_ran(dpf, stats)
 
 
+def test_case_order_by_initial_mismatch(handoff):
+    """Cases started by descending initial max|r| (outages of different
+    severity, two non-finite injections, a planted case) give the same per-case
+    statuses, iteration counts and iterates as the index order, and the oracle's."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9780, n_bus=900, n_branch=1400, n_pv=150)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 10
+    rng = np.random.default_rng(9781)
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = rng.choice(nbr, B).astype(np.int32)
+    S = np.tile(S0, (B, 1))
+    S[2, 5] = np.nan
+    S[7, 9] = np.nan
+    # noisy starts (a start exactly at the planted point makes Adam's first step
+    # normalise rounding noise, which the oracle cannot follow), but case 4 is the
+    # planted point itself without an outage: it stops at once
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm0[4], va0[4] = g.vm, g.va
+    outage[4] = -1
+    steps = 60
+    o = dict(lr=1e-3, sched=oracle.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05)
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    dpf.set_tail_handoff(4)
+    dpf.set_tail_team(8, 16)
+    res = {}
+    for mode in (0, 1):
+        dpf.set_case_order(mode)
+        vm = cu(vm0); va = cu(va0)
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        opts=dpf.Options(tol=1e-9, max_iter=steps, **o))
+        torch.cuda.synchronize()
+        res[mode] = (vm.cpu().numpy(), va.cpu().numpy(), out["iters"].tolist(), out["status"].tolist())
+    assert res[1][2] == res[0][2] and res[1][3] == res[0][3]
+    assert res[0][3][2] == res[0][3][7] == dpf.NONFINITE and res[0][3][4] == dpf.CONVERGED
+    fin = [c for c in range(B) if c not in (2, 7)]
+    assert np.abs(res[1][0][fin] - res[0][0][fin]).max() < 1e-12
+    assert np.abs(res[1][1][fin] - res[0][1][fin]).max() < 1e-12
+    for c in (0, 5):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                                oracle.AdamOptions(tol=1e-9, max_iter=steps, **o))
+        assert res[1][2][c] == ref["iters"] and res[1][3][c] == ref["status"]
+        assert np.abs(res[1][0][c] - ref["vm"]).max() < 1e-10, c
+
+
 def test_split_kernel_abandoned_barriers_fall_back(handoff):
     """With zero barrier wait bounds, teams abandon their barriers (forced from
     the host; every wait still ends) and the items continue on the
