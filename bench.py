@@ -268,7 +268,7 @@ def main():
     # with a tail handoff only the kernels that can hand over compete: the 100-iteration
     # probes cannot see the handoff, and the variants are within ~2% of each other there
     # (a batched kernel winning by noise would leave the whole tail on one CU per case)
-    handoff_kinds = ("streaming", "banded", "banded-stream", "banded-window")
+    handoff_kinds = dpf.binding.HANDOFF_KINDS
     score = {k: full["seconds"][k] + tail["seconds"][k] for k in full["seconds"]
              if args.handoff <= 0 or kinds[k] in handoff_kinds}
     # within 3% of the best the timing difference is noise: prefer the banded-stream

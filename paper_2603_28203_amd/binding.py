@@ -445,6 +445,8 @@ class DPFLoss(torch.autograd.Function):
 
 
 VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window", "banded-batched")
+# the per-item kinds that can hand their tail over (dpf_autotune_set_tail_handoff)
+HANDOFF_KINDS = ("streaming", "banded", "banded-stream", "banded-window")
 
 
 def variants():
@@ -559,7 +561,10 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     fastest in the library's autotune cache for this size class and this number
     of work items (B x sub-grids).  Variants within a fraction ``tie`` of the
     fastest count as equal and the first of them in the table is taken, which
-    keeps the choice stable under timing noise.  Returns {variant: seconds}."""
+    keeps the choice stable under timing noise.  With a tail handoff set, a
+    single-grid call chooses among the kinds that can hand over (streaming,
+    banded, banded-stream, banded-window): the fixed-length probes cannot see the
+    handoff.  Returns {variant: seconds}."""
     opts = opts or Options()
     n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))
     items = int(vm.shape[0]) * (1 if sub_offset is None else len(sub_offset) - 1)
@@ -571,8 +576,13 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
         _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, items, reps, times)
     finally:
         set_tail_handoff(handoff)
-    best = min(times.values())
-    pick = min(i for i, t in times.items() if t <= best * (1.0 + tie))
+    eligible = times
+    if handoff > 0 and sub_offset is None:
+        kinds = {v["index"]: v["kind"] for v in variants()}
+        can = {i: t for i, t in times.items() if kinds[i] in HANDOFF_KINDS}
+        eligible = can or times
+    best = min(eligible.values())
+    pick = min(i for i, t in eligible.items() if t <= best * (1.0 + tie))
     _check(lib().dpf_autotune_set_items(n_max, items, pick))
     return {"choice": pick, "seconds": times, "n_max": n_max, "items": items, "iters": iters}
 

@@ -1825,6 +1825,34 @@ def test_split_kernel_on_grids_of_one_to_three_slices(handoff, n_bus):
     assert split_ran(dpf, stats)
 
 
+def test_autotune_with_handoff_keeps_a_kind_that_hands_over(handoff):
+    """autotune() times every eligible variant; with a tail handoff set it
+    chooses among the kinds that can hand over, and a solve then does."""
+    dpf = handoff
+    base = synth.config1(B=1, seed=9790, n_bus=900, n_branch=1400, n_pv=150)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 6
+    rng = np.random.default_rng(9791)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    dpf.set_tail_handoff(B)
+    dpf.set_tail_team(8, 16)
+    r = dpf.autotune(Yg, g.bus_type, Sd, cu(vm0), cu(va0), iters=5, reps=1)
+    kinds = {v["index"]: v["kind"] for v in dpf.variants()}
+    print("autotune choice", r["choice"], kinds[r["choice"]], flush=True)
+    assert kinds[r["choice"]] in dpf.binding.HANDOFF_KINDS
+    assert len(r["seconds"]) > 1 and dpf.tail_handoff() == B
+    stats = dpf.split_stats()
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=60))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [60] * B
+    assert split_ran(dpf, stats)
+
+
 def test_case_order_by_initial_mismatch(handoff):
     """Cases started by descending initial max|r| (outages of different
     severity, two non-finite injections, a planted case) give the same per-case
