@@ -43,14 +43,14 @@ HBM_PEAK_GBS = 8000.0
 # 0.41 at a window of 256 (padding 1.25x)
 BUS_ORDER_GROUP = 2560
 # the last 192 unfinished cases of the N-1 batch leave the per-item kernel
-# (dpf_autotune_set_tail_handoff); measured 128..256 best, 0 = off
+# (dpf_route_t.tail_handoff); measured 128..256 best, 0 = off
 TAIL_HANDOFF = 192
-# ... and finish on the split kernel (dpf_autotune_set_tail_team): launches of 10 ms,
+# ... and finish on the split kernel (dpf_route_t.tail_team and the fields after it): launches of 10 ms,
 # teams of up to 32 workgroups sized by the square of each case's remaining iteration
 # budget, so that the cases that can still run longest get the most CUs; measured
 # 6.48 s per step against 7.0 s with equal teams and 7.4 s on the multi-workgroup path
 TAIL_TEAM = (32, 4096, 0, 10.0)
-# ... and the cases start by descending initial max|dS| (dpf_autotune_set_case_order):
+# ... and the cases start by descending initial max|dS| (dpf_route_t.case_order):
 # a severe outage that starts late would otherwise set the end of the step; measured
 # 6.12 s per step against 6.33 s in index order
 CASE_ORDER = 1
@@ -122,7 +122,7 @@ def make_cfg2(B):
     return cfg, g, Yg, S, bt, out, vm0, va0
 
 
-def run_fused(Yg, bt, S, out, vm0, va0, opts, steps, warmup):
+def run_fused(Yg, bt, S, out, vm0, va0, opts, steps, warmup, route=None):
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -145,7 +145,7 @@ def run_fused(Yg, bt, S, out, vm0, va0, opts, steps, warmup):
         e1 = torch.cuda.Event(enable_timing=True)
         t0 = time.perf_counter()
         e0.record(stream)
-        dpf.solve(Yg, bt, S, vm, va, opts=opts, outage=out, workspace=ws, outputs=outs)
+        dpf.solve(Yg, bt, S, vm, va, opts=opts, outage=out, workspace=ws, outputs=outs, route=route)
         e1.record(stream)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -279,17 +279,14 @@ def main():
     near = [k for k, v in score.items() if v <= 1.03 * best]
     rank = {"banded-stream": 0, "banded-window": 1, "banded": 1, "banded-batched": 1}
     choice = min(near, key=lambda k: (rank.get(kinds[k], 2), score[k]))
-    dpf.lib().dpf_autotune_set_items(g.n_bus, B, choice)  # the batch's own item bucket
-    tune = {"choice": choice}
     vinfo = dpf.variants()[choice]
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
         f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
-    dpf.set_tail_handoff(args.handoff)
     tt = args.tail_team.split(":")
     tail_team = [int(x) for x in tt[:3]] + [float(tt[3]) if len(tt) > 3 else 0.0]
-    dpf.set_tail_team(*tail_team)
-    dpf.set_case_order(args.case_order)
-    times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup)
+    route = dpf.Route(variant=choice, tail_handoff=args.handoff, tail_team=tail_team[0], tail_chunk=tail_team[1],
+                      tail_min_items=tail_team[2], tail_slice_ms=tail_team[3], case_order=args.case_order)
+    times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup, route)
     t_step = float(np.mean(times))
     t_kern = float(np.mean(kern))
     conv = int((res["status"] == 0).sum())
@@ -311,9 +308,8 @@ def main():
              }[vinfo["kind"]]
     # roofline of the dominant kernel on one launch of it alone: every item active for
     # 200 iterations (no stop test, no handoff), timed with HIP events on its stream
-    dpf.set_tail_handoff(0)
     fixed = dpf.Options(**{**opts.__dict__, "tol": 0.0, "max_iter": 200})
-    tf, kf, _, _, _ = run_fused(Yg, bt, S, out, vm0, va0, fixed, 1, 1)
+    tf, kf, _, _, _ = run_fused(Yg, bt, S, out, vm0, va0, fixed, 1, 1, dpf.Route(variant=choice))
     steady_bytes = B * 200 * n * 96 + 200 * 2 * (20 * nnz + 4 * (n + 1))
     steady = steady_bytes / kf[0] / 1e9
     traffic = pmc_traffic(kname)
@@ -396,9 +392,7 @@ def main():
         scr = solve_options(1000)
         scr.tol = 1e-3
         scr.beta1, scr.beta2, scr.patience = 0.9, 0.999, 1000
-        dpf.set_tail_handoff(args.handoff)
-        ts, _, rs, _, _ = run_fused(Yg, bt, S, out, vm0, va0, scr, 1, 1)
-        dpf.set_tail_handoff(0)
+        ts, _, rs, _, _ = run_fused(Yg, bt, S, out, vm0, va0, scr, 1, 1, route)
         line["screening"] = {"tol": 1e-3, "iter_cap": 1000, "betas": [scr.beta1, scr.beta2], "s": round(ts[0], 4),
                              "converged": int((rs["status"] == 0).sum()),
                              "solves_per_s": round(int((rs["status"] == 0).sum()) / ts[0], 1),
@@ -482,14 +476,12 @@ def cfg3_series(cap, tail_team):
     if tail_team[0] > 0:
         runs = [("sequential", 1, True), ("windows_of_16", 16, True)] + runs
     for name, window, split in runs:
-        if split:
-            dpf.set_tail_team(*tail_team)
-        else:
-            dpf.set_tail_team(0)
-        dpf.solve_series(Yg, g.bus_type, S[:window], vm0, va0, window=window, opts=solve_options(10))
+        rt = dpf.Route(tail_team=tail_team[0], tail_chunk=tail_team[1], tail_min_items=tail_team[2],
+                       tail_slice_ms=tail_team[3]) if split else dpf.Route()
+        dpf.solve_series(Yg, g.bus_type, S[:window], vm0, va0, window=window, opts=solve_options(10), route=rt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        r = dpf.solve_series(Yg, g.bus_type, S, vm0, va0, window=window, opts=opts)
+        r = dpf.solve_series(Yg, g.bus_type, S, vm0, va0, window=window, opts=opts, route=rt)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         it = r["iters"].cpu().numpy()
@@ -498,7 +490,6 @@ def cfg3_series(cap, tail_team):
                      "iters_median": float(np.median(it)), "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
                      "bus_iters_per_s": round(float(it.sum()) * g.n_bus / dt, 1)}
         log(f"cfg3 {name}: {dt:.2f} s, converged {int((st == 0).sum())}/96")
-    dpf.set_tail_team(*tail_team)
     return out
 
 

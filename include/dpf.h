@@ -56,13 +56,14 @@ extern "C" {
 #define DPF_MAX_ITER 1
 #define DPF_NONFINITE 2
 #define DPF_BAD_GRID 3   /* a CSR row is longer than the grid's declared max_row_nnz */
+#define DPF_BAD_OUTAGE 4 /* the case's outage index is neither -1 nor a branch index */
 
 /* learning-rate schedules (Table 2 and Table 3 of the paper use the last two) */
 #define DPF_SCHED_CONSTANT 0
 #define DPF_SCHED_PLATEAU 1  /* reduce-on-plateau, mode min, relative threshold */
 #define DPF_SCHED_STEP 2     /* lr *= factor every `patience` iterations */
 
-/* optimizers (Sec. 6.1 compares Adam, SGD and RMSprop) */
+/* optimizers (Sec. 6.3 names Adam, SGD and RMSprop as the searched optimizers) */
 #define DPF_OPT_ADAM 0
 #define DPF_OPT_SGD 1      /* momentum beta1 (0 = plain gradient descent) */
 #define DPF_OPT_RMSPROP 2  /* smoothing beta2, no momentum, not centred */
@@ -105,7 +106,10 @@ typedef struct dpf_grid {
  *            {best = L; bad = 0} else bad++; during cooldown bad is reset;
  *            if bad > patience {lr = max(lr*factor, min_lr) when the decrease
  *            exceeds sched_eps; cooldown restarts; bad = 0}.
- *   STEP:    lr *= factor after every `patience` iterations.
+ *   STEP:    lr *= factor after every update whose persistent step count t
+ *            (1, 2, ... over all calls that continue one schedule state) is a
+ *            multiple of `patience` (PyTorch's StepLR with step_size = patience,
+ *            gamma = factor), so a resumed call keeps the phase of the decay.
  */
 typedef struct dpf_opts {
     double lr;
@@ -177,8 +181,10 @@ int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const i
  *   g_vm, g_va    : device [B][ld] out, nullable (both or neither)
  *   workspace     : device, >= dpf_mismatch_grad_workspace_bytes(n_bus, B) bytes
  * Results are deterministic (fixed reduction order).  Errors: DPF_EINVAL,
- * DPF_ENOMEM, DPF_EHIP.  Outage indices are not range-checked on the host:
- * an index outside [0, n_branch) is treated as "no outage" by the kernels.
+ * DPF_ENOMEM, DPF_EHIP.  Outage indices live on the device, so the host does not
+ * see them: a case whose index is neither -1 nor in [0, n_branch) gets NaN in
+ * dS, loss, max_mis and every learnable entry of the gradient, so that a
+ * contingency that was never applied cannot pass for the base case.
  */
 int dpf_mismatch_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus_type,
                       const double *s_spec, int32_t s_ld, const int32_t *outage,
@@ -214,6 +220,85 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
                    void *stream);
 
 /*
+ * Per-call routing of dpf_solve_batch: which kernel runs the items and how the
+ * last items of a call finish.  Every setting belongs to the call that passes it
+ * (nothing is process-wide except the autotune cache below), so concurrent calls
+ * on different streams may use different settings.  dpf_route_default fills the
+ * defaults; a NULL route means the defaults.  The same route must be passed to
+ * dpf_solve_workspace_bytes when sizing the workspace of the call.
+ *   variant        : -1 (default): the autotune cache, else the default routing;
+ *                    >= 0: this variant for the items that fit one workgroup
+ *                    (DPF_EINVAL if it cannot hold the largest such sub-grid)
+ *   team_cap       : sub-grids above this many buses take the multi-workgroup path
+ *                    (several workgroups per item, three kernels per iteration,
+ *                    host polls every 32 iterations) even when they would fit one
+ *                    workgroup's LDS; 0 (default) = the LDS limit
+ *   tail_handoff   : single-grid calls: once at most this many items are
+ *                    unfinished, the per-item kernels pause them (every 32
+ *                    iterations they read a finished-items counter) and the call
+ *                    finishes them on the split kernel or the multi-workgroup
+ *                    path, both of which spread each item over many CUs;
+ *                    iteration counts, optimizer and schedule state carry over,
+ *                    so results equal a call without handoff up to the rounding
+ *                    of the other path.  Applies to the streaming, banded and
+ *                    windowed kernels; a call of at most this many items is
+ *                    handed over after its first 32 iterations.  0 (default) = off
+ *   tail_team      : how handed-over items finish.  0 (default): on the
+ *                    multi-workgroup path.  > 0 (at most 1024): on the split
+ *                    kernel, which gives each item a team of at most this many
+ *                    workgroups (each member keeps the exchange vector in LDS; the
+ *                    team synchronises through global memory twice per iteration).
+ *                    With tail_team > 0, a single-grid call of few large items
+ *                    (more than 2048 buses, at most one item per CU, no variant
+ *                    chosen for them) runs them on the split kernel from their
+ *                    first iteration, without the per-item kernel or a handoff
+ *   tail_chunk     : iterations per split-kernel launch, 1..65536 (default 128);
+ *                    launches repeat with the finished items dropped while more
+ *                    than tail_min_items (>= 0, default 0) items are left; the
+ *                    multi-workgroup path finishes the rest
+ *   tail_slice_ms  : 0 (default): equal teams, T = min(tail_team, W / items left,
+ *                    slices of the grid), W = workgroups of the kernel the device
+ *                    holds at once.  In (0, 1000]: a launch also ends after that
+ *                    much time, and teams are sized in proportion to the square of
+ *                    each item's remaining budget max_iter - iters (at least 1, at
+ *                    most tail_team, together at most W)
+ *   tail_first_wait_s, tail_wait_s : the split kernel's barrier wait bounds in
+ *                    seconds, [0, 60] each (defaults 1 at a launch's first
+ *                    barrier, where another stream's kernels may still hold CUs,
+ *                    and 5 after it).  A member that waits longer abandons the
+ *                    barrier; its item then finishes on the multi-workgroup path
+ *                    (every member finishes its part of an iteration before it
+ *                    arrives, so an abandoned barrier leaves a whole iteration)
+ *   case_order     : 1: a call that may hand over its tail (one grid, at most
+ *                    16384 cases) first evaluates every case's max|r| at its start
+ *                    point and starts the cases in descending order of it
+ *                    (non-finite first, ties by index); results per case are those
+ *                    of index order up to the rounding of the tail path.  0
+ *                    (default): index order
+ * A call with tail_handoff > 0, a split-kernel start (tail_team > 0 and few large
+ * items) or items above the LDS or team cap BLOCKS the host until it is done and
+ * cannot be captured in a graph; every other call only enqueues work (one kernel
+ * launch for the items plus a few set-up kernels) and can be captured.
+ * A field out of range makes the call return DPF_EINVAL.
+ */
+typedef struct dpf_route {
+    int32_t variant;
+    int32_t team_cap;
+    int32_t tail_handoff;
+    int32_t tail_team;
+    int32_t tail_chunk;
+    int32_t tail_min_items;
+    double tail_slice_ms;
+    double tail_first_wait_s;
+    double tail_wait_s;
+    int32_t case_order;
+    int32_t reserved; /* 0 */
+} dpf_route_t;
+
+/* Fill *route with the defaults (host; no device call). */
+void dpf_route_default(dpf_route_t *route);
+
+/*
  * dpf_solve_batch -- the DPF iteration (Algorithm 1 with Adam) run to
  * convergence for many independent problems in ONE kernel launch.
  *
@@ -225,7 +310,9 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  * do not share a loss).  An item stops when max|dS| < tol (status 0), when its
  * iteration count reaches max_iter (status 1), or when its mismatch becomes
  * non-finite (status 2); a stopped item leaves the kernel while others go on.
- * Status 3 (DPF_BAD_GRID, iters 0) reports a CSR row longer than g->max_row_nnz.
+ * Status 3 (DPF_BAD_GRID, iters 0) reports a CSR row longer than g->max_row_nnz;
+ * status 4 (DPF_BAD_OUTAGE, iters 0, max_mis and loss NaN, vm/va and the optimizer
+ * state untouched) a case whose outage index is neither -1 nor a branch index.
  * Per call the library re-lays Y out in the workspace as 64-row slices
  * (column-major within a slice) so that each wave reads its rows' neighbour
  * entries with coalesced loads.
@@ -242,7 +329,8 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *   B, ld         : cases; leading dimension of per-case arrays
  *   bus_type      : device int8 [n_bus] (one slack per sub-grid)
  *   s_spec, s_ld  : as in dpf_mismatch_grad
- *   outage        : device int32 [B] or NULL (requires n_sub == 1)
+ *   outage        : device int32 [B] or NULL (requires n_sub == 1): -1 or a branch
+ *                   index per case (see status DPF_BAD_OUTAGE)
  *   vm, va        : device [B][ld] in: start point (flat or warm), out: result
  *                   (the voltages of the last stop test).  Entries that are not
  *                   learnable (|V| at PV/slack, angle at the slack) are unchanged.
@@ -255,25 +343,30 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                   adam_state) of a previous call continues the same iteration
  *                   bit for bit.
  *   opts          : host
+ *   route         : host, nullable (defaults): kernel choice and tail settings of
+ *                   this call (dpf_route_t)
  *   iters, status : device int32 [B*n_sub] out (index c*n_sub + s); iters = number
  *                   of Adam updates applied in this call
  *   max_mis, loss : device double [B*n_sub] out, at the returned voltages
  *   done_ns       : device int64 [B*n_sub] out, nullable: nanoseconds from the start of
  *                   the call's kernels to the item's stop (time to converge per item)
- *   workspace     : device, >= dpf_solve_workspace_bytes(g, n_sub, sub_offset, B, ld) bytes
- * Errors: DPF_EINVAL (sizes, pointers, opts out of range, a sub-grid larger than
- * the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
+ *   workspace     : device, >= dpf_solve_workspace_bytes(g, n_sub, sub_offset, B, ld,
+ *                   route) bytes
+ * Errors: DPF_EINVAL (sizes, pointers, opts or route out of range, a sub-grid
+ * larger than the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
  */
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
                     const int32_t *sub_offset_dev, int32_t B,
                     int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
                     const int32_t *outage, double *vm, double *va, double *adam_state,
-                    double *sched_state, const dpf_opts_t *opts, int32_t *iters,
-                    int32_t *status, double *max_mis, double *loss, int64_t *done_ns,
-                    void *workspace, size_t ws_bytes, void *stream);
+                    double *sched_state, const dpf_opts_t *opts, const dpf_route_t *route,
+                    int32_t *iters, int32_t *status, double *max_mis, double *loss,
+                    int64_t *done_ns, void *workspace, size_t ws_bytes, void *stream);
 
+/* Workspace bytes of the dpf_solve_batch call with these sizes and this route
+ * (nullable); 0 for invalid sizes or an invalid route. */
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
-                                 int32_t B, int32_t ld);
+                                 int32_t B, int32_t ld, const dpf_route_t *route);
 
 /*
  * dpf_solve_series -- a time series of T power flows on one grid (Sec. 6.4: time
@@ -287,15 +380,18 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
  *   vm, va   : device [T][ld] out: the solution returned for each step
  *   iters, status, max_mis, loss, done_ns : [T] as in dpf_solve_batch (done_ns per
  *              window start, nullable)
- *   workspace: >= dpf_solve_series_workspace_bytes(g, window, ld)
+ *   route    : host, nullable: routing of every window's dpf_solve_batch call
+ *   workspace: >= dpf_solve_series_workspace_bytes(g, window, ld, route)
  */
 int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_t *bus_type,
                      const double *s_series, int32_t s_ld, const double *vm0, const double *va0,
-                     double *vm, double *va, int32_t ld, const dpf_opts_t *opts, int32_t *iters,
-                     int32_t *status, double *max_mis, double *loss, int64_t *done_ns,
-                     void *workspace, size_t ws_bytes, void *stream);
+                     double *vm, double *va, int32_t ld, const dpf_opts_t *opts,
+                     const dpf_route_t *route, int32_t *iters, int32_t *status, double *max_mis,
+                     double *loss, int64_t *done_ns, void *workspace, size_t ws_bytes,
+                     void *stream);
 
-size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld);
+size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld,
+                                        const dpf_route_t *route);
 
 /*
  * dpf_order_rcm -- a bus numbering of small bandwidth (reverse Cuthill-McKee on
@@ -337,7 +433,9 @@ int dpf_order_rcm(int32_t n_bus, int32_t n_branch, const int32_t *from, const in
  *   va        : device [B][ld] in: start angles (slack entry = slack angle;
  *               others: the CG start, e.g. 0), out: DC angles (slack unchanged)
  *   iters     : device int32 [B] out, nullable: CG iterations
- *   residual  : device double [B] out, nullable: final ||r||_2 / ||P||_2
+ *   residual  : device double [B] out, nullable: final ||r||_2 / ||P||_2 (NaN, with
+ *               iters 0 and va untouched, for a case whose outage index is neither
+ *               -1 nor a branch index)
  *   workspace : >= dpf_dc_init_workspace_bytes(n_bus, B)
  * Errors: DPF_EINVAL, DPF_ENOMEM, DPF_EUNSUPPORTED (more buses than one
  * workgroup's LDS holds at 8 B per bus), DPF_EHIP.
@@ -350,20 +448,22 @@ int dpf_dc_init(const dpf_grid_t *g_dc, int32_t B, int32_t ld, const int8_t *bus
 size_t dpf_dc_init_workspace_bytes(int32_t n_bus, int32_t B);
 
 /* Largest sub-grid (buses) one workgroup can hold on this device; larger sub-grids
- * are solved by several workgroups (see dpf_autotune_set_team_cap). */
+ * are solved by several workgroups (see dpf_route_t.team_cap). */
 int32_t dpf_solve_max_sub_buses(void);
 
 /*
  * Kernel variants and the autotune cache.  dpf_solve_batch picks a kernel
  * variant (workgroup size, buses per thread, register-resident or streaming
- * state) from the largest sub-grid of the call and the number of work items.
- * Sizes are grouped into classes (the smallest variant that holds them) and
- * item counts into buckets (<= 64, <= 256, more); dpf_autotune_set records, for
- * the class of n_max, which variant to use instead -- a project-side autotuner
- * times the eligible variants on real inputs and stores the fastest.  Without a
+ * state) from the largest sub-grid of the call and the number of work items,
+ * unless the call's route names one.  Sizes are grouped into classes (the
+ * smallest variant that holds them) and item counts into buckets (<= 64, <= 256,
+ * more); dpf_autotune_set records, for the class of n_max, which variant to use
+ * instead -- a project-side autotuner times the eligible variants on real inputs
+ * (each probe names its variant in its route) and stores the fastest.  Without a
  * recorded choice, items above 2048 buses that do not fill the device (items <=
  * compute units) take the multi-workgroup path, the others the default variant
- * of their class.  The cache is process-wide and guarded by a mutex.
+ * of their class.  The cache is the library's only process-wide setting and is
+ * guarded by a mutex.
  *   dpf_solve_variant_count : number of variants
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
  *                             and the kind: register-resident (0), streaming (1),
@@ -389,79 +489,11 @@ int32_t dpf_solve_max_sub_buses(void);
  *   dpf_autotune_set        : record `variant` for every item bucket of the class
  *                             of n_max; DPF_EINVAL if it cannot hold n_max buses
  *   dpf_autotune_set_items  : record it for the bucket of `items` only
- *   dpf_autotune_set_team_cap : sub-grids above `buses` take the multi-workgroup
- *                             path (several workgroups per item, three kernels per
- *                             iteration, host polls every 32 iterations) even when
- *                             they would fit one workgroup's LDS; 0 = the LDS limit
- *   dpf_autotune_set_tail_handoff : tail handoff for single-grid calls: once at
- *                             most `items` of a call's items are unfinished, the
- *                             per-item kernels pause them (every 32 iterations they
- *                             read a finished-items counter) and the call finishes
- *                             them on the split kernel (see below) or the
- *                             multi-workgroup path, both of which spread each item
- *                             over many CUs; iteration counts, optimizer and
- *                             schedule state carry over, so results equal a call
- *                             without handoff up to the rounding of the other path.
- *                             The call then returns only when every item has
- *                             finished (it cannot be captured in a graph).  Applies
- *                             to the streaming, banded and windowed kernels; 0 (the
- *                             default) turns it off.  A call of at most `items`
- *                             items is handed over after its first 32 iterations.
- *                             Set it before sizing the workspace: a handoff call
- *                             needs a larger one
- *   dpf_tail_handoff        : the current handoff threshold (0 = off)
- *   dpf_autotune_set_tail_team : how handed-over items finish.  max_team = 0 (the
- *                             default): on the multi-workgroup path.  max_team > 0:
- *                             on the split kernel, which gives each item a team of
- *                             workgroups (each member keeps the exchange vector in
- *                             LDS; the team synchronises through global memory twice
- *                             per iteration).  Launches run `chunk` iterations
- *                             (1..65536) and are repeated with the finished items
- *                             dropped while more than min_items (>= 0) items are
- *                             left; the multi-workgroup path finishes the rest.
- *                             slice_ms = 0: equal teams, T = min(max_team, W / items
- *                             left, slices of the grid), W = workgroups of the
- *                             kernel the device holds at once.  slice_ms in
- *                             (0, 1000]: a launch also ends after that much time,
- *                             and the teams are sized in proportion to the square of
- *                             each item's remaining budget max_iter - iters (at
- *                             least 1 workgroup, at most max_team, together at most
- *                             W), so that the items that can run longest get the
- *                             most CUs.  A member that waits at a team barrier
- *                             longer than a bound (dpf_autotune_set_tail_waits)
- *                             abandons it; the items not yet finished then continue
- *                             on the multi-workgroup path.  With max_team > 0, a
- *                             single-grid call of few large items (more than 2048
- *                             buses, at most one item per CU, no autotune choice for
- *                             them) that the default routing would give to the
- *                             multi-workgroup path runs them on the split kernel
- *                             from their first iteration, without the per-item
- *                             kernel or a handoff.  Returns DPF_EINVAL for
- *                             arguments out of range
- *   dpf_autotune_set_tail_waits : the split kernel's barrier wait bounds in seconds,
- *                             [0, 60] each (defaults 1 s at a launch's first barrier,
- *                             5 s after it).  Every member finishes its part of an
- *                             iteration before it arrives, so an abandoned barrier
- *                             leaves the state of a whole iteration; a bound of 0
- *                             makes nearly every team abandon its first barrier and
- *                             hand its items to the multi-workgroup path (a way to
- *                             exercise that path).  Returns DPF_EINVAL out of range
- *   dpf_autotune_set_case_order : mode 1: a call that may hand over its tail (see
- *                             dpf_autotune_set_tail_handoff; one grid, at most 16384
- *                             cases) first evaluates every case's max|r| at its start
- *                             point and starts the cases in descending order of it
- *                             (non-finite first, ties by index), so that the cases
- *                             likely to run longest do not start last; results per
- *                             case are those of the natural order up to the rounding
- *                             of the tail path.  mode 0 (the default): cases start in
- *                             index order.  Returns DPF_EINVAL for other modes
- *   dpf_case_order          : the current case order mode
- *   dpf_tail_team           : the current max_team (0 = multi-workgroup path)
+ *   dpf_autotune_reset      : forget every choice
  *   dpf_tail_split_stats    : split-kernel launches, and launches in which a team
- *                             abandoned a barrier, since the library was loaded
- *                             (either pointer may be null)
- *   dpf_autotune_reset      : forget every choice (and the team cap, handoff, tail
- *                             team, wait and case order settings)
+ *                             abandoned a barrier, since the library was loaded,
+ *                             over all calls (statistics only; either pointer may
+ *                             be null)
  * Items larger than the LDS limit always take the multi-workgroup path; a call
  * that has such items returns only after they have finished.
  */
@@ -472,14 +504,6 @@ int dpf_solve_variant_for(int32_t n_max);
 int dpf_solve_variant_for_items(int32_t n_max, int64_t items);
 int dpf_autotune_set(int32_t n_max, int variant);
 int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant);
-int dpf_autotune_set_team_cap(int32_t buses);
-int dpf_autotune_set_tail_handoff(int32_t items);
-int32_t dpf_tail_handoff(void);
-int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms);
-int32_t dpf_tail_team(void);
-int dpf_autotune_set_case_order(int32_t mode);
-int32_t dpf_case_order(void);
-int dpf_autotune_set_tail_waits(double first_s, double later_s);
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned);
 void dpf_autotune_reset(void);
 

@@ -341,7 +341,7 @@ typedef struct {
     int32_t cooldown;   /* plateau: iterations without counting after a decrease */
     double min_lr;      /* plateau: lower bound on lr                             */
     double sched_eps;   /* plateau: decreases smaller than this are skipped       */
-    /* optimizer (Sec. 6.1 compares Adam, SGD and RMSprop): 0 Adam, 1 SGD with
+    /* optimizer (Sec. 6.3 names Adam, SGD and RMSprop): 0 Adam, 1 SGD with
        momentum beta1 (0 = plain), 2 RMSprop with smoothing beta2, no momentum */
     int32_t optimizer;
 } orc_opts_t;
@@ -430,8 +430,9 @@ int32_t orc_solve_adam(int32_t n, const int32_t *rp, const int32_t *ci,
                 bad = 0;
             }
         } else if (o->sched == 2) {
-            /* step: lr = lr0 * gamma^floor(steps / step_size) */
-            int32_t steps = k + 1;
+            /* StepLR: lr = lr0 * gamma^floor(t / step_size), t the persistent count
+               of optimizer steps (a resumed solve continues the decay phase) */
+            int32_t steps = tstart + k + 1;
             if (o->patience > 0 && steps % o->patience == 0) lr = lr * o->factor;
         }
     }

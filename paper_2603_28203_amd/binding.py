@@ -9,6 +9,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import dataclasses
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -18,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpf.so")
 
 DPF_OK, DPF_EINVAL, DPF_ECAP, DPF_EHIP, DPF_ENOMEM, DPF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CONVERGED, MAX_ITER, NONFINITE, BAD_GRID = 0, 1, 2, 3
+CONVERGED, MAX_ITER, NONFINITE, BAD_GRID, BAD_OUTAGE = 0, 1, 2, 3, 4
 SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
 OPT_ADAM, OPT_SGD, OPT_RMSPROP = 0, 1, 2
 PQ, PV, SLACK = 0, 1, 2
@@ -45,6 +46,12 @@ class _Opts(ctypes.Structure):
                 ("max_iter", _i32), ("sched", _i32), ("factor", _f64), ("patience", _i32),
                 ("threshold", _f64), ("cooldown", _i32), ("min_lr", _f64), ("sched_eps", _f64),
                 ("optimizer", _i32)]
+
+
+class _Route(ctypes.Structure):
+    _fields_ = [("variant", _i32), ("team_cap", _i32), ("tail_handoff", _i32), ("tail_team", _i32),
+                ("tail_chunk", _i32), ("tail_min_items", _i32), ("tail_slice_ms", _f64),
+                ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("reserved", _i32)]
 
 
 _lib = None
@@ -79,17 +86,20 @@ def lib():
         L.dpf_dc_init_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_mismatch_grad_workspace_bytes.argtypes = [_i32, _i32]
         L.dpf_mismatch_grad_workspace_bytes.restype = ctypes.c_size_t
+        R = ctypes.POINTER(_Route)
         L.dpf_solve_batch.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _P, _i32, _i32, _P, _P, _i32, _P,
-                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), _P, _P, _P, _P, _P, _P,
+                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), R, _P, _P, _P, _P, _P, _P,
                                       ctypes.c_size_t, _P]
         L.dpf_solve_series.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P, _i32,
-                                       ctypes.POINTER(_Opts), _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+                                       ctypes.POINTER(_Opts), R, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.dpf_solve_series.restype = ctypes.c_int
-        L.dpf_solve_series_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _i32]
+        L.dpf_solve_series_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, R]
         L.dpf_solve_series_workspace_bytes.restype = ctypes.c_size_t
         L.dpf_solve_batch.restype = ctypes.c_int
-        L.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _i32, _i32]
+        L.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _i32, _i32, R]
         L.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
+        L.dpf_route_default.argtypes = [R]
+        L.dpf_route_default.restype = None
         L.dpf_solve_max_sub_buses.restype = _i32
         L.dpf_solve_variant_count.restype = ctypes.c_int
         L.dpf_solve_variant_info.argtypes = [ctypes.c_int, _P, _P, _P]
@@ -107,19 +117,6 @@ def lib():
         L.dpf_autotune_reset.restype = None
         L.dpf_order_rcm.argtypes = [_i32, _i32, _P, _P, _i32, _P, _i32, _P, _P]
         L.dpf_order_rcm.restype = ctypes.c_int
-        L.dpf_autotune_set_team_cap.argtypes = [_i32]
-        L.dpf_autotune_set_team_cap.restype = ctypes.c_int
-        L.dpf_autotune_set_tail_handoff.argtypes = [_i32]
-        L.dpf_autotune_set_tail_handoff.restype = ctypes.c_int
-        L.dpf_tail_handoff.restype = _i32
-        L.dpf_autotune_set_tail_team.argtypes = [_i32, _i32, _i32, ctypes.c_double]
-        L.dpf_autotune_set_tail_team.restype = ctypes.c_int
-        L.dpf_tail_team.restype = _i32
-        L.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
-        L.dpf_autotune_set_tail_waits.restype = ctypes.c_int
-        L.dpf_autotune_set_case_order.argtypes = [_i32]
-        L.dpf_autotune_set_case_order.restype = ctypes.c_int
-        L.dpf_case_order.restype = _i32
         L.dpf_tail_split_stats.argtypes = [_P, _P]
         L.dpf_tail_split_stats.restype = None
         _lib = L
@@ -298,6 +295,34 @@ class Options:
                      self.sched_eps, int(self.optimizer))
 
 
+@dataclass
+class Route:
+    """Per-call routing of dpf_solve_batch (dpf_route_t): kernel variant (-1 =
+    autotune cache / default), team cap, and the tail settings -- handoff
+    threshold, split-kernel team size, iterations and time per launch, items
+    left to the multi-workgroup path, barrier wait bounds -- and the case order
+    (1 = descending initial max|dS|).  The defaults equal dpf_route_default."""
+    variant: int = -1
+    team_cap: int = 0
+    tail_handoff: int = 0
+    tail_team: int = 0
+    tail_chunk: int = 128
+    tail_min_items: int = 0
+    tail_slice_ms: float = 0.0
+    tail_first_wait_s: float = 1.0
+    tail_wait_s: float = 5.0
+    case_order: int = 0
+
+    def c(self) -> _Route:
+        return _Route(int(self.variant), int(self.team_cap), int(self.tail_handoff), int(self.tail_team),
+                      int(self.tail_chunk), int(self.tail_min_items), float(self.tail_slice_ms),
+                      float(self.tail_first_wait_s), float(self.tail_wait_s), int(self.case_order), 0)
+
+
+def _route(route):
+    return None if route is None else ctypes.byref(route.c())
+
+
 class SolveWorkspace:
     """Reusable device workspace for dpf_solve_batch (grown on demand)."""
 
@@ -313,22 +338,23 @@ class SolveWorkspace:
 _default_ws = SolveWorkspace()
 
 
-def solve_workspace_bytes(grid: DeviceGrid, B, ld=None, sub_offset=None) -> int:
+def solve_workspace_bytes(grid: DeviceGrid, B, ld=None, sub_offset=None, route: Route | None = None) -> int:
     ld = grid.n_bus if ld is None else ld
     g = grid.c()
     if sub_offset is None:
-        return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, B, ld))
+        return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, B, ld, _route(route)))
     so = (ctypes.c_int32 * len(sub_offset))(*[int(v) for v in sub_offset])
-    return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), len(sub_offset) - 1, so, B, ld))
+    return int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), len(sub_offset) - 1, so, B, ld, _route(route)))
 
 
 def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = None, outage=None,
           sub_offset=None, adam_state=None, sched_state=None, workspace: SolveWorkspace | None = None,
-          outputs=None):
+          outputs=None, route: Route | None = None):
     """dpf_solve_batch: Adam-DPF to convergence for B cases x n_sub sub-grids.
 
-    vm, va ([B, ld] float64, GPU) are updated in place.  Returns dict with
-    iters, status, max_mis, loss ([B * n_sub], index c * n_sub + s)."""
+    vm, va ([B, ld] float64, GPU) are updated in place; `route` (Route) sets this
+    call's kernel choice and tail settings.  Returns dict with iters, status,
+    max_mis, loss ([B * n_sub], index c * n_sub + s)."""
     opts = opts or Options()
     dev = vm.device
     B, ld = vm.shape
@@ -356,12 +382,16 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
                    "loss": torch.empty(items, dtype=torch.float64, device=dev),
                    "done_ns": torch.empty(items, dtype=torch.int64, device=dev)}
     g = grid.c()
-    wsb = int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), n_sub, so_h, B, ld))
+    rc = None if route is None else route.c()
+    rp = None if rc is None else ctypes.byref(rc)
+    wsb = int(lib().dpf_solve_workspace_bytes(ctypes.byref(g), n_sub, so_h, B, ld, rp))
+    if wsb == 0:
+        raise DPFError(DPF_EINVAL, "invalid sizes or route")
     ws = (workspace or _default_ws).get(wsb, dev)
     o = opts.c()
     _check(lib().dpf_solve_batch(ctypes.byref(g), n_sub, so_h, _ptr(so_d), B, ld, _ptr(bt), _ptr(s), s_ld,
                                  _ptr(out), _ptr(vm), _ptr(va), _ptr(adam_state), _ptr(sched_state),
-                                 ctypes.byref(o), _ptr(outputs["iters"]), _ptr(outputs["status"]),
+                                 ctypes.byref(o), rp, _ptr(outputs["iters"]), _ptr(outputs["status"]),
                                  _ptr(outputs["max_mis"]), _ptr(outputs["loss"]), _ptr(outputs.get("done_ns")),
                                  _ptr(ws), ws.numel(), _stream()))
     if so_d is not None:
@@ -383,7 +413,8 @@ def fresh_sched_state(items: int, lr: float, device="cuda") -> torch.Tensor:
 
 
 def solve_series(grid: DeviceGrid, bus_type, s_series, vm0, va0, *, window: int = 1,
-                 opts: Options | None = None, workspace: SolveWorkspace | None = None):
+                 opts: Options | None = None, workspace: SolveWorkspace | None = None,
+                 route: Route | None = None):
     """dpf_solve_series: T warm-started power flows in windows of `window` steps.
 
     s_series: [T, n] complex128 (GPU); vm0, va0: [n].  Returns dict with vm, va
@@ -404,11 +435,15 @@ def solve_series(grid: DeviceGrid, bus_type, s_series, vm0, va0, *, window: int 
            "loss": torch.empty(T, dtype=torch.float64, device=dev),
            "done_ns": torch.empty(T, dtype=torch.int64, device=dev)}
     g = grid.c()
-    wsb = int(lib().dpf_solve_series_workspace_bytes(ctypes.byref(g), int(window), n))
+    rc = None if route is None else route.c()
+    rp = None if rc is None else ctypes.byref(rc)
+    wsb = int(lib().dpf_solve_series_workspace_bytes(ctypes.byref(g), int(window), n, rp))
+    if wsb == 0:
+        raise DPFError(DPF_EINVAL, "invalid sizes or route")
     ws = (workspace or _default_ws).get(wsb, dev)
     o = opts.c()
     _check(lib().dpf_solve_series(ctypes.byref(g), T, int(window), _ptr(bt), _ptr(s), n, _ptr(vm0), _ptr(va0),
-                                  _ptr(vm), _ptr(va), n, ctypes.byref(o), _ptr(out["iters"]),
+                                  _ptr(vm), _ptr(va), n, ctypes.byref(o), rp, _ptr(out["iters"]),
                                   _ptr(out["status"]), _ptr(out["max_mis"]), _ptr(out["loss"]),
                                   _ptr(out["done_ns"]), _ptr(ws), ws.numel(), _stream()))
     out["vm"] = vm
@@ -500,51 +535,12 @@ def autotune_reset():
     lib().dpf_autotune_reset()
 
 
-def set_team_cap(buses: int):
-    """Route sub-grids above `buses` to the multi-workgroup path (0 = LDS limit)."""
-    _check(lib().dpf_autotune_set_team_cap(int(buses)))
-
-
-def set_tail_handoff(items: int):
-    """dpf_autotune_set_tail_handoff: finish the last `items` unfinished items of a
-    single-grid call on the multi-workgroup path (0 = off)."""
-    _check(lib().dpf_autotune_set_tail_handoff(int(items)))
-
-
-def tail_handoff() -> int:
-    """The current tail handoff threshold (0 = off)."""
-    return int(lib().dpf_tail_handoff())
-
-
-def set_tail_team(max_team: int, chunk: int = 128, min_items: int = 0, slice_ms: float = 0.0):
-    """dpf_autotune_set_tail_team: finish handed-over items on the split kernel,
-    with at most ``max_team`` workgroups per item, relaunched every ``chunk``
-    iterations (and every ``slice_ms`` ms, with teams sized by each item's
-    remaining iteration budget, when > 0) while more than ``min_items`` items
-    are left; the multi-workgroup path takes the rest (max_team 0 = that path
-    only)."""
-    _check(lib().dpf_autotune_set_tail_team(int(max_team), int(chunk), int(min_items), float(slice_ms)))
-
-
-def tail_team() -> int:
-    """The current most workgroups per handed-over item (0 = multi-workgroup path)."""
-    return int(lib().dpf_tail_team())
-
-
-def set_tail_waits(first_s: float = 1.0, later_s: float = 5.0):
-    """dpf_autotune_set_tail_waits: the split kernel's barrier wait bounds (s)."""
-    _check(lib().dpf_autotune_set_tail_waits(float(first_s), float(later_s)))
-
-
-def set_case_order(mode: int):
-    """dpf_autotune_set_case_order: 1 = calls that may hand over their tail start
-    their cases by descending initial max|r|; 0 = index order."""
-    _check(lib().dpf_autotune_set_case_order(int(mode)))
-
-
-def case_order() -> int:
-    """The current case order mode."""
-    return int(lib().dpf_case_order())
+def route_default() -> Route:
+    """dpf_route_default as a Route (the library's defaults)."""
+    r = _Route()
+    lib().dpf_route_default(ctypes.byref(r))
+    return Route(r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items,
+                 r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order)
 
 
 def split_stats() -> dict:
@@ -555,29 +551,26 @@ def split_stats() -> dict:
 
 
 def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_offset=None, opts=None,
-             iters: int = 40, reps: int = 2, tie: float = 0.0):
+             iters: int = 40, reps: int = 2, tie: float = 0.0, route: Route | None = None):
     """Time every kernel variant that can hold the largest sub-grid on copies of
-    the real inputs (``iters`` Adam iterations, no stop test) and record the
-    fastest in the library's autotune cache for this size class and this number
-    of work items (B x sub-grids).  Variants within a fraction ``tie`` of the
-    fastest count as equal and the first of them in the table is taken, which
-    keeps the choice stable under timing noise.  With a tail handoff set, a
+    the real inputs (``iters`` Adam iterations, no stop test; each probe names its
+    variant in its own route, with the tail handoff off) and record the fastest
+    in the library's autotune cache for this size class and this number of work
+    items (B x sub-grids).  Variants within a fraction ``tie`` of the fastest
+    count as equal and the first of them in the table is taken, which keeps the
+    choice stable under timing noise.  With a tail handoff in ``route``, a
     single-grid call chooses among the kinds that can hand over (streaming,
     banded, banded-stream, banded-window): the fixed-length probes cannot see the
     handoff.  Returns {variant: seconds}."""
     opts = opts or Options()
+    route = route or Route()
     n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))
     items = int(vm.shape[0]) * (1 if sub_offset is None else len(sub_offset) - 1)
     probe = Options(**{**opts.__dict__, "tol": 0.0, "max_iter": int(iters)})
     times = {}
-    handoff = tail_handoff()  # timed without it: fixed-length launches would hand every item over
-    set_tail_handoff(0)
-    try:
-        _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, items, reps, times)
-    finally:
-        set_tail_handoff(handoff)
+    _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, reps, times, route)
     eligible = times
-    if handoff > 0 and sub_offset is None:
+    if route.tail_handoff > 0 and sub_offset is None:
         kinds = {v["index"]: v["kind"] for v in variants()}
         can = {i: t for i, t in times.items() if kinds[i] in HANDOFF_KINDS}
         eligible = can or times
@@ -587,12 +580,12 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     return {"choice": pick, "seconds": times, "n_max": n_max, "items": items, "iters": iters}
 
 
-def _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, items, reps, times):
+def _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_max, reps, times, route):
     for v in variants():
         if not (v["kind"].startswith("banded") or v["buses_per_thread"] == 0
                 or v["threads"] * v["buses_per_thread"] >= n_max):
             continue
-        _check(lib().dpf_autotune_set_items(n_max, items, v["index"]))
+        rt = dataclasses.replace(route, variant=v["index"], tail_handoff=0)
         best = None
         for _ in range(reps):
             vm1, va1 = vm.clone(), va.clone()
@@ -600,7 +593,7 @@ def _time_variants(grid, bus_type, s_spec, vm, va, outage, sub_offset, probe, n_
             st = torch.cuda.Event(enable_timing=True)
             en = torch.cuda.Event(enable_timing=True)
             st.record()
-            solve(grid, bus_type, s_spec, vm1, va1, opts=probe, outage=outage, sub_offset=sub_offset)
+            solve(grid, bus_type, s_spec, vm1, va1, opts=probe, outage=outage, sub_offset=sub_offset, route=rt)
             en.record()
             torch.cuda.synchronize()
             dt = st.elapsed_time(en) * 1e-3

@@ -7,8 +7,10 @@
 namespace dpf {
 
 // status of an item handed over from a per-item solve kernel to the multi-workgroup
-// path (internal: that path finishes the item and overwrites the status)
-constexpr int kPaused = 4;
+// path (internal: that path finishes the item and overwrites the status).  It lies
+// outside the public per-case status codes of include/dpf.h (0..4), which the
+// paths compare against it (checked at compile time in dpf.hip).
+constexpr int kPaused = 256;
 
 constexpr int kWave = 64;
 constexpr int8_t kPQ = 0;

@@ -89,6 +89,13 @@ __global__ __launch_bounds__(NT) void dc_pcg_kernel(DcArgs a) {
     double oyi = 0.0;  // Im of the outaged branch's series admittance (= -1/x)
     if (a.ov.outage) {
         const int k = a.ov.outage[c];
+        if (outage_index_bad(k, a.ov.n_branch)) {  // neither -1 nor a branch: va untouched
+            if (threadIdx.x == 0) {
+                if (a.iters) a.iters[c] = 0;
+                if (a.res_out) a.res_out[c] = __longlong_as_double(0x7ff8000000000000LL);
+            }
+            return;
+        }
         if ((unsigned)k < (unsigned)a.ov.n_branch) {
             const int f = a.ov.from[k], t = a.ov.to[k];
             if ((unsigned)f < (unsigned)n && (unsigned)t < (unsigned)n && f != t) {

@@ -21,6 +21,10 @@
 
 namespace {
 
+static_assert(dpf::kPaused != DPF_CONVERGED && dpf::kPaused != DPF_MAX_ITER && dpf::kPaused != DPF_NONFINITE &&
+                  dpf::kPaused != DPF_BAD_GRID && dpf::kPaused != DPF_BAD_OUTAGE,
+              "the internal paused status must differ from every public status code");
+
 thread_local std::string g_err;
 
 int fail(int code, const std::string &msg) {
@@ -85,21 +89,45 @@ constexpr int kGfx950LdsBytes = 160 * 1024;  // LDS per workgroup on gfx950
 // Bytes of static LDS the solve kernels use besides the dynamic exchange array.
 constexpr int kSolveStaticLds = 2 * (1024 / dpf::kWave) * 8 + 256;
 
-std::atomic<int32_t> g_team_cap_override{0};
-std::atomic<int32_t> g_tail_handoff{0};  // unfinished items at which per-item kernels hand over (0 = never)
-std::atomic<int32_t> g_tail_team{0};     // handed-over items: most workgroups per item (0 = multi-workgroup path)
-std::atomic<int32_t> g_tail_chunk{128};  // ... and iterations per launch of the split kernel
-std::atomic<int32_t> g_tail_min{0};      // ... while more than this many items are left
-std::atomic<double> g_tail_slice{0.0};   // ... and ms per launch (0 = iterations only)
-std::atomic<int32_t> g_case_order{0};    // handoff calls: 1 = start cases by descending initial max|r|
-std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // since the library was loaded
-std::atomic<double> g_split_first_wait{1.0}, g_split_wait{5.0};  // barrier wait bounds (s)
+std::atomic<int64_t> g_split_launches{0}, g_split_abandoned{0};  // statistics since the library was loaded
 
-int32_t max_sub_buses_for(const DeviceInfo &d) {
+dpf_route_t default_route() {
+    dpf_route_t r;
+    r.variant = -1;
+    r.team_cap = 0;
+    r.tail_handoff = 0;
+    r.tail_team = 0;
+    r.tail_chunk = 128;
+    r.tail_min_items = 0;
+    r.tail_slice_ms = 0.0;
+    r.tail_first_wait_s = 1.0;
+    r.tail_wait_s = 5.0;
+    r.case_order = 0;
+    r.reserved = 0;
+    return r;
+}
+
+dpf_route_t route_of(const dpf_route_t *r) { return r ? *r : default_route(); }
+
+const char *route_error(const dpf_route_t &r) {
+    if (r.variant < -1) return "route.variant must be -1 or a variant index";
+    if (r.team_cap < 0) return "route.team_cap must be >= 0";
+    if (r.tail_handoff < 0) return "route.tail_handoff must be >= 0";
+    if (r.tail_team < 0 || r.tail_team > 1024) return "route.tail_team must be in [0, 1024]";
+    if (r.tail_chunk < 1 || r.tail_chunk > 65536) return "route.tail_chunk must be in [1, 65536]";
+    if (r.tail_min_items < 0) return "route.tail_min_items must be >= 0";
+    if (!(r.tail_slice_ms >= 0.0 && r.tail_slice_ms <= 1000.0)) return "route.tail_slice_ms must be in [0, 1000]";
+    if (!(r.tail_first_wait_s >= 0.0 && r.tail_first_wait_s <= 60.0) || !(r.tail_wait_s >= 0.0 && r.tail_wait_s <= 60.0))
+        return "route wait bounds must be in [0, 60] s";
+    if (r.case_order < 0 || r.case_order > 1) return "route.case_order must be 0 or 1";
+    if (r.reserved != 0) return "route.reserved must be 0";
+    return nullptr;
+}
+
+int32_t max_sub_buses_for(const DeviceInfo &d, int32_t team_cap) {
     int32_t cap = (d.lds_per_block - kSolveStaticLds) / 16;
     cap = std::min<int32_t>(cap, 10 * 1024);
-    const int32_t o = g_team_cap_override.load();
-    return o > 0 ? std::min(cap, o) : cap;
+    return team_cap > 0 ? std::min(cap, team_cap) : cap;
 }
 
 // ---------------------------------------------------------------- solve variants
@@ -197,14 +225,16 @@ int wide_variant_index() {
     return cnt - 1;
 }
 
+// forced >= 0: the call's route names the variant (nullptr if it cannot hold n_max).
 // *few_large: the multi-workgroup path was chosen by default for few large items
-// (not from the autotune cache)
-const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu, bool *few_large = nullptr) {
+// (not from the autotune cache or the route)
+const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu, int forced = -1, bool *few_large = nullptr) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     int d = default_variant_index(n_max);
     if (few_large) *few_large = false;
     if (d < 0) return nullptr;
+    if (forced >= 0) return forced < cnt && variant_fits(t[forced], n_max) ? &t[forced] : nullptr;
     {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         const int c = g_tune_init ? g_tune[d][items_bucket(items)] : -1;
@@ -226,6 +256,7 @@ struct CallPlan {
     const Variant *v = nullptr;
     int32_t handoff = 0;  // tail handoff threshold for this call (0 = none)
     bool split_direct = false;  // every item on the split kernel from its first iteration
+    dpf_route_t route{};        // the call's settings
 };
 
 bool valid_opts(const dpf_opts_t *o) {
@@ -467,8 +498,9 @@ int pinned_scratch(int dev, size_t n, int32_t **out) {
 // paused when it returns (at most min_items, or a team abandoned a barrier) are
 // left in *rest / *rest_list for the multi-workgroup path.
 int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const DeviceInfo &dev, int32_t *list,
-              int32_t n_list, int32_t B, int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms,
-              int32_t *rest, int32_t **rest_list) {
+              int32_t n_list, int32_t B, const dpf_route_t &route, int32_t *rest, int32_t **rest_list) {
+    const int32_t max_team = route.tail_team, chunk = route.tail_chunk, min_items = route.tail_min_items;
+    const double slice_ms = route.tail_slice_ms;
     hipStream_t sd = dev.side;
     *rest = n_list;
     *rest_list = list;
@@ -505,8 +537,8 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     p.aborted = hdr + 7;
     p.chunk = chunk;
     p.slice = slice_ms > 0.0 ? (int64_t)(slice_ms * 1e6 / dev.ns_per_tick) : 0;
-    p.first_limit = (int64_t)(g_split_first_wait.load() * 1e9 / dev.ns_per_tick);  // other work may hold CUs
-    p.limit = (int64_t)(g_split_wait.load() * 1e9 / dev.ns_per_tick);
+    p.first_limit = (int64_t)(route.tail_first_wait_s * 1e9 / dev.ns_per_tick);  // other work may hold CUs
+    p.limit = (int64_t)(route.tail_wait_s * 1e9 / dev.ns_per_tick);
     p.list_cap = list_cap;
     const bool by_budget = p.slice > 0;
     hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, sd, 1, 1, p.aborted);
@@ -523,7 +555,11 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
         DPF_HIP(hipEventSynchronize(dev.ev_poll));
     }
     std::vector<int64_t> T((size_t)B);
-    while (n_list > std::max(min_items, 0)) {
+    // every launch advances each listed case by at least one update (or finishes or
+    // abandons it), so max_iter + 1 launches finish any list; past that bound the
+    // rest goes to the multi-workgroup path, whose loop is bounded by max_iter too
+    int64_t launches = 0;
+    while (n_list > std::max(min_items, 0) && launches++ <= (int64_t)a.max_iter + 1) {
         int64_t total = 0;
         if (by_budget && n_list <= capacity) {
             auto weight = [&](int32_t k) {
@@ -874,70 +910,16 @@ int dpf_autotune_set_items(int32_t n_max, int64_t items, int variant) {
     return autotune_store(n_max, items, variant, false);
 }
 
-int dpf_autotune_set_team_cap(int32_t buses) {
-    g_err.clear();
-    if (buses < 0) return fail(DPF_EINVAL, "team cap must be >= 0");
-    g_team_cap_override.store(buses);
-    return DPF_OK;
-}
-
-int32_t dpf_tail_handoff(void) { return g_tail_handoff.load(); }
-
-int dpf_autotune_set_tail_handoff(int32_t items) {
-    g_err.clear();
-    if (items < 0) return fail(DPF_EINVAL, "handoff threshold must be >= 0");
-    g_tail_handoff.store(items);
-    return DPF_OK;
-}
-
-int32_t dpf_tail_team(void) { return g_tail_team.load(); }
-
-int dpf_autotune_set_case_order(int32_t mode) {
-    g_err.clear();
-    if (mode < 0 || mode > 1) return fail(DPF_EINVAL, "case order mode must be 0 or 1");
-    g_case_order.store(mode);
-    return DPF_OK;
-}
-
-int32_t dpf_case_order(void) { return g_case_order.load(); }
-
-int dpf_autotune_set_tail_waits(double first_s, double later_s) {
-    g_err.clear();
-    if (!(first_s >= 0.0 && first_s <= 60.0) || !(later_s >= 0.0 && later_s <= 60.0))
-        return fail(DPF_EINVAL, "wait bounds must be in [0, 60] s");
-    g_split_first_wait.store(first_s);
-    g_split_wait.store(later_s);
-    return DPF_OK;
-}
-
 void dpf_tail_split_stats(int64_t *launches, int64_t *abandoned) {
     if (launches) *launches = g_split_launches.load();
     if (abandoned) *abandoned = g_split_abandoned.load();
 }
 
-int dpf_autotune_set_tail_team(int32_t max_team, int32_t chunk, int32_t min_items, double slice_ms) {
-    g_err.clear();
-    if (max_team < 0 || max_team > 1024) return fail(DPF_EINVAL, "max_team must be in [0, 1024]");
-    if (chunk < 1 || chunk > 65536) return fail(DPF_EINVAL, "chunk must be in [1, 65536]");
-    if (min_items < 0) return fail(DPF_EINVAL, "min_items must be >= 0");
-    if (!(slice_ms >= 0.0 && slice_ms <= 1000.0)) return fail(DPF_EINVAL, "slice_ms must be in [0, 1000]");
-    g_tail_team.store(max_team);
-    g_tail_chunk.store(chunk);
-    g_tail_min.store(min_items);
-    g_tail_slice.store(slice_ms);
-    return DPF_OK;
+void dpf_route_default(dpf_route_t *route) {
+    if (route) *route = default_route();
 }
 
 void dpf_autotune_reset(void) {
-    g_team_cap_override.store(0);
-    g_tail_handoff.store(0);
-    g_tail_team.store(0);
-    g_tail_chunk.store(128);
-    g_tail_min.store(0);
-    g_tail_slice.store(0.0);
-    g_case_order.store(0);
-    g_split_first_wait.store(1.0);
-    g_split_wait.store(5.0);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     for (auto &row : g_tune)
         for (int &x : row) x = -1;
@@ -1075,13 +1057,15 @@ int dpf_order_rcm(int32_t n_bus, int32_t n_branch, const int32_t *from, const in
 int32_t dpf_solve_max_sub_buses(void) {
     DeviceInfo d;
     if (device_info(d) != DPF_OK) return 0;
-    return max_sub_buses_for(d);
+    return max_sub_buses_for(d, 0);
 }
 
+// *forced_bad: the route names a variant that cannot hold the call's sub-grids
 static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
-                          const DeviceInfo &dev) {
+                          const DeviceInfo &dev, const dpf_route_t &route, bool *forced_bad = nullptr) {
     CallPlan p;
-    p.cap = max_sub_buses_for(dev);
+    p.route = route;
+    p.cap = max_sub_buses_for(dev, route.team_cap);
     int64_t small = 0;
     for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
         const int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
@@ -1092,11 +1076,13 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
     }
     p.has_small = small > 0;
     bool few_large = false;
-    p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256, &few_large);
+    p.v = pick_variant(std::max(1, p.n_max), (int64_t)B * small, dev.n_cu > 0 ? dev.n_cu : 256, route.variant,
+                       &few_large);
+    if (forced_bad) *forced_bad = route.variant >= 0 && !p.v;
     // few large items of one grid that the split kernel can hold, with the split
     // kernel enabled: it runs them from the first iteration (the multi-workgroup
     // path's iteration is launch-bound for a few items)
-    if (few_large && g_tail_team.load() > 0 && small == 1 && (!sub_offset || n_sub == 1) &&
+    if (few_large && route.tail_team > 0 && small == 1 && (!sub_offset || n_sub == 1) &&
         (size_t)p.n_max * 16 + (size_t)(p.n_max + 31) / 32 * 4 + 512 <= (size_t)dev.lds_per_block)
         p.split_direct = true;
     if (p.v && p.v->mode == dpf::kMulti && sub_offset && n_sub != 1) {  // batched kernel: one grid only
@@ -1110,7 +1096,7 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
         p.has_small = false;
     }
     // tail handoff: single-grid calls whose per-item kernel keeps the state in global memory
-    const int32_t h = g_tail_handoff.load();
+    const int32_t h = route.tail_handoff;
     if (h > 0 && p.v && p.has_small && small == 1 && (!sub_offset || n_sub == 1) &&
         (p.v->mode == dpf::kGlobal || p.v->mode == dpf::kBand || p.v->mode == dpf::kBandStream ||
          p.v->mode == dpf::kWindow))
@@ -1119,8 +1105,10 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
 }
 
 size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
-                                 int32_t ld) {
+                                 int32_t ld, const dpf_route_t *route) {
     if (!g || g->n_bus <= 0 || B <= 0 || ld < g->n_bus) return 0;
+    const dpf_route_t rt = route_of(route);
+    if (route_error(rt)) return 0;
     if (!sub_offset) n_sub = 1;
     DeviceInfo dev;
     if (device_info(dev) != DPF_OK) {
@@ -1128,7 +1116,9 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
         dev.lds_per_block = kGfx950LdsBytes;  // no device visible: size for gfx950
         dev.n_cu = 256;
     }
-    const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev);
+    bool forced_bad = false;
+    const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev, rt, &forced_bad);
+    if (forced_bad) return 0;
     return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap,
                         p.handoff > 0 || p.split_direct).total;
 }
@@ -1136,9 +1126,12 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
                     int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
                     const int32_t *outage, double *vm, double *va, double *adam_state, double *sched_state,
-                    const dpf_opts_t *opts, int32_t *iters, int32_t *status, double *max_mis, double *loss,
-                    int64_t *done_ns, void *workspace, size_t ws_bytes, void *stream) {
+                    const dpf_opts_t *opts, const dpf_route_t *route, int32_t *iters, int32_t *status,
+                    double *max_mis, double *loss, int64_t *done_ns, void *workspace, size_t ws_bytes,
+                    void *stream) {
     g_err.clear();
+    const dpf_route_t rt = route_of(route);
+    if (const char *re = route_error(rt)) return fail(DPF_EINVAL, re);
     if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
     if (B <= 0 || ld < g->n_bus) return fail(DPF_EINVAL, "B must be > 0 and ld >= n_bus");
     if (s_ld != 0 && s_ld < g->n_bus) return fail(DPF_EINVAL, "s_ld must be 0 or >= n_bus");
@@ -1162,7 +1155,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     DeviceInfo dev;
     int rc = device_info(dev);
     if (rc != DPF_OK) return rc;
-    const CallPlan plan = plan_call(g, n_sub, sub_offset, B, dev);
+    bool forced_bad = false;
+    const CallPlan plan = plan_call(g, n_sub, sub_offset, B, dev, rt, &forced_bad);
+    if (forced_bad) return fail(DPF_EINVAL, "route.variant cannot hold the call's largest sub-grid");
     const int32_t cap = plan.cap;  // larger sub-grids take the multi-workgroup path
     const int32_t n_max = plan.n_max;
     const bool has_small = plan.has_small;
@@ -1198,6 +1193,11 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                            g->n_bus, slice_off, g->row_ptr, g->col_idx, (const double2 *)g->val, width, start, scol,
                            sval, sub_bw);
     }
+    // cases with an outage index that is neither -1 nor a branch (after the header is cleared)
+    if (outage)
+        hipLaunchKernelGGL(dpf::outage_check_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B,
+                           dpf::OutageView{outage, g->from, g->to, g->r, g->x, g->b, g->n_branch}, status, iters,
+                           max_mis, loss, bad + 5);
     DPF_HIP(hipGetLastError());
 
     dpf::SolveArgs a{};
@@ -1271,7 +1271,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     // handoff calls of one grid may start their cases by descending initial max|r|:
     // the cases likely to run longest then do not start last (one evaluation of
     // every case with the mismatch kernels, into the solve's scratch, then a rank)
-    if (handoff && !sub_offset && g_case_order.load() == 1 && B <= 16384) {
+    if (handoff && !sub_offset && rt.case_order == 1 && B <= 16384) {
         const int32_t n = g->n_bus;
         const int32_t nblk = (n + dpf::kEvalBlock - 1) / dpf::kEvalBlock;
         int32_t *order = (int32_t *)(ws + L.off_order);
@@ -1298,8 +1298,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         // every item starts paused at iteration 0; the split kernel runs them, and any
         // it leaves (a team abandoned a barrier) finish on the multi-workgroup path
         int32_t *list = (int32_t *)(ws + L.off_list);
-        hipLaunchKernelGGL(dpf::split_start_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, a.status, a.iters,
-                           list);
+        hipLaunchKernelGGL(dpf::split_start_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, a.ov, a.status,
+                           a.iters, list);
         if (a.st_fresh) {
             const int64_t words = 4 * (int64_t)B * ld;
             hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, words,
@@ -1310,8 +1310,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
         int32_t rest = B;
         int32_t *rest_list = list;
-        int rc2 = run_split(a, L, ws, dev, list, B, B, g_tail_team.load(), g_tail_chunk.load(), g_tail_min.load(),
-                            g_tail_slice.load(), &rest, &rest_list);
+        int rc2 = run_split(a, L, ws, dev, list, B, B, rt, &rest, &rest_list);
         if (rc2 != DPF_OK) return rc2;
         rc2 = rest > 0 ? run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, rest_list, rest) : DPF_OK;
         if (rc2 != DPF_OK) return rc2;
@@ -1372,10 +1371,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
             DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
             int32_t rest = paused;
             int32_t *rest_list = list;
-            const int32_t team = g_tail_team.load();
-            if (team > 0) {
-                int rc2 = run_split(a, L, ws, dev, list, paused, B, team, g_tail_chunk.load(), g_tail_min.load(),
-                                    g_tail_slice.load(), &rest, &rest_list);
+            if (rt.tail_team > 0) {
+                int rc2 = run_split(a, L, ws, dev, list, paused, B, rt, &rest, &rest_list);
                 if (rc2 != DPF_OK) return rc2;
             }
             int rc2 = rest > 0 ? run_wide(a, L, ws, 1, nullptr, B, ld, 0, dev, rest_list, rest) : DPF_OK;
@@ -1387,15 +1384,16 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     return DPF_OK;
 }
 
-size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld) {
-    return dpf_solve_workspace_bytes(g, 1, nullptr, window, ld);
+size_t dpf_solve_series_workspace_bytes(const dpf_grid_t *g, int32_t window, int32_t ld,
+                                        const dpf_route_t *route) {
+    return dpf_solve_workspace_bytes(g, 1, nullptr, window, ld, route);
 }
 
 int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_t *bus_type,
                      const double *s_series, int32_t s_ld, const double *vm0, const double *va0, double *vm,
-                     double *va, int32_t ld, const dpf_opts_t *opts, int32_t *iters, int32_t *status,
-                     double *max_mis, double *loss, int64_t *done_ns, void *workspace, size_t ws_bytes,
-                     void *stream) {
+                     double *va, int32_t ld, const dpf_opts_t *opts, const dpf_route_t *route, int32_t *iters,
+                     int32_t *status, double *max_mis, double *loss, int64_t *done_ns, void *workspace,
+                     size_t ws_bytes, void *stream) {
     g_err.clear();
     if (!valid_grid(g)) return fail(DPF_EINVAL, "invalid grid");
     if (T <= 0 || window <= 0 || ld < g->n_bus || s_ld < g->n_bus)
@@ -1413,7 +1411,7 @@ int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_
         DPF_HIP(hipGetLastError());
         int rc = dpf_solve_batch(g, 1, nullptr, nullptr, bw, ld, bus_type, s_series + 2 * (int64_t)t0 * s_ld, s_ld,
                                  nullptr, vm + (int64_t)t0 * ld, va + (int64_t)t0 * ld, nullptr, nullptr, opts,
-                                 iters + t0, status + t0, max_mis + t0, loss + t0,
+                                 route, iters + t0, status + t0, max_mis + t0, loss + t0,
                                  done_ns ? done_ns + t0 : nullptr, workspace, ws_bytes, stream);
         if (rc != DPF_OK) return rc;
     }

@@ -29,6 +29,12 @@ struct OutageView {
     int32_t n_branch;
 };
 
+// An outage index is -1 (no outage) or a branch index; anything else marks the
+// case as bad (the solve reports DPF_BAD_OUTAGE, the evaluations return NaN).
+__host__ __device__ __forceinline__ bool outage_index_bad(int32_t k, int32_t n_branch) {
+    return k != -1 && (uint32_t)k >= (uint32_t)n_branch;
+}
+
 // Rank-2 correction: subtract branch k's pi-model block from row i of Y z.
 // Y_k = [[y + ysh, -y], [-y, y + ysh]] on (f, t).
 __device__ __forceinline__ double2 outage_term(const OutageView &ov, int32_t k, int32_t i, double2 zf, double2 zt,
@@ -91,6 +97,8 @@ __global__ __launch_bounds__(kEvalBlock) void forward_kernel(
                 int32_t f = ov.from[k], t = ov.to[k];
                 if ((i == f || i == t) && (uint32_t)f < (uint32_t)n && (uint32_t)t < (uint32_t)n)
                     acc = csub(acc, outage_term(ov, k, i, Vc[f], Vc[t], f, t));
+            } else if (outage_index_bad(k, ov.n_branch)) {
+                acc = make_double2(__longlong_as_double(0x7ff8000000000000LL), 0.0);  // NaN outputs
             }
         }
         double2 v = Vc[i];

@@ -137,9 +137,13 @@ __device__ __forceinline__ ItemSched load_item_sched(const SolveArgs &a, int out
     return s;
 }
 
-// scheduler step after the optimizer step of iteration `it` (uniform across the
-// workgroup): PyTorch's reduce-on-plateau (mode min, relative threshold) or StepLR
-__device__ __forceinline__ void sched_step(const SolveArgs &a, ItemSched &s, double loss, int it) {
+// scheduler step after an optimizer step (uniform across the workgroup; s.t_step
+// already counts that step): PyTorch's reduce-on-plateau (mode min, relative
+// threshold) or StepLR.  StepLR decays after every `patience`-th update of the
+// item's persistent step count, so a call resumed from its schedule state keeps
+// the phase of the decay (PyTorch's StepLR counts scheduler steps across epochs
+// the same way).
+__device__ __forceinline__ void sched_step(const SolveArgs &a, ItemSched &s, double loss) {
     if (a.sch == DPF_SCHED_PLATEAU) {
         if (loss < s.best * (1.0 - a.threshold)) {
             s.best = loss;
@@ -159,7 +163,7 @@ __device__ __forceinline__ void sched_step(const SolveArgs &a, ItemSched &s, dou
             s.bad = 0;
         }
     } else if (a.sch == DPF_SCHED_STEP) {
-        if (a.patience > 0 && ((it + 1) % a.patience) == 0) s.lr = s.lr * a.factor;
+        if (a.patience > 0 && ((int64_t)s.t_step % a.patience) == 0) s.lr = s.lr * a.factor;
     }
 }
 
@@ -215,16 +219,20 @@ __device__ __forceinline__ double residual_count(const int8_t *__restrict__ bt, 
 }
 
 // the N-1 branch of case c as local bus indices and its pi-model blocks
-// (of = ot = -1 when the case has no outage inside [lo, hi))
+// (of = ot = -1 when the case has no outage inside [lo, hi)); bad: the index is
+// neither -1 nor a branch index, and the kernels leave the case alone (the call's
+// prologue, outage_check_kernel, reports it)
 struct Rank2 {
     int of, ot;
     double2 oy, oyd;
+    bool bad;
 };
 
 __device__ __forceinline__ Rank2 outage_of_case(const OutageView &ov, int c, int lo, int hi) {
-    Rank2 r{-1, -1, make_double2(0.0, 0.0), make_double2(0.0, 0.0)};
+    Rank2 r{-1, -1, make_double2(0.0, 0.0), make_double2(0.0, 0.0), false};
     if (ov.outage) {
         const int32_t k = ov.outage[c];
+        r.bad = outage_index_bad(k, ov.n_branch);
         if ((uint32_t)k < (uint32_t)ov.n_branch) {
             const int32_t f = ov.from[k], t = ov.to[k];
             if (f >= lo && f < hi && t >= lo && t < hi && f != t) {
@@ -276,6 +284,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
 
     // N-1 outage of this case (only meaningful for a single sub-grid)
     const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    if (r2.bad) return;  // reported by the call's prologue
     const int of = r2.of, ot = r2.ot;
     const double2 oy = r2.oy, oyd = r2.oyd;
 
@@ -488,7 +497,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
             }
         }
         // ---------------- schedule step (uniform across the workgroup)
-        sched_step(a, sc, loss, it);
+        sched_step(a, sc, loss);
         if (!dbl) {
             __syncthreads();
 #pragma unroll
@@ -575,6 +584,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 
     // N-1 outage of this case (only meaningful for a single sub-grid)
     const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    if (r2.bad) return;  // reported by the call's prologue
     const int of = r2.of, ot = r2.ot;
     const double2 oy = r2.oy, oyd = r2.oyd;
 
@@ -739,7 +749,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 if (dbl) Xv[il] = v;
                 else if (HOLD) hold[kk % KH] = v;
         DPF_BUS_LOOP_END
-        sched_step(a, sc, loss, it);
+        sched_step(a, sc, loss);
         if (!dbl) {
             __syncthreads();
             if (HOLD) {
@@ -817,6 +827,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
 
     // N-1 outage of this case (only meaningful for a single sub-grid)
     const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    if (r2.bad) return;  // reported by the call's prologue
     const int of = r2.of, ot = r2.ot;
     const double2 oy = r2.oy, oyd = r2.oyd;
 
@@ -1010,7 +1021,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                 X[i - lo] = make_double2(vmi * cs, vmi * sn);
             }
         }
-        sched_step(a, sc, loss, it);
+        sched_step(a, sc, loss);
         __syncthreads();
     }
 
@@ -1070,6 +1081,7 @@ __global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
     const double m_res = residual_count<NT>(a.bt, lo, hi, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
     const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
+    if (r2.bad) return;  // reported by the call's prologue
     const int of = r2.of, ot = r2.ot;
     const double2 oy = r2.oy, oyd = r2.oyd;
 
@@ -1273,7 +1285,7 @@ __global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
         sc.t_step += 1.0;
         sc.b1t = b1t;
         sc.b2t = b2t;
-        sched_step(a, sc, loss, it);
+        sched_step(a, sc, loss);
     }
     // the point returned sits in copy it mod 2: bring copy 1 back to the caller's arrays
     if (it & 1) {
@@ -1359,8 +1371,10 @@ __global__ __launch_bounds__(NT) void team_solve_multi_kernel(SolveArgs a) {
         return alt + (f == 0 ? 0 : f) * a.st_stride + cb;
     };
 
-    // every slot marked in need[] takes the next case of the queue (or goes idle)
-    auto take_cases = [&]() {
+    // every slot marked in need[] takes the next case of the queue (or goes idle);
+    // cases it cannot run (bad grid, bad outage index) are passed over until the
+    // queue is empty
+    auto take_once = [&]() {
         if (tid == 0) {
 #pragma unroll
             for (int k = 0; k < C; ++k)
@@ -1386,8 +1400,13 @@ __global__ __launch_bounds__(NT) void team_solve_multi_kernel(SolveArgs a) {
                 need[k] = true;
                 continue;
             }
-            sc[k] = load_item_sched(a, c);
             r2[k] = outage_of_case(a.ov, c, 0, n);
+            if (r2[k].bad) {  // reported by the call's prologue: take the next case
+                cse[k] = -1;
+                need[k] = true;
+                continue;
+            }
+            sc[k] = load_item_sched(a, c);
             if (a.st_fresh) {
                 for (int il = tid; il < n; il += NT) {
                     field(c, 0, 2)[il] = 0.0;
@@ -1399,14 +1418,16 @@ __global__ __launch_bounds__(NT) void team_solve_multi_kernel(SolveArgs a) {
         }
         __syncthreads();
     };
-    // a bad grid marks every case it takes and takes again until the queue is empty
-    for (;;) {
-        take_cases();
-        bool again = false;
+    auto take_cases = [&]() {
+        for (;;) {
+            take_once();
+            bool again = false;
 #pragma unroll
-        for (int k = 0; k < C; ++k) again |= need[k];
-        if (!again) break;
-    }
+            for (int k = 0; k < C; ++k) again |= need[k];
+            if (!again) break;
+        }
+    };
+    take_cases();
 
     const int nb = (n + BLK - 1) / BLK;
     for (;;) {
@@ -1598,7 +1619,7 @@ __global__ __launch_bounds__(NT) void team_solve_multi_kernel(SolveArgs a) {
                 sc[k].t_step += 1.0;
                 sc[k].b1t *= a.b1;
                 sc[k].b2t *= a.b2;
-                sched_step(a, sc[k], loss, itk[k]);
+                sched_step(a, sc[k], loss);
                 itk[k] += 1;
                 continue;
             }
@@ -1663,6 +1684,21 @@ __global__ __launch_bounds__(1024) void collect_paused_kernel(int32_t n_items, c
         if (status[i] == kPaused) list[atomicAdd(&n, 1)] = i;
     __syncthreads();
     if (threadIdx.x == 0) *count = n;
+}
+
+// Call prologue with an outage list: a case whose index is neither -1 nor a
+// branch index is reported (status DPF_BAD_OUTAGE, no updates, NaN mismatch and
+// loss) and counted as finished for the tail handoff; the kernels skip it.
+__global__ void outage_check_kernel(int32_t B, OutageView ov, int32_t *__restrict__ status,
+                                    int32_t *__restrict__ iters, double *__restrict__ mu,
+                                    double *__restrict__ loss, int32_t *__restrict__ done_count) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= B || !outage_index_bad(ov.outage[c], ov.n_branch)) return;
+    status[c] = DPF_BAD_OUTAGE;
+    iters[c] = 0;
+    mu[c] = __longlong_as_double(0x7ff8000000000000LL);
+    loss[c] = __longlong_as_double(0x7ff8000000000000LL);
+    atomicAdd(done_count, 1);
 }
 
 // Case order of a call: descending initial max|r| (NaN first, ties by index), so

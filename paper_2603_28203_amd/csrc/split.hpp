@@ -140,6 +140,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
     const double m_res = residual_count<NT>(a.bt, 0, n, red);
     const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
     const Rank2 r2 = outage_of_case(a.ov, c, 0, n);
+    if (r2.bad) return;  // reported by the call's prologue (status stays DPF_BAD_OUTAGE); every member leaves
     const int of = r2.of, ot = r2.ot;
     const double2 oy = r2.oy, oyd = r2.oyd;
 
@@ -363,7 +364,9 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             stat = DPF_MAX_ITER;
             break;
         }
-        if (slice_flag) break;  // time slice used up: paused at the start of iteration it
+        // time slice used up: paused at the start of iteration it, once this launch has
+        // applied an update (so that every launch advances every unfinished case)
+        if (slice_flag && it > it0) break;
 
         // ---------------- B: rows of this member
         sc.t_step += 1.0;
@@ -413,7 +416,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
                 sa_c[il] = sa;
             }
         }
-        sched_step(a, sc, loss, it);
+        sched_step(a, sc, loss);
         if (!solo) ok = team_barrier(cnt, ++nbar * T, p.limit, &bar_flag);
         else __syncthreads();
         if (!ok) {
@@ -433,13 +436,16 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
 
 // a call that starts on the split kernel: every case paused at iteration 0 and
 // listed in order
-__global__ void split_start_kernel(int32_t B, int32_t *__restrict__ status, int32_t *__restrict__ iters,
-                                   int32_t *__restrict__ list) {
+__global__ void split_start_kernel(int32_t B, OutageView ov, int32_t *__restrict__ status,
+                                   int32_t *__restrict__ iters, int32_t *__restrict__ list) {
     const int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= B) return;
+    list[c] = c;
+    // a case with a bad outage index keeps the prologue's status, so that it
+    // drops out of the list after the first launch (its team leaves at once)
+    if (ov.outage && outage_index_bad(ov.outage[c], ov.n_branch)) return;
     status[c] = kPaused;
     iters[c] = 0;
-    list[c] = c;
 }
 
 // fresh optimizer moments

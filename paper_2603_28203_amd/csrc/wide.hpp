@@ -119,6 +119,8 @@ __global__ void wide_item_init_kernel(WideArgs a, int32_t cap) {
     WideItem it{};
     it.active = (hi - lo) > cap ? 1 : 0;  // only wide items are run here
     if (a.resume) it.active = a.status[idx] == kPaused ? 1 : 0;
+    // a bad outage index (one sub-grid: item = case) was reported by the prologue
+    if (a.ov.outage && outage_index_bad(a.ov.outage[idx], a.ov.n_branch)) it.active = 0;
     it.owned = it.active;
     it.iters = a.resume && it.active ? a.iters[idx] : 0;
     it.t = 0.0;
@@ -270,7 +272,8 @@ __global__ __launch_bounds__(kWave) void wide_reduce_kernel(WideArgs a) {
                 it.bad = 0;
             }
         } else if (a.sch == DPF_SCHED_STEP) {
-            if (a.patience > 0 && (it.iters % a.patience) == 0) it.lr = it.lr * a.factor;
+            // keyed on the persistent step count, as in the per-item kernels
+            if (a.patience > 0 && ((int64_t)it.t % a.patience) == 0) it.lr = it.lr * a.factor;
         }
     }
     a.items[idx] = it;

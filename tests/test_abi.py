@@ -57,8 +57,8 @@ def test_host_side_validation(lib):
     assert rc == -1 and b"n_bus" in lib.dpf_last_error()
     # mismatch_grad / solve reject a null grid
     assert lib.dpf_mismatch_grad(None, 1, 1, *([None] * 12), ctypes.c_size_t(0), None) == -1
-    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 15), ctypes.c_size_t(0), None) == -1
-    assert lib.dpf_solve_series(None, 1, 1, *([None] * 3), 1, *([None] * 4), 1, *([None] * 7),
+    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 16), ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_solve_series(None, 1, 1, *([None] * 3), 1, *([None] * 4), 1, *([None] * 8),
                                 ctypes.c_size_t(0), None) == -1
     assert lib.dpf_param_grad(None, 1, 1, *([None] * 3), 0, *([None] * 8), 1, None, None,
                               ctypes.c_size_t(0), None) == -1
@@ -75,16 +75,14 @@ def test_host_side_validation(lib):
                               ctypes.c_size_t(0), None) == -1  # B = 0
     assert lib.dpf_dc_init(gp, 1, 100, None, None, 0, None, None, ctypes.c_double(1e-12), 10, None, None,
                            None, ctypes.c_size_t(0), None) == -1  # ld < n_bus
-    lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
-    lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
-                                              ctypes.c_int32, ctypes.c_int32]
-    small = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
-    big = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 2048, 9241)
+    _ws_types(lib)
+    small = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, None)
+    big = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 2048, 9241, None)
     # streaming state: 4 moments + 3 complex scratch per bus-case, plus the sliced matrix
     assert big - small >= 1024 * 9241 * (4 * 8 + 3 * 16) - 1024  # (256-byte alignment of each array)
     # a single item of this size is spread over many workgroups: its layout holds the same state
-    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1, 9241) >= 9241 * (4 * 8 + 3 * 16)
-    assert lib.dpf_solve_workspace_bytes(None, 1, None, 1, 1) == 0
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1, 9241, None) >= 9241 * (4 * 8 + 3 * 16)
+    assert lib.dpf_solve_workspace_bytes(None, 1, None, 1, 1, None) == 0
 
 
 def test_variant_table_and_autotune_cache(lib):
@@ -117,74 +115,92 @@ def test_variant_table_and_autotune_cache(lib):
     assert lib.dpf_solve_variant_cases(n) == -1 and lib.dpf_solve_variant_cases(-1) == -1
 
 
-def test_tail_handoff_setting_and_workspace(lib):
-    """dpf_autotune_set_tail_handoff validates its argument, is undone by the
-    reset, and a call that may hand over needs the larger workspace (the paused
-    item list, a schedule buffer and the multi-workgroup arrays)."""
+class _Route(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32), ("team_cap", ctypes.c_int32), ("tail_handoff", ctypes.c_int32),
+                ("tail_team", ctypes.c_int32), ("tail_chunk", ctypes.c_int32), ("tail_min_items", ctypes.c_int32),
+                ("tail_slice_ms", ctypes.c_double), ("tail_first_wait_s", ctypes.c_double),
+                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+def _ws_types(lib):
     lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
     lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
-                                              ctypes.c_int32, ctypes.c_int32]
+                                              ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(_Route)]
+    lib.dpf_route_default.argtypes = [ctypes.POINTER(_Route)]
+    lib.dpf_route_default.restype = None
+
+
+def _default_route(lib):
+    r = _Route()
+    lib.dpf_route_default(ctypes.byref(r))
+    return r
+
+
+def test_route_defaults_and_field_checks(lib):
+    """dpf_route_default fills the documented defaults, and a route with any field
+    out of range sizes no workspace (the solve call returns DPF_EINVAL for it)."""
+    _ws_types(lib)
+    r = _default_route(lib)
+    assert (r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items) == (-1, 0, 0, 0,
+                                                                                                    128, 0)
+    assert (r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.reserved) == (0.0, 1.0, 5.0, 0, 0)
+    g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
+    ok = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(r))
+    assert ok == lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, None) > 0
+    bad = [("variant", -2), ("variant", 10 ** 6), ("team_cap", -1), ("tail_handoff", -1), ("tail_team", -1),
+           ("tail_team", 1025), ("tail_chunk", 0), ("tail_chunk", 65537), ("tail_min_items", -1),
+           ("tail_slice_ms", -1.0), ("tail_slice_ms", 1001.0), ("tail_slice_ms", float("nan")),
+           ("tail_first_wait_s", -1.0), ("tail_wait_s", 61.0), ("tail_first_wait_s", float("nan")),
+           ("case_order", 2), ("case_order", -1), ("reserved", 1)]
+    for name, val in bad:
+        rb = _default_route(lib)
+        setattr(rb, name, val)
+        assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(rb)) == 0, name
+    # a variant that cannot hold the grid (the 64-thread register-resident one)
+    rb = _default_route(lib)
+    rb.variant = 0
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(rb)) == 0
+
+
+def test_route_tail_handoff_sizes_its_own_call_only(lib):
+    """A route with a tail handoff needs the larger workspace of its call (the
+    paused item list, a schedule buffer and the multi-workgroup arrays); another
+    call's route, the autotune cache reset and sub-grid calls are unaffected: no
+    setting outlives the call that passes it."""
+    _ws_types(lib)
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     lib.dpf_autotune_reset()
     band = [i for i in range(lib.dpf_solve_variant_count()) if _kind(lib, i) == 3][0]
-    assert lib.dpf_autotune_set(9241, band) == 0
-    plain = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
-    assert lib.dpf_autotune_set_tail_handoff(-1) == -1
-    assert lib.dpf_autotune_set_tail_handoff(192) == 0
-    assert lib.dpf_tail_handoff() == 192
-    handed = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
+    plain_r = _default_route(lib)
+    plain_r.variant = band
+    plain = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(plain_r))
+    hand_r = _default_route(lib)
+    hand_r.variant = band
+    hand_r.tail_handoff = 192
+    handed = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(hand_r))
     slices = (9241 + 63) // 64
     assert handed - plain >= 1024 * (4 + 6 * 8 + slices * 16)
-    # sub-grids never hand over: same size with and without the setting
+    # the plain route still sizes the plain call after the handoff route was used
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(plain_r)) == plain
+    # the split-kernel team size does not change the workspace
+    team_r = _default_route(lib)
+    team_r.variant, team_r.tail_handoff, team_r.tail_team, team_r.tail_slice_ms = band, 192, 32, 10.0
+    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(team_r)) == handed
+    # sub-grids never hand over: same size with and without it
     sub = (ctypes.c_int32 * 3)(0, 5000, 9241)
-    with_sub = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241)
-    lib.dpf_autotune_reset()  # also clears the handoff
-    assert lib.dpf_tail_handoff() == 0
-    assert lib.dpf_autotune_set(9241, band) == 0
-    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == plain
-    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241) == with_sub
-    lib.dpf_autotune_reset()
+    hand_r.variant = -1
+    plain_r.variant = -1
+    assert (lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241, ctypes.byref(hand_r)) ==
+            lib.dpf_solve_workspace_bytes(ctypes.byref(g), 2, sub, 1024, 9241, ctypes.byref(plain_r)))
 
 
-def test_tail_team_setting(lib):
-    """dpf_autotune_set_tail_team validates its arguments and is undone by the
-    reset; it does not change the workspace size."""
-    lib.dpf_tail_team.restype = ctypes.c_int32
-    lib.dpf_autotune_set_tail_team.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_double]
-    lib.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
-    lib.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int32, ctypes.c_void_p,
-                                              ctypes.c_int32, ctypes.c_int32]
-    g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
-    lib.dpf_autotune_reset()
-    assert lib.dpf_tail_team() == 0
-    assert lib.dpf_autotune_set_tail_handoff(192) == 0
-    before = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241)
-    for bad in ((-1, 128, 0, 0.0), (1025, 128, 0, 0.0), (8, 0, 0, 0.0), (8, 65537, 0, 0.0), (8, 128, -1, 0.0),
-                (8, 128, 0, -1.0), (8, 128, 0, 1001.0), (8, 128, 0, float("nan"))):
-        assert lib.dpf_autotune_set_tail_team(*bad) == -1, bad
-        assert lib.dpf_tail_team() == 0
-    assert lib.dpf_autotune_set_tail_team(32, 128, 16, 2.5) == 0
-    assert lib.dpf_tail_team() == 32
-    lib.dpf_autotune_set_tail_waits.argtypes = [ctypes.c_double, ctypes.c_double]
-    for bad in ((-1.0, 1.0), (1.0, -1.0), (61.0, 1.0), (float("nan"), 1.0)):
-        assert lib.dpf_autotune_set_tail_waits(*bad) == -1, bad
-    assert lib.dpf_autotune_set_tail_waits(0.0, 0.0) == 0
-    assert lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241) == before
-    lib.dpf_autotune_reset()
-    assert lib.dpf_tail_team() == 0 and lib.dpf_tail_handoff() == 0
-
-
-def test_case_order_setting(lib):
-    """dpf_autotune_set_case_order accepts 0 and 1 only and is undone by the reset."""
-    lib.dpf_case_order.restype = ctypes.c_int32
-    lib.dpf_autotune_set_case_order.argtypes = [ctypes.c_int32]
-    lib.dpf_autotune_reset()
-    assert lib.dpf_case_order() == 0
-    for bad in (-1, 2):
-        assert lib.dpf_autotune_set_case_order(bad) == -1
-    assert lib.dpf_autotune_set_case_order(1) == 0 and lib.dpf_case_order() == 1
-    lib.dpf_autotune_reset()
-    assert lib.dpf_case_order() == 0
+def test_bad_outage_status_is_declared():
+    """An outage index that is neither -1 nor a branch index is reported per case
+    (DPF_BAD_OUTAGE, status 4), and the binding exposes the same code."""
+    text = open(HEADER).read()
+    assert re.search(r"#define DPF_BAD_OUTAGE 4\b", text)
+    from paper_2603_28203_amd import binding
+    assert binding.BAD_OUTAGE == 4
 
 
 def _kind(lib, i):

@@ -5,6 +5,8 @@ Tolerances: 1e-10 normwise relative on mismatch and gradient (per case,
 bit-exact on the Y-bus pattern; 1e-6 relative against central finite
 differences of the GPU loss."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -25,6 +27,49 @@ def dpf():
     import paper_2603_28203_amd as m
     m.lib()
     return m
+
+
+class Routed:
+    """The library module plus one Route that every solve call of a test passes
+    (dpf_solve_batch takes its routing per call; nothing is set process-wide)."""
+
+    def __init__(self, m, **route):
+        self.m = m
+        self.route = m.Route(**route)
+
+    def __getattr__(self, name):
+        return getattr(self.m, name)
+
+    def solve(self, *args, **kw):
+        kw.setdefault("route", dataclasses.replace(self.route))
+        return self.m.solve(*args, **kw)
+
+    def solve_series(self, *args, **kw):
+        kw.setdefault("route", dataclasses.replace(self.route))
+        return self.m.solve_series(*args, **kw)
+
+    def autotune(self, *args, **kw):
+        kw.setdefault("route", dataclasses.replace(self.route))
+        return self.m.autotune(*args, **kw)
+
+    def set_team_cap(self, buses):
+        self.route.team_cap = buses
+
+    def set_tail_handoff(self, items):
+        self.route.tail_handoff = items
+
+    def tail_handoff(self):
+        return self.route.tail_handoff
+
+    def set_tail_team(self, max_team, chunk=128, min_items=0, slice_ms=0.0):
+        self.route.tail_team, self.route.tail_chunk = max_team, chunk
+        self.route.tail_min_items, self.route.tail_slice_ms = min_items, slice_ms
+
+    def set_tail_waits(self, first_s, later_s):
+        self.route.tail_first_wait_s, self.route.tail_wait_s = first_s, later_s
+
+    def set_case_order(self, mode):
+        self.route.case_order = mode
 
 
 def dgrid(dpf, g):
@@ -526,9 +571,8 @@ def test_solve_reports_bad_grid_row_bound(dpf):
 
 @pytest.fixture
 def wide_cap(dpf):
-    """Route sub-grids above 500 buses to the multi-workgroup path."""
-    dpf.set_team_cap(500)
-    yield 500
+    """Solve calls that route sub-grids above 500 buses to the multi-workgroup path."""
+    yield Routed(dpf, team_cap=500)
     dpf.autotune_reset()
 
 
@@ -547,7 +591,7 @@ def test_wide_path_tracks_oracle(dpf, wide_cap):
     steps = 25
     Yg = dgrid(dpf, g)
     vm = cu(vm0[None]); va = cu(va0[None])
-    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    out = wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
     torch.cuda.synchronize()
     ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
     assert out["status"].item() == 1 and out["iters"].item() == steps
@@ -569,7 +613,7 @@ def test_wide_path_outage_and_schedule(dpf, wide_cap):
     Yg = dgrid(dpf, g)
     vm = cu(vm0); va = cu(va0)
     sch = dpf.fresh_sched_state(3, 1e-3)
-    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(out, torch.int32), sched_state=sch,
+    wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(out, torch.int32), sched_state=sch,
               opts=dpf.Options(tol=0.0, max_iter=steps, **kw))
     torch.cuda.synchronize()
     for c in range(3):
@@ -597,7 +641,7 @@ def test_mixed_team_and_wide_items(dpf, wide_cap):
     Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
     vm = cu(vm0[None]); va = cu(va0[None])
     steps = 20
-    o = dpf.solve(Yg, bt, cu(S[None], torch.complex128), vm, va, sub_offset=off.tolist(),
+    o = wide_cap.solve(Yg, bt, cu(S[None], torch.complex128), vm, va, sub_offset=off.tolist(),
                   opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
     torch.cuda.synchronize()
     assert o["iters"].tolist() == [steps] * 4 and o["status"].tolist() == [1] * 4
@@ -619,18 +663,18 @@ def test_wide_path_resume_and_status(dpf, wide_cap):
     base = dpf.Options(lr=1e-3, tol=0.0, max_iter=40)
     vmA = cu(np.tile(vm0, (3, 1))); vaA = cu(np.tile(va0, (3, 1)))
     vmA[2] = cu(g.vm); vaA[2] = cu(g.va)
-    oA = dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=dpf.Options(**{**base.__dict__, "tol": 1e-6}))
+    oA = wide_cap.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=dpf.Options(**{**base.__dict__, "tol": 1e-6}))
     torch.cuda.synchronize()
     assert oA["status"].tolist() == [1, 2, 0] and oA["iters"].tolist() == [40, 0, 0]
     # resume: 2 x 20 iterations == 40 iterations, bit for bit
     vmB = cu(vm0[None]); vaB = cu(va0[None])
-    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmB, vaB, opts=base)
+    wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vmB, vaB, opts=base)
     vmC = cu(vm0[None]); vaC = cu(va0[None])
     st = torch.zeros((4, 1, g.n_bus), dtype=torch.float64, device="cuda")
     sch = dpf.fresh_sched_state(1, base.lr)
     half = dpf.Options(**{**base.__dict__, "max_iter": 20})
-    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
-    dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
+    wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
+    wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
     torch.cuda.synchronize()
     assert torch.equal(vmB, vmC) and torch.equal(vaB, vaC)
 
@@ -845,17 +889,145 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
     if path == "banded":
         band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
         dpf.lib().dpf_autotune_set(n, band)
-    if path == "wide":
-        dpf.set_team_cap(1000)
+    rt = dpf.Route(team_cap=1000) if path == "wide" else None
     print(f"optimizer {kind} on the {path} path, n={n}", flush=True)
     vm = cu(vm0[None]); va = cu(va0[None])
     out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va,
-                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o), route=rt)
     torch.cuda.synchronize()
     assert out["iters"].item() == steps
     assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-10
     assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
     assert np.abs(va[0].cpu().numpy() - va0).max() > 1e-4  # the update moved the iterate
+
+
+@pytest.mark.parametrize("path", ["register", "banded-stream", "split", "wide"])
+def test_step_schedule_on_every_path_and_resumed(dpf, path):
+    """StepLR (Table 3's schedule for the first time step; Sec. 6.3) on the
+    per-item register and banded-stream kernels, on the split kernel (every case
+    handed over after 32 iterations) and on the multi-workgroup path: iterates
+    and the final lr equal the oracle's after 80 steps (8 decays), and two
+    resumed calls of 37 and 43 steps (a split that is not a multiple of the step
+    size) equal one call bit for bit, so the decay keeps its phase."""
+    n = 300 if path == "register" else 3000
+    base = synth.config1(B=1, seed=9900 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0]) if path in ("banded-stream", "split") else base
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    B = 3
+    rng = np.random.default_rng(9901)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type != 2)
+    steps = 80
+    o = dict(lr=1e-3, beta1=0.9802, beta2=0.944, sched=oracle.SCHED_STEP, factor=0.8, patience=10)
+    refs = [oracle.solve_adam(Yo, g.bus_type, S, vm0[c], va0[c], oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
+            for c in range(B)]
+    assert refs[0]["lr"] == pytest.approx(1e-3 * 0.8 ** 8, rel=1e-14)
+    Yg = dgrid(dpf, g)
+    rt = dpf.Route()
+    if path == "banded-stream":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
+    elif path == "split":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
+        rt.tail_handoff, rt.tail_team, rt.tail_chunk = B, 8, 16
+    elif path == "wide":
+        rt.team_cap = 1000
+    Sd = cu(S, torch.complex128)
+    print(f"StepLR on the {path} path, n={n}", flush=True)
+    stats = dpf.split_stats()
+    vm = cu(vm0); va = cu(va0)
+    sch = dpf.fresh_sched_state(B, o["lr"])
+    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, sched_state=sch, route=rt,
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **o))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * B
+    if path == "split":
+        assert split_ran(dpf, stats)
+    for c in range(B):
+        assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, c
+        assert sch[c, 1].item() == refs[c]["lr"], c
+        assert sch[c, 0].item() == steps
+    # resumed: 37 + 43 steps with the caller's moments and schedule
+    vmR = cu(vm0); vaR = cu(va0)
+    st = torch.zeros((4, B, n), dtype=torch.float64, device="cuda")
+    schR = dpf.fresh_sched_state(B, o["lr"])
+    for k in (37, 43):
+        dpf.solve(Yg, g.bus_type, Sd, vmR, vaR, adam_state=st, sched_state=schR, route=rt,
+                  opts=dpf.Options(tol=0.0, max_iter=k, **o))
+    torch.cuda.synchronize()
+    assert torch.equal(schR[:, :2], sch[:, :2])
+    assert torch.equal(vmR, vm) and torch.equal(vaR, va)
+
+
+@pytest.mark.parametrize("path", ["register", "banded-stream", "split-direct", "wide", "batched"])
+def test_bad_outage_index_is_reported(dpf, path):
+    """An outage index that is neither -1 nor a branch index (n_branch, -2) gives
+    status DPF_BAD_OUTAGE with no update, NaN max|dS| and loss, on every solve
+    path; the other cases of the call (no outage, a valid outage) equal their
+    oracle solves.  dpf_mismatch_grad returns NaN for such a case and leaves the
+    others alone; dpf_dc_init reports a NaN residual and leaves its angles."""
+    n = 300 if path == "register" else 3000
+    base = synth.config1(B=1, seed=9950 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0]) if path != "register" else base
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    outage = np.array([-1, len(g.f), int(nbr[3]), -2, int(nbr[7])], dtype=np.int32)
+    B = len(outage)
+    rng = np.random.default_rng(9951)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type != 2)
+    steps = 40
+    Yg = dgrid(dpf, g)
+    rt = dpf.Route()
+    if path == "banded-stream":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
+        # 5 cases, 2 of them bad and counted as finished at once: the 3 others are
+        # handed over at iteration 32
+        rt.tail_handoff, rt.tail_team = 3, 4
+    elif path == "split-direct":
+        rt.tail_team = 8  # few large cases: the split kernel from the first iteration
+    elif path == "wide":
+        rt.team_cap = 1000
+    elif path == "batched":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-batched" and x["cases"] == 2
+                      and x["threads"] == 256][0]["index"]
+    print(f"bad outage indices on the {path} path, n={n}", flush=True)
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32), route=rt,
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    bad = [1, 3]
+    st = out["status"].tolist()
+    it = out["iters"].tolist()
+    for c in range(B):
+        if c in bad:
+            assert st[c] == dpf.BAD_OUTAGE and it[c] == 0, (c, st[c])
+            assert np.isnan(out["max_mis"][c].item()) and np.isnan(out["loss"][c].item())
+            assert np.array_equal(vm[c].cpu().numpy(), vm0[c]) and np.array_equal(va[c].cpu().numpy(), va0[c])
+        else:
+            assert st[c] == dpf.MAX_ITER and it[c] == steps, (c, st[c])
+            ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                                    oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+            assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+            assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+    if path != "register":
+        return
+    r = dpf.mismatch_grad(Yg, g.bus_type, cu(S, torch.complex128), cu(vm0), cu(va0), outage=cu(outage, torch.int32))
+    loss = r["loss"].cpu().numpy()
+    for c in range(B):
+        if c in bad:
+            assert np.isnan(loss[c]) and np.isnan(r["max_mis"][c].item())
+            assert np.isnan(r["g_va"][c].cpu().numpy()[g.bus_type != 2]).all()
+        else:
+            ref = oracle.loss_grad(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, vm0[c], va0[c], S)
+            assert abs(loss[c] - ref[0]) <= 1e-10 * ref[0], c
+    dcg = dpf.build_dc_grid(g.n_bus, g.f, g.t, g.x)
+    va_dc = torch.zeros((B, n), dtype=torch.float64, device="cuda")
+    d = dpf.dc_init(dcg, g.bus_type, cu(S, torch.complex128), va_dc, outage=cu(outage, torch.int32))
+    res = d["residual"].cpu().numpy()
+    assert np.isnan(res[bad]).all() and (d["iters"].cpu().numpy()[bad] == 0).all()
+    assert (va_dc[bad] == 0).all() and (res[[0, 2, 4]] < 1e-10).all()
 
 
 # ---------------------------------------------------------------- parameter gradients
@@ -1403,8 +1575,7 @@ def test_batched_falls_back_for_sub_grids_and_wide_band(tuned):
 
 @pytest.fixture
 def handoff(dpf):
-    yield dpf
-    dpf.set_tail_handoff(0)
+    yield Routed(dpf)
     dpf.autotune_reset()
 
 
@@ -1416,7 +1587,7 @@ def split_ran(dpf, before):
     return after["launches"] > before["launches"] and after["abandoned"] == before["abandoned"]
 
 
-@pytest.mark.parametrize("kind", ["banded-stream", "streaming", "banded-window"])
+@pytest.mark.parametrize("kind", ["banded-stream", "banded", "streaming", "banded-window"])
 @pytest.mark.parametrize("threshold", [5, 64])
 @pytest.mark.parametrize("team", [0, 8])
 def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold, team):
@@ -1618,6 +1789,60 @@ def test_concurrent_handoff_calls_on_two_streams(handoff, team):
         assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12
         assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12
     assert split_ran(dpf, stats) == (team > 0)
+
+
+def test_concurrent_calls_with_different_routes(dpf):
+    """Two host threads, each with its own stream, workspace and route -- one
+    hands its tail over to the split kernel (teams of up to 8) with cases ordered
+    by initial mismatch, the other runs a streaming variant named in its route
+    without handoff -- at the same time: each result equals the same call run
+    alone, so one call's settings do not leak into the other."""
+    import threading
+    base = synth.config1(B=1, seed=9810, n_bus=700, n_branch=1120, n_pv=110)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    band = [x for x in dpf.variants() if x["kind"] == "banded-stream"][0]["index"]
+    stream_v = [x for x in dpf.variants() if x["kind"] == "streaming" and x["buses_per_thread"] == 0][0]["index"]
+    routes = [dpf.Route(variant=band, tail_handoff=64, tail_team=8, tail_chunk=64, case_order=1),
+              dpf.Route(variant=stream_v)]
+    B = 6
+    starts = []
+    for seed in (1, 2):
+        rng = np.random.default_rng(9810 + seed)
+        starts.append((g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0),
+                       g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)))
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=300)
+    Sd = cu(S, torch.complex128)
+
+    def run(k, out):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            vm = cu(starts[k][0]); va = cu(starts[k][1])
+            r = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=opts, workspace=dpf.SolveWorkspace(), route=routes[k])
+            stream.synchronize()
+            out[k] = (vm.cpu().numpy(), va.cpu().numpy(), r["iters"].cpu().numpy())
+
+    stats = dpf.split_stats()
+    alone = {}
+    for k in (0, 1):
+        run(k, alone)
+    assert split_ran(dpf, stats)
+    together = {}
+    th = [threading.Thread(target=run, args=(k, together)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert sorted(together) == [0, 1]
+    for k in (0, 1):
+        assert together[k][2].tolist() == [300] * B
+        assert np.abs(together[k][0] - alone[k][0]).max() < 1e-12, k
+        assert np.abs(together[k][1] - alone[k][1]).max() < 1e-12, k
+    # the two routes ran different kernels: their results differ at the rounding level only
+    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, starts[1][0][0], starts[1][1][0],
+                            oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=300))
+    assert np.abs(together[1][0][0] - ref["vm"]).max() < 1e-9
 
 
 @pytest.mark.parametrize("opt", ["sgd", "rmsprop", "adam-constant"])
@@ -1851,6 +2076,12 @@ def test_autotune_with_handoff_keeps_a_kind_that_hands_over(handoff):
     torch.cuda.synchronize()
     assert out["iters"].tolist() == [60] * B
     assert split_ran(dpf, stats)
+    # the handed-over iterates are the oracle's
+    Yo = oracle.ybus_of(g)
+    for c in (0, B - 1):
+        ref = oracle.solve_adam(Yo, g.bus_type, S, vm0[c], va0[c], oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=60))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
 
 
 def test_case_order_by_initial_mismatch(handoff):

@@ -3,6 +3,8 @@ independent library routines.  None of these re-types the oracle's own
 formulas; each would fail for a plausible mistake in it (dropped term, wrong
 sign or index, transposed operand, wrong mask)."""
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -294,9 +296,9 @@ def test_gradient_equals_scaled_jt_f():
     assert mu == np.abs(f).max()
 
 
-def _torch_adam_reference(Y, bt, S, vm0, va0, steps, lr, betas, eps, plateau=None):
+def _torch_adam_reference(Y, bt, S, vm0, va0, steps, lr, betas, eps, plateau=None, step_lr=None):
     """Same iteration driven by torch.optim.Adam (and optionally torch's
-    ReduceLROnPlateau) with gradients from the oracle."""
+    ReduceLROnPlateau or StepLR) with gradients from the oracle."""
     torch = pytest.importorskip("torch")
     vm = torch.tensor(vm0, dtype=torch.float64)
     va = torch.tensor(va0, dtype=torch.float64)
@@ -306,14 +308,18 @@ def _torch_adam_reference(Y, bt, S, vm0, va0, steps, lr, betas, eps, plateau=Non
     sch = None
     if plateau is not None:
         sch = torch.optim.lr_scheduler.ReduceLROnPlateau(opt, mode="min", **plateau)
+    if step_lr is not None:
+        sch = torch.optim.lr_scheduler.StepLR(opt, **step_lr)
     lrs = []
     for _ in range(steps):
         loss, mu, gvm, gva = oracle.loss_grad(Y, bt, pv.detach().numpy(), pa.detach().numpy(), S)
         pv.grad = torch.tensor(gvm)
         pa.grad = torch.tensor(gva)
         opt.step()
-        if sch is not None:
+        if plateau is not None:
             sch.step(loss)
+        elif sch is not None:
+            sch.step()
         lrs.append(opt.param_groups[0]["lr"])
     return pv.detach().numpy(), pa.detach().numpy(), lrs
 
@@ -334,7 +340,7 @@ def _torch_opt_reference(Y, bt, S, vm0, va0, steps, make_opt):
 
 @pytest.mark.parametrize("kind", ["sgd", "sgd_momentum", "rmsprop"])
 def test_sgd_and_rmsprop_match_torch_optim(kind):
-    """The paper's other optimizers (Sec. 6.1: SGD and RMSprop) with PyTorch's
+    """The paper's other optimizers (Sec. 6.3: SGD and RMSprop) with PyTorch's
     definitions: SGD with momentum beta1 (buffer = first gradient, no
     dampening), RMSprop with smoothing beta2 and eps outside the root."""
     torch = pytest.importorskip("torch")
@@ -395,6 +401,67 @@ def test_plateau_schedule_matches_torch():
     assert abs(res["lr"] - lrs[-1]) <= 1e-15
     assert np.abs(res["vm"] - ref_vm).max() < 1e-9
     assert np.abs(res["va"] - ref_va).max() < 1e-9
+
+
+@pytest.mark.parametrize("min_lr,sched_eps", [(3e-3, 1e-8), (0.0, 3e-3)])
+def test_plateau_clamp_and_eps_guard_match_torch(min_lr, sched_eps):
+    """ReduceLROnPlateau's lower bound (min_lr) and its skip of small decreases
+    (eps) at values where each of them acts: with min_lr = 3e-3 the second
+    decrease is clamped to it and later ones are no-ops; with eps = 3e-3 the
+    first decrease (1e-2 -> 5.47e-3) applies and the second (by 2.5e-3) is
+    skipped."""
+    g = synth.config0(2)["grid"]
+    Y = oracle.ybus_of(g)
+    S = oracle.injections(Y, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    # 500 steps: plateaus end at steps 55, 211 and 418 with the default bounds
+    steps = 500
+    pl = dict(factor=0.547, patience=41, threshold=0.0673, cooldown=97)
+    ref_vm, ref_va, lrs = _torch_adam_reference(Y, g.bus_type, S, vm0, va0, steps, 1e-2, (0.979, 0.963), 1e-8,
+                                                plateau=dict(pl, min_lr=min_lr, eps=sched_eps))
+    if min_lr > 0:
+        assert lrs[-1] == min_lr and 1e-2 * 0.547 in lrs  # clamped after a plain decrease
+    else:
+        assert lrs[-1] == 1e-2 * 0.547  # the second decrease was skipped
+    o = oracle.AdamOptions(lr=1e-2, beta1=0.979, beta2=0.963, tol=0.0, max_iter=steps,
+                           sched=oracle.SCHED_PLATEAU, min_lr=min_lr, sched_eps=sched_eps, **pl)
+    res = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, o)
+    assert res["lr"] == lrs[-1]
+    assert np.abs(res["vm"] - ref_vm).max() < 1e-11
+    assert np.abs(res["va"] - ref_va).max() < 1e-11
+
+
+def test_step_schedule_matches_torch_and_resumes():
+    """StepLR (Table 3's first time step; one of the schedulers searched in
+    Sec. 6.3) against torch.optim.lr_scheduler.StepLR on the oracle's gradients,
+    run in one call and as two resumed calls whose split (37) is not a multiple of
+    the step size (30): the decay follows the persistent step count, so the
+    second call keeps the phase."""
+    g = synth.config0(1)["grid"]
+    Y = oracle.ybus_of(g)
+    S = oracle.injections(Y, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    steps, size, gamma = 100, 30, 0.773
+    ref_vm, ref_va, lrs = _torch_adam_reference(Y, g.bus_type, S, vm0, va0, steps, 1e-2, (0.9802, 0.944), 1e-8,
+                                                step_lr=dict(step_size=size, gamma=gamma))
+    assert lrs[-1] == pytest.approx(1e-2 * gamma ** 3, rel=1e-15)
+    o = oracle.AdamOptions(lr=1e-2, beta1=0.9802, beta2=0.944, tol=0.0, max_iter=steps,
+                           sched=oracle.SCHED_STEP, factor=gamma, patience=size)
+    res = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, o)
+    assert res["iters"] == steps and res["t"] == steps
+    assert res["lr"] == lrs[-1]
+    assert np.abs(res["vm"] - ref_vm).max() < 1e-11
+    assert np.abs(res["va"] - ref_va).max() < 1e-11
+    # two resumed calls: moments, step count and current lr carried over
+    k1 = 37
+    r1 = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, dataclasses.replace(o, max_iter=k1))
+    assert r1["lr"] == lrs[k1 - 1] and r1["t"] == k1
+    r2 = oracle.solve_adam(Y, g.bus_type, S, r1["vm"], r1["va"],
+                           dataclasses.replace(o, lr=r1["lr"], max_iter=steps - k1), state=r1["state"], t0=r1["t"])
+    assert r2["t"] == steps and r2["lr"] == res["lr"]
+    assert np.array_equal(r2["vm"], res["vm"]) and np.array_equal(r2["va"], res["va"])
+    # a call that restarted the phase at the split would decay at 37 + 30 = 67, not at 60
+    assert lrs[59] < lrs[58]
 
 
 def test_stop_test_semantics():
