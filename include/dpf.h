@@ -158,6 +158,26 @@ int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const i
                    int32_t *max_row_nnz_out, void *stream);
 
 /*
+ * dpf_build_ybus_noalloc -- dpf_build_ybus for callers that cannot allocate device
+ * memory (serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results, with the temporaries in a static array of the library
+ * (16 MiB per device, held until the process ends) instead of hipMalloc'd
+ * memory.  No allocation of any kind happens in the call.  The temporaries of a
+ * grid take 16 (n_bus + 1) + 256 + 8 (n_bus + 2 n_branch) + 16 n_bus bytes, each
+ * part rounded up to 256; a grid that needs more than 16 MiB (for example more
+ * than about 260 000 buses at 1.5 branches per bus) is rejected with DPF_EINVAL
+ * before any device work.  Every call on one device shares that device's array:
+ * calls that overlap on one device (two host threads, or two streams) race and
+ * must be serialised by the caller; the call returns with `stream` synchronised,
+ * so calls made one after the other never overlap.  The array is cleared at the
+ * start of each call; nothing of a previous call's contents is used.
+ */
+int dpf_build_ybus_noalloc(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                           const double *r, const double *x, const double *b, int32_t nnz_cap,
+                           int32_t *row_ptr, int32_t *col_idx, double *val, int32_t *nnz_out,
+                           int32_t *max_row_nnz_out, void *stream);
+
+/*
  * dpf_mismatch_grad -- one evaluation of the DPF forward and backward pass for
  * B cases on one grid (Algorithm 1 forward pass and loss.backward(); the
  * gradient is the reverse-mode J^T F product of Sec. 5.1, computed by one

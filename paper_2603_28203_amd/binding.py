@@ -73,6 +73,8 @@ def lib():
                               f"expected {want}): rebuild it with `python -m paper_2603_28203_amd.build`")
         L.dpf_build_ybus.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]
         L.dpf_build_ybus.restype = ctypes.c_int
+        L.dpf_build_ybus_noalloc.argtypes = [_i32, _i32, _P, _P, _P, _P, _P, _i32, _P, _P, _P, _P, _P, _P]
+        L.dpf_build_ybus_noalloc.restype = ctypes.c_int
         L.dpf_mismatch_grad.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P,
                                         _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.dpf_mismatch_grad.restype = ctypes.c_int
@@ -172,8 +174,10 @@ class DeviceGrid:
         return self._c
 
 
-def build_ybus(n_bus: int, f, t, r, x, b, device="cuda") -> DeviceGrid:
-    """dpf_build_ybus on device copies of the branch arrays (synchronises)."""
+def build_ybus(n_bus: int, f, t, r, x, b, device="cuda", noalloc: bool = False) -> DeviceGrid:
+    """dpf_build_ybus on device copies of the branch arrays (synchronises);
+    noalloc=True calls dpf_build_ybus_noalloc, whose temporaries live in the
+    library's static array (the caller's outputs are still torch tensors)."""
     f, t = _dev(f, torch.int32, device), _dev(t, torch.int32, device)
     r, x, b = (_dev(v, torch.float64, device) for v in (r, x, b))
     nbr = int(f.numel())
@@ -183,8 +187,9 @@ def build_ybus(n_bus: int, f, t, r, x, b, device="cuda") -> DeviceGrid:
     val = torch.empty(max(cap, 1), dtype=torch.complex128, device=device)
     nnz = ctypes.c_int32(0)
     mrow = ctypes.c_int32(0)
-    _check(lib().dpf_build_ybus(n_bus, nbr, _ptr(f), _ptr(t), _ptr(r), _ptr(x), _ptr(b), cap, _ptr(row_ptr),
-                                _ptr(col), _ptr(val), ctypes.byref(nnz), ctypes.byref(mrow), _stream()))
+    fn = lib().dpf_build_ybus_noalloc if noalloc else lib().dpf_build_ybus
+    _check(fn(n_bus, nbr, _ptr(f), _ptr(t), _ptr(r), _ptr(x), _ptr(b), cap, _ptr(row_ptr), _ptr(col), _ptr(val),
+              ctypes.byref(nnz), ctypes.byref(mrow), _stream()))
     k = nnz.value
     return DeviceGrid(n_bus, k, row_ptr, col[:k].clone(), val[:k].clone(), mrow.value, f, t, r, x, b)
 

@@ -41,6 +41,12 @@ int fail(int code, const std::string &msg) {
 
 size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
+// Temporaries of dpf_build_ybus_noalloc: one array per device, kept for the life
+// of the process.  Host code uses the address hipGetSymbolAddress returns for the
+// current device (DeviceInfo::ybus_scratch), never the name itself.
+constexpr size_t kYbusScratchBytes = (size_t)16 << 20;
+__device__ __align__(256) char scratch[kYbusScratchBytes];
+
 // Per-device limits, queried once per device.
 struct DeviceInfo {
     int lds_per_block = 0;  // bytes
@@ -50,6 +56,7 @@ struct DeviceInfo {
     hipStream_t side = nullptr;      // stream of the multi-workgroup path
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
     int32_t *pinned_count = nullptr; // host-pinned poll target (two words)
+    void *ybus_scratch = nullptr;    // this device's copy of `scratch`
     int index = 0;
 };
 std::mutex g_dev_mu;
@@ -77,6 +84,7 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_out, hipEventDisableTiming));
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_poll, hipEventDisableTiming));
         DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, 2 * sizeof(int32_t), hipHostMallocDefault));
+        DPF_HIP(hipGetSymbolAddress((void **)&g_dev[dev].ybus_scratch, HIP_SYMBOL(scratch)));
         g_dev[dev].index = dev;
         g_dev[dev].ok = true;
     }
@@ -614,35 +622,40 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
     return DPF_OK;
 }
 
-}  // namespace
+// Temporaries of the Y-bus build: deg[n+1] fill[n+1] soff[n+1] ucount[n+1] err[64]
+// (int32, cleared), then the slot list int2[n + 2 n_branch] and the diagonal
+// double2[n], each region 256-byte aligned.
+struct YbusTemps {
+    size_t bytes_i = 0, bytes_s = 0, bytes_d = 0;
+    size_t total() const { return bytes_i + bytes_s + bytes_d; }
+};
 
-extern "C" {
+YbusTemps ybus_temps(int32_t n_bus, int32_t n_branch) {
+    YbusTemps t;
+    t.bytes_i = align_up(sizeof(int32_t) * (4 * (size_t)(n_bus + 1) + 64), 256);
+    t.bytes_s = align_up(sizeof(int2) * ((size_t)n_bus + 2 * (size_t)n_branch), 256);
+    t.bytes_d = align_up(sizeof(double2) * (size_t)n_bus, 256);
+    return t;
+}
 
-const char *dpf_last_error(void) { return g_err.c_str(); }
-
-#ifndef DPF_SOURCE_HASH
-#define DPF_SOURCE_HASH "unknown"
-#endif
-const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64) src " DPF_SOURCE_HASH; }
-
-int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
-                   const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
-                   double *val, int32_t *nnz_out, int32_t *max_row_nnz_out, void *stream) {
-    g_err.clear();
+int ybus_check_args(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
+                    const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
+                    double *val, int32_t *nnz_out) {
     if (n_bus <= 0 || n_branch < 0) return fail(DPF_EINVAL, "n_bus must be > 0 and n_branch >= 0");
     if (n_branch > 0 && (!from || !to || !r || !x || !b)) return fail(DPF_EINVAL, "null branch array");
     if (!row_ptr || !nnz_out || (nnz_cap > 0 && (!col_idx || !val)) || nnz_cap < 0)
         return fail(DPF_EINVAL, "null output array or negative nnz_cap");
     if ((int64_t)n_bus + 2 * (int64_t)n_branch > INT32_MAX) return fail(DPF_EINVAL, "grid too large");
-    hipStream_t st = (hipStream_t)stream;
-    const int32_t nslot = n_bus + 2 * n_branch;
-    // temporaries: deg[n+1] fill[n+1] soff[n+1] ucount[n+1] err[1], slots, diag
-    size_t bytes_i = align_up(sizeof(int32_t) * (4 * (size_t)(n_bus + 1) + 64), 256);
-    size_t bytes_s = align_up(sizeof(int2) * (size_t)nslot, 256);
-    size_t bytes_d = align_up(sizeof(double2) * (size_t)n_bus, 256);
-    char *tmp = nullptr;
-    DPF_HIP(hipStreamSynchronize(st));
-    DPF_HIP(hipMalloc((void **)&tmp, bytes_i + bytes_s + bytes_d));
+    return DPF_OK;
+}
+
+// The Y-bus build on temporaries at `tmp` (laid out as ybus_temps says); returns
+// with the stream synchronised (the result count is read back on the way).
+int build_ybus_on(char *tmp, const YbusTemps &T, int32_t n_bus, int32_t n_branch, const int32_t *from,
+                  const int32_t *to, const double *r, const double *x, const double *b, int32_t nnz_cap,
+                  int32_t *row_ptr, int32_t *col_idx, double *val, int32_t *nnz_out, int32_t *max_row_nnz_out,
+                  hipStream_t st) {
+    const size_t bytes_i = T.bytes_i, bytes_s = T.bytes_s;
     int32_t *deg = (int32_t *)tmp;
     int32_t *fill = deg + (n_bus + 1);
     int32_t *soff = fill + (n_bus + 1);
@@ -652,13 +665,12 @@ int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const i
     double2 *diag = (double2 *)(tmp + bytes_i + bytes_s);
     int rc = DPF_OK;
     int32_t herr = 0, nnz = 0;
-    auto cleanup = [&]() {
-        (void)hipStreamSynchronize(st);
-        (void)hipFree(tmp);
-    };
     do {
-        hipError_t e = hipMemsetAsync(tmp, 0, bytes_i, st);
-        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("hipMemsetAsync: ") + hipGetErrorString(e)); break; }
+        // the counters start at zero (a fill kernel, so that a reused scratch is cleared too)
+        hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((bytes_i / 8 + 255) / 256)), dim3(256), 0, st,
+                           (int64_t)(bytes_i / 8), (double *)tmp);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("clear: ") + hipGetErrorString(e)); break; }
         const int bs = 256;
         int gb = std::max(1, (n_branch + bs - 1) / bs);
         if (n_branch > 0)
@@ -692,8 +704,55 @@ int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const i
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) { rc = fail(DPF_EHIP, std::string("ybus values: ") + hipGetErrorString(e)); break; }
     } while (0);
-    cleanup();
+    (void)hipStreamSynchronize(st);
     return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dpf_last_error(void) { return g_err.c_str(); }
+
+#ifndef DPF_SOURCE_HASH
+#define DPF_SOURCE_HASH "unknown"
+#endif
+const char *dpf_version(void) { return "libdpf 0.1 (gfx950, FP64) src " DPF_SOURCE_HASH; }
+
+int dpf_build_ybus(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to, const double *r,
+                   const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr, int32_t *col_idx,
+                   double *val, int32_t *nnz_out, int32_t *max_row_nnz_out, void *stream) {
+    g_err.clear();
+    int rc = ybus_check_args(n_bus, n_branch, from, to, r, x, b, nnz_cap, row_ptr, col_idx, val, nnz_out);
+    if (rc != DPF_OK) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    const YbusTemps T = ybus_temps(n_bus, n_branch);
+    char *tmp = nullptr;
+    DPF_HIP(hipStreamSynchronize(st));
+    DPF_HIP(hipMalloc((void **)&tmp, T.total()));
+    rc = build_ybus_on(tmp, T, n_bus, n_branch, from, to, r, x, b, nnz_cap, row_ptr, col_idx, val, nnz_out,
+                       max_row_nnz_out, st);
+    (void)hipFree(tmp);
+    return rc;
+}
+
+int dpf_build_ybus_noalloc(int32_t n_bus, int32_t n_branch, const int32_t *from, const int32_t *to,
+                           const double *r, const double *x, const double *b, int32_t nnz_cap, int32_t *row_ptr,
+                           int32_t *col_idx, double *val, int32_t *nnz_out, int32_t *max_row_nnz_out,
+                           void *stream) {
+    g_err.clear();
+    int rc = ybus_check_args(n_bus, n_branch, from, to, r, x, b, nnz_cap, row_ptr, col_idx, val, nnz_out);
+    if (rc != DPF_OK) return rc;
+    const YbusTemps T = ybus_temps(n_bus, n_branch);
+    if (T.total() > kYbusScratchBytes)
+        return fail(DPF_EINVAL, "grid too large for the library's static scratch (" + std::to_string(T.total()) +
+                                    " bytes needed, " + std::to_string(kYbusScratchBytes) +
+                                    " available): use dpf_build_ybus");
+    DeviceInfo dev;
+    rc = device_info(dev);
+    if (rc != DPF_OK) return rc;
+    return build_ybus_on((char *)dev.ybus_scratch, T, n_bus, n_branch, from, to, r, x, b, nnz_cap, row_ptr,
+                         col_idx, val, nnz_out, max_row_nnz_out, (hipStream_t)stream);
 }
 
 size_t dpf_mismatch_grad_workspace_bytes(int32_t n_bus, int32_t B) {
