@@ -232,9 +232,16 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the time-series and uneven-batch lines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference for counter scaling)")
+    ap.add_argument("--roofline-only", type=str, default=None, metavar="KIND",
+                    help="only build the N-1 batch and run the roofline launch (all cases, 200 iterations, "
+                         "warm-up then timed) on the 1024-thread, 4-bus variant of KIND (e.g. banded-pair): "
+                         "the run that rocprofv3 counter passes profile")
     args = ap.parse_args()
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.roofline_only:
+        roofline_only(args.roofline_only, args.cases)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -420,6 +427,21 @@ def main():
                                 "case_iters_per_s": round(cb["case_iters_per_s"], 1),
                                 "single_thread_case_iters_per_s": round(one["case_iters_per_s"], 1)}
     print(json.dumps(line), flush=True)
+
+
+def roofline_only(kind, B):
+    """The roofline launch alone (for counter passes): every case of the N-1 batch
+    active for 200 iterations, no stop test, no handoff; one warm-up launch, then
+    the timed one."""
+    import paper_2603_28203_amd as dpf
+
+    dpf.lib()
+    cfg, g, Yg, S, bt, out, vm0, va0 = make_cfg2(B)
+    v = [x for x in dpf.variants() if x["kind"] == kind and x["threads"] == 1024 and x["buses_per_thread"] == 4][0]
+    fixed = dataclasses.replace(solve_options(200), tol=0.0)
+    _, kf, _, _, _ = run_fused(Yg, bt, S, out, vm0, va0, fixed, 1, 1, dpf.Route(variant=v["index"]))
+    print(json.dumps({"roofline_only": kind, "variant": v, "cases": B, "launch_s": round(kf[0], 5),
+                      "ms_per_iter": round(kf[0] / 200 * 1e3, 4)}), flush=True)
 
 
 def renumbered(g, sub_offset=None):

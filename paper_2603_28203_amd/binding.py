@@ -484,9 +484,10 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window", "banded-batched")
+VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window", "banded-batched",
+                 "banded-pair")
 # the per-item kinds that can hand their tail over (dpf_autotune_set_tail_handoff)
-HANDOFF_KINDS = ("streaming", "banded", "banded-stream", "banded-window")
+HANDOFF_KINDS = ("streaming", "banded", "banded-stream", "banded-window", "banded-pair")
 
 
 def variants():

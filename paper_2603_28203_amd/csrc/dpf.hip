@@ -13,6 +13,7 @@
 #include "common.hpp"
 #include "dc.hpp"
 #include "eval.hpp"
+#include "pair.hpp"
 #include "sell.hpp"
 #include "solve.hpp"
 #include "split.hpp"
@@ -170,6 +171,12 @@ template <int NT, int C>
 Variant make_multi_variant() {
     return Variant{NT, C, dpf::kMulti, dpf::team_solve_multi_kernel<NT, C>};
 }
+// banded, barrier-free gradient sweep, state in (|V|, theta) and moment pairs
+template <int NT, int J>
+Variant make_pair_variant() {
+    return Variant{NT, J, dpf::kPair, dpf::team_solve_pair_kernel<NT, J>};
+}
+
 
 // Register-resident variants up to 2048 buses per item, streaming above (the
 // 1024-thread streaming variant takes any size with holds in scratch; the 512-thread
@@ -192,7 +199,7 @@ const Variant *variant_table(int *count) {
         make_window_variant<256, 1>(),      make_window_variant<128, 2>(),        make_window_variant<128, 1>(),
         make_window_variant<512, 1>(),      make_window_variant<256, 2>(),        make_multi_variant<256, 2>(),
         make_multi_variant<256, 3>(),       make_multi_variant<256, 4>(),         make_multi_variant<512, 2>(),
-        make_multi_variant<128, 4>(),
+        make_multi_variant<128, 4>(),       make_pair_variant<1024, 4>(),         make_pair_variant<1024, 2>(),
         Variant{0, 0, dpf::kWide, nullptr},
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
@@ -296,7 +303,8 @@ struct SolveLayout {
 };
 
 static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
-                                int32_t ld, bool streaming, int32_t team_cap, bool handoff = false) {
+                                int32_t ld, bool streaming, int32_t team_cap, bool handoff = false,
+                                bool pairs = false) {
     SolveLayout L;
     for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
         int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
@@ -327,8 +335,8 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
     if (streaming) {
         L.off_mom = o;  // Adam moments [4][B][ld] when the caller passes none
         o += align_up(sizeof(double) * 4 * (size_t)B * ld, 256);
-        L.off_scr = o;  // V, a*I and w [3][B][ld] complex
-        o += align_up(sizeof(double2) * 3 * (size_t)B * ld, 256);
+        L.off_scr = o;  // V, a*I and w [3][B][ld] complex (paired state: I and the three pairs, [4][B][ld])
+        o += align_up(sizeof(double2) * (pairs ? 4 : 3) * (size_t)B * ld, 256);
     }
     if (wide) {
         L.off_wcount = o;
@@ -1158,7 +1166,7 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
     const int32_t h = route.tail_handoff;
     if (h > 0 && p.v && p.has_small && small == 1 && (!sub_offset || n_sub == 1) &&
         (p.v->mode == dpf::kGlobal || p.v->mode == dpf::kBand || p.v->mode == dpf::kBandStream ||
-         p.v->mode == dpf::kWindow))
+         p.v->mode == dpf::kWindow || p.v->mode == dpf::kPair))
         p.handoff = h;
     return p;
 }
@@ -1179,7 +1187,8 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
     const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev, rt, &forced_bad);
     if (forced_bad) return 0;
     return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap,
-                        p.handoff > 0 || p.split_direct).total;
+                        p.handoff > 0 || p.split_direct, p.v && p.v->mode == dpf::kPair && p.has_small)
+        .total;
 }
 
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, const int32_t *sub_offset_dev,
@@ -1223,8 +1232,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     const Variant *v = plan.v;
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
     const bool handoff = plan.handoff > 0;
+    const bool pairs = v->mode == dpf::kPair && has_small;
     const SolveLayout L =
-        solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff || plan.split_direct);
+        solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff || plan.split_direct, pairs);
     const bool has_wide = L.w_total > 0;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -1394,8 +1404,19 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
             v_lds = (size_t)aw.lds_cap * 16;
             grid = (items + v->k - 1) / v->k;
         }
+        const dim3 pgrid((g->n_bus + 255) / 256, B);
+        double2 *P = a.scratch + a.st_stride;  // the pairs follow I in the scratch
+        if (pairs)
+            hipLaunchKernelGGL(dpf::pair_in_kernel, pgrid, dim3(256), 0, st, g->n_bus, (int64_t)ld, B, vm, va, a.st,
+                               a.st_stride, a.st_fresh, P, P + a.st_stride, P + 2 * a.st_stride);
         DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)v_lds));
         hipLaunchKernelGGL(v->fn, dim3(grid), dim3(v->nt), v_lds, st, aw);
+        DPF_HIP(hipGetLastError());
+        // the pairs back to the caller's layout (every item, paused ones included) before
+        // any other path reads the state
+        if (pairs)
+            hipLaunchKernelGGL(dpf::pair_out_kernel, pgrid, dim3(256), 0, st, g->n_bus, (int64_t)ld, B, vm, va, a.st,
+                               a.st_stride, P, P + a.st_stride, P + 2 * a.st_stride);
         DPF_HIP(hipGetLastError());
         if (dpf::is_banded(v->mode)) {
             // items whose bandwidth exceeds the banded block go to the general variant

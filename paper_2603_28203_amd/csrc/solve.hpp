@@ -33,9 +33,18 @@
 
 namespace dpf {
 
-enum StoreMode { kReg = 0, kGlobal = 1, kBand = 2, kBandStream = 3, kWide = 4, kWindow = 5, kMulti = 6 };
+enum StoreMode {
+    kReg = 0,
+    kGlobal = 1,
+    kBand = 2,
+    kBandStream = 3,
+    kWide = 4,
+    kWindow = 5,
+    kMulti = 6,
+    kPair = 7
+};
 __host__ __device__ constexpr bool is_banded(int mode) {
-    return mode == kBand || mode == kBandStream || mode == kWindow || mode == kMulti;
+    return mode == kBand || mode == kBandStream || mode == kWindow || mode == kMulti || mode == kPair;
 }
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched

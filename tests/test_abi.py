@@ -94,7 +94,7 @@ def test_variant_table_and_autotune_cache(lib):
         assert lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == 0
         assert t.value % 64 == 0 and t.value <= 1024  # 0 for the multi-workgroup entry
         seen_stream |= st.value == 1
-        assert st.value in (0, 1, 2, 3, 4, 5, 6)  # register, streaming, banded(-stream), wide, windowed, batched
+        assert st.value in range(8)  # register, streaming, banded(-stream), wide, windowed, batched, paired
         assert lib.dpf_solve_variant_cases(i) >= 1
     assert seen_stream
     assert lib.dpf_solve_variant_info(n, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == -1

@@ -901,7 +901,56 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
     assert np.abs(va[0].cpu().numpy() - va0).max() > 1e-4  # the update moved the iterate
 
 
-@pytest.mark.parametrize("path", ["register", "banded-stream", "split", "wide"])
+@pytest.mark.parametrize("J", [2, 4])
+def test_paired_state_kernel_equals_the_banded_kernel(dpf, J):
+    """The paired-state kernel does the banded kernel's arithmetic in the same
+    order: on a degree-grouped 9241-bus grid with outages, a plateau schedule and
+    the caller's moments, its iterates, moments, schedule states and outputs
+    equal the 1024-thread banded-stream kernel's bit for bit, from fresh moments
+    and over two resumed half calls."""
+    base = synth.config2(B=6)
+    g = renumber(base["grid"], dpf.rcm_order(base["grid"].n_bus, base["grid"].f, base["grid"].t, group=2560)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B, n = 6, g.n_bus
+    rng = np.random.default_rng(9960)
+    outage = base["outage"].astype(np.int32)
+    outage[0] = -1
+    vm0 = g.vm[None] + rng.normal(0, 1e-3, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-3, (B, n)) * (g.bus_type != 2)
+    Yg = dgrid(dpf, g)
+    kinds = {k: [x for x in dpf.variants() if x["kind"] == k and x["threads"] == 1024 and x["buses_per_thread"] == J][0]
+             for k in ("banded-stream", "banded-pair")}
+    opts = dpf.Options(lr=1e-4, beta1=0.995, beta2=0.995, eps=1e-14, tol=0.0, max_iter=60, sched=dpf.SCHED_PLATEAU,
+                       factor=0.5, patience=7, threshold=0.2)
+    Sd, od = cu(S, torch.complex128), cu(outage, torch.int32)
+    res = {}
+    for k, v in kinds.items():
+        print(f"paired vs banded: {k} {v}", flush=True)
+        rt = dpf.Route(variant=v["index"])
+        vm = cu(vm0); va = cu(va0)
+        sch = dpf.fresh_sched_state(B, opts.lr)
+        o1 = dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=od, sched_state=sch, opts=opts, route=rt)
+        vmR = cu(vm0); vaR = cu(va0)
+        st = torch.zeros((4, B, n), dtype=torch.float64, device="cuda")
+        schR = dpf.fresh_sched_state(B, opts.lr)
+        half = dpf.Options(**{**opts.__dict__, "max_iter": 30})
+        for _ in range(2):
+            o2 = dpf.solve(Yg, g.bus_type, Sd, vmR, vaR, outage=od, adam_state=st, sched_state=schR, opts=half,
+                           route=rt)
+        torch.cuda.synchronize()
+        res[k] = [x.cpu().numpy() for x in (vm, va, sch, o1["max_mis"], o1["loss"], vmR, vaR, st, schR,
+                                             o2["max_mis"])]
+        assert np.array_equal(res[k][0], res[k][5]) and np.array_equal(res[k][1], res[k][6])  # resume = one call
+    for a_, b_ in zip(res["banded-stream"], res["banded-pair"]):
+        assert np.array_equal(a_, b_)
+    ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[3])), g.bus_type, S, vm0[3], va0[3],
+                            oracle.AdamOptions(lr=1e-4, beta1=0.995, beta2=0.995, eps=1e-14, tol=0.0, max_iter=60,
+                                               sched=oracle.SCHED_PLATEAU, factor=0.5, patience=7, threshold=0.2))
+    assert np.abs(res["banded-pair"][0][3] - ref["vm"]).max() < 1e-10
+    assert np.abs(res["banded-pair"][1][3] - ref["va"]).max() < 1e-10
+
+
+@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split", "wide"])
 def test_step_schedule_on_every_path_and_resumed(dpf, path):
     """StepLR (Table 3's schedule for the first time step; Sec. 6.3) on the
     per-item register and banded-stream kernels, on the split kernel (every case
@@ -911,7 +960,8 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     size) equal one call bit for bit, so the decay keeps its phase."""
     n = 300 if path == "register" else 3000
     base = synth.config1(B=1, seed=9900 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
-    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0]) if path in ("banded-stream", "split") else base
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0]) if path in ("banded-stream", "banded-pair",
+                                                                                   "split") else base
     Yo = oracle.ybus_of(g)
     S = oracle.injections(Yo, g.vm, g.va)
     B = 3
@@ -925,8 +975,8 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     assert refs[0]["lr"] == pytest.approx(1e-3 * 0.8 ** 8, rel=1e-14)
     Yg = dgrid(dpf, g)
     rt = dpf.Route()
-    if path == "banded-stream":
-        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
+    if path in ("banded-stream", "banded-pair"):
+        rt.variant = [x for x in dpf.variants() if x["kind"] == path and x["threads"] == 1024][0]["index"]
     elif path == "split":
         rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
         rt.tail_handoff, rt.tail_team, rt.tail_chunk = B, 8, 16
@@ -960,7 +1010,7 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     assert torch.equal(vmR, vm) and torch.equal(vaR, va)
 
 
-@pytest.mark.parametrize("path", ["register", "banded-stream", "split-direct", "wide", "batched"])
+@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "wide", "batched"])
 def test_bad_outage_index_is_reported(dpf, path):
     """An outage index that is neither -1 nor a branch index (n_branch, -2) gives
     status DPF_BAD_OUTAGE with no update, NaN max|dS| and loss, on every solve
@@ -980,8 +1030,8 @@ def test_bad_outage_index_is_reported(dpf, path):
     steps = 40
     Yg = dgrid(dpf, g)
     rt = dpf.Route()
-    if path == "banded-stream":
-        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
+    if path in ("banded-stream", "banded-pair"):
+        rt.variant = [x for x in dpf.variants() if x["kind"] == path and x["threads"] == 1024][0]["index"]
         # 5 cases, 2 of them bad and counted as finished at once: the 3 others are
         # handed over at iteration 32
         rt.tail_handoff, rt.tail_team = 3, 4
@@ -1587,7 +1637,7 @@ def split_ran(dpf, before):
     return after["launches"] > before["launches"] and after["abandoned"] == before["abandoned"]
 
 
-@pytest.mark.parametrize("kind", ["banded-stream", "banded", "streaming", "banded-window"])
+@pytest.mark.parametrize("kind", ["banded-stream", "banded-pair", "banded", "streaming", "banded-window"])
 @pytest.mark.parametrize("threshold", [5, 64])
 @pytest.mark.parametrize("team", [0, 8])
 def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold, team):
@@ -1687,8 +1737,9 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff, team):
     assert split_ran(dpf, stats) == (team > 0)
 
 
-@pytest.mark.parametrize("team,n_finite", [(0, 124), (32, 124), (16, 8)])
-def test_bench_configuration_at_full_size_with_handoff(handoff, team, n_finite):
+@pytest.mark.parametrize("kind,team,n_finite", [("banded-stream", 0, 124), ("banded-stream", 32, 124),
+                                                ("banded-stream", 16, 8), ("banded-pair", 32, 124)])
+def test_bench_configuration_at_full_size_with_handoff(handoff, kind, team, n_finite):
     """The bench's launch configuration at its full size: 1024 outage cases of
     the 9241-bus grid (RCM numbering degree-grouped in windows of 2560), the 1024 x 4 banded-stream
     kernel, the bench's optimizer settings and a tail handoff at 192 cases.  All
@@ -1717,7 +1768,7 @@ def test_bench_configuration_at_full_size_with_handoff(handoff, team, n_finite):
     steps = 40
     o = dict(lr=1e-4, beta1=0.995, beta2=0.995, eps=1e-14, sched=oracle.SCHED_PLATEAU, factor=0.5,
              patience=300, threshold=1e-3)
-    v = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024
+    v = [x for x in dpf.variants() if x["kind"] == kind and x["threads"] == 1024
          and x["buses_per_thread"] == 4][0]
     assert bw <= 4096
     dpf.lib().dpf_autotune_set(n, v["index"])
@@ -2199,7 +2250,7 @@ def test_random_grids_on_default_and_banded_paths(tuned, seed):
     refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
                               oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
     Yg = dgrid(dpf, g)
-    banded = [v for v in dpf.variants() if v["kind"] in ("banded", "banded-stream", "banded-window",
+    banded = [v for v in dpf.variants() if v["kind"] in ("banded", "banded-stream", "banded-pair", "banded-window",
                                                           "banded-batched")]
     pick = banded[int(rng.integers(len(banded)))]
     for choice in (None, pick):
