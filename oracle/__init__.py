@@ -25,6 +25,12 @@ LIB = os.path.join(HERE, "libdpf_oracle.so")
 
 CFLAGS = ["-O2", "-std=c11", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp",
           "-fPIC", "-shared"]
+# the same source for the benchmark's CPU-baseline leg, optimised for the host it
+# runs on (built there at run time: -march=native code may not run on another CPU);
+# -ffp-contract=off keeps the arithmetic, and so the results, those of the pinned build
+NATIVE_LIB = os.path.join(HERE, "libdpf_oracle_native.so")
+NATIVE_CFLAGS = ["-O3", "-march=native", "-std=c11", "-ffp-contract=off", "-fcx-limited-range", "-fopenmp",
+                 "-fPIC", "-shared"]
 
 PQ, PV, SLACK = 0, 1, 2
 
@@ -38,36 +44,56 @@ def build(force: bool = False) -> str:
     return LIB
 
 
+def build_native() -> str:
+    """Compile the oracle with NATIVE_CFLAGS for this host (always rebuilt)."""
+    tmp = NATIVE_LIB + ".tmp"
+    subprocess.check_call(["gcc", *NATIVE_CFLAGS, SRC, "-o", tmp, "-lm"])
+    os.replace(tmp, NATIVE_LIB)
+    return NATIVE_LIB
+
+
 _lib = None
+_native = None
 
 
-def _load():
-    global _lib
+def _load(native: bool = False):
+    """The ctypes library of the oracle (native=True: the host-optimised build,
+    compiled on first use)."""
+    global _lib, _native
+    if native:
+        if _native is None:
+            build_native()
+            _native = _bind(ctypes.CDLL(NATIVE_LIB))
+        return _native
     if _lib is None:
         build()
-        lib = ctypes.CDLL(LIB)
-        P = ctypes.c_void_p
-        i32 = ctypes.c_int32
-        d = ctypes.c_double
-        lib.orc_ybus.argtypes = [i32, i32, P, P, P, P, P, i32, i32, P, P, P]
-        lib.orc_ybus.restype = ctypes.c_int
-        lib.orc_polar.argtypes = [i32, P, P, P]
-        lib.orc_current.argtypes = [i32, P, P, P, P, P]
-        lib.orc_mismatch.argtypes = [i32, P, P, P, P, P, P, P]
-        lib.orc_residual_count.argtypes = [i32, P]
-        lib.orc_residual_count.restype = i32
-        lib.orc_loss_from_mismatch.argtypes = [i32, P, P, P]
-        lib.orc_loss_from_mismatch.restype = d
-        lib.orc_dS_dV.argtypes = [i32, P, P, P, P, P, P, P]
-        lib.orc_param_grad.argtypes = [i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P]
-        lib.orc_loss_grad.argtypes = [i32, P, P, P, P, P, P, P, P, P, P]
-        lib.orc_loss_grad.restype = d
-        lib.orc_solve_adam.argtypes = [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
-        lib.orc_solve_adam.restype = i32
-        lib.orc_solve_adam_batch.argtypes = [i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P]
-        lib.orc_num_threads.restype = i32
-        _lib = lib
+        _lib = _bind(ctypes.CDLL(LIB))
     return _lib
+
+
+def _bind(lib):
+    """Argument and result types of the oracle's C functions."""
+    P = ctypes.c_void_p
+    i32 = ctypes.c_int32
+    d = ctypes.c_double
+    lib.orc_ybus.argtypes = [i32, i32, P, P, P, P, P, i32, i32, P, P, P]
+    lib.orc_ybus.restype = ctypes.c_int
+    lib.orc_polar.argtypes = [i32, P, P, P]
+    lib.orc_current.argtypes = [i32, P, P, P, P, P]
+    lib.orc_mismatch.argtypes = [i32, P, P, P, P, P, P, P]
+    lib.orc_residual_count.argtypes = [i32, P]
+    lib.orc_residual_count.restype = i32
+    lib.orc_loss_from_mismatch.argtypes = [i32, P, P, P]
+    lib.orc_loss_from_mismatch.restype = d
+    lib.orc_dS_dV.argtypes = [i32, P, P, P, P, P, P, P]
+    lib.orc_param_grad.argtypes = [i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_loss_grad.argtypes = [i32, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_loss_grad.restype = d
+    lib.orc_solve_adam.argtypes = [i32, P, P, P, P, P, P, P, P, P, P, P, P, P]
+    lib.orc_solve_adam.restype = i32
+    lib.orc_solve_adam_batch.argtypes = [i32, i32, P, P, P, P, P, i32, P, P, P, P, P, P, P]
+    lib.orc_num_threads.restype = i32
+    return lib
 
 
 def _p(a):
@@ -277,10 +303,12 @@ class AdamOptions:
                      int(self.cooldown), self.min_lr, self.sched_eps, int(self.optimizer))
 
 
-def solve_adam(Y: CSR, bus_type, s_spec, vm0, va0, opts: AdamOptions, state=None, t0: int = 0):
+def solve_adam(Y: CSR, bus_type, s_spec, vm0, va0, opts: AdamOptions, state=None, t0: int = 0,
+               native: bool = False):
     """One DPF solve (Algorithm 1 with Adam).  Returns a dict with vm, va,
-    status (0 converged, 1 max_iter, 2 non-finite), iters, mu, lr, state, t."""
-    lib = _load()
+    status (0 converged, 1 max_iter, 2 non-finite), iters, mu, lr, state, t.
+    native=True runs the host-optimised build of the same source."""
+    lib = _load(native)
     bt, s = _i8(bus_type), _c128(s_spec)
     vm, va = _f64(vm0).copy(), _f64(va0).copy()
     st = np.zeros(4 * Y.n) if state is None else _f64(state).copy()

@@ -85,11 +85,18 @@ class AutogradDPF:
         mu = torch.maximum(rP.abs().amax(dim=1), rQ.abs().amax(dim=1))
         return loss, mu
 
-    def solve(self, vm0, va0, opts: Options, poll: int = 1, max_iter=None, time_only_iters=None):
-        """Run the iteration; returns dict like dpf.solve plus the final vm, va.
+    def solve(self, vm0, va0, opts: Options, poll: int = 1, max_iter=None, time_only_iters=None,
+              time_budget_s=None):
+        """Run the iteration; returns dict like dpf.solve plus the final vm, va,
+        the number of loop passes and whether the time budget ended the run.
 
         time_only_iters: run exactly that many iterations without stop tests
-        (for per-iteration timing)."""
+        (for per-iteration timing).  time_budget_s: at each host poll, stop once
+        this much wall time has passed (cases still running keep status 1)."""
+        import time as _time
+
+        t_start = _time.perf_counter()
+        budget_hit = False
         vm = vm0.clone().requires_grad_(True)
         va = va0.clone().requires_grad_(True)
         Bc = vm.shape[0]
@@ -121,8 +128,12 @@ class AutogradDPF:
                     active = active & ~nonfin & ~conv
                     if it == n_run:
                         break
-                    if it % poll == 0 and not bool(active.any()):
-                        break
+                    if it % poll == 0:
+                        if not bool(active.any()):
+                            break
+                        if time_budget_s is not None and _time.perf_counter() - t_start > time_budget_s:
+                            budget_hit = True
+                            break
                 elif it == n_run:
                     break
             gvm, gva = torch.autograd.grad(loss.sum(), (vm, va))
@@ -153,6 +164,8 @@ class AutogradDPF:
                     cool = torch.where(red, torch.full_like(cool, opts.cooldown), cool)
                     bad = torch.where(red, torch.zeros_like(bad), bad)
                 elif opts.sched == SCHED_STEP and opts.patience > 0:
-                    stepped = active & ((iters % opts.patience) == 0)
+                    # StepLR on the case's step count t (the solve starts at t = 0)
+                    stepped = active & ((t.long() % opts.patience) == 0)
                     lr = torch.where(stepped, lr * opts.factor, lr)
-        return {"vm": vm.detach(), "va": va.detach(), "status": status, "iters": iters, "max_mis": mu_out}
+        return {"vm": vm.detach(), "va": va.detach(), "status": status, "iters": iters, "max_mis": mu_out,
+                "loops": it, "budget_hit": budget_hit}

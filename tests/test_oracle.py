@@ -464,6 +464,21 @@ def test_step_schedule_matches_torch_and_resumes():
     assert lrs[59] < lrs[58]
 
 
+def test_native_build_computes_the_same_iterates():
+    """The benchmark's CPU-baseline leg runs the oracle built with -O3
+    -march=native for its host; with FP contraction still off it must take the
+    pinned build's iterates bit for bit (the baseline times the oracle, not a
+    different program)."""
+    g = synth.config0(1)["grid"]
+    Y = oracle.ybus_of(g)
+    S = oracle.injections(Y, g.vm, g.va)
+    vm0, va0 = synth.flat_start(g)
+    o = oracle.AdamOptions(lr=1e-2, tol=0.0, max_iter=300, sched=oracle.SCHED_PLATEAU, factor=0.5, patience=20)
+    a = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, o)
+    b = oracle.solve_adam(Y, g.bus_type, S, vm0, va0, o, native=True)
+    assert np.array_equal(a["vm"], b["vm"]) and np.array_equal(a["va"], b["va"]) and a["lr"] == b["lr"]
+
+
 def test_stop_test_semantics():
     g = synth.config0(0)["grid"]
     Y = oracle.ybus_of(g)
