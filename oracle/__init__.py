@@ -66,8 +66,10 @@ def _load(native: bool = False):
             _native = _bind(ctypes.CDLL(NATIVE_LIB))
         return _native
     if _lib is None:
-        build()
-        _lib = _bind(ctypes.CDLL(LIB))
+        path = os.environ.get("DPF_ORACLE_LIB")  # another build of the same source (the sanitizer test)
+        if not path:
+            path = build()
+        _lib = _bind(ctypes.CDLL(path))
     return _lib
 
 

@@ -115,6 +115,17 @@ __device__ __forceinline__ double opt_update(int kind, double lr, double b1, dou
 }
 
 // ---------------------------------------------------------------- sin / cos
+// The polynomial kernels and the Cody-Waite constants below follow fdlibm, whose
+// notice is kept as its licence asks:
+//   ====================================================
+//   Copyright (C) 1993 by Sun Microsystems, Inc. All rights reserved.
+//
+//   Developed at SunPro, a Sun Microsystems, Inc. business.
+//   Permission to use, copy, modify, and distribute this
+//   software is freely granted, provided that this notice
+//   is preserved.
+//   ====================================================
+//
 // sincos for the voltage angles, after fdlibm (Sun Microsystems, 1993): a
 // three-step Cody-Waite reduction by pi/2 (valid for |x| < 2^19 pi/2) and the
 // fdlibm minimax polynomials on [-pi/4, pi/4] (error < 1 ulp).  Larger finite
