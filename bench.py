@@ -639,9 +639,12 @@ def cfg3_series(cap, tail_team):
 
 def cfg4_uneven(cap):
     """Uneven batch: 128 grids of log-uniform size in [100, 80000] buses plus one
-    of 80000, concatenated as sub-grids of one call (the ones above one CU's LDS
-    take the multi-workgroup path).  Each grid's PQ loads are scaled by
-    U(0.98, 1.02) from its planted state, which is also the start point."""
+    of 80000, concatenated as sub-grids of one call, each numbered by reverse
+    Cuthill-McKee.  The call runs every grid in one persistent launch of teams
+    (a grid above one CU's LDS spread over several workgroups); the same call on
+    the host-driven multi-workgroup path is timed beside it.  Each grid's PQ
+    loads are scaled by U(0.98, 1.02) from its planted state, which is also the
+    start point."""
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -656,7 +659,7 @@ def cfg4_uneven(cap):
                      r=np.concatenate([gg.r for gg in grids]), x=np.concatenate([gg.x for gg in grids]),
                      b=np.concatenate([gg.b for gg in grids]), bus_type=np.concatenate([gg.bus_type for gg in grids]),
                      vm=np.concatenate([gg.vm for gg in grids]), va=np.concatenate([gg.va for gg in grids]))
-    g, _ = renumbered(cat, sub_offset=off)
+    g, bw = renumbered(cat, sub_offset=off, group=0)
     Yg = dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
     S0 = base_injections(Yg, g)
     rng = np.random.default_rng(np.random.SeedSequence(cfg["seed"]).spawn(1)[0])
@@ -668,6 +671,17 @@ def cfg4_uneven(cap):
     va0 = torch.tensor(g.va[None], device="cuda")
     dpf.solve(Yg, g.bus_type, S, vm0.clone(), va0.clone(), opts=solve_options(20), sub_offset=off.tolist())
     torch.cuda.synchronize()
+    # the host-driven multi-workgroup path on the same call, for comparison
+    host = dpf.Route(wide_host=1)
+    dpf.solve(Yg, g.bus_type, S, vm0.clone(), va0.clone(), opts=solve_options(20), sub_offset=off.tolist(),
+              route=host)
+    vm, va = vm0.clone(), va0.clone()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    r_host = dpf.solve(Yg, g.bus_type, S, vm, va, opts=opts, sub_offset=off.tolist(), route=host)
+    torch.cuda.synchronize()
+    dt_host = time.perf_counter() - t0
+    conv_host = int((r_host["status"].cpu().numpy() == 0).sum())
     vm, va = vm0.clone(), va0.clone()
     t0 = time.perf_counter()
     r = dpf.solve(Yg, g.bus_type, S, vm, va, opts=opts, sub_offset=off.tolist())
@@ -683,13 +697,19 @@ def cfg4_uneven(cap):
     alg = bus_iters * 96 + int(it.max()) * 2 * (20 * nnz_rows + 4 * (g.n_bus + len(grids)))
     return {"workload": f"{len(grids)} grids, {g.n_bus} buses (log-uniform 100..80000 + one 80000), "
                         f"PQ loads x U(0.98, 1.02), planted start, cap {cap}",
+            "path": "one persistent launch of teams (the call enqueues the sliced-ELL build, a plan "
+                    "kernel and the solve kernel; no host wait)",
+            "bus_order": f"reverse Cuthill-McKee per grid (largest bandwidth {bw})",
             "iter_cap": cap, "s": round(dt, 3), "converged": conv, "solves_per_s": round(conv / dt, 3),
             "bus_iters_per_s": round(bus_iters / dt, 1),
             "alg_GBps": round(alg / dt / 1e9, 1),
             "time_to_stop_ms_p50": round(float(np.percentile(done, 50)), 2),
             "time_to_stop_ms_p99": round(float(np.percentile(done, 99)), 2),
             "grids_above_one_cu": int((sizes > dpf.max_sub_buses()).sum()),
-            "max_mis_median": float(np.median(r["max_mis"].cpu().numpy()))}
+            "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
+            "host_driven_path": {"s": round(dt_host, 3), "converged": conv_host,
+                                 "what": "the same call with route.wide_host = 1: grids above one CU's LDS on "
+                                         "the multi-workgroup path (host polls), the others one workgroup each"}}
 
 
 def graph_replay(calls=200, iters=10):

@@ -57,6 +57,7 @@ extern "C" {
 #define DPF_NONFINITE 2
 #define DPF_BAD_GRID 3   /* a CSR row is longer than the grid's declared max_row_nnz */
 #define DPF_BAD_OUTAGE 4 /* the case's outage index is neither -1 nor a branch index */
+#define DPF_UNFINISHED 5 /* the item's team of workgroups did not assemble in time (see dpf_route_t) */
 
 /* learning-rate schedules (Table 2 and Table 3 of the paper use the last two) */
 #define DPF_SCHED_CONSTANT 0
@@ -249,10 +250,12 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *   variant        : -1 (default): the autotune cache, else the default routing;
  *                    >= 0: this variant for the items that fit one workgroup
  *                    (DPF_EINVAL if it cannot hold the largest such sub-grid)
- *   team_cap       : sub-grids above this many buses take the multi-workgroup path
- *                    (several workgroups per item, three kernels per iteration,
- *                    host polls every 32 iterations) even when they would fit one
- *                    workgroup's LDS; 0 (default) = the LDS limit
+ *   team_cap       : sub-grids above this many buses are solved by several
+ *                    workgroups per item (see wide_host) even when they would fit
+ *                    one workgroup's LDS, and a member of a persistent team holds
+ *                    at most this many buses' exchange values in LDS (the rest of
+ *                    its columns it reads from global memory); 0 (default) = the
+ *                    LDS limit
  *   tail_handoff   : single-grid calls: once at most this many items are
  *                    unfinished, the per-item kernels pause them (every 32
  *                    iterations they read a finished-items counter) and the call
@@ -282,23 +285,42 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    much time, and teams are sized in proportion to the square of
  *                    each item's remaining budget max_iter - iters (at least 1, at
  *                    most tail_team, together at most W)
- *   tail_first_wait_s, tail_wait_s : the split kernel's barrier wait bounds in
- *                    seconds, [0, 60] each (defaults 1 at a launch's first
- *                    barrier, where another stream's kernels may still hold CUs,
- *                    and 5 after it).  A member that waits longer abandons the
- *                    barrier; its item then finishes on the multi-workgroup path
- *                    (every member finishes its part of an iteration before it
- *                    arrives, so an abandoned barrier leaves a whole iteration)
+ *   tail_first_wait_s, tail_wait_s : barrier wait bounds of the teams of
+ *                    workgroups, in seconds, [0, 60] each (defaults 1 and 5).
+ *                    Split kernel: tail_first_wait_s at a launch's first barrier,
+ *                    where another stream's kernels may still hold CUs,
+ *                    tail_wait_s after it; a member that waits longer abandons the
+ *                    barrier and the item finishes on the multi-workgroup path.
+ *                    Persistent teams (wide_host = 0): a unit's first barrier waits
+ *                    as long as its team or the launch makes progress and is
+ *                    abandoned after tail_first_wait_s without any; later
+ *                    barriers after tail_wait_s; an abandoned item ends with
+ *                    status DPF_UNFINISHED.  Every member finishes its part of an
+ *                    iteration before it arrives, so an abandoned barrier leaves
+ *                    the state of a whole iteration
  *   case_order     : 1: a call that may hand over its tail (one grid, at most
  *                    16384 cases) first evaluates every case's max|r| at its start
  *                    point and starts the cases in descending order of it
  *                    (non-finite first, ties by index); results per case are those
  *                    of index order up to the rounding of the tail path.  0
  *                    (default): index order
+ *   wide_host      : how a call with sub-grids above the LDS limit (or team_cap),
+ *                    or with few large items (more than 2048 buses, at most one
+ *                    item per CU, no variant chosen for them), runs.  0 (default):
+ *                    every item of the call in ONE persistent launch of as many
+ *                    workgroups as the device holds; an item is a unit of one or
+ *                    more workgroups (a team, each member holding its rows and their
+ *                    neighbours in LDS, synchronised through global memory twice
+ *                    per iteration) taken from a device-side queue; a one-workgroup
+ *                    kernel plans team sizes and order from the sub-grid sizes and
+ *                    bandwidths.  1: the multi-workgroup path (three kernels per
+ *                    iteration, host polls every 32 iterations)
  * A call with tail_handoff > 0, a split-kernel start (tail_team > 0 and few large
- * items) or items above the LDS or team cap BLOCKS the host until it is done and
- * cannot be captured in a graph; every other call only enqueues work (one kernel
- * launch for the items plus a few set-up kernels) and can be captured.
+ * items) or the multi-workgroup path (wide_host = 1 with items above the LDS or
+ * team cap, or variant naming that path) BLOCKS the host until it is done and
+ * cannot be captured in a graph; every other call, persistent teams included,
+ * only enqueues work (one kernel launch for the items plus a few set-up kernels)
+ * and can be captured.
  * A field out of range makes the call return DPF_EINVAL.
  */
 typedef struct dpf_route {
@@ -312,7 +334,7 @@ typedef struct dpf_route {
     double tail_first_wait_s;
     double tail_wait_s;
     int32_t case_order;
-    int32_t reserved; /* 0 */
+    int32_t wide_host;
 } dpf_route_t;
 
 /* Fill *route with the defaults (host; no device call). */
@@ -332,7 +354,11 @@ void dpf_route_default(dpf_route_t *route);
  * non-finite (status 2); a stopped item leaves the kernel while others go on.
  * Status 3 (DPF_BAD_GRID, iters 0) reports a CSR row longer than g->max_row_nnz;
  * status 4 (DPF_BAD_OUTAGE, iters 0, max_mis and loss NaN, vm/va and the optimizer
- * state untouched) a case whose outage index is neither -1 nor a branch index.
+ * state untouched) a case whose outage index is neither -1 nor a branch index;
+ * status 5 (DPF_UNFINISHED) an item of the persistent teams whose team could not
+ * assemble within the route's wait bounds (the device was busy with other work):
+ * vm/va, adam_state and sched_state hold the state after `iters` updates, so a
+ * call that passes them back continues the item.
  * Per call the library re-lays Y out in the workspace as 64-row slices
  * (column-major within a slice) so that each wave reads its rows' neighbour
  * entries with coalesced loads.

@@ -19,7 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdpf.so")
 
 DPF_OK, DPF_EINVAL, DPF_ECAP, DPF_EHIP, DPF_ENOMEM, DPF_EUNSUPPORTED = 0, -1, -2, -3, -4, -5
-CONVERGED, MAX_ITER, NONFINITE, BAD_GRID, BAD_OUTAGE = 0, 1, 2, 3, 4
+CONVERGED, MAX_ITER, NONFINITE, BAD_GRID, BAD_OUTAGE, UNFINISHED = 0, 1, 2, 3, 4, 5
 SCHED_CONSTANT, SCHED_PLATEAU, SCHED_STEP = 0, 1, 2
 OPT_ADAM, OPT_SGD, OPT_RMSPROP = 0, 1, 2
 PQ, PV, SLACK = 0, 1, 2
@@ -51,7 +51,7 @@ class _Opts(ctypes.Structure):
 class _Route(ctypes.Structure):
     _fields_ = [("variant", _i32), ("team_cap", _i32), ("tail_handoff", _i32), ("tail_team", _i32),
                 ("tail_chunk", _i32), ("tail_min_items", _i32), ("tail_slice_ms", _f64),
-                ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("reserved", _i32)]
+                ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("wide_host", _i32)]
 
 
 _lib = None
@@ -305,8 +305,10 @@ class Route:
     """Per-call routing of dpf_solve_batch (dpf_route_t): kernel variant (-1 =
     autotune cache / default), team cap, and the tail settings -- handoff
     threshold, split-kernel team size, iterations and time per launch, items
-    left to the multi-workgroup path, barrier wait bounds -- and the case order
-    (1 = descending initial max|dS|).  The defaults equal dpf_route_default."""
+    left to the multi-workgroup path, barrier wait bounds -- the case order
+    (1 = descending initial max|dS|) and how sub-grids above one workgroup run
+    (wide_host 0: persistent teams in the call's one launch, 1: the host-driven
+    multi-workgroup path).  The defaults equal dpf_route_default."""
     variant: int = -1
     team_cap: int = 0
     tail_handoff: int = 0
@@ -317,11 +319,13 @@ class Route:
     tail_first_wait_s: float = 1.0
     tail_wait_s: float = 5.0
     case_order: int = 0
+    wide_host: int = 0
 
     def c(self) -> _Route:
         return _Route(int(self.variant), int(self.team_cap), int(self.tail_handoff), int(self.tail_team),
                       int(self.tail_chunk), int(self.tail_min_items), float(self.tail_slice_ms),
-                      float(self.tail_first_wait_s), float(self.tail_wait_s), int(self.case_order), 0)
+                      float(self.tail_first_wait_s), float(self.tail_wait_s), int(self.case_order),
+                      int(self.wide_host))
 
 
 def _route(route):
@@ -353,13 +357,16 @@ def solve_workspace_bytes(grid: DeviceGrid, B, ld=None, sub_offset=None, route: 
 
 
 def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = None, outage=None,
-          sub_offset=None, adam_state=None, sched_state=None, workspace: SolveWorkspace | None = None,
-          outputs=None, route: Route | None = None):
+          sub_offset=None, sub_offset_dev=None, adam_state=None, sched_state=None,
+          workspace: SolveWorkspace | None = None, outputs=None, route: Route | None = None):
     """dpf_solve_batch: Adam-DPF to convergence for B cases x n_sub sub-grids.
 
     vm, va ([B, ld] float64, GPU) are updated in place; `route` (Route) sets this
-    call's kernel choice and tail settings.  Returns dict with iters, status,
-    max_mis, loss ([B * n_sub], index c * n_sub + s)."""
+    call's kernel choice and tail settings.  sub_offset (host sequence) gives the
+    sub-grid offsets; sub_offset_dev, an int32 device tensor of the same values,
+    spares the call its host-to-device copy (a call captured in a graph needs
+    it).  Returns dict with iters, status, max_mis, loss ([B * n_sub], index
+    c * n_sub + s)."""
     opts = opts or Options()
     dev = vm.device
     B, ld = vm.shape
@@ -369,6 +376,8 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
         else _dev(bus_type, torch.int8, dev)
     s = s_spec if (torch.is_tensor(s_spec) and s_spec.dtype == torch.complex128 and s_spec.device == dev
                    and s_spec.is_contiguous()) else _dev(s_spec, torch.complex128, dev)
+    if s.dim() == 2 and s.shape[0] != B:
+        raise ValueError(f"s_spec has {s.shape[0]} rows for {B} cases (pass one row per case, or a 1-D shared row)")
     s_ld = 0 if s.dim() == 1 else s.shape[1]
     out = None if outage is None else (outage if (torch.is_tensor(outage) and outage.dtype == torch.int32
                                                   and outage.device == dev) else _dev(outage, torch.int32, dev))
@@ -378,7 +387,15 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
         so_list = [int(v) for v in (sub_offset.tolist() if torch.is_tensor(sub_offset) else sub_offset)]
         n_sub = len(so_list) - 1
         so_h = (ctypes.c_int32 * len(so_list))(*so_list)
-        so_d = torch.tensor(so_list, dtype=torch.int32, device=dev)
+        if sub_offset_dev is not None:
+            if not (torch.is_tensor(sub_offset_dev) and sub_offset_dev.dtype == torch.int32 and
+                    sub_offset_dev.device == dev and sub_offset_dev.is_contiguous() and
+                    sub_offset_dev.numel() == len(so_list)):
+                raise ValueError("sub_offset_dev must be a contiguous int32 tensor on vm's device, "
+                                 "as long as sub_offset")
+            so_d = sub_offset_dev
+        else:
+            so_d = torch.tensor(so_list, dtype=torch.int32, device=dev)
     items = B * n_sub
     if outputs is None:
         outputs = {"iters": torch.empty(items, dtype=torch.int32, device=dev),
@@ -546,7 +563,7 @@ def route_default() -> Route:
     r = _Route()
     lib().dpf_route_default(ctypes.byref(r))
     return Route(r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items,
-                 r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order)
+                 r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.wide_host)
 
 
 def split_stats() -> dict:

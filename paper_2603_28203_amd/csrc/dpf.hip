@@ -17,13 +17,15 @@
 #include "sell.hpp"
 #include "solve.hpp"
 #include "split.hpp"
+#include "teams.hpp"
 #include "wide.hpp"
 #include "ybus.hpp"
 
 namespace {
 
 static_assert(dpf::kPaused != DPF_CONVERGED && dpf::kPaused != DPF_MAX_ITER && dpf::kPaused != DPF_NONFINITE &&
-                  dpf::kPaused != DPF_BAD_GRID && dpf::kPaused != DPF_BAD_OUTAGE,
+                  dpf::kPaused != DPF_BAD_GRID && dpf::kPaused != DPF_BAD_OUTAGE &&
+                  dpf::kPaused != DPF_UNFINISHED,
               "the internal paused status must differ from every public status code");
 
 thread_local std::string g_err;
@@ -112,7 +114,7 @@ dpf_route_t default_route() {
     r.tail_first_wait_s = 1.0;
     r.tail_wait_s = 5.0;
     r.case_order = 0;
-    r.reserved = 0;
+    r.wide_host = 0;
     return r;
 }
 
@@ -129,7 +131,7 @@ const char *route_error(const dpf_route_t &r) {
     if (!(r.tail_first_wait_s >= 0.0 && r.tail_first_wait_s <= 60.0) || !(r.tail_wait_s >= 0.0 && r.tail_wait_s <= 60.0))
         return "route wait bounds must be in [0, 60] s";
     if (r.case_order < 0 || r.case_order > 1) return "route.case_order must be 0 or 1";
-    if (r.reserved != 0) return "route.reserved must be 0";
+    if (r.wide_host < 0 || r.wide_host > 1) return "route.wide_host must be 0 or 1";
     return nullptr;
 }
 
@@ -271,6 +273,7 @@ struct CallPlan {
     const Variant *v = nullptr;
     int32_t handoff = 0;  // tail handoff threshold for this call (0 = none)
     bool split_direct = false;  // every item on the split kernel from its first iteration
+    bool teams = false;         // every item in one persistent launch of teams (teams.hpp)
     dpf_route_t route{};        // the call's settings
 };
 
@@ -298,21 +301,25 @@ struct SolveLayout {
     size_t off_bw = 0, off_mom = 0, off_scr = 0, off_wcount = 0, off_woff = 0, off_mres = 0, off_part = 0,
            off_items = 0, off_list = 0, off_list2 = 0, off_sched = 0, off_bar = 0, off_tfirst = 0,
            off_order = 0;
+    size_t off_thdr = 0, off_tunit = 0, off_tfirst2 = 0, off_tbar = 0, off_tpart = 0;  // persistent teams
     int32_t h_total = 0;  // tail handoff: slices of the (single) grid, 0 without handoff
     size_t total = 0;
 };
 
 static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset, int32_t B,
                                 int32_t ld, bool streaming, int32_t team_cap, bool handoff = false,
-                                bool pairs = false) {
+                                bool pairs = false, bool teams = false) {
     SolveLayout L;
+    int64_t team_part = 0;  // member partials: at most min(slices, members cap) per item
     for (int32_t s = 0; s < (sub_offset ? n_sub : 1); ++s) {
         int32_t ns = sub_offset ? sub_offset[s + 1] - sub_offset[s] : g->n_bus;
         L.n_slices += (ns + 63) / 64;
-        if (ns > team_cap) L.w_total += (ns + 63) / 64;
+        if (ns > team_cap && !teams) L.w_total += (ns + 63) / 64;
+        team_part += std::max<int64_t>(1, std::min<int64_t>((ns + 63) / 64, dpf::kTeamMaxMembers));
     }
     if (handoff) L.h_total = L.n_slices;
     const bool wide = L.w_total > 0 || handoff;
+    streaming = streaming || teams;
     const int32_t part_slices = std::max(L.w_total, L.h_total);
     streaming = streaming || wide;
     int64_t wmax = g->max_row_nnz > 0 ? g->max_row_nnz : std::max<int32_t>(g->nnz, 1);
@@ -363,6 +370,19 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
         o += align_up(sizeof(int32_t) * (size_t)(B + 1), 256);
         L.off_order = o;  // case order: [B] int32 order, [B] max|r|, [B] loss, residual count
         o += align_up(sizeof(int32_t) * (size_t)B, 256) + 2 * align_up(sizeof(double) * (size_t)B, 256) + 256;
+    }
+    if (teams) {
+        const int64_t items = (int64_t)B * (sub_offset ? n_sub : 1);
+        L.off_thdr = o;  // ticket counter, tickets, units, progress count
+        o += 256;
+        L.off_tunit = o;
+        o += align_up(sizeof(int32_t) * (size_t)items, 256);
+        L.off_tfirst2 = o;
+        o += align_up(sizeof(int32_t) * (size_t)(items + 1), 256);
+        L.off_tbar = o;  // one 64-bit arrival counter per unit, 256 bytes apart
+        o += align_up(sizeof(long long) * dpf::kTeamBarStride * (size_t)items, 256);
+        L.off_tpart = o;
+        o += align_up(sizeof(double2) * (size_t)(B * team_part), 256);
     }
     L.total = o;
     return L;
@@ -627,6 +647,50 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
             break;
         }
     }
+    return DPF_OK;
+}
+
+// Bytes of static LDS the persistent team kernel uses besides its window.
+constexpr int kTeamStaticLds = 2 * (dpf::kTeamThreads / dpf::kWave) * 8 + 64;
+
+// Persistent teams (teams.hpp): every item of the call in one launch on `st`, with
+// a device-side plan; nothing waits on the host, so the call can be captured.
+int run_teams(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, int32_t n_sub, int32_t B,
+              const DeviceInfo &dev, const dpf_route_t &route, hipStream_t st) {
+    dpf::SolveArgs a = a0;
+    a.handoff = 0;
+    const int lds = (dev.lds_per_block - kTeamStaticLds) / 16 * 16;
+    if (lds < 16 * dpf::kWave) return fail(DPF_EUNSUPPORTED, "too little LDS for the team kernel");
+    void (*fn)(dpf::SolveArgs, dpf::TeamArgs) = dpf::team_solve_persist_kernel<dpf::kTeamThreads>;
+    DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
+    int per_cu = 0;
+    DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, dpf::kTeamThreads, lds));
+    if (per_cu < 1) return fail(DPF_EUNSUPPORTED, "the team kernel does not fit a compute unit");
+    const int grid = per_cu * dev.n_cu;
+    dpf::TeamArgs p{};
+    p.hdr = (int32_t *)(ws + L.off_thdr);
+    p.unit_item = (int32_t *)(ws + L.off_tunit);
+    p.first = (int32_t *)(ws + L.off_tfirst2);
+    p.bar = (long long *)(ws + L.off_tbar);
+    p.part = (double2 *)(ws + L.off_tpart);
+    p.Ig = a.scratch;
+    p.Vg = a.scratch + a.st_stride;
+    p.Wg = a.scratch + 2 * a.st_stride;
+    p.first_limit = (int64_t)(route.tail_first_wait_s * 1e9 / dev.ns_per_tick);
+    p.limit = (int64_t)(route.tail_wait_s * 1e9 / dev.ns_per_tick);
+    p.win = lds / 16;  // a route's team cap also caps the window (members then hold fewer buses)
+    if (route.team_cap > 0) p.win = std::min(p.win, std::max<int32_t>(dpf::kWave, route.team_cap));
+    p.grid = grid;
+    p.tmax = std::max(1, std::min(dpf::kTeamMaxMembers, grid / 2));
+    if (a.st_fresh) {
+        const int64_t words = 4 * (int64_t)B * a.ld;
+        hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, words,
+                           a.st);
+    }
+    hipLaunchKernelGGL(dpf::team_plan_kernel, dim3(1), dim3(dpf::kPlanThreads), 0, st, n_sub, a.sub_off, a.n_bus,
+                       a.sub_bw, B, p);
+    hipLaunchKernelGGL(fn, dim3(grid), dim3(dpf::kTeamThreads), (size_t)lds, st, a, p);
+    DPF_HIP(hipGetLastError());
     return DPF_OK;
 }
 
@@ -1162,6 +1226,16 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
         p.n_max = 0;
         p.has_small = false;
     }
+    // sub-grids above the cap (or every sub-grid, when few large items chose the
+    // multi-workgroup path by default): all items on persistent teams, unless the
+    // route asks for the host-driven path or names it as the variant
+    const bool any_large = p.v && small < (sub_offset ? (int64_t)n_sub : 1);
+    const bool wide_named = route.variant >= 0 && p.v && p.v->mode == dpf::kWide;
+    if (p.v && !p.split_direct && route.wide_host == 0 && !wide_named &&
+        (any_large || p.v->mode == dpf::kWide)) {
+        p.teams = true;
+        p.has_small = false;
+    }
     // tail handoff: single-grid calls whose per-item kernel keeps the state in global memory
     const int32_t h = route.tail_handoff;
     if (h > 0 && p.v && p.has_small && small == 1 && (!sub_offset || n_sub == 1) &&
@@ -1187,7 +1261,7 @@ size_t dpf_solve_workspace_bytes(const dpf_grid_t *g, int32_t n_sub, const int32
     const CallPlan p = plan_call(g, n_sub, sub_offset, B, dev, rt, &forced_bad);
     if (forced_bad) return 0;
     return solve_layout(g, n_sub, sub_offset, B, ld, p.v && p.v->mode != dpf::kReg, p.cap,
-                        p.handoff > 0 || p.split_direct, p.v && p.v->mode == dpf::kPair && p.has_small)
+                        p.handoff > 0 || p.split_direct, p.v && p.v->mode == dpf::kPair && p.has_small, p.teams)
         .total;
 }
 
@@ -1233,8 +1307,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
     const bool handoff = plan.handoff > 0;
     const bool pairs = v->mode == dpf::kPair && has_small;
-    const SolveLayout L =
-        solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap, handoff || plan.split_direct, pairs);
+    const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap,
+                                       handoff || plan.split_direct, pairs, plan.teams);
     const bool has_wide = L.w_total > 0;
     if (!workspace || ws_bytes < L.total) return fail(DPF_ENOMEM, "workspace too small");
     hipStream_t st = (hipStream_t)stream;
@@ -1290,7 +1364,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.handoff = handoff ? plan.handoff : 0;
     a.total_items = B * n_sub;
     a.team_cap = cap;
-    if (v->mode != dpf::kReg || has_wide) {
+    if (v->mode != dpf::kReg || has_wide || plan.teams) {
         double *mom = (double *)(ws + L.off_mom);
         a.scratch = (double2 *)(ws + L.off_scr);
         a.st = adam_state ? adam_state : mom;
@@ -1361,6 +1435,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipGetLastError());
         a.order = order;
     }
+    if (plan.teams) return run_teams(a, L, ws, n_sub, B, dev, rt, st);
     std::unique_lock<std::mutex> side_lock;  // concurrent blocking calls on one device take turns
     if (has_wide || handoff || plan.split_direct) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
     if (plan.split_direct) {

@@ -1,0 +1,519 @@
+// Persistent teams: every item of a call in ONE launch, sub-grids larger than one
+// workgroup's LDS included, with no host wait (the call only enqueues kernels and
+// can be captured in a graph).
+//
+// The launch holds as many workgroups as the device runs at once.  Each item
+// (case c, sub-grid s) is a unit of T_s tickets, T_s = 1 for sub-grids up to the
+// per-member row target, else enough members that each holds its rows and both
+// halos (the sub-grid's bandwidth) in LDS.  A workgroup takes the next ticket from
+// a device counter, becomes member m of that ticket's unit, runs the unit to its
+// end and takes another ticket.  Tickets are handed out in unit order, so at most
+// one unit at a time has members waiting for the rest of its team; every other
+// unit either runs complete or has not started, and the units that run finish and
+// free their workgroups for the waiting team.  A team of T members therefore
+// always assembles when T workgroups fit on the device (T is capped at half of
+// the launch).
+//
+// A member owns rows [rlo, rhi) of its sub-grid (whole 64-row slices) and keeps in
+// LDS a window of the exchanged vector: its rows plus the sub-grid's bandwidth on
+// each side as far as the LDS holds (the whole sub-grid when it fits).  An entry
+// outside the window (a bandwidth wider than the LDS allows, or the two buses of
+// an outage branch whose admittance entry the matrix does not store) is read from
+// global memory instead, so every member is correct whatever the numbering; the
+// plan keeps that path cold.  Per iteration (the order of Algorithm 1, the
+// adjoint of Sec. 5.1, the update of Sec. 4.1):
+//   X <- V of the window (global, written by the owners)
+//   A : rows of the member: I = Y V (+ the rank-2 outage term), dS, loss terms,
+//       w = a conj(V) -> global; the member's (loss sum, max|r|) -> global
+//   -- team barrier --
+//   every member reduces the T partials in the same fixed order (one loss,
+//   max|r| and stop decision for the whole team); X <- w of the window
+//   B : rows of the member: h = Y^T w, G, optimizer step; |V|, theta, moments and
+//       V = polar(|V|, theta) -> global; schedule step
+//   -- team barrier --
+// What crosses a barrier is written and read with device-scope accesses (see
+// common.hpp) and each thread waits for its stores before the arrival is counted.
+// A team of one uses workgroup barriers only.
+//
+// Waits: the first barrier of a unit (after the members publish V of their rows)
+// may wait for members still finishing other units; it is abandoned only when
+// neither the team's arrival count nor the launch's progress count (bumped by
+// every running unit every 64 iterations and when it ends) has moved for the
+// first bound.  Later barriers, with the whole team running, use the second bound.
+// An abandoned unit leaves its item with status DPF_UNFINISHED at the state of a
+// whole iteration, as the split kernel's teams do.
+//
+// Plan (one workgroup, on the device, from the sub-grid sizes and the
+// bandwidths the sliced-ELL build measured): for w = 1..8 waves of the launch's
+// G workgroups, the smallest per-member row target R (a multiple of 64) whose
+// team sizes sum to at most w*G members; the w with the least w*(R + kTeamRowsPerBarrier)
+// wins.  Units are then ordered by per-member load, largest first (half-octave
+// buckets, index order inside a bucket), so that long units start first and
+// single-member units fill the gaps.  The plan changes only where and when an
+// item runs, and the team size, which fixes the order in which the members'
+// partial loss sums are added.
+#pragma once
+
+#include "../../include/dpf.h"
+#include "common.hpp"
+#include "solve.hpp"
+
+namespace dpf {
+
+constexpr int kTeamThreads = 512;
+constexpr int kPlanThreads = 256;
+constexpr int kTeamMaxMembers = 128;
+constexpr int kLoadKeys = 32;      // half-octave buckets of the per-member load
+constexpr int kTeamMaxWaves = 8;
+constexpr int kTeamRowsPerBarrier = 512;  // the plan's price of a barrier pair, in rows
+constexpr int kTeamBarStride = 32;        // one 64-bit counter per 256 bytes
+constexpr long long kTeamAbort = 1LL << 62;
+
+struct TeamArgs {
+    int32_t *hdr;          // [0] next ticket, [1] tickets, [2] units, [3] progress count
+    int32_t *unit_item;    // [items] item of each unit, in ticket order
+    int32_t *first;        // [items + 1] first ticket of each unit
+    long long *bar;        // [items][kTeamBarStride] arrival counter of each unit
+    double2 *part;         // [tickets] member partials (loss sum, max|r|), unit u's at first[u]
+    double2 *Ig, *Vg, *Wg; // [B][ld] I of the A sweep, V, exchanged w
+    int64_t first_limit;   // wall-clock ticks a unit's first barrier waits without progress
+    int64_t limit;         // ... and every later barrier
+    int32_t win;           // complex entries of the LDS window
+    int32_t grid;          // workgroups of the launch
+    int32_t tmax;          // members per team at most
+};
+
+// members of every item of sub-grid (n buses, bandwidth bw) at row target R
+__device__ __forceinline__ int team_size(int n, int bw, int R, int win, int tmax) {
+    if (n <= R && n <= win) return 1;
+    const int ns = (n + kWave - 1) / kWave;
+    const int fit = ((win - 2 * bw) / kWave) * kWave;  // rows that fit beside both halos
+    const int rs = max(min(R, fit), kWave) / kWave;     // slices per member
+    const int T = (ns + rs - 1) / rs;
+    return max(1, min(T, min(ns, tmax)));
+}
+
+// bucket of a per-member load of L rows: floor(2 log2 L), at most kLoadKeys - 1
+__device__ __forceinline__ int load_key(int L) {
+    if (L <= 1) return 0;
+    const int lg = 31 - __clz(L);
+    const int half = (long long)L * L >= (1LL << (2 * lg + 1)) ? 1 : 0;
+    return min(kLoadKeys - 1, 2 * lg + half);
+}
+
+template <int NT>
+__device__ __forceinline__ long long block_sum_ll(long long v, long long *buf) {
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) buf[threadIdx.x] += buf[threadIdx.x + o];
+        __syncthreads();
+    }
+    const long long r = buf[0];
+    __syncthreads();
+    return r;
+}
+
+__global__ __launch_bounds__(kPlanThreads) void team_plan_kernel(int32_t n_sub, const int32_t *__restrict__ sub_off,
+                                                                 int32_t n_bus, const int32_t *__restrict__ sub_bw,
+                                                                 int32_t B, TeamArgs p) {
+    __shared__ int32_t cnt[kLoadKeys][kPlanThreads];
+    __shared__ int32_t wtot[kPlanThreads / kWave][kLoadKeys];
+    __shared__ long long buf[kPlanThreads];
+    __shared__ int32_t sh_R;
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1), wv = tid / kWave;
+    auto n_of = [&](int s) { return sub_off ? sub_off[s + 1] - sub_off[s] : n_bus; };
+    auto members = [&](int R) {
+        long long m = 0;
+        for (int s = tid; s < n_sub; s += kPlanThreads) m += team_size(n_of(s), sub_bw[s], R, p.win, p.tmax);
+        return block_sum_ll<kPlanThreads>(m, buf) * B;
+    };
+
+    // ---- per-member row target
+    const long long total = (long long)B * n_bus;
+    const int rcap = max(kWave, (p.win / kWave) * kWave);
+    int bestR = rcap;
+    long long best = -1;
+    for (int w = 1; w <= kTeamMaxWaves; ++w) {
+        const long long cap_m = (long long)w * p.grid;
+        const long long need = (total + cap_m - 1) / cap_m;
+        int lo = (int)min<long long>(rcap, max<long long>(kWave, (need + kWave - 1) / kWave * kWave));
+        int hi = rcap;
+        if (members(hi) > cap_m) continue;  // not even at the largest rows
+        while (lo < hi) {                   // smallest R (multiple of 64) that fits w waves
+            const int mid = (lo / kWave + hi / kWave) / 2 * kWave;
+            if (members(mid) <= cap_m) hi = mid;
+            else lo = mid + kWave;
+        }
+        const long long cost = (long long)w * (hi + kTeamRowsPerBarrier);
+        if (best < 0 || cost < best) {
+            best = cost;
+            bestR = hi;
+        }
+    }
+    if (tid == 0) sh_R = bestR;
+    __syncthreads();
+    const int R = sh_R;
+
+    // ---- units in descending per-member load (stable counting sort over the buckets)
+    const int items = B * n_sub;
+    const int per = (items + kPlanThreads - 1) / kPlanThreads;
+    const int i0 = min(tid * per, items), i1 = min(i0 + per, items);
+    auto key_of = [&](int item) {
+        const int s = item / B;
+        const int n = n_of(s);
+        const int T = team_size(n, sub_bw[s], R, p.win, p.tmax);
+        return load_key((n + T - 1) / T);
+    };
+    for (int b = 0; b < kLoadKeys; ++b) cnt[b][tid] = 0;
+    for (int i = i0; i < i1; ++i) cnt[key_of(i)][tid] += 1;
+    int c[kLoadKeys];
+#pragma unroll
+    for (int b = 0; b < kLoadKeys; ++b) {
+        c[b] = cnt[b][tid];
+        int incl = c[b];
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        c[b] = incl - c[b];  // exclusive within the wave
+        if (lane == kWave - 1) wtot[wv][b] = incl;
+    }
+    __syncthreads();
+    {
+        int base = 0;  // units of the buckets above b, then of the earlier waves in b
+        for (int b = kLoadKeys - 1; b >= 0; --b) {
+            int tot = 0, before = 0;
+            for (int k = 0; k < kPlanThreads / kWave; ++k) {
+                tot += wtot[k][b];
+                before += k < wv ? wtot[k][b] : 0;
+            }
+            cnt[b][tid] = base + before;  // this thread's first slot in bucket b (own counts above)
+            base += tot;
+        }
+    }
+#pragma unroll
+    for (int b = 0; b < kLoadKeys; ++b) cnt[b][tid] += c[b];
+    for (int i = i0; i < i1; ++i) {
+        const int k = key_of(i);
+        p.unit_item[cnt[k][tid]] = i;
+        cnt[k][tid] += 1;
+    }
+    __syncthreads();
+
+    // ---- first ticket of each unit: exclusive scan of the team sizes in unit order
+    long long own = 0;
+    for (int u = i0; u < i1; ++u) {
+        const int s = p.unit_item[u] / B;
+        own += team_size(n_of(s), sub_bw[s], R, p.win, p.tmax);
+    }
+    buf[tid] = own;
+    __syncthreads();
+    long long before = 0;
+    for (int k = 0; k < tid; ++k) before += buf[k];
+    for (int u = i0; u < i1; ++u) {
+        p.first[u] = (int32_t)before;
+        const int s = p.unit_item[u] / B;
+        before += team_size(n_of(s), sub_bw[s], R, p.win, p.tmax);
+    }
+    if (tid == kPlanThreads - 1) {
+        p.first[items] = (int32_t)before;
+        p.hdr[0] = 0;
+        p.hdr[1] = (int32_t)before;
+        p.hdr[2] = items;
+        p.hdr[3] = 0;
+    }
+    for (int u = tid; u < items; u += kPlanThreads) p.bar[(int64_t)u * kTeamBarStride] = 0;
+}
+
+// Arrival barrier of the T members of one unit; false when it was abandoned.
+// first: the unit's first barrier, which waits while the arrival count or the
+// launch's progress count moves and abandons after `limit` ticks without either;
+// later barriers abandon after `limit` ticks.
+__device__ __forceinline__ bool unit_barrier(long long *cnt, long long target, int64_t limit, bool first,
+                                             const int32_t *progress, int *flag) {
+    dev_stores_done();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        long long v = (long long)atomicAdd((unsigned long long *)cnt, 1ULL) + 1;
+        bool ok = (v & kTeamAbort) == 0;
+        int64_t t0 = wall_clock64();
+        int32_t pv = first ? __hip_atomic_load(const_cast<int32_t *>(progress), __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT)
+                           : 0;
+        long long lv = v;
+        while (ok && v < target) {
+            __builtin_amdgcn_s_sleep(1);
+            v = __hip_atomic_load(cnt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (v & kTeamAbort) {
+                ok = false;
+            } else if (v < target) {
+                if (first) {
+                    const int32_t pg = __hip_atomic_load(const_cast<int32_t *>(progress), __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_AGENT);
+                    if (pg != pv || v != lv) {
+                        pv = pg;
+                        lv = v;
+                        t0 = wall_clock64();
+                        continue;
+                    }
+                }
+                if (wall_clock64() - t0 > limit) {
+                    // abandon only if no member arrived meanwhile (else poll again)
+                    if ((long long)atomicCAS((unsigned long long *)cnt, (unsigned long long)v,
+                                             (unsigned long long)(v | kTeamAbort)) == v)
+                        ok = false;
+                }
+            }
+        }
+        *flag = ok ? 1 : 0;
+    }
+    __syncthreads();
+    return *flag != 0;
+}
+
+// member `mem` of the T members of unit u
+template <int NT>
+__device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &p, int u, int mem, int T,
+                                            double2 *__restrict__ X, double (*red)[NT / kWave], int *bar_flag) {
+    const int tid = threadIdx.x;
+    const int lane = tid & (kWave - 1);
+    const int item = p.unit_item[u];
+    const int sidx = item / a.B;
+    const int c = item - sidx * a.B;
+    const int s0 = a.sub_off ? a.sub_off[sidx] : 0;
+    const int n = (a.sub_off ? a.sub_off[sidx + 1] : a.n_bus) - s0;
+    const int out_idx = c * a.n_sub + sidx;
+    long long *cnt = p.bar + (int64_t)u * kTeamBarStride;
+    double2 *part = p.part + p.first[u];
+    int32_t *progress = p.hdr + 3;
+    if (*a.bad_grid) {  // a row longer than the declared bound (see DPF_BAD_GRID)
+        if (mem == 0 && tid == 0) {
+            a.status[out_idx] = DPF_BAD_GRID;
+            a.iters[out_idx] = 0;
+        }
+        return;
+    }
+    const Rank2 r2 = outage_of_case(a.ov, c, s0, s0 + n);
+    if (r2.bad) return;  // reported by the call's prologue; every member leaves
+    const int of = r2.of, ot = r2.ot;
+    const double2 oy = r2.oy, oyd = r2.oyd;
+    ItemSched sc = load_item_sched(a, out_idx);
+    const double m_res = residual_count<NT>(a.bt, s0, s0 + n, red);
+    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
+
+    // rows of the member and its LDS window [xlo, xlo + wn) (sub-grid-local)
+    const int ns = (n + kWave - 1) / kWave;
+    const int rlo = (int)((int64_t)mem * ns / T) * kWave;
+    const int rhi = min((int)((int64_t)(mem + 1) * ns / T) * kWave, n);
+    int xlo = 0, wn = n;
+    if (n > p.win) {
+        const int rows = rhi - rlo;
+        const int H = rows < p.win ? min(a.sub_bw[sidx], (p.win - rows) / 2) : 0;
+        xlo = max(0, rlo - H);
+        wn = min(p.win, min(n, rhi + H) - xlo);
+    }
+
+    const int64_t cb = (int64_t)c * a.ld + s0;
+    double *__restrict__ vm_c = a.vm + cb;
+    double *__restrict__ va_c = a.va + cb;
+    double *__restrict__ mv_c = a.st + cb;
+    double *__restrict__ ma_c = a.st + a.st_stride + cb;
+    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb;
+    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *__restrict__ Ig = p.Ig + cb;
+    double2 *__restrict__ Vg = p.Vg + cb;
+    double2 *__restrict__ Wg = p.Wg + cb;
+    const double2 *__restrict__ Sc = a.s_spec + (int64_t)c * a.s_ld + s0;
+    const int8_t *__restrict__ btp = a.bt + s0;
+    const int slice0 = a.sell.slice_off[sidx];
+    const int32_t *__restrict__ swidth = a.sell.width;
+    const int32_t *__restrict__ sstart = a.sell.start;
+    const int32_t *__restrict__ scol = a.sell.col;
+    const double2 *__restrict__ sval = a.sell.val;
+
+    const bool solo = T == 1;
+    auto ld2 = [&](const double2 *q) { return solo ? *q : ld_dev2(q); };
+    auto st2 = [&](double2 *q, double2 v) {
+        if (solo) *q = v;
+        else st_dev2(q, v);
+    };
+    auto in_win = [&](int col) { return (unsigned)(col - xlo) < (unsigned)wn; };
+    // exchanged value of a column: the LDS window, else the global copy g
+    auto xat = [&](int col, const double2 *g) { return in_win(col) ? X[col - xlo] : ld2(g + col); };
+
+    // V of the member's rows for the team
+    for (int il = rlo + tid; il < rhi; il += NT) {
+        double sn, cs;
+        const double vmi = vm_c[il];
+        fast_sincos(va_c[il], sn, cs);
+        st2(Vg + il, make_double2(vmi * cs, vmi * sn));
+    }
+    long long nbar = 0;
+    bool ok = true;
+    if (!solo) ok = unit_barrier(cnt, ++nbar * T, p.first_limit, true, progress, bar_flag);
+    else __syncthreads();
+
+    int it = 0, stat = DPF_UNFINISHED;
+    double mu = 0.0, loss = 0.0;
+    while (ok) {
+        for (int k = tid; k < wn; k += NT) X[k] = ld2(Vg + xlo + k);
+        __syncthreads();
+        // ---------------- A: rows of this member
+        double lsum = 0.0, lmax = 0.0;
+        for (int il = rlo + tid; il < rhi; il += NT) {
+            const int8_t tk = btp[il];
+            const double2 sp = Sc[il];
+            const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+            const int wdt = swidth[gsl];
+            const int base = sstart[gsl] * kWave + lane;
+            double2 acc = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], Vg), acc);
+            if (il == of) acc = csub(acc, csub(cmul(oyd, xat(of, Vg)), cmul(oy, xat(ot, Vg))));
+            else if (il == ot) acc = csub(acc, csub(cmul(oyd, xat(ot, Vg)), cmul(oy, xat(of, Vg))));
+            const double2 v = xat(il, Vg);
+            const double2 d = csub(cmulc(v, acc), sp);
+            const double rP = tk != kSlack ? d.x : 0.0;
+            const double rQ = tk == kPQ ? d.y : 0.0;
+            lsum += rP * rP + rQ * rQ;
+            lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
+            Ig[il] = acc;
+            st2(Wg + il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
+        }
+        block_reduce2<NT>(lsum, lmax, red);
+        __syncthreads();
+        block_reduce2_finish<NT>(lsum, lmax, red);
+        if (!solo) {
+            if (tid == 0) st_dev2(part + mem, make_double2(lsum, lmax));
+            ok = unit_barrier(cnt, ++nbar * T, p.limit, false, progress, bar_flag);
+            if (!ok) break;
+            // team totals: the T partials reduced in the same order by every member
+            // (their loads overlap the refill of X with w)
+            double s = 0.0, m = 0.0;
+            if (tid < T) {
+                const double2 pp = ld_dev2(part + tid);
+                s = pp.x;
+                m = pp.y;
+            }
+            for (int k = tid; k < wn; k += NT) X[k] = ld_dev2(Wg + xlo + k);
+            block_reduce2<NT>(s, m, red);
+            __syncthreads();
+            block_reduce2_finish<NT>(s, m, red);
+            __syncthreads();
+            lsum = s;
+            lmax = m;
+        } else {
+            __syncthreads();
+            for (int k = tid; k < wn; k += NT) X[k] = Wg[xlo + k];
+            __syncthreads();
+        }
+        loss = m_res > 0.0 ? lsum / m_res : 0.0;
+        mu = isnan(lsum) ? lsum : lmax;
+        if (!(isfinite(loss) && isfinite(mu))) {
+            stat = DPF_NONFINITE;
+            break;
+        }
+        if (mu < a.tol) {
+            stat = DPF_CONVERGED;
+            break;
+        }
+        if (it >= a.max_iter) {
+            stat = DPF_MAX_ITER;
+            break;
+        }
+
+        // ---------------- B: rows of this member
+        sc.t_step += 1.0;
+        sc.b1t *= a.b1;
+        sc.b2t *= a.b2;
+        const double bc1 = 1.0 - sc.b1t;
+        const double bc2 = 1.0 - sc.b2t;
+        for (int il = rlo + tid; il < rhi; il += NT) {
+            const int8_t tk = btp[il];
+            const double2 I = Ig[il];
+            const double2 sp = Sc[il];
+            const double2 v = ld2(Vg + il);
+            double vmi = vm_c[il], vai = va_c[il];
+            const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+            const int wdt = swidth[gsl];
+            const int base = sstart[gsl] * kWave + lane;
+            double2 h = make_double2(0.0, 0.0);
+#pragma unroll 4
+            for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], Wg), h);
+            if (il == of) h = csub(h, csub(cmul(oyd, xat(of, Wg)), cmul(oy, xat(ot, Wg))));
+            else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, Wg)), cmul(oy, xat(of, Wg))));
+            const double2 d = csub(cmulc(v, I), sp);
+            const double rP = tk != kSlack ? d.x : 0.0;
+            const double rQ = tk == kPQ ? d.y : 0.0;
+            const double2 ai = cmul(make_double2(two_over_m * rP, two_over_m * rQ), I);
+            const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
+            if (tk == kPQ) {
+                const double g = (G.x * v.x + G.y * v.y) / vmi;
+                double mv = mv_c[il], sv = sv_c[il];
+                vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                vm_c[il] = vmi;
+                mv_c[il] = mv;
+                sv_c[il] = sv;
+            }
+            if (tk != kSlack) {
+                const double g = G.y * v.x - G.x * v.y;
+                double ma = ma_c[il], sa = sa_c[il];
+                vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
+                va_c[il] = vai;
+                ma_c[il] = ma;
+                sa_c[il] = sa;
+                double sn, cs;
+                fast_sincos(vai, sn, cs);
+                st2(Vg + il, make_double2(vmi * cs, vmi * sn));
+            }
+        }
+        sched_step(a, sc, loss);
+        ++it;
+        if (mem == 0 && tid == 0 && (it & 63) == 0) atomicAdd(progress, 1);
+        if (!solo) {
+            ok = unit_barrier(cnt, ++nbar * T, p.limit, false, progress, bar_flag);
+            if (!ok) break;  // the members that arrived applied this iteration's step
+        } else {
+            __syncthreads();
+        }
+    }
+    if (mem != 0 || tid != 0) return;
+    atomicAdd(progress, 1);
+    finish_item(a, out_idx, it, ok ? stat : DPF_UNFINISHED, mu, loss, sc);
+}
+
+template <int NT>
+__global__ __launch_bounds__(NT) void team_solve_persist_kernel(SolveArgs a, TeamArgs p) {
+    extern __shared__ double2 X[];
+    __shared__ double red[2][NT / kWave];
+    __shared__ int bar_flag;
+    __shared__ int sh_t, sh_u;
+    const int tid = threadIdx.x;
+    const int n_tickets = p.hdr[1];
+    const int n_units = p.hdr[2];
+    for (;;) {
+        if (tid == 0) {
+            const int t = atomicAdd(p.hdr, 1);
+            int u = 0;  // largest u with first[u] <= t
+            if (t < n_tickets)
+                for (int hi_u = n_units - 1; u < hi_u;) {
+                    const int m = (u + hi_u + 1) >> 1;
+                    if (p.first[m] <= t) u = m;
+                    else hi_u = m - 1;
+                }
+            sh_t = t;
+            sh_u = u;
+        }
+        __syncthreads();
+        const int t = sh_t, u = sh_u;
+        __syncthreads();
+        if (t >= n_tickets) break;
+        team_member<NT>(a, p, u, t - p.first[u], p.first[u + 1] - p.first[u], X, red, &bar_flag);
+        __syncthreads();
+    }
+}
+
+}  // namespace dpf

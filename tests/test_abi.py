@@ -119,7 +119,7 @@ class _Route(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("team_cap", ctypes.c_int32), ("tail_handoff", ctypes.c_int32),
                 ("tail_team", ctypes.c_int32), ("tail_chunk", ctypes.c_int32), ("tail_min_items", ctypes.c_int32),
                 ("tail_slice_ms", ctypes.c_double), ("tail_first_wait_s", ctypes.c_double),
-                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("wide_host", ctypes.c_int32)]
 
 
 def _ws_types(lib):
@@ -143,7 +143,7 @@ def test_route_defaults_and_field_checks(lib):
     r = _default_route(lib)
     assert (r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items) == (-1, 0, 0, 0,
                                                                                                     128, 0)
-    assert (r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.reserved) == (0.0, 1.0, 5.0, 0, 0)
+    assert (r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.wide_host) == (0.0, 1.0, 5.0, 0, 0)
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     ok = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(r))
     assert ok == lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, None) > 0
@@ -151,7 +151,7 @@ def test_route_defaults_and_field_checks(lib):
            ("tail_team", 1025), ("tail_chunk", 0), ("tail_chunk", 65537), ("tail_min_items", -1),
            ("tail_slice_ms", -1.0), ("tail_slice_ms", 1001.0), ("tail_slice_ms", float("nan")),
            ("tail_first_wait_s", -1.0), ("tail_wait_s", 61.0), ("tail_first_wait_s", float("nan")),
-           ("case_order", 2), ("case_order", -1), ("reserved", 1)]
+           ("case_order", 2), ("case_order", -1), ("wide_host", 2), ("wide_host", -1)]
     for name, val in bad:
         rb = _default_route(lib)
         setattr(rb, name, val)
@@ -201,6 +201,41 @@ def test_bad_outage_status_is_declared():
     assert re.search(r"#define DPF_BAD_OUTAGE 4\b", text)
     from paper_2603_28203_amd import binding
     assert binding.BAD_OUTAGE == 4
+
+
+def test_unfinished_status_is_declared():
+    """An item of the persistent teams whose team did not assemble in time is
+    reported per item (DPF_UNFINISHED, status 5), and the binding exposes it."""
+    text = open(HEADER).read()
+    assert re.search(r"#define DPF_UNFINISHED 5\b", text)
+    from paper_2603_28203_amd import binding
+    assert binding.UNFINISHED == 5
+
+
+def test_wide_host_sizes_its_own_path(lib):
+    """A call with a sub-grid above one workgroup's LDS sizes the persistent
+    teams' arrays by default (plan tables, one barrier counter per item, member
+    partials) and the multi-workgroup path's with wide_host = 1; calls whose
+    sub-grids all fit are sized the same either way."""
+    _ws_types(lib)
+    n_big = 30000
+    g = _Grid(n_big + 28, 140000, 10, 1, 1, 1, 0, None, None, None, None, None)
+    sub = (ctypes.c_int32 * 4)(0, 14, n_big + 14, n_big + 28)
+    teams_r = _default_route(lib)
+    host_r = _default_route(lib)
+    host_r.wide_host = 1
+    B = 2
+    wt = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 3, sub, B, g.n_bus, ctypes.byref(teams_r))
+    wh = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 3, sub, B, g.n_bus, ctypes.byref(host_r))
+    assert wt > 0 and wh > 0 and wt != wh
+    items = B * 3
+    # at least: moments and three complex scratch vectors per bus and case, units,
+    # first tickets, barrier counters and one partial per member
+    slices = 1 + (n_big + 63) // 64 + 1
+    assert wt >= B * g.n_bus * (4 * 8 + 3 * 16) + items * (4 + 4 + 256) + B * (1 + min(slices - 2, 128) + 1) * 16
+    small = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
+    assert (lib.dpf_solve_workspace_bytes(ctypes.byref(small), 1, None, 1024, 9241, ctypes.byref(host_r)) ==
+            lib.dpf_solve_workspace_bytes(ctypes.byref(small), 1, None, 1024, 9241, ctypes.byref(teams_r)))
 
 
 def _kind(lib, i):

@@ -569,10 +569,13 @@ def test_solve_reports_bad_grid_row_bound(dpf):
 # ---------------------------------------------------------------- multi-workgroup path
 
 
-@pytest.fixture
-def wide_cap(dpf):
-    """Solve calls that route sub-grids above 500 buses to the multi-workgroup path."""
-    yield Routed(dpf, team_cap=500)
+@pytest.fixture(params=["teams", "host"])
+def wide_cap(dpf, request):
+    """Solve calls that route sub-grids above 500 buses to several workgroups per
+    item: persistent teams whose members hold at most 500 buses' exchange values
+    in LDS (columns beyond the window come from global memory), or the
+    host-driven multi-workgroup path."""
+    yield Routed(dpf, team_cap=500, wide_host=0 if request.param == "teams" else 1)
     dpf.autotune_reset()
 
 
@@ -677,6 +680,182 @@ def test_wide_path_resume_and_status(dpf, wide_cap):
     wide_cap.solve(Yg, g.bus_type, cu(S, torch.complex128), vmC, vaC, opts=half, adam_state=st, sched_state=sch)
     torch.cuda.synchronize()
     assert torch.equal(vmB, vmC) and torch.equal(vaB, vaC)
+
+
+# ---------------------------------------------------------------- persistent teams
+
+
+def _concat_grids(grids):
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    f = np.concatenate([gg.f + o for gg, o in zip(grids, off)])
+    t = np.concatenate([gg.t + o for gg, o in zip(grids, off)])
+    r = np.concatenate([gg.r for gg in grids]); x = np.concatenate([gg.x for gg in grids])
+    b = np.concatenate([gg.b for gg in grids]); bt = np.concatenate([gg.bus_type for gg in grids])
+    return off, f, t, r, x, b, bt
+
+
+def test_uneven_batch_above_the_lds_limit_in_one_captured_launch(dpf):
+    """An uneven batch in one call on the persistent teams: a sub-grid above one
+    workgroup's LDS in a small-bandwidth numbering (members hold their rows and
+    halos), one above it in the generator's numbering (many columns come from
+    global memory), a 300-bus and two 14-bus sub-grids, two cases each.  Every
+    item equals its separate oracle solve after 12 steps; the whole call,
+    captured in a HIP graph, replays bit for bit (three replays with eager resets
+    and synchronisations between them), and every item reports a stop time."""
+    cap = dpf.max_sub_buses()
+    n1, n2 = cap + 1700, cap + 300
+    g1 = synth.config1(B=1, seed=8700, n_bus=n1, n_branch=int(1.5 * n1), n_pv=n1 // 6)["grid"]
+    g1 = renumber(g1, dpf.rcm_order(g1.n_bus, g1.f, g1.t)[0])
+    g2 = synth.config1(B=1, seed=8701, n_bus=n2, n_branch=int(1.5 * n2), n_pv=n2 // 6)["grid"]
+    g3 = synth.config1(B=1, seed=8702, n_bus=300, n_branch=440, n_pv=50)["grid"]
+    grids = [g1, synth.config0(0)["grid"], g2, g3, synth.config0(1)["grid"]]
+    off, f, t, r, x, b, bt = _concat_grids(grids)
+    S = np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids])
+    B = 2
+    starts = [[_perturbed_start(gg, 40 + 7 * k + c) for k, gg in enumerate(grids)] for c in range(B)]
+    vm0 = np.stack([np.concatenate([s_[0] for s_ in row]) for row in starts])
+    va0 = np.stack([np.concatenate([s_[1] for s_ in row]) for row in starts])
+    Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
+    steps = 12
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=steps)
+    Sd = cu(S, torch.complex128)  # one injection row shared by both cases
+    btd = cu(bt, torch.int8)
+    sod = cu(off, torch.int32)
+    ws = dpf.SolveWorkspace()
+    items = B * len(grids)
+    outs = {"iters": torch.empty(items, dtype=torch.int32, device="cuda"),
+            "status": torch.empty(items, dtype=torch.int32, device="cuda"),
+            "max_mis": torch.empty(items, dtype=torch.float64, device="cuda"),
+            "loss": torch.empty(items, dtype=torch.float64, device="cuda"),
+            "done_ns": torch.empty(items, dtype=torch.int64, device="cuda")}
+    print(f"persistent teams: sub-grids {np.diff(off).tolist()} (cap {cap}), {B} cases", flush=True)
+    vm_e = cu(vm0); va_e = cu(va0)
+    ref = dpf.solve(Yg, btd, Sd, vm_e, va_e, opts=opts, sub_offset=off.tolist(), sub_offset_dev=sod, workspace=ws,
+                  outputs=outs)
+    torch.cuda.synchronize()
+    ref = {k: v.clone() for k, v in ref.items()}
+    assert ref["iters"].tolist() == [steps] * items and ref["status"].tolist() == [dpf.MAX_ITER] * items
+    assert (ref["done_ns"] > 0).all()
+    for c in range(B):
+        for k, gg in enumerate(grids):
+            sl = slice(off[k], off[k + 1])
+            o = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[sl], vm0[c, sl], va0[c, sl],
+                                  oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+            assert np.abs(vm_e[c, sl].cpu().numpy() - o["vm"]).max() < 1e-10, (c, k)
+            assert np.abs(va_e[c, sl].cpu().numpy() - o["va"]).max() < 1e-10, (c, k)
+            assert abs(ref["max_mis"][c * len(grids) + k].item() - o["mu"]) <= 1e-9 * o["mu"], (c, k)
+    print("persistent teams: capture", flush=True)
+    vm = cu(vm0); va = cu(va0)
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dpf.solve(Yg, btd, Sd, vm, va, opts=opts, sub_offset=off.tolist(), sub_offset_dev=sod, workspace=ws,
+                  outputs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dpf.solve(Yg, btd, Sd, vm, va, opts=opts, sub_offset=off.tolist(), sub_offset_dev=sod, workspace=ws,
+                  outputs=outs)
+    for rep in range(3):
+        vm.copy_(cu(vm0)); va.copy_(cu(va0))
+        outs["iters"].fill_(-7)
+        torch.cuda.synchronize()
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(vm, vm_e) and torch.equal(va, va_e), rep
+        for k in ("iters", "status", "max_mis", "loss"):
+            assert torch.equal(outs[k], ref[k]), (rep, k)
+
+
+def test_teams_single_grid_above_the_lds_limit_with_outages(dpf):
+    """One grid above the LDS limit (small-bandwidth numbering) with N-1
+    outages, a plateau schedule and caller-held state, on the persistent teams:
+    every case equals its oracle solve, and two resumed calls of 6 + 9 steps
+    equal one call of 15 bit for bit."""
+    n = dpf.max_sub_buses() + 900
+    base = synth.config1(B=1, seed=8800, n_bus=n, n_branch=int(1.5 * n), n_pv=n // 6)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.array([-1, int(nbr[5]), int(nbr[len(nbr) // 2])], dtype=np.int32)
+    B = len(outage)
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    rng = np.random.default_rng(8801)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type != 2)
+    kw = dict(lr=1e-3, sched=1, factor=0.5, patience=2, threshold=0.05, cooldown=1)
+    steps = 15
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    od = cu(outage, torch.int32)
+    print(f"persistent teams, one grid of {n} buses, outages {outage.tolist()}", flush=True)
+    vm = cu(vm0); va = cu(va0)
+    sch = dpf.fresh_sched_state(B, kw["lr"])
+    st = torch.zeros((4, B, n), dtype=torch.float64, device="cuda")
+    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=od, adam_state=st, sched_state=sch,
+                    opts=dpf.Options(tol=0.0, max_iter=steps, **kw))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * B and out["status"].tolist() == [dpf.MAX_ITER] * B
+    for c in range(B):
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(tol=0.0, max_iter=steps, **kw))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+        assert sch[c, 1].item() == pytest.approx(ref["lr"], rel=1e-15), c
+    vmR = cu(vm0); vaR = cu(va0)
+    schR = dpf.fresh_sched_state(B, kw["lr"])
+    stR = torch.zeros((4, B, n), dtype=torch.float64, device="cuda")
+    for k in (6, 9):
+        dpf.solve(Yg, g.bus_type, Sd, vmR, vaR, outage=od, adam_state=stR, sched_state=schR,
+                  opts=dpf.Options(tol=0.0, max_iter=k, **kw))
+    torch.cuda.synchronize()
+    assert torch.equal(vmR, vm) and torch.equal(vaR, va) and torch.equal(schR, sch)
+
+
+def test_teams_abandoned_barriers_leave_whole_iterations(dpf):
+    """With a zero wait bound after a unit's first barrier (forced from the
+    host: every member that has to wait abandons at once), team items end with
+    DPF_UNFINISHED at the state of a whole number of updates, which the oracle
+    reproduces; a second call with the normal bounds continues every item from
+    there to the oracle's state after the combined count."""
+    g = synth.config1(B=1, seed=8900, n_bus=1354, n_branch=1990, n_pv=225)["grid"]
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    B = 3
+    rng = np.random.default_rng(8901)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    steps = 30
+    vm = cu(vm0); va = cu(va0)
+    st = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
+    sch = dpf.fresh_sched_state(B, 1e-3)
+    print("persistent teams with a zero barrier wait", flush=True)
+    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, adam_state=st, sched_state=sch,
+                    route=dpf.Route(team_cap=500, tail_wait_s=0.0), opts=dpf.Options(lr=1e-3, tol=0.0,
+                                                                                     max_iter=steps))
+    torch.cuda.synchronize()
+    status = out["status"].tolist()
+    first = out["iters"].tolist()
+    assert set(status) <= {dpf.MAX_ITER, dpf.UNFINISHED} and dpf.UNFINISHED in status, status
+    for c in range(B):
+        assert (status[c] == dpf.MAX_ITER) == (first[c] == steps), (c, status[c], first[c])
+        assert sch[c, 0].item() == first[c]
+        ref = oracle.solve_adam(Yo, g.bus_type, S, vm0[c], va0[c], oracle.AdamOptions(lr=1e-3, tol=0.0,
+                                                                                      max_iter=first[c]))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+    print(f"persistent teams: continued after {first}", flush=True)
+    out2 = dpf.solve(Yg, g.bus_type, Sd, vm, va, adam_state=st, sched_state=sch, route=dpf.Route(team_cap=500),
+                     opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out2["status"].tolist() == [dpf.MAX_ITER] * B and out2["iters"].tolist() == [steps] * B
+    for c in range(B):
+        ref = oracle.solve_adam(Yo, g.bus_type, S, vm0[c], va0[c], oracle.AdamOptions(lr=1e-3, tol=0.0,
+                                                                                      max_iter=first[c] + steps))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
 
 
 # ---------------------------------------------------------------- time series
@@ -864,7 +1043,7 @@ def test_banded_and_general_sub_grids_in_one_call(tuned):
 # ---------------------------------------------------------------- SGD and RMSprop
 
 
-@pytest.mark.parametrize("path", ["register", "streaming", "banded", "wide"])
+@pytest.mark.parametrize("path", ["register", "streaming", "banded", "teams", "wide"])
 @pytest.mark.parametrize("kind", ["sgd", "rmsprop"])
 def test_other_optimizers_track_oracle(tuned, path, kind):
     """SGD (with momentum) and RMSprop, the paper's alternatives to Adam, on
@@ -889,7 +1068,7 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
     if path == "banded":
         band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
         dpf.lib().dpf_autotune_set(n, band)
-    rt = dpf.Route(team_cap=1000) if path == "wide" else None
+    rt = {"teams": dpf.Route(team_cap=1000), "wide": dpf.Route(team_cap=1000, wide_host=1)}.get(path)
     print(f"optimizer {kind} on the {path} path, n={n}", flush=True)
     vm = cu(vm0[None]); va = cu(va0[None])
     out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va,
@@ -950,7 +1129,7 @@ def test_paired_state_kernel_equals_the_banded_kernel(dpf, J):
     assert np.abs(res["banded-pair"][1][3] - ref["va"]).max() < 1e-10
 
 
-@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split", "wide"])
+@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split", "teams", "wide"])
 def test_step_schedule_on_every_path_and_resumed(dpf, path):
     """StepLR (Table 3's schedule for the first time step; Sec. 6.3) on the
     per-item register and banded-stream kernels, on the split kernel (every case
@@ -980,8 +1159,8 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     elif path == "split":
         rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-stream" and x["threads"] == 1024][0]["index"]
         rt.tail_handoff, rt.tail_team, rt.tail_chunk = B, 8, 16
-    elif path == "wide":
-        rt.team_cap = 1000
+    elif path in ("teams", "wide"):
+        rt.team_cap, rt.wide_host = 1000, int(path == "wide")
     Sd = cu(S, torch.complex128)
     print(f"StepLR on the {path} path, n={n}", flush=True)
     stats = dpf.split_stats()
@@ -1010,7 +1189,8 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     assert torch.equal(vmR, vm) and torch.equal(vaR, va)
 
 
-@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "wide", "batched"])
+@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "teams", "wide",
+                                  "batched"])
 def test_bad_outage_index_is_reported(dpf, path):
     """An outage index that is neither -1 nor a branch index (n_branch, -2) gives
     status DPF_BAD_OUTAGE with no update, NaN max|dS| and loss, on every solve
@@ -1037,8 +1217,8 @@ def test_bad_outage_index_is_reported(dpf, path):
         rt.tail_handoff, rt.tail_team = 3, 4
     elif path == "split-direct":
         rt.tail_team = 8  # few large cases: the split kernel from the first iteration
-    elif path == "wide":
-        rt.team_cap = 1000
+    elif path in ("teams", "wide"):
+        rt.team_cap, rt.wide_host = 1000, int(path == "wide")
     elif path == "batched":
         rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-batched" and x["cases"] == 2
                       and x["threads"] == 256][0]["index"]
