@@ -272,7 +272,7 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    workgroups (each member keeps the exchange vector in LDS; the
  *                    team synchronises through global memory twice per iteration).
  *                    With tail_team > 0, a single-grid call of few large items
- *                    (more than 2048 buses, at most one item per CU, no variant
+ *                    (more than 2048 buses, at most one item per two CUs, no variant
  *                    chosen for them) runs them on the split kernel from their
  *                    first iteration, without the per-item kernel or a handoff
  *   tail_chunk     : iterations per split-kernel launch, 1..65536 (default 128);
@@ -306,7 +306,7 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    (default): index order
  *   wide_host      : how a call with sub-grids above the LDS limit (or team_cap),
  *                    or with few large items (more than 2048 buses, at most one
- *                    item per CU, no variant chosen for them), runs.  0 (default):
+ *                    item per two CUs, no variant chosen for them), runs.  0 (default):
  *                    every item of the call in ONE persistent launch of as many
  *                    workgroups as the device holds; an item is a unit of one or
  *                    more workgroups (a team, each member holding its rows and their

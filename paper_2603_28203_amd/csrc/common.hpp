@@ -76,6 +76,37 @@ __device__ __forceinline__ void st_dev2(double2 *p, double2 v) {
     st_dev(&p->y, v.y);
 }
 __device__ __forceinline__ double2 ld_dev2(const double2 *p) { return make_double2(ld_dev(&p->x), ld_dev(&p->y)); }
+// The same device-scope access for 16 bytes in one instruction: a buffer
+// load/store with the SC1 cache policy (the policy of the relaxed agent-scope
+// loads and stores above) through a resource built from `base` and `bytes`,
+// which MUST be the same in every lane of the wave (they are taken from the
+// first active lane, so that the resource lives in scalar registers); DEV =
+// false is an ordinary cached access.  The resource's range check makes an
+// index at or past `bytes` read zero and drop a store.
+constexpr int kCachePolicySC1 = 16;
+constexpr int kBufferWord3 = 0x00020000;  // 32-bit data format, gfx9 family
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *base, uint32_t bytes) {
+    const unsigned long long b = (unsigned long long)base;
+    const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b & 0xffffffffULL));
+    const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(b >> 32));
+    void *ub = (void *)(((unsigned long long)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc(ub, 0, __builtin_amdgcn_readfirstlane((int)bytes), kBufferWord3);
+}
+template <bool DEV>
+__device__ __forceinline__ double2 buf_ld2(const double2 *base, uint32_t bytes, int idx) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(buffer_of(base, bytes), (int)((uint32_t)idx * 16u), 0,
+                                                         DEV ? kCachePolicySC1 : 0);
+    double2 out;
+    __builtin_memcpy(&out, &v, sizeof(out));
+    return out;
+}
+template <bool DEV>
+__device__ __forceinline__ void buf_st2(double2 *base, uint32_t bytes, int idx, double2 x) {
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(buffer_of(base, bytes), 0, 0, 0)) v;
+    __builtin_memcpy(&v, &x, sizeof(x));
+    __builtin_amdgcn_raw_buffer_store_b128(v, buffer_of(base, bytes), (int)((uint32_t)idx * 16u), 0,
+                                           DEV ? kCachePolicySC1 : 0);
+}
 // this thread's stores have completed (and the compiler keeps every earlier
 // memory access before this point)
 __device__ __forceinline__ void dev_stores_done() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }

@@ -221,10 +221,11 @@ bool g_tune_init = false;
 
 int items_bucket(int64_t items) { return items <= 64 ? 0 : (items <= 256 ? 1 : 2); }
 
-// Items larger than this (buses) that do not fill the chip (items <= CUs) are solved
-// faster spread over many workgroups than one workgroup each (measured: 9241 buses,
-// 1 to 256 cases, 1.25x to 5x; 3000 buses, 1 to 64 cases, 1.15x to 1.6x; 1354 buses:
-// one workgroup wins).
+// Items larger than this (buses) that fill at most half of the chip (2 items <= CUs)
+// are solved faster spread over several workgroups than one workgroup each (measured
+// on the persistent teams: 9241 buses, 64 cases, 38 against 68 us per iteration; 1354
+// buses: one workgroup wins; 256 cases of 3000 buses, one per CU: the per-item
+// streaming kernel, 29 against 39 us).
 constexpr int32_t kWideDefaultBuses = 2048;
 
 // first workgroup-per-item (non-banded) variant that holds n_max buses
@@ -257,7 +258,7 @@ const Variant *pick_variant(int32_t n_max, int64_t items, int n_cu, int forced =
         const int c = g_tune_init ? g_tune[d][items_bucket(items)] : -1;
         if (c >= 0 && c < cnt && variant_fits(t[c], n_max)) return &t[c];
     }
-    if (n_max > kWideDefaultBuses && items <= n_cu) {
+    if (n_max > kWideDefaultBuses && items <= n_cu / 2) {
         if (few_large) *few_large = true;
         return &t[wide_variant_index()];
     }

@@ -505,11 +505,14 @@ def test_solve_every_variant_tracks_oracle(dpf, n_bus):
 
 
 def test_default_routing_spreads_few_large_items(dpf):
-    """Without a recorded choice, a few items above 2048 buses take the
-    multi-workgroup path; many items, or small ones, one workgroup each."""
+    """Without a recorded choice, a few items above 2048 buses (at most one per
+    two CUs) are spread over several workgroups each; many items, or small
+    ones, run one workgroup each."""
     dpf.autotune_reset()
     wide = [v["index"] for v in dpf.variants() if v["kind"] == "wide"][0]
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
     assert dpf.variant_for(9241, 1) == wide and dpf.variant_for(9241, 64) == wide
+    assert dpf.variant_for(9241, n_cu // 2) == wide and dpf.variant_for(9241, n_cu // 2 + 1) != wide
     assert dpf.variant_for(9241, 4096) != wide
     assert dpf.variant_for(1354, 1) != wide
     dpf.lib().dpf_autotune_set_items(9241, 1, dpf.variant_for(9241))
