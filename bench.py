@@ -379,18 +379,17 @@ def main():
                         iters=100, reps=2)
     kinds = {v["index"]: v["kind"] for v in dpf.variants()}
     # with a tail handoff only the kernels that can hand over compete: the 100-iteration
-    # probes cannot see the handoff, and the variants are within ~2% of each other there
-    # (a batched kernel winning by noise would leave the whole tail on one CU per case)
+    # probes cannot see the handoff
     handoff_kinds = dpf.binding.HANDOFF_KINDS
     score = {k: full["seconds"][k] + tail["seconds"][k] for k in full["seconds"]
              if args.handoff <= 0 or kinds[k] in handoff_kinds}
     # within 3% of the best the timing difference is noise: prefer the paired-state
     # banded kernel (bit-identical to the banded-stream kernel and 5% faster per
-    # iteration, the kernel whose counters profiles/ holds), then the banded-stream one,
-    # then any banded kernel (fewer HBM bytes per bus-iteration than the streaming ones)
+    # iteration, the kernel whose counters profiles/ holds), then the banded-stream one
+    # (fewer HBM bytes per bus-iteration than the streaming kernel)
     best = min(score.values())
     near = [k for k, v in score.items() if v <= 1.03 * best]
-    rank = {"banded-pair": 0, "banded-stream": 1, "banded-window": 2, "banded": 2, "banded-batched": 2}
+    rank = {"banded-pair": 0, "banded-stream": 1}
     choice = min(near, key=lambda k: (rank.get(kinds[k], 2), score[k]))
     vinfo = dpf.variants()[choice]
     log(f"autotune: variant {choice} {vinfo} (full { {k: round(v * 1e3, 2) for k, v in full['seconds'].items()} } ms, "
@@ -414,11 +413,8 @@ def main():
     achieved = alg_bytes / t_kern / 1e9
     kname = {"banded-pair": f"team_solve_pair_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
              "register": f"team_solve_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, 0>",
-             "streaming": f"team_solve_stream_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
-             "banded": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, true>",
-             "banded-stream": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}, false>",
-             "banded-window": f"team_solve_window_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
-             "banded-batched": f"team_solve_multi_kernel<{vinfo['threads']}, {vinfo['cases']}>",
+             "streaming": f"team_solve_stream_kernel<{vinfo['threads']}>",
+             "banded-stream": f"team_solve_band_kernel<{vinfo['threads']}, {vinfo['buses_per_thread']}>",
              }[vinfo["kind"]]
     # roofline of the dominant kernel on one launch of it alone: every item active for
     # 200 iterations (no stop test, no handoff), timed with HIP events on its stream

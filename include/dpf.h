@@ -263,8 +263,8 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    path, both of which spread each item over many CUs;
  *                    iteration counts, optimizer and schedule state carry over,
  *                    so results equal a call without handoff up to the rounding
- *                    of the other path.  Applies to the streaming, banded and
- *                    windowed kernels; a call of at most this many items is
+ *                    of the other path.  Applies to the streaming and banded
+ *                    kernels; a call of at most this many items is
  *                    handed over after its first 32 iterations.  0 (default) = off
  *   tail_team      : how handed-over items finish.  0 (default): on the
  *                    multi-workgroup path.  > 0 (at most 1024): on the split
@@ -506,29 +506,28 @@ int32_t dpf_solve_max_sub_buses(void);
  * more); dpf_autotune_set records, for the class of n_max, which variant to use
  * instead -- a project-side autotuner times the eligible variants on real inputs
  * (each probe names its variant in its route) and stores the fastest.  Without a
- * recorded choice, items above 2048 buses that do not fill the device (items <=
- * compute units) take the multi-workgroup path, the others the default variant
- * of their class.  The cache is the library's only process-wide setting and is
- * guarded by a mutex.
+ * recorded choice, items above 2048 buses that fill at most half of the device
+ * (items <= compute units / 2) are spread over several workgroups each (the
+ * persistent teams, or the multi-workgroup path with route.wide_host = 1; the
+ * index reported for them is that of kind 3), the others take the default
+ * variant of their class.  The cache is the library's only process-wide setting
+ * and is guarded by a mutex.
  *   dpf_solve_variant_count : number of variants
  *   dpf_solve_variant_info  : threads per workgroup, buses per thread (0 = any),
  *                             and the kind: register-resident (0), streaming (1),
- *                             banded (2), banded with a barrier-free gradient
- *                             sweep (3), multi-workgroup (4: not a kernel of
- *                             its own -- every sub-grid of the call is spread
- *                             over many workgroups), banded with a window of
- *                             8 blocks in LDS and one pipelined sweep per
- *                             iteration (5), or the same for several cases of
- *                             a single-grid call per workgroup, sharing the
- *                             matrix loads (6: buses_per_thread is 1, see
- *                             dpf_solve_variant_cases); host outs.  A banded variant
+ *                             banded with a barrier-free gradient sweep (2),
+ *                             multi-workgroup (3: not a kernel of its own --
+ *                             every sub-grid of the call is spread over many
+ *                             workgroups), banded with the state kept as
+ *                             (|V|, theta) and moment pairs (4); host outs.  A
+ *                             banded variant
  *                             (buses per thread = buses per thread per block)
  *                             serves the sub-grids whose bandwidth max|row - col|
  *                             is at most threads * buses_per_thread (see
  *                             dpf_order_rcm); the same call runs the other
  *                             sub-grids with the default variant of their size
- *   dpf_solve_variant_cases : cases per workgroup of a variant (1 except kind 6),
- *                             DPF_EINVAL for a bad index
+ *   dpf_solve_variant_cases : cases per workgroup of a variant (1 for every
+ *                             variant), DPF_EINVAL for a bad index
  *   dpf_solve_variant_for   : variant index dpf_solve_batch would use for many
  *                             items, -1 if none
  *   dpf_solve_variant_for_items : the same for `items` work items
@@ -540,8 +539,8 @@ int32_t dpf_solve_max_sub_buses(void);
  *                             abandoned a barrier, since the library was loaded,
  *                             over all calls (statistics only; either pointer may
  *                             be null)
- * Items larger than the LDS limit always take the multi-workgroup path; a call
- * that has such items returns only after they have finished.
+ * Items larger than the LDS limit always run on several workgroups each (see
+ * dpf_route_t.wide_host for which path and whether the call blocks).
  */
 int dpf_solve_variant_count(void);
 int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread, int32_t *streaming);

@@ -501,17 +501,17 @@ class DPFLoss(torch.autograd.Function):
 # ---------------------------------------------------------------- autotuner
 
 
-VARIANT_KINDS = ("register", "streaming", "banded", "banded-stream", "wide", "banded-window", "banded-batched",
-                 "banded-pair")
-# the per-item kinds that can hand their tail over (dpf_autotune_set_tail_handoff)
-HANDOFF_KINDS = ("streaming", "banded", "banded-stream", "banded-window", "banded-pair")
+VARIANT_KINDS = ("register", "streaming", "banded-stream", "wide", "banded-pair")
+# the per-item kinds that can hand their tail over (dpf_route_t.tail_handoff)
+HANDOFF_KINDS = ("streaming", "banded-stream", "banded-pair")
 
 
 def variants():
     """The solve kernel variants: list of dicts (index, threads, buses_per_thread,
     kind, streaming, cases).  For a banded variant buses_per_thread counts the buses
     of one block; it serves sub-grids of bandwidth <= threads * buses_per_thread.
-    `cases` is the number of cases one workgroup solves at a time."""
+    `cases` is the number of cases one workgroup solves at a time (1 for every
+    variant built)."""
     L = lib()
     out = []
     for i in range(L.dpf_solve_variant_count()):
@@ -583,8 +583,8 @@ def autotune(grid: DeviceGrid, bus_type, s_spec, vm, va, *, outage=None, sub_off
     count as equal and the first of them in the table is taken, which keeps the
     choice stable under timing noise.  With a tail handoff in ``route``, a
     single-grid call chooses among the kinds that can hand over (streaming,
-    banded, banded-stream, banded-window): the fixed-length probes cannot see the
-    handoff.  Returns {variant: seconds}."""
+    banded-stream, banded-pair): the fixed-length probes cannot see the handoff.
+    Returns {variant: seconds}."""
     opts = opts or Options()
     route = route or Route()
     n_max = grid.n_bus if sub_offset is None else int(max(b - a for a, b in zip(sub_offset[:-1], sub_offset[1:])))

@@ -92,20 +92,20 @@ __device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_of(const void *base, ui
     void *ub = (void *)(((unsigned long long)hi << 32) | lo);
     return __builtin_amdgcn_make_buffer_rsrc(ub, 0, __builtin_amdgcn_readfirstlane((int)bytes), kBufferWord3);
 }
+// element idx (16 bytes each) through a resource made once (buffer_of) and kept in
+// scalar registers; a loop around these stays free of lane-uniformity operations
 template <bool DEV>
-__device__ __forceinline__ double2 buf_ld2(const double2 *base, uint32_t bytes, int idx) {
-    const auto v = __builtin_amdgcn_raw_buffer_load_b128(buffer_of(base, bytes), (int)((uint32_t)idx * 16u), 0,
-                                                         DEV ? kCachePolicySC1 : 0);
+__device__ __forceinline__ double2 rsrc_ld2(__amdgpu_buffer_rsrc_t r, int idx) {
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)((uint32_t)idx * 16u), 0, DEV ? kCachePolicySC1 : 0);
     double2 out;
     __builtin_memcpy(&out, &v, sizeof(out));
     return out;
 }
 template <bool DEV>
-__device__ __forceinline__ void buf_st2(double2 *base, uint32_t bytes, int idx, double2 x) {
-    decltype(__builtin_amdgcn_raw_buffer_load_b128(buffer_of(base, bytes), 0, 0, 0)) v;
+__device__ __forceinline__ void rsrc_st2(__amdgpu_buffer_rsrc_t r, int idx, double2 x) {
+    decltype(__builtin_amdgcn_raw_buffer_load_b128(r, 0, 0, 0)) v;
     __builtin_memcpy(&v, &x, sizeof(x));
-    __builtin_amdgcn_raw_buffer_store_b128(v, buffer_of(base, bytes), (int)((uint32_t)idx * 16u), 0,
-                                           DEV ? kCachePolicySC1 : 0);
+    __builtin_amdgcn_raw_buffer_store_b128(v, r, (int)((uint32_t)idx * 16u), 0, DEV ? kCachePolicySC1 : 0);
 }
 // this thread's stores have completed (and the compiler keeps every earlier
 // memory access before this point)

@@ -156,52 +156,39 @@ template <int NT, int K>
 Variant make_variant() {
     return Variant{NT, K, dpf::kReg, dpf::team_solve_kernel<NT, K, dpf::kReg>};
 }
-template <int NT, int K>
+// any number of buses per thread (k = 0)
+template <int NT>
 Variant make_stream_variant() {
-    return Variant{NT, K, dpf::kGlobal, dpf::team_solve_stream_kernel<NT, K>};
+    return Variant{NT, 0, dpf::kGlobal, dpf::team_solve_stream_kernel<NT>};
 }
-template <int NT, int J, bool PIPE = true>
-Variant make_band_variant() {
-    return Variant{NT, J, PIPE ? dpf::kBand : dpf::kBandStream, dpf::team_solve_band_kernel<NT, J, PIPE>};
-}
+// banded, barrier-free gradient sweep (k = J buses per thread per block)
 template <int NT, int J>
-Variant make_window_variant() {
-    return Variant{NT, J, dpf::kWindow, dpf::team_solve_window_kernel<NT, J>};
+Variant make_band_variant() {
+    return Variant{NT, J, dpf::kBandStream, dpf::team_solve_band_kernel<NT, J>};
 }
-// k = cases per workgroup (one bus per thread per block)
-template <int NT, int C>
-Variant make_multi_variant() {
-    return Variant{NT, C, dpf::kMulti, dpf::team_solve_multi_kernel<NT, C>};
-}
-// banded, barrier-free gradient sweep, state in (|V|, theta) and moment pairs
+// the same with the state in (|V|, theta) and moment pairs
 template <int NT, int J>
 Variant make_pair_variant() {
     return Variant{NT, J, dpf::kPair, dpf::team_solve_pair_kernel<NT, J>};
 }
 
 
-// Register-resident variants up to 2048 buses per item, streaming above (the
-// 1024-thread streaming variant takes any size with holds in scratch; the 512-thread
-// ones keep held exchange values in registers).  The banded variants (k = buses per
-// thread per block) serve sub-grids whose bandwidth is at most threads * k; the others
-// go to the default variant of the size in the same call.  The windowed ones keep
-// 8 blocks of threads * k buses in LDS whatever the sub-grid size, so that several
-// items share a compute unit; the batched windowed ones (k = cases per workgroup)
-// run k cases of a single-grid call per workgroup on one stream of matrix loads.  The last entry is not a
+// Register-resident variants up to 2048 buses per item, the 1024-thread streaming
+// variant above (any size).  The banded variants (k = buses per thread per block)
+// serve sub-grids whose bandwidth is at most threads * k; the others go to the
+// default variant of the size in the same call.  The last entry is not a
 // workgroup-per-item kernel: it sends every sub-grid of the call to the
-// multi-workgroup path, which spreads one item over many CUs.
+// multi-workgroup path, which spreads one item over many CUs.  Kinds measured and
+// retired as dominated on every workload timed (64 to 4096 cases of 300 to 9241
+// buses): streaming kernels of 512 threads holding exchange values in registers,
+// banded kernels with a pipelined gradient sweep, windowed kernels (rings of
+// blocks in LDS) and their batched form (several cases per workgroup).
 const Variant *variant_table(int *count) {
     static const Variant table[] = {
-        make_variant<64, 1>(),  make_variant<128, 1>(), make_variant<256, 1>(), make_variant<256, 2>(),
-        make_variant<512, 2>(), make_variant<512, 3>(), make_variant<512, 4>(), make_stream_variant<512, 8>(),
-        make_stream_variant<512, 12>(), make_stream_variant<1024, 0>(), make_stream_variant<512, 16>(),
-        make_stream_variant<512, 20>(), make_band_variant<1024, 1>(), make_band_variant<1024, 2>(),
-        make_band_variant<512, 2>(),    make_band_variant<1024, 1, false>(), make_band_variant<1024, 2, false>(),
-        make_band_variant<512, 2, false>(), make_band_variant<1024, 3, false>(), make_band_variant<1024, 4, false>(),
-        make_window_variant<256, 1>(),      make_window_variant<128, 2>(),        make_window_variant<128, 1>(),
-        make_window_variant<512, 1>(),      make_window_variant<256, 2>(),        make_multi_variant<256, 2>(),
-        make_multi_variant<256, 3>(),       make_multi_variant<256, 4>(),         make_multi_variant<512, 2>(),
-        make_multi_variant<128, 4>(),       make_pair_variant<1024, 4>(),         make_pair_variant<1024, 2>(),
+        make_variant<64, 1>(),          make_variant<128, 1>(),       make_variant<256, 1>(),
+        make_variant<256, 2>(),         make_variant<512, 2>(),       make_variant<512, 3>(),
+        make_variant<512, 4>(),         make_stream_variant<1024>(),  make_band_variant<1024, 2>(),
+        make_band_variant<1024, 4>(),   make_pair_variant<1024, 4>(), make_pair_variant<1024, 2>(),
         Variant{0, 0, dpf::kWide, nullptr},
     };
     *count = (int)(sizeof(table) / sizeof(table[0]));
@@ -989,7 +976,7 @@ int dpf_solve_variant_info(int idx, int32_t *threads, int32_t *buses_per_thread,
     if (idx < 0 || idx >= cnt || !threads || !buses_per_thread || !streaming)
         return fail(DPF_EINVAL, "variant index out of range or null output");
     *threads = t[idx].nt;
-    *buses_per_thread = t[idx].mode == dpf::kMulti ? 1 : t[idx].k;
+    *buses_per_thread = t[idx].k;
     *streaming = t[idx].mode;
     return DPF_OK;
 }
@@ -999,7 +986,7 @@ int dpf_solve_variant_cases(int idx) {
     int cnt = 0;
     const Variant *t = variant_table(&cnt);
     if (idx < 0 || idx >= cnt) return fail(DPF_EINVAL, "variant index out of range");
-    return t[idx].mode == dpf::kMulti ? t[idx].k : 1;
+    return 1;
 }
 
 int dpf_solve_variant_for_items(int32_t n_max, int64_t items) {
@@ -1217,11 +1204,6 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
     if (few_large && route.tail_team > 0 && small == 1 && (!sub_offset || n_sub == 1) &&
         (size_t)p.n_max * 16 + (size_t)(p.n_max + 31) / 32 * 4 + 512 <= (size_t)dev.lds_per_block)
         p.split_direct = true;
-    if (p.v && p.v->mode == dpf::kMulti && sub_offset && n_sub != 1) {  // batched kernel: one grid only
-        int cnt = 0;
-        const int d = default_variant_index(std::max(1, p.n_max));
-        p.v = d >= 0 ? &variant_table(&cnt)[d] : nullptr;
-    }
     if (p.v && p.v->mode == dpf::kWide) {  // every sub-grid to the multi-workgroup path
         p.cap = 0;
         p.n_max = 0;
@@ -1240,8 +1222,7 @@ static CallPlan plan_call(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub
     // tail handoff: single-grid calls whose per-item kernel keeps the state in global memory
     const int32_t h = route.tail_handoff;
     if (h > 0 && p.v && p.has_small && small == 1 && (!sub_offset || n_sub == 1) &&
-        (p.v->mode == dpf::kGlobal || p.v->mode == dpf::kBand || p.v->mode == dpf::kBandStream ||
-         p.v->mode == dpf::kWindow || p.v->mode == dpf::kPair))
+        (p.v->mode == dpf::kGlobal || p.v->mode == dpf::kBandStream || p.v->mode == dpf::kPair))
         p.handoff = h;
     return p;
 }
@@ -1360,7 +1341,6 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.sub_bw = sub_bw;
     a.band_nt = 0;
     a.bad_grid = bad;
-    a.queue = bad + 4;  // header word 4: the batched kernel's case queue
     a.done_count = bad + 5;  // header word 5: finished items (tail handoff)
     a.handoff = handoff ? plan.handoff : 0;
     a.total_items = B * n_sub;
@@ -1468,25 +1448,14 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
     }
     if (has_small) {
-        // the windowed kernel's LDS is a fixed pair of 4-block rings
-        dpf::SolveArgs aw = a;
-        size_t v_lds = lds_bytes;
-        int grid = items;
-        if (v->mode == dpf::kWindow) {
-            aw.lds_cap = 8 * v->nt * v->k;
-            v_lds = (size_t)aw.lds_cap * 16;
-        } else if (v->mode == dpf::kMulti) {  // k cases per workgroup, more from the queue
-            aw.lds_cap = 8 * v->nt * v->k;
-            v_lds = (size_t)aw.lds_cap * 16;
-            grid = (items + v->k - 1) / v->k;
-        }
         const dim3 pgrid((g->n_bus + 255) / 256, B);
         double2 *P = a.scratch + a.st_stride;  // the pairs follow I in the scratch
         if (pairs)
             hipLaunchKernelGGL(dpf::pair_in_kernel, pgrid, dim3(256), 0, st, g->n_bus, (int64_t)ld, B, vm, va, a.st,
                                a.st_stride, a.st_fresh, P, P + a.st_stride, P + 2 * a.st_stride);
-        DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)v_lds));
-        hipLaunchKernelGGL(v->fn, dim3(grid), dim3(v->nt), v_lds, st, aw);
+        DPF_HIP(hipFuncSetAttribute((const void *)v->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds_bytes));
+        hipLaunchKernelGGL(v->fn, dim3(items), dim3(v->nt), lds_bytes, st, a);
         DPF_HIP(hipGetLastError());
         // the pairs back to the caller's layout (every item, paused ones included) before
         // any other path reads the state
@@ -1499,7 +1468,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
             int cnt = 0;
             const Variant *f = &variant_table(&cnt)[default_variant_index(std::max(1, n_max))];
             dpf::SolveArgs b = a;
-            b.band_nt = v->mode == dpf::kMulti ? v->nt : v->nt * v->k;  // the banded block
+            b.band_nt = v->nt * v->k;  // the banded block
             DPF_HIP(hipFuncSetAttribute((const void *)f->fn, hipFuncAttributeMaxDynamicSharedMemorySize,
                                         (int)lds_bytes));
             hipLaunchKernelGGL(f->fn, dim3(items), dim3(f->nt), lds_bytes, st, b);

@@ -26,8 +26,8 @@ struct SellView {
 };
 
 // slices per sub-grid: ceil(n_s / 64); clears the per-sub-grid bandwidth
-// (thread 0 also clears the bad-grid flag and the two counters that follow
-// `queue`: the case queue and the finished-item count)
+// (thread 0 also clears the bad-grid flag and the two header words at `queue`,
+// the second of which counts finished items for the tail handoff)
 __global__ void sell_count_kernel(int32_t n_sub, const int32_t *__restrict__ sub_off, int32_t n_bus,
                                   int32_t *__restrict__ nslice, int32_t *__restrict__ bw, int32_t *__restrict__ bad,
                                   int32_t *__restrict__ queue) {

@@ -34,18 +34,13 @@
 namespace dpf {
 
 enum StoreMode {
-    kReg = 0,
-    kGlobal = 1,
-    kBand = 2,
-    kBandStream = 3,
-    kWide = 4,
-    kWindow = 5,
-    kMulti = 6,
-    kPair = 7
+    kReg = 0,         // state in registers
+    kGlobal = 1,      // streaming: state in global memory
+    kBandStream = 2,  // banded, barrier-free gradient sweep
+    kWide = 3,        // the multi-workgroup path for a whole call
+    kPair = 4         // banded, state kept as (|V|, theta) and moment pairs
 };
-__host__ __device__ constexpr bool is_banded(int mode) {
-    return mode == kBand || mode == kBandStream || mode == kWindow || mode == kMulti || mode == kPair;
-}
+__host__ __device__ constexpr bool is_banded(int mode) { return mode == kBandStream || mode == kPair; }
 
 constexpr int kSchedWords = 6;  // per-item schedule state, see SolveArgs::sched
 
@@ -71,7 +66,6 @@ struct SolveArgs {
     int32_t band_nt;         // > 0: sub-grids with sub_bw <= band_nt belong to the banded kernel
     int32_t team_cap;        // items above this size belong to the multi-workgroup path
     const int32_t *bad_grid; // set when a row exceeded the declared width bound
-    int32_t *queue;          // next unstarted case (batched windowed kernel), cleared per call
     int32_t handoff;         // > 0: tail handoff threshold in unfinished items (see handoff_due)
     int32_t total_items;     // items of the call
     int32_t *done_count;     // items finished so far (handoff only), cleared per call
@@ -539,26 +533,20 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
 }
 
 // Streaming variant for large sub-grids.  Every per-bus value lives in global
-// memory (the caller's vm/va/Adam arrays and the scratch arrays V and a*I) and
-// is streamed once per iteration; the only per-bus registers are `hold`, which
-// carry w (after phase A) and the new V (after phase B) across the barrier of
-// the single-buffered LDS exchange.  K = buses per thread is a compile-time
-// bound so that `hold` stays in registers; the per-bus address arithmetic is
-// re-derived inside the iteration (opaque_index) instead of being kept live.
+// memory (the caller's vm/va/Adam arrays and the scratch arrays a*I and w) and
+// is streamed once per iteration, with a runtime loop over any number of buses
+// per thread.  With the single-buffered LDS exchange, w goes through the scratch
+// array W and the new V is rebuilt from |V| and theta (both L2-resident), which
+// keeps the register count low enough for 1024-thread workgroups; the per-bus
+// address arithmetic is re-derived inside the iteration (opaque_index) instead
+// of being kept live.
 __device__ __forceinline__ uint32_t opaque_index(uint32_t i) {
     asm volatile("" : "+v"(i));
     return i;
 }
 
-template <int NT, int K>
+template <int NT>
 __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
-    // K > 0: each thread owns at most K buses and holds w / new V in registers.
-    // K == 0: runtime loop over any number of buses per thread; w goes through
-    // the scratch array W and the new V is re-read from V (both L2-resident),
-    // which keeps the register count low enough for 1024-thread workgroups.
-    constexpr bool HOLD = K > 0;
-    constexpr int KH = HOLD ? K : 1;
-    constexpr int KLOOP = HOLD ? K : (1 << 30);
     extern __shared__ double2 X[];
     __shared__ double red[2][NT / kWave];
 
@@ -572,7 +560,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     const int out_idx = c * a.n_sub + sidx;
     if (n > a.team_cap) return;  // handled by the multi-workgroup path
     if (a.band_nt > 0 && a.sub_bw[sidx] <= a.band_nt) return;  // handled by the banded kernel
-    if (n < 0 || (HOLD && n > NT * K) || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
+    if (n < 0 || n > a.lds_cap || *a.bad_grid) {  // see DPF_BAD_GRID
         if (tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;
             a.iters[out_idx] = 0;
@@ -599,7 +587,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 
     const int64_t cb = (int64_t)c * a.ld;
     const int64_t sb = (int64_t)c * a.s_ld;
-    double2 *__restrict__ Wg = HOLD ? nullptr : a.scratch + 2 * a.st_stride + cb;
+    double2 *__restrict__ Wg = a.scratch + 2 * a.st_stride + cb;
     double *__restrict__ vm_c = a.vm + cb;
     double *__restrict__ va_c = a.va + cb;
     double *__restrict__ mv_c = a.st + cb;
@@ -629,15 +617,12 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
     }
     __syncthreads();
 
-    double2 hold[KH];
-#pragma unroll
-    for (int k = 0; k < KH; ++k) hold[k] = make_double2(0.0, 0.0);
-    // bus loop of one phase: unrolled over the K owned buses, or a runtime loop
-#define DPF_BUS_LOOP_BEGIN                                                              \
-    _Pragma("unroll KH") for (int kk = 0; kk < KLOOP; ++kk) {                           \
-        const uint32_t i = opaque_index((uint32_t)(lo + tid + kk * NT));                \
-        if (!HOLD && (int)i >= hi) break;                                               \
-        if ((int)i < hi) {
+    // bus loop of one phase
+#define DPF_BUS_LOOP_BEGIN                                               \
+    for (int kk = 0;; ++kk) {                                            \
+        const uint32_t i = opaque_index((uint32_t)(lo + tid + kk * NT)); \
+        if ((int)i >= hi) break;                                         \
+        {
 #define DPF_BUS_LOOP_END \
     }                    \
     }
@@ -675,22 +660,12 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 aIg[i] = cmul(av, acc);
                 const double2 w = cmulc(av, v);
                 if (dbl) Xw[il] = w;
-                else if (HOLD) hold[kk % KH] = w;
                 else Wg[i] = w;
         DPF_BUS_LOOP_END
         block_reduce2<NT>(lsum, lmax, red);
         __syncthreads();
-        if (!dbl) {
-            if (HOLD) {
-#pragma unroll
-                for (int k = 0; k < KH; ++k) {
-                    const int i = lo + tid + k * NT;
-                    if (i < hi) Xw[i - lo] = hold[k];
-                }
-            } else {
-                for (int i = lo + tid; i < hi; i += NT) Xw[i - lo] = Wg[i];
-            }
-        }
+        if (!dbl)
+            for (int i = lo + tid; i < hi; i += NT) Xw[i - lo] = Wg[i];
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
@@ -756,24 +731,15 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 fast_sincos(vai, sn, cs);
                 v = make_double2(vmi * cs, vmi * sn);
                 if (dbl) Xv[il] = v;
-                else if (HOLD) hold[kk % KH] = v;
         DPF_BUS_LOOP_END
         sched_step(a, sc, loss);
         if (!dbl) {
             __syncthreads();
-            if (HOLD) {
-#pragma unroll
-                for (int k = 0; k < KH; ++k) {
-                    const int i = lo + tid + k * NT;
-                    if (i < hi) Xv[i - lo] = hold[k];
-                }
-            } else {
-                for (int i = lo + tid; i < hi; i += NT) {
-                    double sn, cs;
-                    const double vmi = vm_c[i];
-                    fast_sincos(va_c[i], sn, cs);
-                    Xv[i - lo] = make_double2(vmi * cs, vmi * sn);
-                }
+            for (int i = lo + tid; i < hi; i += NT) {
+                double sn, cs;
+                const double vmi = vm_c[i];
+                fast_sincos(va_c[i], sn, cs);
+                Xv[i - lo] = make_double2(vmi * cs, vmi * sn);
             }
         }
         __syncthreads();
@@ -796,13 +762,15 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
 //       w = a conj(V); I goes to scratch for the second sweep.  After a barrier
 //       the w of block s-1 replaces V there (its readers, blocks s-2..s, are done).
 //   stop test on the reduced max|r|
-//   B/U sweep, step s: rows of block s gather w, rebuild dS and a*I from I and V,
-//       form the gradient, apply Adam and compute the new V.  After a barrier the
-//       new V of block s-1 replaces w there.
-// Per bus and iteration this moves |V|, theta and the four moments once each way
-// plus I (16 B written, 16 B read), and evaluates one polar conversion per sweep;
-// there is no V or w round trip through memory.
-template <int NT, int J, bool PIPE>
+//   gradient sweep, one pass without barriers (w stays in X throughout): rows
+//       gather w, rebuild dS and a*I from I and V, form the gradient and apply
+//       the optimizer step; then X is refilled with the new V from |V| and theta.
+// Per bus and iteration this moves |V|, theta and the four moments once each way,
+// I (16 B written, 16 B read) and the refill's |V| and theta (16 B read); there is
+// no w round trip through memory.  (A pipelined gradient sweep that overwrote w
+// block by block with the new V moved 16 B less but, with a barrier per block,
+// ran slower: the lockstep waves stopped overlapping loads and arithmetic.)
+template <int NT, int J>
 __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
     constexpr int BLK = NT * J;
     extern __shared__ double2 X[];
@@ -948,16 +916,13 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
         sc.b2t *= a.b2;
         const double bc1 = 1.0 - sc.b1t;
         const double bc2 = 1.0 - sc.b2t;
-        // PIPE: block steps with a barrier each, the new V held for one step.
-        // Otherwise: one barrier-free pass (w stays in X throughout), then the
-        // new V is rebuilt from |V| and theta in a refill pass.
-        for (int s = 0; s <= (PIPE ? nb : nb - 1); ++s) {
-            double2 vn[J];
+        // one barrier-free pass (w stays in X throughout), then the new V is
+        // rebuilt from |V| and theta in a refill pass
+        for (int s = 0; s < nb; ++s) {
 #pragma unroll
             for (int j = 0; j < J; ++j) {
-                vn[j] = make_double2(0.0, 0.0);
                 const int il = s * BLK + j * NT + tid;
-                if (s < nb && il < n) {
+                if (il < n) {
                     const int i = lo + il;
                     // every global load of this bus first, so that they overlap the gather
                     const int8_t tk = btp[i];
@@ -1001,662 +966,21 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                         ma_c[i] = ma;
                         sa_c[i] = sa;
                     }
-                    if (PIPE) {
-                        double sn, cs;
-                        fast_sincos(vai, sn, cs);
-                        vn[j] = make_double2(vmi * cs, vmi * sn);
-                    }
                 }
-            }
-            if (PIPE) {
-                __syncthreads();
-                if (s > 0) {
-#pragma unroll
-                    for (int j = 0; j < J; ++j) {
-                        const int il = (s - 1) * BLK + j * NT + tid;
-                        if (il < n) X[il] = hold[j];
-                    }
-                }
-#pragma unroll
-                for (int j = 0; j < J; ++j) hold[j] = vn[j];
             }
         }
-        if (!PIPE) {
-            __syncthreads();
-            for (int i = lo + tid; i < hi; i += NT) {
-                double sn, cs;
-                const double vmi = vm_c[i];
-                fast_sincos(va_c[i], sn, cs);
-                X[i - lo] = make_double2(vmi * cs, vmi * sn);
-            }
+        __syncthreads();
+        for (int i = lo + tid; i < hi; i += NT) {
+            double sn, cs;
+            const double vmi = vm_c[i];
+            fast_sincos(va_c[i], sn, cs);
+            X[i - lo] = make_double2(vmi * cs, vmi * sn);
         }
         sched_step(a, sc, loss);
         __syncthreads();
     }
 
     if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
-}
-
-// Windowed variant for banded sub-grids of any size: one sweep per iteration
-// over blocks of BLK = NT*J consecutive buses, with the LDS holding only four
-// blocks of V and four of w.  A sweep runs three stages as a pipeline, each two
-// blocks behind the stage it reads from (rows of block b read blocks b-1..b+1
-// when the bandwidth is at most BLK), one barrier per step:
-//   S3, block s-4: h = Y^T w; G = a I + conj(h); optimizer step on |V|, theta
-//                  and the moments
-//   S1, block s  : V = polar(|V|, theta) -> V ring (the slot S3 just read its own
-//                  V from: both belong to the same thread)
-//   S2, block s-2: I = Y V, dS, loss terms; a = (2/m)(r^P + j r^Q) (a*I kept in
-//                  registers for S3); w = a conj(V) -> w ring
-// The state (|V|, theta, moments) is double-buffered: sweep k reads copy k mod 2
-// and writes the other, so the stop test on the loss of sweep k's own S2 can
-// come after that sweep has computed its update; a stop discards the update and
-// the point tested is the one returned (copied to the caller's arrays when it
-// sits in the second copy), as in the order of Algorithm 1.  Per bus and
-// iteration this moves |V|, theta and the four moments once each way (the
-// 96-byte floor), two products with Y and one polar conversion.
-// HBM loads are issued one step ahead (|V|, theta of block s+1, the moments of
-// block s-3), so that their latency overlaps the barrier and the LDS work.
-template <int NT, int J>
-__global__ __launch_bounds__(NT) void team_solve_window_kernel(SolveArgs a) {
-    constexpr int BLK = NT * J;
-    constexpr int RM = 4 * BLK - 1;  // ring index mask (both rings hold 4 blocks)
-    extern __shared__ double2 X[];
-    double2 *__restrict__ RV = X;
-    double2 *__restrict__ RW = X + 4 * BLK;
-    __shared__ double red[2][NT / kWave];
-
-    const int tid = threadIdx.x;
-    const int item = a.order ? a.order[blockIdx.x] : (int)blockIdx.x;
-    const int sidx = item / a.B;
-    const int c = item - sidx * a.B;
-    const int lo = a.sub_off ? a.sub_off[sidx] : 0;
-    const int hi = a.sub_off ? a.sub_off[sidx + 1] : a.n_bus;
-    const int n = hi - lo;
-    const int out_idx = c * a.n_sub + sidx;
-    if (n > a.team_cap) return;        // handled by the multi-workgroup path
-    if (a.sub_bw[sidx] > BLK) return;  // bandwidth too large: the general kernel takes it
-    if (n < 0 || a.lds_cap < 8 * BLK || *a.bad_grid) {  // see DPF_BAD_GRID
-        if (tid == 0) {
-            a.status[out_idx] = DPF_BAD_GRID;
-            a.iters[out_idx] = 0;
-        }
-        return;
-    }
-    const int slice0 = a.sell.slice_off[sidx];
-    const int lane = tid & (kWave - 1);
-
-    ItemSched sc = load_item_sched(a, out_idx);
-    const double m_res = residual_count<NT>(a.bt, lo, hi, red);
-    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
-    const Rank2 r2 = outage_of_case(a.ov, c, lo, hi);
-    if (r2.bad) return;  // reported by the call's prologue
-    const int of = r2.of, ot = r2.ot;
-    const double2 oy = r2.oy, oyd = r2.oyd;
-
-    // copy 0: the caller's arrays; copy 1: the scratch arrays [6][B][ld]
-    const int64_t cb = (int64_t)c * a.ld + lo;
-    const int64_t sb = (int64_t)c * a.s_ld + lo;
-    double *const alt = (double *)a.scratch;
-    double *const state[2][6] = {
-        {a.vm + cb, a.va + cb, a.st + cb, a.st + 2 * a.st_stride + cb, a.st + a.st_stride + cb,
-         a.st + 3 * a.st_stride + cb},
-        {alt + cb, alt + a.st_stride + cb, alt + 2 * a.st_stride + cb, alt + 3 * a.st_stride + cb,
-         alt + 4 * a.st_stride + cb, alt + 5 * a.st_stride + cb}};  // vm, va, m_vm, s_vm, m_va, s_va
-    const double2 *__restrict__ Sc = a.s_spec + sb;
-    const int8_t *__restrict__ btp = a.bt + lo;
-    const int32_t *__restrict__ swidth = a.sell.width;
-    const int32_t *__restrict__ sstart = a.sell.start;
-    const int32_t *__restrict__ scol = a.sell.col;
-    const double2 *__restrict__ sval = a.sell.val;
-
-    if (a.st_fresh) {
-        for (int il = tid; il < n; il += NT) {
-            state[0][2][il] = 0.0;
-            state[0][3][il] = 0.0;
-            state[0][4][il] = 0.0;
-            state[0][5][il] = 0.0;
-        }
-    }
-
-    // (Y R)_i for local row il of ring R, with the outage block removed
-    auto row_product = [&](const double2 *__restrict__ R, int il) -> double2 {
-        const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
-        const int wdt = swidth[gsl];
-        const int base = sstart[gsl] * kWave + lane;
-        double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-        for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], R[scol[base + q * kWave] & RM], acc);
-        if (il == of) acc = csub(acc, csub(cmul(oyd, R[of & RM]), cmul(oy, R[ot & RM])));
-        else if (il == ot) acc = csub(acc, csub(cmul(oyd, R[ot & RM]), cmul(oy, R[of & RM])));
-        return acc;
-    };
-
-    const int nb = (n + BLK - 1) / BLK;
-    int it = 0, stat = DPF_MAX_ITER;
-    double mu = 0.0, loss = 0.0;
-    __shared__ int pause_flag;
-    for (;; ++it) {
-        if (handoff_due(a, it, &pause_flag)) {  // the point reached sits in copy it mod 2
-            stat = kPaused;
-            break;
-        }
-        const int rd = it & 1;
-        const double *__restrict__ vm_r = state[rd][0];
-        const double *__restrict__ va_r = state[rd][1];
-        const double *__restrict__ mv_r = state[rd][2];
-        const double *__restrict__ sv_r = state[rd][3];
-        const double *__restrict__ ma_r = state[rd][4];
-        const double *__restrict__ sa_r = state[rd][5];
-        double *__restrict__ vm_w = state[rd ^ 1][0];
-        double *__restrict__ va_w = state[rd ^ 1][1];
-        double *__restrict__ mv_w = state[rd ^ 1][2];
-        double *__restrict__ sv_w = state[rd ^ 1][3];
-        double *__restrict__ ma_w = state[rd ^ 1][4];
-        double *__restrict__ sa_w = state[rd ^ 1][5];
-        // the step this sweep computes (kept only if the stop test passes)
-        const double b1t = sc.b1t * a.b1, b2t = sc.b2t * a.b2;
-        const double bc1 = 1.0 - b1t, bc2 = 1.0 - b2t;
-        const double lr = sc.lr;
-        // register pipelines: qm/qa[d] = |V|, theta of block s-d+1 at step s
-        // ([0] is the prefetch), pI[d] = a*I of block s-d-2, pm = moments of block s-4
-        double qm[6][J], qa[6][J];
-        double2 pI[3][J];
-        double pm[4][J];
-#pragma unroll
-        for (int j = 0; j < J; ++j) {
-#pragma unroll
-            for (int d = 0; d < 6; ++d) qm[d][j] = qa[d][j] = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) pI[d][j] = make_double2(0.0, 0.0);
-#pragma unroll
-            for (int d = 0; d < 4; ++d) pm[d][j] = 0.0;
-            const int il = j * NT + tid;
-            if (il < n) {
-                qm[0][j] = vm_r[il];
-                qa[0][j] = va_r[il];
-            }
-        }
-        double lsum = 0.0, lmax = 0.0;
-        for (int s = 0; s < nb + 4; ++s) {
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-#pragma unroll
-                for (int d = 5; d > 0; --d) {
-                    qm[d][j] = qm[d - 1][j];
-                    qa[d][j] = qa[d - 1][j];
-                }
-            }
-            // S3: block s-4 (reads its own V before S1 reuses the slot)
-            if (s >= 4) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const int il = (s - 4) * BLK + j * NT + tid;
-                    if (il < n) {
-                        const int8_t tk = btp[il];
-                        const double2 h = row_product(RW, il);
-                        const double2 v = RV[il & RM];
-                        const double2 ai = pI[2][j];
-                        const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
-                        double vmi = qm[5][j], vai = qa[5][j];
-                        if (tk == kPQ) {
-                            const double g = (G.x * v.x + G.y * v.y) / vmi;
-                            double mv = pm[0][j], sv = pm[1][j];
-                            vmi = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
-                            mv_w[il] = mv;
-                            sv_w[il] = sv;
-                        }
-                        if (tk != kSlack) {
-                            const double g = G.y * v.x - G.x * v.y;
-                            double ma = pm[2][j], sa = pm[3][j];
-                            vai = opt_update(a.opt, lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
-                            ma_w[il] = ma;
-                            sa_w[il] = sa;
-                        }
-                        vm_w[il] = vmi;
-                        va_w[il] = vai;
-                    }
-                }
-            }
-            // S1: block s
-            if (s < nb) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const int il = s * BLK + j * NT + tid;
-                    if (il < n) {
-                        double sn, cs;
-                        fast_sincos(qa[1][j], sn, cs);
-                        RV[il & RM] = make_double2(qm[1][j] * cs, qm[1][j] * sn);
-                    }
-                }
-            }
-            // S2: block s-2
-            if (s >= 2 && s - 2 < nb) {
-#pragma unroll
-                for (int j = 0; j < J; ++j) {
-                    const int il = (s - 2) * BLK + j * NT + tid;
-                    double2 ai = make_double2(0.0, 0.0);
-                    if (il < n) {
-                        const int8_t tk = btp[il];
-                        const double2 sp = Sc[il];
-                        const double2 I = row_product(RV, il);
-                        const double2 v = RV[il & RM];
-                        const double2 d = csub(cmulc(v, I), sp);
-                        const double rP = tk != kSlack ? d.x : 0.0;
-                        const double rQ = tk == kPQ ? d.y : 0.0;
-                        lsum += rP * rP + rQ * rQ;
-                        lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
-                        const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
-                        ai = cmul(av, I);
-                        RW[il & RM] = cmulc(av, v);
-                    }
-                    pI[0][j] = ai;
-                }
-            }
-            // prefetch for the next step: |V|, theta of block s+1, moments of block s-3
-#pragma unroll
-            for (int j = 0; j < J; ++j) {
-                const int il = (s + 1) * BLK + j * NT + tid;
-                if (s + 1 < nb && il < n) {
-                    qm[0][j] = vm_r[il];
-                    qa[0][j] = va_r[il];
-                }
-                const int im = (s - 3) * BLK + j * NT + tid;
-                if (s >= 3 && s - 3 < nb && im < n) {
-                    pm[0][j] = mv_r[im];
-                    pm[1][j] = sv_r[im];
-                    pm[2][j] = ma_r[im];
-                    pm[3][j] = sa_r[im];
-                }
-#pragma unroll
-                for (int d = 2; d > 0; --d) pI[d][j] = pI[d - 1][j];
-            }
-            __syncthreads();
-        }
-        block_reduce2<NT>(lsum, lmax, red);
-        __syncthreads();
-        block_reduce2_finish<NT>(lsum, lmax, red);
-        loss = m_res > 0.0 ? lsum / m_res : 0.0;
-        mu = isnan(lsum) ? lsum : lmax;
-        if (!(isfinite(loss) && isfinite(mu))) {
-            stat = DPF_NONFINITE;
-            break;
-        }
-        if (mu < a.tol) {
-            stat = DPF_CONVERGED;
-            break;
-        }
-        if (it >= a.max_iter) {
-            stat = DPF_MAX_ITER;
-            break;
-        }
-        // keep the step
-        sc.t_step += 1.0;
-        sc.b1t = b1t;
-        sc.b2t = b2t;
-        sched_step(a, sc, loss);
-    }
-    // the point returned sits in copy it mod 2: bring copy 1 back to the caller's arrays
-    if (it & 1) {
-        for (int il = tid; il < n; il += NT) {
-            const int8_t tk = btp[il];
-            state[0][0][il] = state[1][0][il];
-            state[0][1][il] = state[1][1][il];
-            if (tk == kPQ) {
-                state[0][2][il] = state[1][2][il];
-                state[0][3][il] = state[1][3][il];
-            }
-            if (tk != kSlack) {
-                state[0][4][il] = state[1][4][il];
-                state[0][5][il] = state[1][5][il];
-            }
-        }
-    }
-
-    if (tid == 0) finish_item(a, out_idx, it, stat, mu, loss, sc);
-}
-
-// Batched windowed variant (one grid, many cases): the windowed sweep above run
-// for C cases at once, each in a slot of its own (its own V and w rings,
-// register pipelines, step count and schedule), with each load of the shared
-// sliced-ELL matrix serving all C slots.  On gfx950 the solve is bound by the
-// vector-memory path (L1 misses to L2, most of them the matrix, which every
-// case re-reads every iteration); sharing the matrix loads cuts the vector loads
-// and L2 requests per case by about a third at C = 2, at the price of C sets of
-// rings and pipeline registers per workgroup.  Cases come from a queue: a workgroup starts with up to C of
-// them and, when a case stops, its slot takes the next unstarted case at the
-// end of that sweep, so that cases of very different iteration counts keep the
-// slots busy.  Only single-grid calls use it; an idle slot computes on its
-// rings without touching memory.
-template <int NT, int C>
-__global__ __launch_bounds__(NT) void team_solve_multi_kernel(SolveArgs a) {
-    constexpr int BLK = NT;
-    constexpr int RM = 4 * BLK - 1;
-    extern __shared__ double2 X[];  // slot k: V ring at X + 8 BLK k, w ring 4 BLK further
-    __shared__ double red[2][C][NT / kWave];
-    __shared__ int32_t take[C];
-
-    const int tid = threadIdx.x;
-    const int n = a.n_bus;
-    if (n > a.team_cap) return;       // handled by the multi-workgroup path
-    if (a.sub_bw[0] > BLK) return;    // bandwidth too large: the general kernel takes every case
-    const bool bad = n < 0 || a.lds_cap < 8 * BLK * C || *a.bad_grid;
-    const int lane = tid & (kWave - 1);
-    const int wv = tid / kWave;
-
-    const double m_res = residual_count<NT>(a.bt, 0, n, red[0]);
-    const double two_over_m = m_res > 0.0 ? 2.0 / m_res : 0.0;
-    double *const alt = (double *)a.scratch;
-    const int32_t *__restrict__ swidth = a.sell.width;
-    const int32_t *__restrict__ sstart = a.sell.start;
-    const int32_t *__restrict__ scol = a.sell.col;
-    const double2 *__restrict__ sval = a.sell.val;
-    const int8_t *__restrict__ btp = a.bt;
-    const int slice0 = a.sell.slice_off[0];
-    const bool s_shared = a.s_ld == 0;
-
-    // slot state (uniform across the workgroup)
-    int cse[C], itk[C];
-    ItemSched sc[C];
-    Rank2 r2[C];
-    bool need[C];
-#pragma unroll
-    for (int k = 0; k < C; ++k) {
-        cse[k] = -1;
-        itk[k] = 0;
-        need[k] = true;
-    }
-
-    // state arrays of case c, copy q: 0 = the caller's, 1 = scratch [6][B][ld]
-    // (fields: vm, va, m_vm, s_vm, m_va, s_va)
-    auto field = [&](int c, int q, int f) -> double * {
-        const int64_t cb = (int64_t)c * a.ld;
-        if (q == 0) {
-            if (f == 0) return a.vm + cb;
-            if (f == 1) return a.va + cb;
-            const int mom = f == 2 ? 0 : (f == 3 ? 2 : (f == 4 ? 1 : 3));  // caller order m_vm, m_va, s_vm, s_va
-            return a.st + mom * a.st_stride + cb;
-        }
-        return alt + (f == 0 ? 0 : f) * a.st_stride + cb;
-    };
-
-    // every slot marked in need[] takes the next case of the queue (or goes idle);
-    // cases it cannot run (bad grid, bad outage index) are passed over until the
-    // queue is empty
-    auto take_once = [&]() {
-        if (tid == 0) {
-#pragma unroll
-            for (int k = 0; k < C; ++k)
-                if (need[k]) take[k] = atomicAdd(a.queue, 1);
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            if (!need[k]) continue;
-            need[k] = false;
-            const int c = __builtin_amdgcn_readfirstlane(take[k]);
-            if (c >= a.B) {
-                cse[k] = -1;
-                continue;
-            }
-            cse[k] = c;
-            itk[k] = 0;
-            if (bad) {  // see DPF_BAD_GRID
-                if (tid == 0) {
-                    a.status[c] = DPF_BAD_GRID;
-                    a.iters[c] = 0;
-                }
-                need[k] = true;
-                continue;
-            }
-            r2[k] = outage_of_case(a.ov, c, 0, n);
-            if (r2[k].bad) {  // reported by the call's prologue: take the next case
-                cse[k] = -1;
-                need[k] = true;
-                continue;
-            }
-            sc[k] = load_item_sched(a, c);
-            if (a.st_fresh) {
-                for (int il = tid; il < n; il += NT) {
-                    field(c, 0, 2)[il] = 0.0;
-                    field(c, 0, 3)[il] = 0.0;
-                    field(c, 0, 4)[il] = 0.0;
-                    field(c, 0, 5)[il] = 0.0;
-                }
-            }
-        }
-        __syncthreads();
-    };
-    auto take_cases = [&]() {
-        for (;;) {
-            take_once();
-            bool again = false;
-#pragma unroll
-            for (int k = 0; k < C; ++k) again |= need[k];
-            if (!again) break;
-        }
-    };
-    take_cases();
-
-    const int nb = (n + BLK - 1) / BLK;
-    for (;;) {
-        bool any = false;
-#pragma unroll
-        for (int k = 0; k < C; ++k) any |= cse[k] >= 0;
-        if (!any) break;
-
-        double lr[C], bc1[C], bc2[C];
-        const double *rd_m[C], *rd_a[C];
-        double p1m[C], p1a[C];         // |V|, theta of block s+1 (for S1)
-        double p3[6][C];               // state of block s-3 (for S3)
-        double2 pI[3][C];              // a*I from S2 to S3
-        double lsum[C], lmax[C];
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            lr[k] = sc[k].lr;
-            bc1[k] = 1.0 - sc[k].b1t * a.b1;
-            bc2[k] = 1.0 - sc[k].b2t * a.b2;
-            const int c = cse[k] >= 0 ? cse[k] : 0;
-            const int q = itk[k] & 1;
-            rd_m[k] = field(c, q, 0);
-            rd_a[k] = field(c, q, 1);
-            p1m[k] = p1a[k] = 0.0;
-#pragma unroll
-            for (int f = 0; f < 6; ++f) p3[f][k] = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; ++d) pI[d][k] = make_double2(0.0, 0.0);
-            lsum[k] = lmax[k] = 0.0;
-            if (cse[k] >= 0 && tid < n) {
-                p1m[k] = rd_m[k][tid];
-                p1a[k] = rd_a[k][tid];
-            }
-        }
-
-        for (int s = 0; s < nb + 4; ++s) {
-            // S3: block s-4 (each slot reads its own V before S1 reuses the slot)
-            {
-                const int il = (s - 4) * BLK + tid;
-                if (s >= 4 && il < n) {
-                    const int8_t tk = btp[il];
-                    const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
-                    const int wdt = swidth[gsl];
-                    const int base = sstart[gsl] * kWave + lane;
-                    double2 h[C];
-#pragma unroll
-                    for (int k = 0; k < C; ++k) h[k] = make_double2(0.0, 0.0);
-#pragma unroll 2
-                    for (int q = 0; q < wdt; ++q) {
-                        const double2 y = sval[base + q * kWave];
-                        const int col = scol[base + q * kWave] & RM;
-#pragma unroll
-                        for (int k = 0; k < C; ++k) h[k] = cfma(y, X[8 * BLK * k + 4 * BLK + col], h[k]);
-                    }
-#pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        if (cse[k] < 0) continue;
-                        const double2 *W = X + 8 * BLK * k + 4 * BLK;
-                        const int of = r2[k].of, ot = r2[k].ot;
-                        if (il == of) h[k] = csub(h[k], csub(cmul(r2[k].oyd, W[of & RM]), cmul(r2[k].oy, W[ot & RM])));
-                        else if (il == ot) h[k] = csub(h[k], csub(cmul(r2[k].oyd, W[ot & RM]), cmul(r2[k].oy, W[of & RM])));
-                        const double2 v = X[8 * BLK * k + (il & RM)];
-                        const double2 ai = pI[2][k];
-                        const double2 G = make_double2(ai.x + h[k].x, ai.y - h[k].y);
-                        double vmi = p3[0][k], vai = p3[1][k];
-                        const int c = cse[k], qw = (itk[k] & 1) ^ 1;
-                        if (tk == kPQ) {
-                            const double g = (G.x * v.x + G.y * v.y) / vmi;
-                            double mv = p3[2][k], sv = p3[3][k];
-                            vmi = opt_update(a.opt, lr[k], a.b1, a.b2, a.eps, bc1[k], bc2[k], vmi, g, mv, sv);
-                            field(c, qw, 2)[il] = mv;
-                            field(c, qw, 3)[il] = sv;
-                        }
-                        if (tk != kSlack) {
-                            const double g = G.y * v.x - G.x * v.y;
-                            double ma = p3[4][k], sa = p3[5][k];
-                            vai = opt_update(a.opt, lr[k], a.b1, a.b2, a.eps, bc1[k], bc2[k], vai, g, ma, sa);
-                            field(c, qw, 4)[il] = ma;
-                            field(c, qw, 5)[il] = sa;
-                        }
-                        field(c, qw, 0)[il] = vmi;
-                        field(c, qw, 1)[il] = vai;
-                    }
-                }
-            }
-            // S1: block s
-            {
-                const int il = s * BLK + tid;
-                if (s < nb && il < n) {
-#pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        double sn, cs;
-                        fast_sincos(p1a[k], sn, cs);
-                        X[8 * BLK * k + (il & RM)] = make_double2(p1m[k] * cs, p1m[k] * sn);
-                    }
-                }
-            }
-            // S2: block s-2
-            {
-                const int il = (s - 2) * BLK + tid;
-                if (s >= 2 && s - 2 < nb && il < n) {
-                    const int8_t tk = btp[il];
-                    const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
-                    const int wdt = swidth[gsl];
-                    const int base = sstart[gsl] * kWave + lane;
-                    double2 I[C];
-#pragma unroll
-                    for (int k = 0; k < C; ++k) I[k] = make_double2(0.0, 0.0);
-#pragma unroll 2
-                    for (int q = 0; q < wdt; ++q) {
-                        const double2 y = sval[base + q * kWave];
-                        const int col = scol[base + q * kWave] & RM;
-#pragma unroll
-                        for (int k = 0; k < C; ++k) I[k] = cfma(y, X[8 * BLK * k + col], I[k]);
-                    }
-                    double2 sp0 = make_double2(0.0, 0.0);
-                    if (s_shared) sp0 = a.s_spec[il];
-#pragma unroll
-                    for (int k = 0; k < C; ++k) {
-                        if (cse[k] < 0) continue;
-                        const double2 *V = X + 8 * BLK * k;
-                        const int of = r2[k].of, ot = r2[k].ot;
-                        if (il == of) I[k] = csub(I[k], csub(cmul(r2[k].oyd, V[of & RM]), cmul(r2[k].oy, V[ot & RM])));
-                        else if (il == ot) I[k] = csub(I[k], csub(cmul(r2[k].oyd, V[ot & RM]), cmul(r2[k].oy, V[of & RM])));
-                        const double2 sp = s_shared ? sp0 : a.s_spec[(int64_t)cse[k] * a.s_ld + il];
-                        const double2 v = V[il & RM];
-                        const double2 d = csub(cmulc(v, I[k]), sp);
-                        const double rP = tk != kSlack ? d.x : 0.0;
-                        const double rQ = tk == kPQ ? d.y : 0.0;
-                        lsum[k] += rP * rP + rQ * rQ;
-                        lmax[k] = fmax(lmax[k], fmax(fabs(rP), fabs(rQ)));
-                        const double2 av = make_double2(two_over_m * rP, two_over_m * rQ);
-                        pI[0][k] = cmul(av, I[k]);
-                        X[8 * BLK * k + 4 * BLK + (il & RM)] = cmulc(av, v);
-                    }
-                }
-            }
-            // prefetch for the next step: |V|, theta of block s+1, state of block s-3
-            {
-                const int il1 = (s + 1) * BLK + tid;
-                const int il3 = (s - 3) * BLK + tid;
-#pragma unroll
-                for (int k = 0; k < C; ++k) {
-                    if (cse[k] < 0) continue;
-                    if (s + 1 < nb && il1 < n) {
-                        p1m[k] = rd_m[k][il1];
-                        p1a[k] = rd_a[k][il1];
-                    }
-                    if (s >= 3 && s - 3 < nb && il3 < n) {
-                        const int c = cse[k], q = itk[k] & 1;
-#pragma unroll
-                        for (int f = 0; f < 6; ++f) p3[f][k] = field(c, q, f)[il3];
-                    }
-                    pI[2][k] = pI[1][k];
-                    pI[1][k] = pI[0][k];
-                }
-            }
-            __syncthreads();
-        }
-        // per-slot loss and max|r| of the point this sweep started from
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            lsum[k] = wave_sum(lsum[k]);
-            lmax[k] = wave_max(lmax[k]);
-            if (lane == 0) {
-                red[0][k][wv] = lsum[k];
-                red[1][k][wv] = lmax[k];
-            }
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < C; ++k) {
-            double ls = 0.0, lm = 0.0;
-#pragma unroll
-            for (int w = 0; w < NT / kWave; ++w) {
-                ls += red[0][k][w];
-                lm = fmax(lm, red[1][k][w]);
-            }
-            ls = uniform(ls);
-            lm = uniform(lm);
-            if (cse[k] < 0) continue;
-            const double loss = m_res > 0.0 ? ls / m_res : 0.0;
-            const double mu = isnan(ls) ? ls : lm;
-            int stat = -1;
-            if (!(isfinite(loss) && isfinite(mu))) stat = DPF_NONFINITE;
-            else if (mu < a.tol) stat = DPF_CONVERGED;
-            else if (itk[k] >= a.max_iter) stat = DPF_MAX_ITER;
-            if (stat < 0) {  // keep the step
-                sc[k].t_step += 1.0;
-                sc[k].b1t *= a.b1;
-                sc[k].b2t *= a.b2;
-                sched_step(a, sc[k], loss);
-                itk[k] += 1;
-                continue;
-            }
-            const int c = cse[k];
-            if (itk[k] & 1) {  // the point returned sits in copy 1
-                for (int il = tid; il < n; il += NT) {
-                    const int8_t tk = btp[il];
-                    field(c, 0, 0)[il] = field(c, 1, 0)[il];
-                    field(c, 0, 1)[il] = field(c, 1, 1)[il];
-                    if (tk == kPQ) {
-                        field(c, 0, 2)[il] = field(c, 1, 2)[il];
-                        field(c, 0, 3)[il] = field(c, 1, 3)[il];
-                    }
-                    if (tk != kSlack) {
-                        field(c, 0, 4)[il] = field(c, 1, 4)[il];
-                        field(c, 0, 5)[il] = field(c, 1, 5)[il];
-                    }
-                }
-            }
-            if (tid == 0) finish_item(a, c, itk[k], stat, mu, loss, sc[k]);
-            need[k] = true;
-        }
-        bool refill = false;
-#pragma unroll
-        for (int k = 0; k < C; ++k) refill |= need[k];
-        if (refill) take_cases();
-        else __syncthreads();  // red is rewritten by the next sweep
-    }
 }
 
 // start point of every step of a time-series window: rows [0, gridDim.y) of dst

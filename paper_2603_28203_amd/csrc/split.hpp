@@ -316,7 +316,8 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
                                    __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         if (!solo) {
-            ok = team_barrier(cnt, ++nbar * T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
+            ++nbar;
+            ok = team_barrier(cnt, nbar * T, nbar == 1 ? p.first_limit : p.limit, &bar_flag);
             if (!ok) break;
         } else {
             __syncthreads();

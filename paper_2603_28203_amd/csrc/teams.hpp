@@ -341,24 +341,29 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     // at device scope, 16 bytes per access, through uniform bases; a team of one
     // uses cached accesses
     const bool solo = T == 1;
-    const uint32_t nb = (uint32_t)n * 16u;
-    auto ld2 = [&](const double2 *base, uint32_t bytes, int idx) {
-        return solo ? buf_ld2<false>(base, bytes, idx) : buf_ld2<true>(base, bytes, idx);
+    const __amdgpu_buffer_rsrc_t rV = buffer_of(Vg, (uint32_t)n * 16u);  // whole sub-grid
+    const __amdgpu_buffer_rsrc_t rW = buffer_of(Wg, (uint32_t)n * 16u);
+    const __amdgpu_buffer_rsrc_t rVx = buffer_of(Vg + xlo, (uint32_t)wn * 16u);  // the window
+    const __amdgpu_buffer_rsrc_t rWx = buffer_of(Wg + xlo, (uint32_t)wn * 16u);
+    const __amdgpu_buffer_rsrc_t rPart = buffer_of(part, (uint32_t)T * 16u);
+    auto ld2 = [solo](__amdgpu_buffer_rsrc_t r, int idx) {
+        return solo ? rsrc_ld2<false>(r, idx) : rsrc_ld2<true>(r, idx);
     };
-    auto st2 = [&](double2 *base, uint32_t bytes, int idx, double2 v) {
-        if (solo) buf_st2<false>(base, bytes, idx, v);
-        else buf_st2<true>(base, bytes, idx, v);
+    auto st2 = [solo](__amdgpu_buffer_rsrc_t r, int idx, double2 v) {
+        if (solo) rsrc_st2<false>(r, idx, v);
+        else rsrc_st2<true>(r, idx, v);
     };
-    auto in_win = [&](int col) { return (unsigned)(col - xlo) < (unsigned)wn; };
-    // exchanged value of a column: the LDS window, else the global copy g
-    auto xat = [&](int col, const double2 *g) { return in_win(col) ? X[col - xlo] : ld2(g, nb, col); };
+    // exchanged value of a column: the LDS window, else the global copy behind r
+    auto xat = [&, xlo, wn](int col, __amdgpu_buffer_rsrc_t r) {
+        return (unsigned)(col - xlo) < (unsigned)wn ? X[col - xlo] : ld2(r, col);
+    };
 
     // V of the member's rows for the team
     for (int il = rlo + tid; il < rhi; il += NT) {
         double sn, cs;
         const double vmi = vm_c[il];
         fast_sincos(va_c[il], sn, cs);
-        st2(Vg, nb, il, make_double2(vmi * cs, vmi * sn));
+        st2(rV, il, make_double2(vmi * cs, vmi * sn));
     }
     long long nbar = 0;
     bool ok = true;
@@ -368,7 +373,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     int it = 0, stat = DPF_UNFINISHED;
     double mu = 0.0, loss = 0.0;
     while (ok) {
-        for (int k = tid; k < wn; k += NT) X[k] = ld2(Vg + xlo, (uint32_t)wn * 16u, k);
+        for (int k = tid; k < wn; k += NT) X[k] = ld2(rVx, k);
         __syncthreads();
         // ---------------- A: rows of this member
         double lsum = 0.0, lmax = 0.0;
@@ -380,34 +385,34 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int base = sstart[gsl] * kWave + lane;
             double2 acc = make_double2(0.0, 0.0);
 #pragma unroll 4
-            for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], Vg), acc);
-            if (il == of) acc = csub(acc, csub(cmul(oyd, xat(of, Vg)), cmul(oy, xat(ot, Vg))));
-            else if (il == ot) acc = csub(acc, csub(cmul(oyd, xat(ot, Vg)), cmul(oy, xat(of, Vg))));
-            const double2 v = xat(il, Vg);
+            for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], rV), acc);
+            if (il == of) acc = csub(acc, csub(cmul(oyd, xat(of, rV)), cmul(oy, xat(ot, rV))));
+            else if (il == ot) acc = csub(acc, csub(cmul(oyd, xat(ot, rV)), cmul(oy, xat(of, rV))));
+            const double2 v = xat(il, rV);
             const double2 d = csub(cmulc(v, acc), sp);
             const double rP = tk != kSlack ? d.x : 0.0;
             const double rQ = tk == kPQ ? d.y : 0.0;
             lsum += rP * rP + rQ * rQ;
             lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
             Ig[il] = acc;
-            st2(Wg, nb, il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
+            st2(rW, il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
         }
         block_reduce2<NT>(lsum, lmax, red);
         __syncthreads();
         block_reduce2_finish<NT>(lsum, lmax, red);
         if (!solo) {
-            if (tid == 0) buf_st2<true>(part, (uint32_t)T * 16u, mem, make_double2(lsum, lmax));
+            if (tid == 0) rsrc_st2<true>(rPart, mem, make_double2(lsum, lmax));
             ok = unit_barrier(cnt, ++nbar * T, p.limit, false, progress, bar_flag);
             if (!ok) break;
             // team totals: the T partials reduced in the same order by every member
             // (their loads overlap the refill of X with w)
             double s = 0.0, m = 0.0;
             if (tid < T) {
-                const double2 pp = buf_ld2<true>(part, (uint32_t)T * 16u, tid);
+                const double2 pp = rsrc_ld2<true>(rPart, tid);
                 s = pp.x;
                 m = pp.y;
             }
-            for (int k = tid; k < wn; k += NT) X[k] = buf_ld2<true>(Wg + xlo, (uint32_t)wn * 16u, k);
+            for (int k = tid; k < wn; k += NT) X[k] = rsrc_ld2<true>(rWx, k);
             block_reduce2<NT>(s, m, red);
             __syncthreads();
             block_reduce2_finish<NT>(s, m, red);
@@ -444,16 +449,16 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int8_t tk = btp[il];
             const double2 I = Ig[il];
             const double2 sp = Sc[il];
-            const double2 v = ld2(Vg, nb, il);
+            const double2 v = ld2(rV, il);
             double vmi = vm_c[il], vai = va_c[il];
             const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 h = make_double2(0.0, 0.0);
 #pragma unroll 4
-            for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], Wg), h);
-            if (il == of) h = csub(h, csub(cmul(oyd, xat(of, Wg)), cmul(oy, xat(ot, Wg))));
-            else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, Wg)), cmul(oy, xat(of, Wg))));
+            for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], rW), h);
+            if (il == of) h = csub(h, csub(cmul(oyd, xat(of, rW)), cmul(oy, xat(ot, rW))));
+            else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, rW)), cmul(oy, xat(of, rW))));
             const double2 d = csub(cmulc(v, I), sp);
             const double rP = tk != kSlack ? d.x : 0.0;
             const double rQ = tk == kPQ ? d.y : 0.0;
@@ -476,7 +481,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
                 sa_c[il] = sa;
                 double sn, cs;
                 fast_sincos(vai, sn, cs);
-                st2(Vg, nb, il, make_double2(vmi * cs, vmi * sn));
+                st2(rV, il, make_double2(vmi * cs, vmi * sn));
             }
         }
         sched_step(a, sc, loss);

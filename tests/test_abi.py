@@ -94,7 +94,7 @@ def test_variant_table_and_autotune_cache(lib):
         assert lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == 0
         assert t.value % 64 == 0 and t.value <= 1024  # 0 for the multi-workgroup entry
         seen_stream |= st.value == 1
-        assert st.value in range(8)  # register, streaming, banded(-stream), wide, windowed, batched, paired
+        assert st.value in range(5)  # register, streaming, banded-stream, wide, paired
         assert lib.dpf_solve_variant_cases(i) >= 1
     assert seen_stream
     assert lib.dpf_solve_variant_info(n, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st)) == -1
@@ -105,13 +105,12 @@ def test_variant_table_and_autotune_cache(lib):
     assert lib.dpf_autotune_set(9241, d) == 0
     lib.dpf_autotune_reset()
     assert lib.dpf_solve_variant_for(14) == 0
-    # cases per workgroup: 1 except for the batched kind, whose info reports 1 bus per thread
+    # cases per workgroup: 1 for every variant
     kinds = []
     for i in range(n):
         lib.dpf_solve_variant_info(i, ctypes.byref(t), ctypes.byref(k), ctypes.byref(st))
         kinds.append((st.value, k.value, lib.dpf_solve_variant_cases(i)))
-    assert any(c > 1 for s, _, c in kinds if s == 6)
-    assert all(c == 1 for s, _, c in kinds if s != 6) and all(b == 1 for s, b, _ in kinds if s == 6)
+    assert all(c == 1 for _, _, c in kinds)
     assert lib.dpf_solve_variant_cases(n) == -1 and lib.dpf_solve_variant_cases(-1) == -1
 
 
@@ -170,7 +169,7 @@ def test_route_tail_handoff_sizes_its_own_call_only(lib):
     _ws_types(lib)
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     lib.dpf_autotune_reset()
-    band = [i for i in range(lib.dpf_solve_variant_count()) if _kind(lib, i) == 3][0]
+    band = [i for i in range(lib.dpf_solve_variant_count()) if _kind(lib, i) == 2][0]
     plain_r = _default_route(lib)
     plain_r.variant = band
     plain = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(plain_r))

@@ -975,13 +975,13 @@ def test_banded_variants_track_oracle(tuned, n_bus, group):
             assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
 
 
-@pytest.mark.parametrize("chord", [(1023, 2047), (1023, 2048)])
+@pytest.mark.parametrize("chord", [(1000, 3048), (1000, 3049)])
 def test_banded_block_boundary(tuned, chord):
-    """A chain grid with one chord at bandwidth exactly one block (1024: the
-    banded 1024-thread kernel takes it) and one more (1025: it must leave the
-    item to the general kernel, since rows of block 0 would read block 2)."""
+    """A chain grid with one chord at bandwidth exactly one block (2048: the
+    banded 1024 x 2 kernels take it) and one more (2049: they must leave the
+    item to the general kernel, since rows of a block would read two blocks on)."""
     dpf = tuned
-    n = 3000
+    n = 5000
     rng = np.random.default_rng(sum(chord))
     f = np.concatenate([np.arange(n - 1), [chord[0]]]).astype(np.int32)
     t = np.concatenate([np.arange(1, n), [chord[1]]]).astype(np.int32)
@@ -1000,7 +1000,7 @@ def test_banded_block_boundary(tuned, chord):
     ref = oracle.solve_adam(Yo, bt, S, vm0, va0, oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
     Yg = dgrid(dpf, g)
     for v in dpf.variants():
-        if not (v["kind"].startswith("banded") and v["threads"] == 1024 and v["buses_per_thread"] == 1):
+        if not (v["kind"].startswith("banded") and v["threads"] == 1024 and v["buses_per_thread"] == 2):
             continue
         dpf.lib().dpf_autotune_set(n, v["index"])
         vm = cu(vm0[None]); va = cu(va0[None])
@@ -1027,7 +1027,7 @@ def test_banded_and_general_sub_grids_in_one_call(tuned):
     vm0 = np.concatenate([gg.vm for gg in grids]) + rng.normal(0, 1e-2, off[-1]) * (bt == 0)
     va0 = np.concatenate([gg.va for gg in grids]) + rng.normal(0, 1e-2, off[-1]) * (bt != 2)
     Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
-    band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
+    band = [v["index"] for v in dpf.variants() if v["kind"] == "banded-stream" and v["threads"] == 1024][0]
     dpf.lib().dpf_autotune_set(2600, band)
     steps = 8
     vm = cu(vm0[None]); va = cu(va0[None])
@@ -1046,7 +1046,7 @@ def test_banded_and_general_sub_grids_in_one_call(tuned):
 # ---------------------------------------------------------------- SGD and RMSprop
 
 
-@pytest.mark.parametrize("path", ["register", "streaming", "banded", "teams", "wide"])
+@pytest.mark.parametrize("path", ["register", "streaming", "banded-stream", "teams", "wide"])
 @pytest.mark.parametrize("kind", ["sgd", "rmsprop"])
 def test_other_optimizers_track_oracle(tuned, path, kind):
     """SGD (with momentum) and RMSprop, the paper's alternatives to Adam, on
@@ -1054,7 +1054,7 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
     dpf = tuned
     n = 300 if path == "register" else 3000
     g = synth.config1(B=1, seed=9100 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
-    if path == "banded":
+    if path == "banded-stream":
         g = renumber(g, dpf.rcm_order(g.n_bus, g.f, g.t)[0])
     Yo = oracle.ybus_of(g)
     S = oracle.injections(Yo, g.vm, g.va)
@@ -1068,8 +1068,8 @@ def test_other_optimizers_track_oracle(tuned, path, kind):
         o = dict(lr=1e-3, beta2=0.99, eps=1e-8, optimizer=dpf.OPT_RMSPROP)
     ref = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(tol=0.0, max_iter=steps, **o))
     Yg = dgrid(dpf, g)
-    if path == "banded":
-        band = [v["index"] for v in dpf.variants() if v["kind"] == "banded" and v["threads"] == 1024][0]
+    if path == "banded-stream":
+        band = [v["index"] for v in dpf.variants() if v["kind"] == "banded-stream" and v["threads"] == 1024][0]
         dpf.lib().dpf_autotune_set(n, band)
     rt = {"teams": dpf.Route(team_cap=1000), "wide": dpf.Route(team_cap=1000, wide_host=1)}.get(path)
     print(f"optimizer {kind} on the {path} path, n={n}", flush=True)
@@ -1192,8 +1192,7 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     assert torch.equal(vmR, vm) and torch.equal(vaR, va)
 
 
-@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "teams", "wide",
-                                  "batched"])
+@pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "teams", "wide"])
 def test_bad_outage_index_is_reported(dpf, path):
     """An outage index that is neither -1 nor a branch index (n_branch, -2) gives
     status DPF_BAD_OUTAGE with no update, NaN max|dS| and loss, on every solve
@@ -1222,9 +1221,6 @@ def test_bad_outage_index_is_reported(dpf, path):
         rt.tail_team = 8  # few large cases: the split kernel from the first iteration
     elif path in ("teams", "wide"):
         rt.team_cap, rt.wide_host = 1000, int(path == "wide")
-    elif path == "batched":
-        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-batched" and x["cases"] == 2
-                      and x["threads"] == 256][0]["index"]
     print(f"bad outage indices on the {path} path, n={n}", flush=True)
     vm = cu(vm0); va = cu(va0)
     out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32), route=rt,
@@ -1453,356 +1449,6 @@ def test_solve_at_the_lds_limit(tuned, extra):
     assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-10
 
 
-# ---------------------------------------------------------------- windowed banded kernel
-
-
-def window_variants(dpf, blk=None):
-    return [v for v in dpf.variants() if v["kind"] == "banded-window"
-            and (blk is None or v["threads"] * v["buses_per_thread"] == blk)]
-
-
-@pytest.mark.parametrize("n_bus", [14, 100, 257, 700, 3000])
-def test_window_variants_track_oracle(tuned, n_bus):
-    """The windowed kernel on sub-grids of one to a dozen blocks (ragged last
-    block included), with N-1 outages and a plateau schedule that lowers the
-    learning rate inside the run: iterates, max|dS| and the schedule state equal
-    the oracle's."""
-    dpf = tuned
-    if n_bus == 14:
-        base = synth.config0(3)["grid"]
-    else:
-        base = synth.config1(B=1, seed=9300 + n_bus, n_bus=n_bus, n_branch=int(1.6 * n_bus),
-                             n_pv=max(1, n_bus // 6))["grid"]
-    perm, bw = dpf.rcm_order(base.n_bus, base.f, base.t)
-    g = renumber(base, perm)
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    nb = synth.non_bridge_branches(g.n_bus, g.f, g.t)
-    outage = np.array([-1] + sorted(np.random.default_rng(2).choice(nb, 2, replace=False).tolist()), np.int32)
-    B = 3
-    rng = np.random.default_rng(n_bus + 1)
-    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
-    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
-    steps = 9
-    pl = dict(sched=oracle.SCHED_PLATEAU, factor=0.5, patience=1, threshold=0.5, cooldown=1)
-    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S, vm0[c], va0[c],
-                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps, **pl)) for c in range(B)]
-    assert min(r["lr"] for r in refs) < 1e-3  # the schedule acted
-    Yg = dgrid(dpf, g)
-    vs = window_variants(dpf)
-    assert vs
-    for v in vs:
-        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-        print(f"window parity n={g.n_bus} bw={bw} variant={v}", flush=True)
-        vm = cu(vm0); va = cu(va0)
-        sch = torch.tensor([[0.0, 1e-3, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
-        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
-                        sched_state=sch, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps, **pl))
-        torch.cuda.synchronize()
-        assert out["iters"].tolist() == [steps] * B and out["status"].tolist() == [1] * B
-        for c in range(B):
-            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, v
-            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-11, v
-            assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
-            assert sch[c, 1].item() == pytest.approx(refs[c]["lr"], rel=1e-15)
-
-
-@pytest.mark.parametrize("far", [256, 257])
-def test_window_block_boundary(tuned, far):
-    """A chain with one chord of bandwidth exactly one 256-bus block (the
-    windowed kernel takes it) or one more (rows would read two blocks ahead: the
-    general kernel must take the item); both equal the oracle."""
-    dpf = tuned
-    n = 700
-    rng = np.random.default_rng(far)
-    f = np.concatenate([np.arange(n - 1), [300]]).astype(np.int32)
-    t = np.concatenate([np.arange(1, n), [300 + far]]).astype(np.int32)
-    m = len(f)
-    bt = np.zeros(n, dtype=np.int8)
-    bt[0] = 2
-    bt[rng.choice(np.arange(1, n), n // 6, replace=False)] = 1
-    g = synth.Grid(n_bus=n, f=f, t=t, r=rng.uniform(0.01, 0.1, m), x=rng.uniform(0.05, 0.3, m),
-                   b=rng.uniform(0, 0.05, m), bus_type=bt, vm=rng.uniform(0.98, 1.02, n),
-                   va=np.concatenate([[0.0], rng.uniform(-0.05, 0.05, n - 1)]))
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    vm0 = g.vm + rng.normal(0, 1e-2, n) * (bt == 0)
-    va0 = g.va + rng.normal(0, 1e-2, n) * (bt != 2)
-    steps = 8
-    outage = np.array([m - 1], np.int32)  # the chord itself (the chain stays connected)
-    ref = oracle.solve_adam(oracle.ybus_of(g, skip=m - 1), bt, S, vm0, va0,
-                            oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
-    Yg = dgrid(dpf, g)
-    for v in window_variants(dpf, blk=256):
-        dpf.lib().dpf_autotune_set(n, v["index"])
-        vm = cu(vm0[None]); va = cu(va0[None])
-        dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
-                  opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
-        torch.cuda.synchronize()
-        assert np.abs(vm[0].cpu().numpy() - ref["vm"]).max() < 1e-11, v
-        assert np.abs(va[0].cpu().numpy() - ref["va"]).max() < 1e-11, v
-
-
-def test_window_resume_and_convergence(tuned):
-    """Two half-length calls with the moments and schedule passed through equal
-    one call (bit for bit), and a solve to tolerance from the flat start ends
-    on the planted solution at about the oracle's iteration count."""
-    dpf = tuned
-    g = synth.config0(2)["grid"]
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    Yg = dgrid(dpf, g)
-    Sd = cu(S, torch.complex128)
-    vm0, va0 = synth.flat_start(g)
-    v = window_variants(dpf, blk=128)[0]
-    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-    opts = dpf.Options(tol=0.0, max_iter=120, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05,
-                       cooldown=3)
-    vmA = cu(vm0[None]); vaA = cu(va0[None])
-    dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=opts)
-    vmB = cu(vm0[None]); vaB = cu(va0[None])
-    st = torch.zeros((4, 1, g.n_bus), dtype=torch.float64, device="cuda")
-    sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]], dtype=torch.float64, device="cuda")
-    half = dpf.Options(**{**opts.__dict__, "max_iter": 60})
-    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
-    dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
-    torch.cuda.synchronize()
-    assert torch.equal(vmA, vmB) and torch.equal(vaA, vaB)
-    assert sch[0, 0].item() == 120
-    # to tolerance
-    g = synth.config0(0)["grid"]
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    vm0, va0 = synth.flat_start(g)
-    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0, va0, oracle.AdamOptions(max_iter=20000))
-    vm = cu(vm0[None]); va = cu(va0[None])
-    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(max_iter=20000))
-    torch.cuda.synchronize()
-    assert out["status"].item() == ref["status"] == 0
-    assert abs(out["iters"].item() - ref["iters"]) <= max(3, ref["iters"] // 20)
-    assert out["max_mis"].item() < 1e-6
-    assert np.abs(vm[0].cpu().numpy() - g.vm).max() < 1e-5
-
-
-def test_window_edge_cases(tuned):
-    """max_iter = 0 (only the start point is measured), a start that is already
-    a solution, a NaN injection, and a lone slack bus, on the windowed kernel."""
-    dpf = tuned
-    g = synth.config0(0)["grid"]
-    Yo = oracle.ybus_of(g)
-    S = oracle.injections(Yo, g.vm, g.va)
-    v = window_variants(dpf, blk=256)[0]
-    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-    vm0, va0 = synth.flat_start(g)
-    B = 3
-    Sb = np.tile(S, (B, 1))
-    Sb[1, 4] = np.nan
-    vm = cu(np.tile(vm0, (B, 1))); va = cu(np.tile(va0, (B, 1)))
-    vm[2] = cu(g.vm); va[2] = cu(g.va)  # case 2 starts at the solution
-    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(Sb, torch.complex128), vm, va, opts=dpf.Options(max_iter=7))
-    torch.cuda.synchronize()
-    assert out["status"].tolist() == [1, 2, 0] and out["iters"].tolist() == [7, 0, 0]
-    ref0 = oracle.solve_adam(Yo, g.bus_type, S, vm0, va0, oracle.AdamOptions(tol=0.0, max_iter=0))
-    vm = cu(vm0[None]); va = cu(va0[None])
-    out = dpf.solve(dgrid(dpf, g), g.bus_type, cu(S, torch.complex128), vm, va,
-                    opts=dpf.Options(tol=0.0, max_iter=0))
-    torch.cuda.synchronize()
-    assert out["iters"].item() == 0 and out["status"].item() == 1
-    assert abs(out["max_mis"].item() - ref0["mu"]) <= 1e-12 * ref0["mu"]
-    assert torch.equal(vm, cu(vm0[None])) and torch.equal(va, cu(va0[None]))
-    one = synth.Grid(n_bus=1, f=np.zeros(0, np.int32), t=np.zeros(0, np.int32), r=np.zeros(0), x=np.zeros(0),
-                     b=np.zeros(0), bus_type=np.array([2], np.int8), vm=np.ones(1), va=np.zeros(1))
-    dpf.lib().dpf_autotune_set(1, v["index"])
-    vm = cu(np.ones((2, 1))); va = cu(np.zeros((2, 1)))
-    out = dpf.solve(dgrid(dpf, one), one.bus_type, cu(np.zeros(1), torch.complex128), vm, va,
-                    opts=dpf.Options(max_iter=50))
-    torch.cuda.synchronize()
-    assert out["status"].tolist() == [0, 0] and out["iters"].tolist() == [0, 0]
-
-
-# ---------------------------------------------------------------- batched windowed kernel
-
-
-def batched_variants(dpf):
-    return [v for v in dpf.variants() if v["kind"] == "banded-batched"]
-
-
-@pytest.mark.parametrize("shared_s", [True, False])
-def test_batched_variants_track_oracle(tuned, shared_s):
-    """Several cases per workgroup with cases taken from a queue: 9 cases with
-    N-1 outages, two non-finite injections and one start at the solution (all
-    three stop at once and their slots take new cases), shared or per-case
-    S_spec; every case equals its own oracle solve."""
-    dpf = tuned
-    base = synth.config1(B=1, seed=9500, n_bus=700, n_branch=1120, n_pv=110)["grid"]
-    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
-    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    B = 9
-    rng = np.random.default_rng(95)
-    S = np.tile(S0, (B, 1))
-    if not shared_s:
-        S = S * rng.uniform(0.97, 1.03, (B, 1))
-    S[1, 5] = np.nan
-    S[6, 9] = np.nan
-    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
-    outage = np.where(np.arange(B) % 3 == 0, -1, rng.choice(nbr, B)).astype(np.int32)
-    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
-    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
-    vm0[4], va0[4] = g.vm, g.va  # case 4 starts at the solution of the base case
-    outage[4] = -1
-    if not shared_s:
-        S[4] = S0
-    steps = 9
-    tol = 1e-9
-    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
-                              oracle.AdamOptions(lr=1e-3, tol=tol, max_iter=steps)) for c in range(B)]
-    assert [r["status"] for r in refs] == [1, 2, 1, 1, 0, 1, 2, 1, 1]
-    Yg = dgrid(dpf, g)
-    Sd = cu(S, torch.complex128)
-    vs = batched_variants(dpf)
-    assert vs
-    for v in vs:
-        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-        print(f"batched parity variant={v} shared={shared_s}", flush=True)
-        vm = cu(vm0); va = cu(va0)
-        out = dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=cu(outage, torch.int32),
-                        opts=dpf.Options(lr=1e-3, tol=tol, max_iter=steps))
-        torch.cuda.synchronize()
-        assert out["status"].tolist() == [r["status"] for r in refs], v
-        assert out["iters"].tolist() == [r["iters"] for r in refs], v
-        for c in range(B):
-            if refs[c]["status"] == 2:
-                continue
-            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, (v, c)
-            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-11, (v, c)
-            if refs[c]["status"] == 0:
-                assert out["max_mis"][c].item() < tol
-            else:
-                assert abs(out["max_mis"][c].item() - refs[c]["mu"]) <= 1e-9 * refs[c]["mu"]
-
-
-def test_batched_shared_spec_row(tuned):
-    """A single S_spec row shared by every case (leading dimension 0) gives the
-    per-case results of the same row repeated."""
-    dpf = tuned
-    base = synth.config1(B=1, seed=9501, n_bus=600, n_branch=960, n_pv=100)["grid"]
-    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    B = 5
-    rng = np.random.default_rng(96)
-    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
-    outage = rng.choice(nbr, B).astype(np.int32)
-    vm0 = np.tile(g.vm, (B, 1)); va0 = np.tile(g.va, (B, 1))
-    Yg = dgrid(dpf, g)
-    steps = 12
-    res = {}
-    for v in [dpf.variant_for(g.n_bus)] + [x["index"] for x in batched_variants(dpf)]:
-        dpf.lib().dpf_autotune_set(g.n_bus, v)
-        for rows in ("shared", "tiled"):
-            Sd = cu(S, torch.complex128) if rows == "shared" else cu(np.tile(S, (B, 1)), torch.complex128)
-            vm = cu(vm0); va = cu(va0)
-            dpf.solve(Yg, g.bus_type, Sd, vm, va, outage=cu(outage, torch.int32),
-                      opts=dpf.Options(lr=1e-4, eps=1e-14, tol=0.0, max_iter=steps))
-            torch.cuda.synchronize()
-            res[(v, rows)] = (vm.cpu().numpy(), va.cpu().numpy())
-        assert np.array_equal(res[(v, "shared")][0], res[(v, "tiled")][0])
-        assert np.array_equal(res[(v, "shared")][1], res[(v, "tiled")][1])
-        assert np.abs(res[(v, "shared")][1] - va0).max() > 0  # the iterates moved
-
-
-def test_batched_resume_convergence_and_bad_grid(tuned):
-    """Two half-length calls (moments and schedule passed through) equal one
-    call bit for bit; solves to tolerance from the flat start end on the planted
-    solution near the oracle's iteration count; a bad grid marks every case."""
-    dpf = tuned
-    g = synth.config0(0)["grid"]
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    Yg = dgrid(dpf, g)
-    Sd = cu(S, torch.complex128)
-    vm0, va0 = synth.flat_start(g)
-    B = 5
-    rng = np.random.default_rng(97)
-    vmB0 = np.tile(vm0, (B, 1)) + rng.normal(0, 1e-3, (B, g.n_bus)) * (g.bus_type == 0)
-    vaB0 = np.tile(va0, (B, 1)) + rng.normal(0, 1e-3, (B, g.n_bus)) * (g.bus_type != 2)
-    opts = dpf.Options(tol=0.0, max_iter=120, sched=dpf.SCHED_PLATEAU, factor=0.5, patience=5, threshold=0.05,
-                       cooldown=3)
-    half = dpf.Options(**{**opts.__dict__, "max_iter": 60})
-    for v in batched_variants(dpf):
-        dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-        vmA = cu(vmB0); vaA = cu(vaB0)
-        dpf.solve(Yg, g.bus_type, Sd, vmA, vaA, opts=opts)
-        vmB = cu(vmB0); vaB = cu(vaB0)
-        st = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
-        sch = torch.tensor([[0.0, opts.lr, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
-        dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
-        dpf.solve(Yg, g.bus_type, Sd, vmB, vaB, opts=half, adam_state=st, sched_state=sch)
-        torch.cuda.synchronize()
-        assert torch.equal(vmA, vmB) and torch.equal(vaA, vaB), v
-        assert sch[:, 0].tolist() == [120.0] * B
-    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0, va0, oracle.AdamOptions(max_iter=20000))
-    v = batched_variants(dpf)[0]
-    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
-    vm = cu(np.tile(vm0, (3, 1))); va = cu(np.tile(va0, (3, 1)))
-    out = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=dpf.Options(max_iter=20000))
-    torch.cuda.synchronize()
-    assert out["status"].tolist() == [0, 0, 0] and ref["status"] == 0
-    assert len(set(out["iters"].tolist())) == 1
-    assert abs(out["iters"][0].item() - ref["iters"]) <= max(3, ref["iters"] // 20)
-    assert np.abs(vm.cpu().numpy() - g.vm[None]).max() < 1e-5
-    Yb = dgrid(dpf, g)
-    Yb.max_row_nnz = 2
-    Yb._c = None
-    vm = cu(np.tile(vm0, (B, 1))); va = cu(np.tile(va0, (B, 1)))
-    out = dpf.solve(Yb, g.bus_type, Sd, vm, va, opts=dpf.Options(max_iter=5))
-    torch.cuda.synchronize()
-    assert out["status"].tolist() == [dpf.BAD_GRID] * B and out["iters"].tolist() == [0] * B
-    assert np.array_equal(vm.cpu().numpy(), np.tile(vm0, (B, 1)))
-
-
-def test_batched_falls_back_for_sub_grids_and_wide_band(tuned):
-    """The batched kernel only takes single-grid calls of small bandwidth: a
-    call with sub-grids, and a grid whose bandwidth exceeds the block, still
-    equal the oracle (the general kernel takes them)."""
-    dpf = tuned
-    n = 700
-    rng = np.random.default_rng(98)
-    f = np.concatenate([np.arange(n - 1), [50]]).astype(np.int32)
-    t = np.concatenate([np.arange(1, n), [650]]).astype(np.int32)  # bandwidth 600 > 512
-    m = len(f)
-    bt = np.zeros(n, dtype=np.int8)
-    bt[0] = 2
-    bt[rng.choice(np.arange(1, n), n // 6, replace=False)] = 1
-    g = synth.Grid(n_bus=n, f=f, t=t, r=rng.uniform(0.01, 0.1, m), x=rng.uniform(0.05, 0.3, m),
-                   b=rng.uniform(0, 0.05, m), bus_type=bt, vm=rng.uniform(0.98, 1.02, n),
-                   va=np.concatenate([[0.0], rng.uniform(-0.05, 0.05, n - 1)]))
-    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
-    B = 3
-    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (bt == 0)
-    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (bt != 2)
-    steps = 6
-    refs = [oracle.solve_adam(oracle.ybus_of(g), bt, S, vm0[c], va0[c],
-                              oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
-    Yg = dgrid(dpf, g)
-    for v in batched_variants(dpf):
-        dpf.lib().dpf_autotune_set(n, v["index"])
-        vm = cu(vm0); va = cu(va0)
-        dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
-        torch.cuda.synchronize()
-        for c in range(B):
-            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-11, v
-    # two sub-grids in one call (each the chain grid): the default kernel takes the call
-    off = [0, n, 2 * n]
-    g2 = (np.concatenate([f, f + n]), np.concatenate([t, t + n]))
-    Y2 = dpf.build_ybus(2 * n, g2[0], g2[1], np.tile(g.r, 2), np.tile(g.x, 2), np.tile(g.b, 2))
-    bt2 = np.tile(bt, 2)
-    S2 = np.tile(S, 2)
-    for v in batched_variants(dpf):
-        dpf.lib().dpf_autotune_set(n, v["index"])
-        vm = cu(np.tile(vm0[:1], (1, 2))); va = cu(np.tile(va0[:1], (1, 2)))
-        out = dpf.solve(Y2, bt2, cu(S2[None], torch.complex128), vm, va, sub_offset=off,
-                        opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
-        torch.cuda.synchronize()
-        assert out["iters"].tolist() == [steps, steps]
-        assert np.abs(vm[0, :n].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
-        assert np.abs(vm[0, n:].cpu().numpy() - refs[0]["vm"]).max() < 1e-11
-
-
 # ---------------------------------------------------------------- tail handoff
 
 
@@ -1820,7 +1466,7 @@ def split_ran(dpf, before):
     return after["launches"] > before["launches"] and after["abandoned"] == before["abandoned"]
 
 
-@pytest.mark.parametrize("kind", ["banded-stream", "banded-pair", "banded", "streaming", "banded-window"])
+@pytest.mark.parametrize("kind", ["banded-stream", "banded-pair", "streaming"])
 @pytest.mark.parametrize("threshold", [5, 64])
 @pytest.mark.parametrize("team", [0, 8])
 def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, threshold, team):
@@ -2412,8 +2058,8 @@ def test_split_kernel_abandoned_barriers_fall_back(handoff):
 def test_random_grids_on_default_and_banded_paths(tuned, seed):
     """Seeded random grids (20 to 2500 buses, branch ratio 1.3 to 1.9, 5% to 40%
     PV buses), 1 to 5 cases with random outages and per-case S_spec: the default
-    routing and one randomly drawn banded, windowed or batched variant (on the
-    small-bandwidth numbering) both follow the oracle for a few steps."""
+    routing and one randomly drawn banded variant (on the small-bandwidth
+    numbering) both follow the oracle for a few steps."""
     dpf = tuned
     rng = np.random.default_rng(31000 + seed)
     n = int(rng.integers(20, 2500))
@@ -2433,8 +2079,7 @@ def test_random_grids_on_default_and_banded_paths(tuned, seed):
     refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
                               oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)) for c in range(B)]
     Yg = dgrid(dpf, g)
-    banded = [v for v in dpf.variants() if v["kind"] in ("banded", "banded-stream", "banded-pair", "banded-window",
-                                                          "banded-batched")]
+    banded = [v for v in dpf.variants() if v["kind"] in ("banded-stream", "banded-pair")]
     pick = banded[int(rng.integers(len(banded)))]
     for choice in (None, pick):
         dpf.autotune_reset()
