@@ -608,11 +608,12 @@ def cfg3_series(cap, tail_team):
     out = {"workload": f"96-step time series on the 9241-bus grid, cap {cap} iterations per step",
            "iter_cap": cap}
     # few large items of one grid: the split kernel from the first iteration (the
-    # bench's tail settings, when on), and the multi-workgroup path (split kernel off).
+    # bench's tail settings, when on), and the default routing with the split kernel
+    # off (persistent teams: one launch per window, nothing waits on the host).
     # The autotune choices of the N-1 batch are dropped first: a stored choice for a
     # few items (the 32-case probe) would override the default routing of the windows
     dpf.autotune_reset()
-    runs = [("sequential_multi_workgroup", 1, False), ("windows_of_16_multi_workgroup", 16, False)]
+    runs = [("sequential_teams", 1, False), ("windows_of_16_teams", 16, False)]
     if tail_team[0] > 0:
         runs = [("sequential", 1, True), ("windows_of_16", 16, True)] + runs
     for name, window, split in runs:

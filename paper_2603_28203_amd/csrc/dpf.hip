@@ -639,7 +639,7 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
 }
 
 // Bytes of static LDS the persistent team kernel uses besides its window.
-constexpr int kTeamStaticLds = 2 * (dpf::kTeamThreads / dpf::kWave) * 8 + 64;
+constexpr int kTeamStaticLds = 2 * (dpf::kTeamThreads / dpf::kWave) * 8 + (dpf::kTeamThreads / dpf::kWave) * 4 + 64;
 
 // Persistent teams (teams.hpp): every item of the call in one launch on `st`, with
 // a device-side plan; nothing waits on the host, so the call can be captured.
@@ -647,8 +647,12 @@ int run_teams(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, int32_t 
               const DeviceInfo &dev, const dpf_route_t &route, hipStream_t st) {
     dpf::SolveArgs a = a0;
     a.handoff = 0;
-    const int lds = (dev.lds_per_block - kTeamStaticLds) / 16 * 16;
-    if (lds < 16 * dpf::kWave) return fail(DPF_EUNSUPPORTED, "too little LDS for the team kernel");
+    // the window (16 B per column) and the 16-bit halo list behind it
+    const int64_t avail = (int64_t)dev.lds_per_block - kTeamStaticLds - 2 * dpf::kTeamHaloCap;
+    int32_t win = (int32_t)std::min<int64_t>(std::max<int64_t>(avail, 0) / 16, 65536);  // 16-bit offsets
+    if (route.team_cap > 0) win = std::min(win, std::max<int32_t>(dpf::kWave, route.team_cap));
+    if (win < dpf::kWave) return fail(DPF_EUNSUPPORTED, "too little LDS for the team kernel");
+    const int lds = win * 16 + 2 * dpf::kTeamHaloCap;
     void (*fn)(dpf::SolveArgs, dpf::TeamArgs) = dpf::team_solve_persist_kernel<dpf::kTeamThreads>;
     DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, lds));
     int per_cu = 0;
@@ -666,8 +670,7 @@ int run_teams(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, int32_t 
     p.Wg = a.scratch + 2 * a.st_stride;
     p.first_limit = (int64_t)(route.tail_first_wait_s * 1e9 / dev.ns_per_tick);
     p.limit = (int64_t)(route.tail_wait_s * 1e9 / dev.ns_per_tick);
-    p.win = lds / 16;  // a route's team cap also caps the window (members then hold fewer buses)
-    if (route.team_cap > 0) p.win = std::min(p.win, std::max<int32_t>(dpf::kWave, route.team_cap));
+    p.win = win;  // a route's team cap also caps the window (members then hold fewer buses)
     p.grid = grid;
     p.tmax = std::max(1, std::min(dpf::kTeamMaxMembers, grid / 2));
     if (a.st_fresh) {

@@ -11,8 +11,8 @@
 // one unit at a time has members waiting for the rest of its team; every other
 // unit either runs complete or has not started, and the units that run finish and
 // free their workgroups for the waiting team.  A team of T members therefore
-// always assembles when T workgroups fit on the device (T is capped at half of
-// the launch).
+// always assembles when T workgroups fit on the device (T is capped at 32 and at
+// half of the launch).
 //
 // A member owns rows [rlo, rhi) of its sub-grid (whole 64-row slices) and keeps in
 // LDS a window of the exchanged vector: its rows plus the sub-grid's bandwidth on
@@ -60,16 +60,20 @@
 
 namespace dpf {
 
-// 1024 threads (16 waves, one workgroup per CU): 27 VGPRs spill at the 128-register
+// 1024 threads (16 waves, one workgroup per CU): ~30 VGPRs spill at the 128-register
 // limit, yet an iteration runs 1.2-1.5x faster than at 512 threads without spills
-// (measured on 64 cases of 9241 buses, 256 cases of 3000 and the uneven batch)
+// (measured on 64 cases of 9241 buses, 256 cases of 3000 and the uneven batch).
+// The gathers unroll by 2 (by 4: 44 spilled registers and 5-10% slower).
 constexpr int kTeamThreads = 1024;
 constexpr int kPlanThreads = 256;
-constexpr int kTeamMaxMembers = 128;
+// members per team at most: one 9241-bus case takes 14 us per iteration on 32
+// members, 19 us on 128 (more arrivals per barrier, more halo per row)
+constexpr int kTeamMaxMembers = 32;
 constexpr int kLoadKeys = 32;      // half-octave buckets of the per-member load
 constexpr int kTeamMaxWaves = 8;
 constexpr int kTeamRowsPerBarrier = 512;  // the plan's price of a barrier pair, in rows
 constexpr int kTeamBarStride = 32;        // one 64-bit counter per 256 bytes
+constexpr int kTeamHaloCap = 2048;        // halo columns a member's refill list holds
 constexpr long long kTeamAbort = 1LL << 62;
 
 struct TeamArgs {
@@ -81,7 +85,8 @@ struct TeamArgs {
     double2 *Ig, *Vg, *Wg; // [B][ld] I of the A sweep, V, exchanged w
     int64_t first_limit;   // wall-clock ticks a unit's first barrier waits without progress
     int64_t limit;         // ... and every later barrier
-    int32_t win;           // complex entries of the LDS window
+    int32_t win;           // complex entries of the LDS window (followed in LDS by the
+                           // 16-bit halo list, kTeamHaloCap entries)
     int32_t grid;          // workgroups of the launch
     int32_t tmax;          // members per team at most
 };
@@ -280,7 +285,8 @@ __device__ __forceinline__ bool unit_barrier(long long *cnt, long long target, i
 // member `mem` of the T members of unit u
 template <int NT>
 __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &p, int u, int mem, int T,
-                                            double2 *__restrict__ X, double (*red)[NT / kWave], int *bar_flag) {
+                                            double2 *__restrict__ X, double (*red)[NT / kWave], int *bar_flag,
+                                            int *scan_part) {
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
     const int item = p.unit_item[u];
@@ -358,6 +364,73 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         return (unsigned)(col - xlo) < (unsigned)wn ? X[col - xlo] : ld2(r, col);
     };
 
+    // The member's own rows and the halo columns of the window they read (their
+    // neighbours outside [rlo, rhi), the two buses of the outage): the refills load
+    // the rows as a range and the halo columns from a 16-bit list of window offsets
+    // behind X (at most kTeamHaloCap; a longer halo refills the whole window).  A
+    // window is wider than what the member reads whenever the bandwidth exceeds
+    // the halo its rows actually touch.  The bitmap that builds the list lives in
+    // X, which is filled only after it has been read.
+    uint32_t *need = reinterpret_cast<uint32_t *>(X);
+    uint16_t *hlist = reinterpret_cast<uint16_t *>(X + p.win);
+    const int nwords = (wn + 31) / 32;
+    for (int k = tid; k < nwords; k += NT) need[k] = 0u;
+    __syncthreads();
+    auto mark = [&](int col) {
+        const int x = col - xlo;
+        if ((unsigned)x < (unsigned)wn && (col < rlo || col >= rhi)) atomicOr(need + (x >> 5), 1u << (x & 31));
+    };
+    for (int il = rlo + tid; il < rhi; il += NT) {
+        const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
+        const int wdt = swidth[gsl];
+        const int base = sstart[gsl] * kWave + lane;
+        for (int q = 0; q < wdt; ++q) mark(scol[base + q * kWave]);
+    }
+    if (of >= 0 && tid < 2) mark(tid == 0 ? of : ot);
+    __syncthreads();
+    int n_halo = 0;  // -1: more than the list holds
+    {
+        const int per = (nwords + NT - 1) / NT;  // contiguous words per thread
+        const int w0 = min(tid * per, nwords), w1 = min(w0 + per, nwords);
+        int cnt_b = 0;
+        for (int w = w0; w < w1; ++w) cnt_b += __popc(need[w]);
+        int incl = cnt_b;  // inclusive scan over the wave, then over the waves
+#pragma unroll
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(incl, o, kWave);
+            if (lane >= o) incl += y;
+        }
+        if (lane == kWave - 1) scan_part[tid / kWave] = incl;
+        __syncthreads();
+        int before = 0;
+        for (int k = 0; k < NT / kWave; ++k) {
+            before += k < tid / kWave ? scan_part[k] : 0;
+            n_halo += scan_part[k];
+        }
+        if (n_halo <= kTeamHaloCap) {
+            int pos = before + incl - cnt_b;
+            for (int w = w0; w < w1; ++w)
+                for (uint32_t bits = need[w]; bits != 0u; bits &= bits - 1u)
+                    hlist[pos++] = (uint16_t)(w * 32 + __ffs(bits) - 1);
+        } else {
+            n_halo = -1;
+        }
+        __syncthreads();
+    }
+    const int own0 = rlo - xlo, own1 = min(rhi, xlo + wn) - xlo;  // own rows inside the window
+    // X <- the columns the rows read, through resource r (window offsets)
+    auto fill = [&](auto &&load) {
+        if (n_halo < 0) {
+            for (int k = tid; k < wn; k += NT) X[k] = load(k);
+            return;
+        }
+        for (int k = own0 + tid; k < own1; k += NT) X[k] = load(k);
+        for (int k = tid; k < n_halo; k += NT) {
+            const int x = hlist[k];
+            X[x] = load(x);
+        }
+    };
+
     // V of the member's rows for the team
     for (int il = rlo + tid; il < rhi; il += NT) {
         double sn, cs;
@@ -373,7 +446,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     int it = 0, stat = DPF_UNFINISHED;
     double mu = 0.0, loss = 0.0;
     while (ok) {
-        for (int k = tid; k < wn; k += NT) X[k] = ld2(rVx, k);
+        fill([&](int x) { return ld2(rVx, x); });
         __syncthreads();
         // ---------------- A: rows of this member
         double lsum = 0.0, lmax = 0.0;
@@ -384,7 +457,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
+#pragma unroll 2
             for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], rV), acc);
             if (il == of) acc = csub(acc, csub(cmul(oyd, xat(of, rV)), cmul(oy, xat(ot, rV))));
             else if (il == ot) acc = csub(acc, csub(cmul(oyd, xat(ot, rV)), cmul(oy, xat(of, rV))));
@@ -412,7 +485,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
                 s = pp.x;
                 m = pp.y;
             }
-            for (int k = tid; k < wn; k += NT) X[k] = rsrc_ld2<true>(rWx, k);
+            fill([&](int x) { return rsrc_ld2<true>(rWx, x); });
             block_reduce2<NT>(s, m, red);
             __syncthreads();
             block_reduce2_finish<NT>(s, m, red);
@@ -421,7 +494,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             lmax = m;
         } else {
             __syncthreads();
-            for (int k = tid; k < wn; k += NT) X[k] = Wg[xlo + k];
+            fill([&](int x) { return Wg[xlo + x]; });
             __syncthreads();
         }
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
@@ -455,7 +528,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 h = make_double2(0.0, 0.0);
-#pragma unroll 4
+#pragma unroll 2
             for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], rW), h);
             if (il == of) h = csub(h, csub(cmul(oyd, xat(of, rW)), cmul(oy, xat(ot, rW))));
             else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, rW)), cmul(oy, xat(of, rW))));
@@ -505,6 +578,7 @@ __global__ __launch_bounds__(NT) void team_solve_persist_kernel(SolveArgs a, Tea
     __shared__ double red[2][NT / kWave];
     __shared__ int bar_flag;
     __shared__ int sh_t, sh_u;
+    __shared__ int scan_part[NT / kWave];
     const int tid = threadIdx.x;
     const int n_tickets = p.hdr[1];
     const int n_units = p.hdr[2];
@@ -525,7 +599,7 @@ __global__ __launch_bounds__(NT) void team_solve_persist_kernel(SolveArgs a, Tea
         const int t = __builtin_amdgcn_readfirstlane(sh_t), u = __builtin_amdgcn_readfirstlane(sh_u);
         __syncthreads();
         if (t >= n_tickets) break;
-        team_member<NT>(a, p, u, t - p.first[u], p.first[u + 1] - p.first[u], X, red, &bar_flag);
+        team_member<NT>(a, p, u, t - p.first[u], p.first[u + 1] - p.first[u], X, red, &bar_flag, scan_part);
         __syncthreads();
     }
 }

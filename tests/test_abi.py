@@ -231,7 +231,7 @@ def test_wide_host_sizes_its_own_path(lib):
     # at least: moments and three complex scratch vectors per bus and case, units,
     # first tickets, barrier counters and one partial per member
     slices = 1 + (n_big + 63) // 64 + 1
-    assert wt >= B * g.n_bus * (4 * 8 + 3 * 16) + items * (4 + 4 + 256) + B * (1 + min(slices - 2, 128) + 1) * 16
+    assert wt >= B * g.n_bus * (4 * 8 + 3 * 16) + items * (4 + 4 + 256) + B * (1 + min(slices - 2, 32) + 1) * 16
     small = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     assert (lib.dpf_solve_workspace_bytes(ctypes.byref(small), 1, None, 1024, 9241, ctypes.byref(host_r)) ==
             lib.dpf_solve_workspace_bytes(ctypes.byref(small), 1, None, 1024, 9241, ctypes.byref(teams_r)))
