@@ -341,6 +341,23 @@ typedef struct dpf_route {
 void dpf_route_default(dpf_route_t *route);
 
 /*
+ * Optional per-item trace of the stop-test quantity of dpf_solve_batch (the
+ * loss curves of Sec. 6.4 show its decay): max|dS| of iteration k of the call,
+ * tested before that iteration's update, is written to max_mis[item*len + k/every]
+ * for every k that is a multiple of `every` and below len*every, where item =
+ * c*n_sub + s and k counts from 0 in each call.  Slots past an item's stop are
+ * left as they were (fill them, e.g. with NaN, before the call).
+ *   max_mis : device double [B*n_sub][len]
+ *   every   : > 0 when len > 0
+ *   len     : slots per item; 0 = no trace
+ */
+typedef struct dpf_trace {
+    double *max_mis;
+    int32_t every;
+    int32_t len;
+} dpf_trace_t;
+
+/*
  * dpf_solve_batch -- the DPF iteration (Algorithm 1 with Adam) run to
  * convergence for many independent problems in ONE kernel launch.
  *
@@ -396,9 +413,10 @@ void dpf_route_default(dpf_route_t *route);
  *   max_mis, loss : device double [B*n_sub] out, at the returned voltages
  *   done_ns       : device int64 [B*n_sub] out, nullable: nanoseconds from the start of
  *                   the call's kernels to the item's stop (time to converge per item)
+ *   trace         : host, nullable: the optional max|dS| trace (dpf_trace_t)
  *   workspace     : device, >= dpf_solve_workspace_bytes(g, n_sub, sub_offset, B, ld,
  *                   route) bytes
- * Errors: DPF_EINVAL (sizes, pointers, opts or route out of range, a sub-grid
+ * Errors: DPF_EINVAL (sizes, pointers, opts, route or trace out of range, a sub-grid
  * larger than the solver supports), DPF_ENOMEM, DPF_EUNSUPPORTED, DPF_EHIP.
  */
 int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offset,
@@ -407,7 +425,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                     const int32_t *outage, double *vm, double *va, double *adam_state,
                     double *sched_state, const dpf_opts_t *opts, const dpf_route_t *route,
                     int32_t *iters, int32_t *status, double *max_mis, double *loss,
-                    int64_t *done_ns, void *workspace, size_t ws_bytes, void *stream);
+                    int64_t *done_ns, const dpf_trace_t *trace, void *workspace, size_t ws_bytes,
+                    void *stream);
 
 /* Workspace bytes of the dpf_solve_batch call with these sizes and this route
  * (nullable); 0 for invalid sizes or an invalid route. */

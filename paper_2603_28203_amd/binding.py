@@ -54,6 +54,10 @@ class _Route(ctypes.Structure):
                 ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("wide_host", _i32)]
 
 
+class _Trace(ctypes.Structure):
+    _fields_ = [("max_mis", _P), ("every", _i32), ("len", _i32)]
+
+
 _lib = None
 
 
@@ -90,8 +94,8 @@ def lib():
         L.dpf_mismatch_grad_workspace_bytes.restype = ctypes.c_size_t
         R = ctypes.POINTER(_Route)
         L.dpf_solve_batch.argtypes = [ctypes.POINTER(_Grid), _i32, _P, _P, _i32, _i32, _P, _P, _i32, _P,
-                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), R, _P, _P, _P, _P, _P, _P,
-                                      ctypes.c_size_t, _P]
+                                      _P, _P, _P, _P, ctypes.POINTER(_Opts), R, _P, _P, _P, _P, _P,
+                                      ctypes.POINTER(_Trace), _P, ctypes.c_size_t, _P]
         L.dpf_solve_series.argtypes = [ctypes.POINTER(_Grid), _i32, _i32, _P, _P, _i32, _P, _P, _P, _P, _i32,
                                        ctypes.POINTER(_Opts), R, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
         L.dpf_solve_series.restype = ctypes.c_int
@@ -358,15 +362,18 @@ def solve_workspace_bytes(grid: DeviceGrid, B, ld=None, sub_offset=None, route: 
 
 def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = None, outage=None,
           sub_offset=None, sub_offset_dev=None, adam_state=None, sched_state=None,
-          workspace: SolveWorkspace | None = None, outputs=None, route: Route | None = None):
+          workspace: SolveWorkspace | None = None, outputs=None, route: Route | None = None,
+          trace_every: int = 0, trace_len: int = 0):
     """dpf_solve_batch: Adam-DPF to convergence for B cases x n_sub sub-grids.
 
     vm, va ([B, ld] float64, GPU) are updated in place; `route` (Route) sets this
     call's kernel choice and tail settings.  sub_offset (host sequence) gives the
     sub-grid offsets; sub_offset_dev, an int32 device tensor of the same values,
     spares the call its host-to-device copy (a call captured in a graph needs
-    it).  Returns dict with iters, status, max_mis, loss ([B * n_sub], index
-    c * n_sub + s)."""
+    it).  With trace_len > 0 the result also holds "trace" ([B * n_sub,
+    trace_len] float64, NaN where an item had stopped): max|dS| of iterations 0,
+    trace_every, 2 trace_every, ... of this call.  Returns dict with iters,
+    status, max_mis, loss ([B * n_sub], index c * n_sub + s)."""
     opts = opts or Options()
     dev = vm.device
     B, ld = vm.shape
@@ -403,6 +410,11 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
                    "max_mis": torch.empty(items, dtype=torch.float64, device=dev),
                    "loss": torch.empty(items, dtype=torch.float64, device=dev),
                    "done_ns": torch.empty(items, dtype=torch.int64, device=dev)}
+    tr = None
+    if trace_len:
+        if "trace" not in outputs:
+            outputs["trace"] = torch.full((items, int(trace_len)), float("nan"), dtype=torch.float64, device=dev)
+        tr = _Trace(_ptr(outputs["trace"]), int(trace_every), int(trace_len))
     g = grid.c()
     rc = None if route is None else route.c()
     rp = None if rc is None else ctypes.byref(rc)
@@ -415,7 +427,7 @@ def solve(grid: DeviceGrid, bus_type, s_spec, vm, va, *, opts: Options | None = 
                                  _ptr(out), _ptr(vm), _ptr(va), _ptr(adam_state), _ptr(sched_state),
                                  ctypes.byref(o), rp, _ptr(outputs["iters"]), _ptr(outputs["status"]),
                                  _ptr(outputs["max_mis"]), _ptr(outputs["loss"]), _ptr(outputs.get("done_ns")),
-                                 _ptr(ws), ws.numel(), _stream()))
+                                 None if tr is None else ctypes.byref(tr), _ptr(ws), ws.numel(), _stream()))
     if so_d is not None:
         outputs["_keep"] = so_d  # keep the device offsets alive until the stream has used them
     return outputs

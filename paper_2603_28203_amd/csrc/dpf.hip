@@ -430,6 +430,9 @@ int run_wide(const dpf::SolveArgs &a, const SolveLayout &L, char *ws, int32_t n_
     w.status = a.status;
     w.mu_out = a.mu_out;
     w.loss_out = a.loss_out;
+    w.trace = a.trace;
+    w.trace_every = a.trace_every;
+    w.trace_len = a.trace_len;
     w.done_ns = a.done_ns;
     w.stamp = a.stamp;
     w.ns_per_tick = a.ns_per_tick;
@@ -1254,8 +1257,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
                     int32_t B, int32_t ld, const int8_t *bus_type, const double *s_spec, int32_t s_ld,
                     const int32_t *outage, double *vm, double *va, double *adam_state, double *sched_state,
                     const dpf_opts_t *opts, const dpf_route_t *route, int32_t *iters, int32_t *status,
-                    double *max_mis, double *loss, int64_t *done_ns, void *workspace, size_t ws_bytes,
-                    void *stream) {
+                    double *max_mis, double *loss, int64_t *done_ns, const dpf_trace_t *trace, void *workspace,
+                    size_t ws_bytes, void *stream) {
     g_err.clear();
     const dpf_route_t rt = route_of(route);
     if (const char *re = route_error(rt)) return fail(DPF_EINVAL, re);
@@ -1265,6 +1268,8 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     if (!bus_type || !s_spec || !vm || !va || !iters || !status || !max_mis || !loss)
         return fail(DPF_EINVAL, "null argument");
     if (!valid_opts(opts)) return fail(DPF_EINVAL, "invalid optimizer options");
+    if (trace && (trace->len < 0 || (trace->len > 0 && (trace->every <= 0 || !trace->max_mis))))
+        return fail(DPF_EINVAL, "trace: len >= 0, and every > 0 with a buffer when len > 0");
     if ((sub_offset == nullptr) != (sub_offset_dev == nullptr))
         return fail(DPF_EINVAL, "sub_offset and sub_offset_dev: both or neither");
     if (!sub_offset) n_sub = 1;
@@ -1385,6 +1390,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     a.mu_out = max_mis;
     a.loss_out = loss;
     a.done_ns = done_ns;
+    a.trace = trace && trace->len > 0 ? trace->max_mis : nullptr;
+    a.trace_every = trace && trace->len > 0 ? trace->every : 1;
+    a.trace_len = trace && trace->len > 0 ? trace->len : 0;
     a.stamp = (const int64_t *)(ws + 8);  // header words 2-3
     a.ns_per_tick = dev.ns_per_tick;
 
@@ -1540,7 +1548,7 @@ int dpf_solve_series(const dpf_grid_t *g, int32_t T, int32_t window, const int8_
         int rc = dpf_solve_batch(g, 1, nullptr, nullptr, bw, ld, bus_type, s_series + 2 * (int64_t)t0 * s_ld, s_ld,
                                  nullptr, vm + (int64_t)t0 * ld, va + (int64_t)t0 * ld, nullptr, nullptr, opts,
                                  route, iters + t0, status + t0, max_mis + t0, loss + t0,
-                                 done_ns ? done_ns + t0 : nullptr, workspace, ws_bytes, stream);
+                                 done_ns ? done_ns + t0 : nullptr, nullptr, workspace, ws_bytes, stream);
         if (rc != DPF_OK) return rc;
     }
     return DPF_OK;

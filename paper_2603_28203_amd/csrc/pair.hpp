@@ -184,6 +184,7 @@ __global__ __launch_bounds__(NT) void team_solve_pair_kernel(SolveArgs a) {
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, true, out_idx, it, mu);
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
             break;

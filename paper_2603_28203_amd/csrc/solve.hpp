@@ -89,6 +89,8 @@ struct SolveArgs {
     double *mu_out;
     double *loss_out;
     int64_t *done_ns;         // per item: ns from the call's start stamp to completion, or null
+    double *trace;            // per item [trace_len]: max|r| every trace_every iterations, or null
+    int32_t trace_every, trace_len;
     const int64_t *stamp;     // wall clock at the start of the call
     double ns_per_tick;
 };
@@ -183,6 +185,14 @@ __device__ __forceinline__ bool handoff_due(const SolveArgs &a, int it, int *fla
                 a.handoff;
     __syncthreads();
     return *flag != 0;
+}
+
+// optional trace of the stop-test quantity: max|r| of iteration `it` of this call
+// (tested before its update) goes to slot it / trace_every when it is a multiple
+// of trace_every and the slot exists; one thread writes (thread 0 of `writer`)
+__device__ __forceinline__ void trace_mu(const SolveArgs &a, bool writer, int out_idx, int it, double mu) {
+    if (a.trace_len > 0 && writer && threadIdx.x == 0 && it % a.trace_every == 0 && it / a.trace_every < a.trace_len)
+        a.trace[(int64_t)out_idx * a.trace_len + it / a.trace_every] = mu;
 }
 
 // per-item results and the schedule state, written by one thread
@@ -402,6 +412,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, true, out_idx, it, mu);
         if (!dbl) __syncthreads();  // w fully in X before phase B reads it
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
@@ -669,6 +680,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, true, out_idx, it, mu);
         if (!dbl) __syncthreads();
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
@@ -897,6 +909,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
         block_reduce2_finish<NT>(lsum, lmax, red);
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, true, out_idx, it, mu);
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
             break;

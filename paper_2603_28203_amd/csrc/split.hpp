@@ -353,6 +353,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
         }
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, mem == 0, c, it, mu);
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
             break;

@@ -499,6 +499,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         }
         loss = m_res > 0.0 ? lsum / m_res : 0.0;
         mu = isnan(lsum) ? lsum : lmax;
+        trace_mu(a, mem == 0, out_idx, it, mu);
         if (!(isfinite(loss) && isfinite(mu))) {
             stat = DPF_NONFINITE;
             break;

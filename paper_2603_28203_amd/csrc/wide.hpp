@@ -57,6 +57,8 @@ struct WideArgs {
     double min_lr, sched_eps;
     int32_t *iters, *status;
     double *mu_out, *loss_out;
+    double *trace;       // per item [trace_len], max|r| every trace_every iterations, or null
+    int32_t trace_every, trace_len;
     int32_t *active_count;
     int64_t *done_ns;
     const int64_t *stamp;
@@ -234,6 +236,8 @@ __global__ __launch_bounds__(kWave) void wide_reduce_kernel(WideArgs a) {
     const double mm = a.m_res[s];
     it.loss = mm > 0.0 ? ls / mm : 0.0;
     it.mu = isnan(ls) ? ls : lm;
+    if (a.trace_len > 0 && it.iters % a.trace_every == 0 && it.iters / a.trace_every < a.trace_len)
+        a.trace[(int64_t)idx * a.trace_len + it.iters / a.trace_every] = it.mu;
     if (!(isfinite(it.loss) && isfinite(it.mu))) {
         it.status = DPF_NONFINITE;
         it.active = 0;

@@ -57,7 +57,7 @@ def test_host_side_validation(lib):
     assert rc == -1 and b"n_bus" in lib.dpf_last_error()
     # mismatch_grad / solve reject a null grid
     assert lib.dpf_mismatch_grad(None, 1, 1, *([None] * 12), ctypes.c_size_t(0), None) == -1
-    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 16), ctypes.c_size_t(0), None) == -1
+    assert lib.dpf_solve_batch(None, 1, None, None, 1, 1, *([None] * 17), ctypes.c_size_t(0), None) == -1
     assert lib.dpf_solve_series(None, 1, 1, *([None] * 3), 1, *([None] * 4), 1, *([None] * 8),
                                 ctypes.c_size_t(0), None) == -1
     assert lib.dpf_param_grad(None, 1, 1, *([None] * 3), 0, *([None] * 8), 1, None, None,

@@ -1192,6 +1192,59 @@ def test_step_schedule_on_every_path_and_resumed(dpf, path):
     assert torch.equal(vmR, vm) and torch.equal(vaR, va)
 
 
+@pytest.mark.parametrize("path", ["register", "banded-pair", "split", "teams", "wide"])
+def test_max_mismatch_trace_on_every_path(dpf, path):
+    """The optional per-item trace of max|dS| (every 5 iterations, 8 slots over a
+    30-iteration call) equals the oracle's max|dS| after 0, 5, ..., 30 updates on
+    the register and paired-state kernels, the split kernel (every case handed
+    over after 32 iterations of a 40-iteration call, so slots before and after
+    the handoff), the persistent teams and the multi-workgroup path; slots past
+    the call's last iteration stay NaN, and a call without a trace writes none."""
+    n = 300 if path == "register" else 3000
+    base = synth.config1(B=1, seed=9960 + n, n_bus=n, n_branch=int(1.47 * n), n_pv=n // 6)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0]) if path != "register" else base
+    Yo = oracle.ybus_of(g)
+    S = oracle.injections(Yo, g.vm, g.va)
+    B = 2
+    rng = np.random.default_rng(9961)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, n)) * (g.bus_type != 2)
+    steps = 40 if path == "split" else 30
+    every, length = 5, 10 if path == "split" else 8
+    rt = dpf.Route()
+    if path == "banded-pair":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == path and x["threads"] == 1024][0]["index"]
+    elif path == "split":
+        rt.variant = [x for x in dpf.variants() if x["kind"] == "banded-pair" and x["threads"] == 1024][0]["index"]
+        rt.tail_handoff, rt.tail_team, rt.tail_chunk = B, 8, 4
+    elif path in ("teams", "wide"):
+        rt.team_cap, rt.wide_host = 1000, int(path == "wide")
+    Yg = dgrid(dpf, g)
+    print(f"max|dS| trace on the {path} path, n={n}", flush=True)
+    stats = dpf.split_stats()
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, route=rt, trace_every=every,
+                    trace_len=length, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    if path == "split":
+        assert split_ran(dpf, stats)
+    tr = out["trace"].cpu().numpy()
+    assert tr.shape == (B, length)
+    for c in range(B):
+        for k in range(length):
+            if k * every > steps:
+                assert np.isnan(tr[c, k]), (c, k)
+                continue
+            ref = oracle.solve_adam(Yo, g.bus_type, S, vm0[c], va0[c],
+                                    oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=k * every))
+            assert abs(tr[c, k] - ref["mu"]) <= 1e-9 * ref["mu"], (c, k, tr[c, k], ref["mu"])
+        assert tr[c, steps // every] == out["max_mis"][c].item()
+    plain = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), cu(vm0), cu(va0), route=rt,
+                      opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert "trace" not in plain
+
+
 @pytest.mark.parametrize("path", ["register", "banded-stream", "banded-pair", "split-direct", "teams", "wide"])
 def test_bad_outage_index_is_reported(dpf, path):
     """An outage index that is neither -1 nor a branch index (n_branch, -2) gives
