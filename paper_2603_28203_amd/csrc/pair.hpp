@@ -1,5 +1,5 @@
 // Banded solve with paired state: the A/W and gradient sweeps of the
-// barrier-free banded kernel (team_solve_band_kernel<NT, J, false>), with the
+// barrier-free banded kernel (team_solve_band_kernel<NT, J>), with the
 // per-bus state of a case held in the workspace as three complex-sized pairs
 //     P0 = (|V|, theta),  P1 = (m_vm, m_va),  P2 = (s_vm, s_va)
 // instead of six separate arrays.  Same arithmetic in the same order, so the
