@@ -771,6 +771,42 @@ def test_uneven_batch_above_the_lds_limit_in_one_captured_launch(dpf):
             assert torch.equal(outs[k], ref[k]), (rep, k)
 
 
+@pytest.mark.parametrize("path", ["teams", "host"])
+def test_uneven_batch_with_an_80000_bus_grid(dpf, path):
+    """The uneven batch's largest grid at its full size: one 80 000-bus grid and
+    four of log-uniform size (a grid of the uneven-batch generator, numbered
+    per sub-grid with degree grouping in windows of 512 as the bench does) in
+    one call, on the persistent teams and on the host-driven multi-workgroup
+    path; every sub-grid equals its oracle solve after 5 steps."""
+    cfg = synth.config4(seed=4100, n_grids=4, lo=100, hi=20000, big=80000)
+    grids = cfg["grids"]
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    perm = dpf.rcm_order(int(off[-1]), np.concatenate([gg.f + o for gg, o in zip(grids, off)]),
+                         np.concatenate([gg.t + o for gg, o in zip(grids, off)]), sub_offset=off.tolist(),
+                         group=512)[0]
+    grids = [renumber(gg, perm[off[k]:off[k + 1]] - off[k]) for k, gg in enumerate(grids)]
+    off, f, t, r, x, b, bt = _concat_grids(grids)
+    S = np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids])
+    starts = [_perturbed_start(gg, 60 + k) for k, gg in enumerate(grids)]
+    vm0 = np.concatenate([s_[0] for s_ in starts]); va0 = np.concatenate([s_[1] for s_ in starts])
+    Yg = dpf.build_ybus(int(off[-1]), f, t, r, x, b)
+    steps = 5
+    print(f"80k uneven batch on the {path} path: sub-grids {np.diff(off).tolist()}", flush=True)
+    vm = cu(vm0[None]); va = cu(va0[None])
+    out = dpf.solve(Yg, bt, cu(S, torch.complex128), vm, va, sub_offset=off.tolist(),
+                    route=dpf.Route(wide_host=int(path == "host")),
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * len(grids) and out["status"].tolist() == [dpf.MAX_ITER] * len(grids)
+    for k, gg in enumerate(grids):
+        sl = slice(off[k], off[k + 1])
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[sl], vm0[sl], va0[sl],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[0, sl].cpu().numpy() - ref["vm"]).max() < 1e-10, k
+        assert np.abs(va[0, sl].cpu().numpy() - ref["va"]).max() < 1e-10, k
+        assert abs(out["max_mis"][k].item() - ref["mu"]) <= 1e-9 * ref["mu"], k
+
+
 def test_teams_single_grid_above_the_lds_limit_with_outages(dpf):
     """One grid above the LDS limit (small-bandwidth numbering) with N-1
     outages, a plateau schedule and caller-held state, on the persistent teams:
