@@ -685,11 +685,43 @@ def cfg4_uneven(cap):
     torch.cuda.synchronize()
     dt_host = time.perf_counter() - t0
     conv_host = int((r_host["status"].cpu().numpy() == 0).sum())
+    # the persistent launch, eagerly and then captured once in a HIP graph and replayed
+    # (same workspace, outputs and device offsets, so the call enqueues no copy)
+    items = len(grids)
+    bt = torch.tensor(g.bus_type, dtype=torch.int8, device="cuda")
+    sod = torch.tensor(off, dtype=torch.int32, device="cuda")
+    ws = dpf.SolveWorkspace()
+    outs = {k: torch.empty(items, dtype=dt_, device="cuda") for k, dt_ in
+            (("iters", torch.int32), ("status", torch.int32), ("max_mis", torch.float64),
+             ("loss", torch.float64), ("done_ns", torch.int64))}
     vm, va = vm0.clone(), va0.clone()
     t0 = time.perf_counter()
-    r = dpf.solve(Yg, g.bus_type, S, vm, va, opts=opts, sub_offset=off.tolist())
+    r = dpf.solve(Yg, bt, S, vm, va, opts=opts, sub_offset=off.tolist(), sub_offset_dev=sod, workspace=ws,
+                  outputs=outs)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    r = {k: v.clone() for k, v in r.items() if k != "_keep"}
+    vm_e, va_e = vm.clone(), va.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dpf.solve(Yg, bt, S, vm, va, opts=solve_options(20), sub_offset=off.tolist(), sub_offset_dev=sod,
+                  workspace=ws, outputs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dpf.solve(Yg, bt, S, vm, va, opts=opts, sub_offset=off.tolist(), sub_offset_dev=sod, workspace=ws,
+                  outputs=outs)
+    vm.copy_(vm0)
+    va.copy_(va0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    dt_graph = time.perf_counter() - t0
+    graph_equal = bool(torch.equal(vm, vm_e) and torch.equal(va, va_e) and
+                       all(torch.equal(outs[k], r[k]) for k in ("iters", "status", "max_mis", "loss")))
     it = r["iters"].cpu().numpy().astype(np.int64)
     st = r["status"].cpu().numpy()
     done = r["done_ns"].cpu().numpy() * 1e-6
@@ -705,6 +737,7 @@ def cfg4_uneven(cap):
             "bus_order": f"reverse Cuthill-McKee per grid, degree-grouped in windows of {CFG4_ORDER_GROUP} "
                          f"(largest bandwidth {bw})",
             "iter_cap": cap, "s": round(dt, 3), "converged": conv, "solves_per_s": round(conv / dt, 3),
+            "graph_replay_s": round(dt_graph, 3), "graph_replay_equals_eager": graph_equal,
             "bus_iters_per_s": round(bus_iters / dt, 1),
             "alg_GBps": round(alg / dt / 1e9, 1),
             "time_to_stop_ms_p50": round(float(np.percentile(done, 50)), 2),
