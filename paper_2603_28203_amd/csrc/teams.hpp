@@ -24,12 +24,14 @@
 // adjoint of Sec. 5.1, the update of Sec. 4.1):
 //   X <- V of the window (global, written by the owners)
 //   A : rows of the member: I = Y V (+ the rank-2 outage term), dS, loss terms,
-//       w = a conj(V) -> global; the member's (loss sum, max|r|) -> global
+//       a*I -> global (own rows), w = a conj(V) -> global; the member's
+//       (loss sum, max|r|) -> global
 //   -- team barrier --
 //   every member reduces the T partials in the same fixed order (one loss,
 //   max|r| and stop decision for the whole team); X <- w of the window
-//   B : rows of the member: h = Y^T w, G, optimizer step; |V|, theta, moments and
-//       V = polar(|V|, theta) -> global; schedule step
+//   B : rows of the member: h = Y^T w, G = a*I + conj(h) with V rebuilt from
+//       |V| and theta, optimizer step; |V|, theta, moments and V = polar(|V|,
+//       theta) -> global; schedule step
 //   -- team barrier --
 // What crosses a barrier is written and read with device-scope accesses (see
 // common.hpp) and each thread waits for its stores before the arrival is counted.
@@ -82,7 +84,7 @@ struct TeamArgs {
     int32_t *first;        // [items + 1] first ticket of each unit
     long long *bar;        // [items][kTeamBarStride] arrival counter of each unit
     double2 *part;         // [tickets] member partials (loss sum, max|r|), unit u's at first[u]
-    double2 *Ig, *Vg, *Wg; // [B][ld] I of the A sweep, V, exchanged w
+    double2 *Ig, *Vg, *Wg; // [B][ld] a*I of the A sweep, V, exchanged w
     int64_t first_limit;   // wall-clock ticks a unit's first barrier waits without progress
     int64_t limit;         // ... and every later barrier
     int32_t win;           // complex entries of the LDS window (followed in LDS by the
@@ -467,7 +469,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const double rQ = tk == kPQ ? d.y : 0.0;
             lsum += rP * rP + rQ * rQ;
             lmax = fmax(lmax, fmax(fabs(rP), fabs(rQ)));
-            Ig[il] = acc;
+            Ig[il] = cmul(make_double2(two_over_m * rP, two_over_m * rQ), acc);  // a*I for the B sweep
             st2(rW, il, cmulc(make_double2(two_over_m * rP, two_over_m * rQ), v));
         }
         block_reduce2<NT>(lsum, lmax, red);
@@ -521,9 +523,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         const double bc2 = 1.0 - sc.b2t;
         for (int il = rlo + tid; il < rhi; il += NT) {
             const int8_t tk = btp[il];
-            const double2 I = Ig[il];
-            const double2 sp = Sc[il];
-            const double2 v = ld2(rV, il);
+            const double2 ai = Ig[il];
             double vmi = vm_c[il], vai = va_c[il];
             const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
             const int wdt = swidth[gsl];
@@ -533,10 +533,13 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], xat(scol[base + q * kWave], rW), h);
             if (il == of) h = csub(h, csub(cmul(oyd, xat(of, rW)), cmul(oy, xat(ot, rW))));
             else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, rW)), cmul(oy, xat(of, rW))));
-            const double2 d = csub(cmulc(v, I), sp);
-            const double rP = tk != kSlack ? d.x : 0.0;
-            const double rQ = tk == kPQ ? d.y : 0.0;
-            const double2 ai = cmul(make_double2(two_over_m * rP, two_over_m * rQ), I);
+            // V of this row, rebuilt from |V| and theta (the same bits the owner published)
+            double2 v;
+            {
+                double sn0, cs0;
+                fast_sincos(vai, sn0, cs0);
+                v = make_double2(vmi * cs0, vmi * sn0);
+            }
             const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
             if (tk == kPQ) {
                 const double g = (G.x * v.x + G.y * v.y) / vmi;
