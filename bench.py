@@ -67,12 +67,16 @@ def log(msg):
 ROOFLINE_KERNEL_SOURCES = ("common.hpp", "eval.hpp", "sell.hpp", "solve.hpp", "pair.hpp")
 
 
-def kernel_source_hash() -> str:
+# ... and those of the persistent team kernel (the uneven batch)
+TEAM_KERNEL_SOURCES = ("common.hpp", "eval.hpp", "sell.hpp", "solve.hpp", "teams.hpp")
+
+
+def kernel_source_hash(sources=ROOFLINE_KERNEL_SOURCES) -> str:
     """Hash of the roofline kernels' device-code headers, with comments and blank
     space removed: edits to comments leave it alone."""
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2603_28203_amd", "csrc")
-    for f in ROOFLINE_KERNEL_SOURCES:
+    for f in sources:
         with open(os.path.join(csrc, f)) as fh:
             text = re.sub(r"/\*.*?\*/", "", fh.read(), flags=re.S)
         text = re.sub(r"//[^\n]*", "", text)
@@ -303,15 +307,15 @@ def heldout_seed(seed, B, opts, route, cap):
             "what": "the same optimizer, kernel and tail settings, no re-tuning"}
 
 
-def pmc_traffic(kernel_name):
+def pmc_traffic(kernel_name, summary="solve_nminus1_1024x9241_hbm.json", sources=ROOFLINE_KERNEL_SOURCES):
     """HBM bytes per launch from a committed rocprofv3 counter summary of the
     current kernel source, else None."""
-    p = os.path.join(ROOT, "profiles", "solve_nminus1_1024x9241_hbm.json")
+    p = os.path.join(ROOT, "profiles", summary)
     if not os.path.exists(p):
         return None
     with open(p) as fh:
         d = json.load(fh)
-    if d.get("kernel_source_hash") != kernel_source_hash() or d.get("kernel") != kernel_name:
+    if d.get("kernel_source_hash") != kernel_source_hash(sources) or d.get("kernel") != kernel_name:
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -338,6 +342,9 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the time-series and uneven-batch lines")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (the reference for counter scaling)")
+    ap.add_argument("--uneven-only", action="store_true",
+                    help="only run the uneven-batch line (129 grids, one persistent launch) and print it: the run "
+                         "that rocprofv3 profiles for that kernel")
     ap.add_argument("--roofline-only", type=str, default=None, metavar="KIND",
                     help="only build the N-1 batch and run the roofline launch (all cases, 200 iterations, "
                          "warm-up then timed) on the 1024-thread, 4-bus variant of KIND (e.g. banded-pair): "
@@ -348,6 +355,9 @@ def main():
         return
     if args.roofline_only:
         roofline_only(args.roofline_only, args.cases)
+        return
+    if args.uneven_only:
+        print(json.dumps({"cfg4": cfg4_uneven(2000)}), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -728,8 +738,14 @@ def cfg4_uneven(cap):
     sizes = np.diff(off)
     bus_iters = float((it * sizes).sum())
     conv = int((st == 0).sum())
-    nnz_rows = int(Yg.nnz)
-    alg = bus_iters * 96 + int(it.max()) * 2 * (20 * nnz_rows + 4 * (g.n_bus + len(grids)))
+    # algorithmic bytes: the state floor per bus-iteration (|V|, theta and four moments read
+    # and written, 96 B, + this grid's own injections read, 16 B) + each grid's CSR twice per
+    # iteration of that grid (one case per grid: nothing shares either)
+    rp = Yg.row_ptr.cpu().numpy().astype(np.int64)
+    nnz_g = rp[off[1:]] - rp[off[:-1]]
+    alg = bus_iters * 112 + float((it * 2 * (20 * nnz_g + 4 * (sizes + 1))).sum())
+    kern = "team_solve_persist_kernel<1024>"
+    traffic = pmc_traffic(kern, "uneven_129grids_teams_hbm.json", TEAM_KERNEL_SOURCES)
     return {"workload": f"{len(grids)} grids, {g.n_bus} buses (log-uniform 100..80000 + one 80000), "
                         f"PQ loads x U(0.98, 1.02), planted start, cap {cap}",
             "path": "one persistent launch of teams (the call enqueues the sliced-ELL build, a plan "
@@ -740,6 +756,12 @@ def cfg4_uneven(cap):
             "graph_replay_s": round(dt_graph, 3), "graph_replay_equals_eager": graph_equal,
             "bus_iters_per_s": round(bus_iters / dt, 1),
             "alg_GBps": round(alg / dt / 1e9, 1),
+            "roofline": {"bound": "hbm", "kernel": kern, "what": "the eager call (sliced-ELL build, plan and the "
+                         "persistent launch, which takes all but ~1 ms of it)",
+                         "achieved": round(alg / dt / 1e9, 1), "peak": 8000.0, "unit": "GB/s",
+                         "frac": round(alg / dt / 8e12, 4),
+                         "traffic": None if traffic is None else round(traffic / dt / 1e9, 1),
+                         "alg_bytes": alg},
             "time_to_stop_ms_p50": round(float(np.percentile(done, 50)), 2),
             "time_to_stop_ms_p99": round(float(np.percentile(done, 99)), 2),
             "grids_above_one_cu": int((sizes > dpf.max_sub_buses()).sum()),
