@@ -50,6 +50,11 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 constexpr size_t kYbusScratchBytes = (size_t)16 << 20;
 __device__ __align__(256) char scratch[kYbusScratchBytes];
 
+// Progress count of the persistent teams, one per device and shared by every
+// launch on it (a team waiting for members held by another launch sees that
+// launch's progress); only ever incremented and compared for change.
+__device__ int32_t team_progress;
+
 // Per-device limits, queried once per device.
 struct DeviceInfo {
     int lds_per_block = 0;  // bytes
@@ -60,6 +65,7 @@ struct DeviceInfo {
     hipEvent_t ev_in = nullptr, ev_out = nullptr, ev_poll = nullptr;
     int32_t *pinned_count = nullptr; // host-pinned poll target (two words)
     void *ybus_scratch = nullptr;    // this device's copy of `scratch`
+    int32_t *team_progress = nullptr;  // this device's copy of `team_progress`
     int index = 0;
 };
 std::mutex g_dev_mu;
@@ -88,6 +94,7 @@ int device_info(DeviceInfo &out) {
         DPF_HIP(hipEventCreateWithFlags(&g_dev[dev].ev_poll, hipEventDisableTiming));
         DPF_HIP(hipHostMalloc((void **)&g_dev[dev].pinned_count, 2 * sizeof(int32_t), hipHostMallocDefault));
         DPF_HIP(hipGetSymbolAddress((void **)&g_dev[dev].ybus_scratch, HIP_SYMBOL(scratch)));
+        DPF_HIP(hipGetSymbolAddress((void **)&g_dev[dev].team_progress, HIP_SYMBOL(team_progress)));
         g_dev[dev].index = dev;
         g_dev[dev].ok = true;
     }
@@ -361,7 +368,7 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
     }
     if (teams) {
         const int64_t items = (int64_t)B * (sub_offset ? n_sub : 1);
-        L.off_thdr = o;  // ticket counter, tickets, units, progress count
+        L.off_thdr = o;  // ticket counter, tickets, units
         o += 256;
         L.off_tunit = o;
         o += align_up(sizeof(int32_t) * (size_t)items, 256);
@@ -664,6 +671,7 @@ int run_teams(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, int32_t 
     const int grid = per_cu * dev.n_cu;
     dpf::TeamArgs p{};
     p.hdr = (int32_t *)(ws + L.off_thdr);
+    p.progress = dev.team_progress;
     p.unit_item = (int32_t *)(ws + L.off_tunit);
     p.first = (int32_t *)(ws + L.off_tfirst2);
     p.bar = (long long *)(ws + L.off_tbar);

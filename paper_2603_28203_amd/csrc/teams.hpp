@@ -38,10 +38,11 @@
 // A team of one uses workgroup barriers only.
 //
 // Waits: the first barrier of a unit (after the members publish V of their rows)
-// may wait for members still finishing other units; it is abandoned only when
-// neither the team's arrival count nor the launch's progress count (bumped by
-// every running unit every 64 iterations and when it ends) has moved for the
-// first bound.  Later barriers, with the whole team running, use the second bound.
+// may wait for members still finishing other units, of this launch or of another
+// persistent launch on the device that holds the CUs; it is abandoned only when
+// neither the team's arrival count nor the device's progress count (bumped by
+// every running unit of every launch every 64 iterations and when it ends) has
+// moved for the first bound.  Later barriers, with the whole team running, use the second bound.
 // An abandoned unit leaves its item with status DPF_UNFINISHED at the state of a
 // whole iteration, as the split kernel's teams do.
 //
@@ -79,7 +80,8 @@ constexpr int kTeamHaloCap = 2048;        // halo columns a member's refill list
 constexpr long long kTeamAbort = 1LL << 62;
 
 struct TeamArgs {
-    int32_t *hdr;          // [0] next ticket, [1] tickets, [2] units, [3] progress count
+    int32_t *hdr;          // [0] next ticket, [1] tickets, [2] units
+    int32_t *progress;     // the device's progress count (one per device, shared by all launches)
     int32_t *unit_item;    // [items] item of each unit, in ticket order
     int32_t *first;        // [items + 1] first ticket of each unit
     long long *bar;        // [items][kTeamBarStride] arrival counter of each unit
@@ -233,14 +235,13 @@ __global__ __launch_bounds__(kPlanThreads) void team_plan_kernel(int32_t n_sub, 
         p.hdr[0] = 0;
         p.hdr[1] = (int32_t)before;
         p.hdr[2] = items;
-        p.hdr[3] = 0;
     }
     for (int u = tid; u < items; u += kPlanThreads) p.bar[(int64_t)u * kTeamBarStride] = 0;
 }
 
 // Arrival barrier of the T members of one unit; false when it was abandoned.
 // first: the unit's first barrier, which waits while the arrival count or the
-// launch's progress count moves and abandons after `limit` ticks without either;
+// device's progress count moves and abandons after `limit` ticks without either;
 // later barriers abandon after `limit` ticks.
 __device__ __forceinline__ bool unit_barrier(long long *cnt, long long target, int64_t limit, bool first,
                                              const int32_t *progress, int *flag) {
@@ -299,7 +300,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     const int out_idx = c * a.n_sub + sidx;
     long long *cnt = p.bar + (int64_t)u * kTeamBarStride;
     double2 *part = p.part + p.first[u];
-    int32_t *progress = p.hdr + 3;
+    int32_t *progress = p.progress;
     if (*a.bad_grid) {  // a row longer than the declared bound (see DPF_BAD_GRID)
         if (mem == 0 && tid == 0) {
             a.status[out_idx] = DPF_BAD_GRID;

@@ -1814,6 +1814,51 @@ def test_concurrent_calls_with_different_routes(dpf):
     assert np.abs(together[1][0][0] - ref["vm"]).max() < 1e-9
 
 
+def test_concurrent_persistent_team_calls(dpf):
+    """Two host threads, each with its own stream and workspace, run persistent-team
+    calls at the same time (cases of a 1354-bus grid split over teams by a team cap
+    of 500, enough items to fill the device): the launches overlap and compete for
+    the CUs, every item still finishes (no team gives up waiting, since the waits
+    follow the progress of every launch on the device) and each result equals the
+    same call run alone bit for bit."""
+    import threading
+    g = synth.config1(B=1, seed=9820, n_bus=1354, n_branch=1990, n_pv=225)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    B = 24
+    starts = []
+    for seed in (1, 2):
+        rng = np.random.default_rng(9820 + seed)
+        starts.append((g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0),
+                       g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)))
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=400)
+    route = dpf.Route(team_cap=500)
+
+    def run(k, out):
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            vm = cu(starts[k][0]); va = cu(starts[k][1])
+            r = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=opts, workspace=dpf.SolveWorkspace(), route=route)
+            stream.synchronize()
+            out[k] = (vm.cpu().numpy(), va.cpu().numpy(), r["iters"].cpu().numpy(), r["status"].cpu().numpy())
+
+    print("two persistent-team calls, alone then together", flush=True)
+    alone = {}
+    for k in (0, 1):
+        run(k, alone)
+    together = {}
+    th = [threading.Thread(target=run, args=(k, together)) for k in (0, 1)]
+    for t in th:
+        t.start()
+    for t in th:
+        t.join(timeout=120)
+    assert sorted(together) == [0, 1]
+    for k in (0, 1):
+        assert together[k][3].tolist() == [dpf.MAX_ITER] * B and together[k][2].tolist() == [400] * B, k
+        assert np.array_equal(together[k][0], alone[k][0]) and np.array_equal(together[k][1], alone[k][1]), k
+
+
 @pytest.mark.parametrize("opt", ["sgd", "rmsprop", "adam-constant"])
 def test_split_kernel_optimizers_and_shared_injections(handoff, opt):
     """The split kernel (every case handed over after 32 iterations, teams of up
