@@ -345,6 +345,8 @@ def main():
     ap.add_argument("--uneven-only", action="store_true",
                     help="only run the uneven-batch line (129 grids, one persistent launch) and print it: the run "
                          "that rocprofv3 profiles for that kernel")
+    ap.add_argument("--uneven-conv-cap", type=int, default=100000,
+                    help="iteration cap of the uneven batch's run to convergence (0: skip it)")
     ap.add_argument("--roofline-only", type=str, default=None, metavar="KIND",
                     help="only build the N-1 batch and run the roofline launch (all cases, 200 iterations, "
                          "warm-up then timed) on the 1024-thread, 4-bus variant of KIND (e.g. banded-pair): "
@@ -357,7 +359,7 @@ def main():
         roofline_only(args.roofline_only, args.cases)
         return
     if args.uneven_only:
-        print(json.dumps({"cfg4": cfg4_uneven(2000)}), flush=True)
+        print(json.dumps({"cfg4": cfg4_uneven(2000, args.uneven_conv_cap)}), flush=True)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -532,7 +534,7 @@ def main():
         log("cfg3: time series, sequential vs windows of 16")
         line["cfg3"] = cfg3_series(1000, tail_team)
         log("cfg4: uneven batch of 129 grids")
-        line["cfg4"] = cfg4_uneven(2000)
+        line["cfg4"] = cfg4_uneven(2000, args.uneven_conv_cap)
 
     if not args.no_cpu:
         log("cpu baseline: the oracle (built -O3 -march=native here) on a bounded sample")
@@ -647,14 +649,15 @@ def cfg3_series(cap, tail_team):
 CFG4_ORDER_GROUP = 512
 
 
-def cfg4_uneven(cap):
+def cfg4_uneven(cap, conv_cap=0):
     """Uneven batch: 128 grids of log-uniform size in [100, 80000] buses plus one
     of 80000, concatenated as sub-grids of one call, each numbered by reverse
     Cuthill-McKee and degree-grouped.  The call runs every grid in one persistent launch of teams
     (a grid above one CU's LDS spread over several workgroups); the same call on
     the host-driven multi-workgroup path is timed beside it.  Each grid's PQ
     loads are scaled by U(0.98, 1.02) from its planted state, which is also the
-    start point."""
+    start point.  With conv_cap > 0 the persistent call is run once more with
+    that iteration cap, for the per-grid time to converge."""
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -746,6 +749,36 @@ def cfg4_uneven(cap):
     alg = bus_iters * 112 + float((it * 2 * (20 * nnz_g + 4 * (sizes + 1))).sum())
     kern = "team_solve_persist_kernel<1024>"
     traffic = pmc_traffic(kern, "uneven_129grids_teams_hbm.json", TEAM_KERNEL_SOURCES)
+    conv_run = None
+    if conv_cap:
+        vm, va = vm0.clone(), va0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rc_ = dpf.solve(Yg, bt, S, vm, va, opts=solve_options(conv_cap), sub_offset=off.tolist(),
+                        sub_offset_dev=sod, workspace=ws)
+        torch.cuda.synchronize()
+        dtc = time.perf_counter() - t0
+        st_c = rc_["status"].cpu().numpy()
+        it_c = rc_["iters"].cpu().numpy().astype(np.int64)
+        mm_c = rc_["max_mis"].cpu().numpy()
+        done_c = rc_["done_ns"].cpu().numpy() * 1e-6
+        ok = st_c == 0
+        conv_c = int(ok.sum())
+        by_size = []
+        for lo, hi in ((100, 1000), (1000, 5000), (5000, 20000), (20000, 80001)):
+            m = (sizes >= lo) & (sizes < hi)
+            by_size.append({"buses": [lo, hi - 1 if hi == 80001 else hi], "grids": int(m.sum()),
+                            "converged": int((ok & m).sum()),
+                            "max_mis_median": float(np.median(mm_c[m])) if m.any() else None})
+        q = (lambda v, p_: round(float(np.percentile(v, p_)), 2)) if conv_c else (lambda v, p_: None)
+        conv_run = {"iter_cap": conv_cap, "s": round(dtc, 3), "converged": conv_c,
+                    "solves_per_s": round(conv_c / dtc, 3),
+                    "bus_iters_per_s": round(float((it_c * sizes).sum()) / dtc, 1),
+                    "time_to_converge_ms_p50": q(done_c[ok], 50), "time_to_converge_ms_p99": q(done_c[ok], 99),
+                    "iters_converged_p50": q(it_c[ok], 50), "iters_converged_p99": q(it_c[ok], 99),
+                    "by_size": by_size,
+                    "what": "the same persistent call with a larger iteration cap: the time to converge is "
+                            "each converged grid's finish time from the call's start"}
     return {"workload": f"{len(grids)} grids, {g.n_bus} buses (log-uniform 100..80000 + one 80000), "
                         f"PQ loads x U(0.98, 1.02), planted start, cap {cap}",
             "path": "one persistent launch of teams (the call enqueues the sliced-ELL build, a plan "
@@ -766,6 +799,7 @@ def cfg4_uneven(cap):
             "time_to_stop_ms_p99": round(float(np.percentile(done, 99)), 2),
             "grids_above_one_cu": int((sizes > dpf.max_sub_buses()).sum()),
             "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
+            "to_convergence": conv_run,
             "host_driven_path": {"s": round(dt_host, 3), "converged": conv_host,
                                  "what": "the same call with route.wide_host = 1: grids above one CU's LDS on "
                                          "the multi-workgroup path (host polls), the others one workgroup each"}}
