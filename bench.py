@@ -805,10 +805,12 @@ def cfg4_uneven(cap, conv_cap=0):
                                          "the multi-workgroup path (host polls), the others one workgroup each"}}
 
 
-def graph_replay(calls=200, iters=10):
+def graph_replay(calls=200, iters=10, per_graph=20):
     """Small repeated solves (the 14-bus grid, 10 iterations per call): one
-    dpf_solve_batch call issued eagerly (seven launches) against the same call
-    captured once in a HIP graph and replayed."""
+    dpf_solve_batch call issued eagerly (two launches: the sliced-ELL build and the
+    solve kernel) against the same call
+    captured once in a HIP graph and replayed, and against a loop of per_graph
+    such calls captured as one graph."""
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -849,8 +851,21 @@ def graph_replay(calls=200, iters=10):
         graph.replay()
     torch.cuda.synchronize()
     replay = (time.perf_counter() - t0) / calls
+    # a loop of `per_graph` calls captured as one graph: one replay launches them all
+    many = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(many):
+        for _ in range(per_graph):
+            call()
+    torch.cuda.synchronize()
+    reps = max(1, calls // per_graph)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        many.replay()
+    torch.cuda.synchronize()
+    replay_many = (time.perf_counter() - t0) / (reps * per_graph)
     return {"workload": f"14-bus grid, one case, {iters} iterations per call", "calls": calls,
-            "eager_us_per_call": round(eager * 1e6, 1), "graph_us_per_call": round(replay * 1e6, 1)}
+            "eager_us_per_call": round(eager * 1e6, 1), "graph_us_per_call": round(replay * 1e6, 1),
+            "calls_per_graph": per_graph, "graph_of_calls_us_per_call": round(replay_many * 1e6, 1)}
 
 
 def copy_calibration(nbytes=1 << 30, reps=3):

@@ -1323,16 +1323,22 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     if (done_ns) hipLaunchKernelGGL(dpf::stamp_kernel, dim3(1), dim3(64), 0, st, (int64_t *)(ws + 8));
     // sliced-ELL copy of Y for this call (the flag is cleared by a kernel, not a memset,
     // so that the whole call can be captured in a graph)
-    hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub, sub_offset_dev,
-                       g->n_bus, nslice, sub_bw, bad, bad + 4);  // clears header words 0, 4 and 5
-    hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
-    if (L.n_slices > 0) {
-        hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
-                           g->n_bus, slice_off, g->row_ptr, wmax, width, bad);
-        hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, L.n_slices, width, 0, start);
-        hipLaunchKernelGGL(dpf::sell_fill_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub, sub_offset_dev,
-                           g->n_bus, slice_off, g->row_ptr, g->col_idx, (const double2 *)g->val, width, start, scol,
-                           sval, sub_bw);
+    if (n_sub <= dpf::kSellSmallSubs && L.n_slices <= dpf::kSellSmallSlices) {  // small grids: one launch
+        hipLaunchKernelGGL(dpf::sell_small_kernel, dim3(1), dim3(dpf::kSellSmallThreads), 0, st, n_sub,
+                           sub_offset_dev, g->n_bus, g->row_ptr, g->col_idx, (const double2 *)g->val, wmax, nslice,
+                           slice_off, width, start, scol, sval, sub_bw, bad, bad + 4);
+    } else {
+        hipLaunchKernelGGL(dpf::sell_count_kernel, dim3((n_sub + 255) / 256), dim3(256), 0, st, n_sub,
+                           sub_offset_dev, g->n_bus, nslice, sub_bw, bad, bad + 4);  // clears header words 0, 4 and 5
+        hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, n_sub, nslice, 0, slice_off);
+        if (L.n_slices > 0) {
+            hipLaunchKernelGGL(dpf::sell_width_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub,
+                               sub_offset_dev, g->n_bus, slice_off, g->row_ptr, wmax, width, bad);
+            hipLaunchKernelGGL(dpf::scan_kernel, dim3(1), dim3(1024), 0, st, L.n_slices, width, 0, start);
+            hipLaunchKernelGGL(dpf::sell_fill_kernel, dim3(L.n_slices), dim3(dpf::kWave), 0, st, n_sub,
+                               sub_offset_dev, g->n_bus, slice_off, g->row_ptr, g->col_idx, (const double2 *)g->val,
+                               width, start, scol, sval, sub_bw);
+        }
     }
     // cases with an outage index that is neither -1 nor a branch (after the header is cleared)
     if (outage)

@@ -444,6 +444,50 @@ def test_solve_sub_grids_equal_separate_solves(dpf):
         assert np.abs(va[0, off[k]:off[k + 1]].cpu().numpy() - ref["va"]).max() < 1e-9
 
 
+def test_one_launch_sliced_build_equals_the_multi_kernel_build(dpf):
+    """A call with at most 64 slices (4096 rows) builds its sliced-ELL copy of Y in
+    one workgroup, a larger one with five kernels: three 1400-bus grids as
+    sub-grids of a call of two (44 slices) and of three (66 slices) give
+    bit-identical iterates for the two they share, and follow the oracle; so do
+    single grids of 4096 and 4097 buses (64 and 65 slices)."""
+    grids = [synth.config1(B=1, seed=s, n_bus=1400, n_branch=2000, n_pv=200)["grid"] for s in (41, 42, 43)]
+    S = [oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) for gg in grids]
+    starts = [perturbed_states(gg, 1, 50 + k, sd=0.01) for k, gg in enumerate(grids)]
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=8)
+
+    def call(gs, st, ss):
+        off = np.cumsum([0] + [gg.n_bus for gg in gs])
+        cat = lambda key: np.concatenate([getattr(gg, key) + (o if key in ("f", "t") else 0)
+                                          for gg, o in zip(gs, off)])
+        Yg = dpf.build_ybus(int(off[-1]), cat("f"), cat("t"), cat("r"), cat("x"), cat("b"))
+        vm = cu(np.concatenate([v[0] for v, _ in st])[None])
+        va = cu(np.concatenate([a[0] for _, a in st])[None])
+        print(f"sliced build: {len(gs)} sub-grids, {int(off[-1])} buses", flush=True)
+        out = dpf.solve(Yg, cat("bus_type"), cu(np.concatenate(ss)[None], torch.complex128), vm, va,
+                        sub_offset=off.tolist() if len(gs) > 1 else None, opts=opts)
+        torch.cuda.synchronize()
+        assert out["iters"].tolist() == [8] * len(gs)
+        return off, vm[0].cpu().numpy(), va[0].cpu().numpy()
+
+    off2, vm2, va2 = call(grids[:2], starts[:2], S[:2])
+    off3, vm3, va3 = call(grids, starts, S)
+    assert np.array_equal(vm2, vm3[:off2[-1]]) and np.array_equal(va2, va3[:off2[-1]])
+    for k, gg in enumerate(grids):
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[k], starts[k][0][0], starts[k][1][0],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=8))
+        assert np.abs(vm3[off3[k]:off3[k + 1]] - ref["vm"]).max() < 1e-10
+        assert np.abs(va3[off3[k]:off3[k + 1]] - ref["va"]).max() < 1e-10
+    for n in (4096, 4097):
+        gg = synth.config1(B=1, seed=44, n_bus=n, n_branch=int(1.45 * n), n_pv=n // 6)["grid"]
+        sg = oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va)
+        st = perturbed_states(gg, 1, 60, sd=0.01)
+        _, vm, va = call([gg], [st], [sg])
+        ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, sg, st[0][0], st[1][0],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=8))
+        assert np.abs(vm - ref["vm"]).max() < 1e-10, n
+        assert np.abs(va - ref["va"]).max() < 1e-10, n
+
+
 def test_solve_rejects_bad_arguments(dpf):
     g = synth.config0(0)["grid"]
     Yg = dgrid(dpf, g)
