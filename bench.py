@@ -646,7 +646,7 @@ def cfg3_series(cap, tail_team):
     return out
 
 
-CFG4_ORDER_GROUP = 512
+CFG4_ORDER_GROUP = 1536
 
 
 def cfg4_uneven(cap, conv_cap=0):
@@ -672,9 +672,11 @@ def cfg4_uneven(cap, conv_cap=0):
                      r=np.concatenate([gg.r for gg in grids]), x=np.concatenate([gg.x for gg in grids]),
                      b=np.concatenate([gg.b for gg in grids]), bus_type=np.concatenate([gg.bus_type for gg in grids]),
                      vm=np.concatenate([gg.vm for gg in grids]), va=np.concatenate([gg.va for gg in grids]))
-    # degree-grouped in windows of 512 buses: slices of even degree (4.3 stored
+    # degree-grouped in windows of 1536 buses: slices of even degree (4.0 stored
     # entries per row against 7.1 for plain reverse Cuthill-McKee), at a bandwidth
-    # (at most ~1000) whose halos a team member still holds in LDS
+    # (at most ~2900) whose halos a team member still holds in LDS beside its rows
+    # (windows of 640 to 1792 run within 3% of each other; 2048 and above shrink
+    # the rows per member)
     g, bw = renumbered(cat, sub_offset=off, group=CFG4_ORDER_GROUP)
     Yg = dpf.build_ybus(g.n_bus, g.f, g.t, g.r, g.x, g.b)
     S0 = base_injections(Yg, g)

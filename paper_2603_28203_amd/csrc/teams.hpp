@@ -421,6 +421,17 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         __syncthreads();
     }
     const int own0 = rlo - xlo, own1 = min(rhi, xlo + wn) - xlo;  // own rows inside the window
+    // The sweeps take the member's rows in chunks of NT; in chunk k wave v takes the
+    // chunk's slice (v + 5k) mod 16 (a different slice order per chunk).  With a
+    // fixed order, a numbering whose heavy slices recur every 512 or 1024 rows (rows
+    // sorted by degree in windows of that size) gives the same waves the widest
+    // slices in every chunk, and the workgroup waits for them at the sweep's end:
+    // about 9% of the time of the uneven batch.
+    static_assert((NT / kWave & (NT / kWave - 1)) == 0, "waves per workgroup: a power of two");
+    const int nchunk = (rhi - rlo + NT - 1) / NT;
+    auto row_of = [&](int k) {
+        return rlo + k * NT + ((((tid / kWave) + 5 * k) & (NT / kWave - 1)) * kWave) + lane;
+    };
     // X <- the columns the rows read, through resource r (window offsets)
     auto fill = [&](auto &&load) {
         if (n_halo < 0) {
@@ -453,7 +464,9 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         __syncthreads();
         // ---------------- A: rows of this member
         double lsum = 0.0, lmax = 0.0;
-        for (int il = rlo + tid; il < rhi; il += NT) {
+        for (int k = 0; k < nchunk; ++k) {
+            const int il = row_of(k);
+            if (il >= rhi) continue;
             const int8_t tk = btp[il];
             const double2 sp = Sc[il];
             const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
@@ -522,7 +535,9 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
         sc.b2t *= a.b2;
         const double bc1 = 1.0 - sc.b1t;
         const double bc2 = 1.0 - sc.b2t;
-        for (int il = rlo + tid; il < rhi; il += NT) {
+        for (int k = 0; k < nchunk; ++k) {
+            const int il = row_of(k);
+            if (il >= rhi) continue;
             const int8_t tk = btp[il];
             const double2 ai = Ig[il];
             double vmi = vm_c[il], vai = va_c[il];
