@@ -337,8 +337,9 @@ static SolveLayout solve_layout(const dpf_grid_t *g, int32_t n_sub, const int32_
     if (streaming) {
         L.off_mom = o;  // Adam moments [4][B][ld] when the caller passes none
         o += align_up(sizeof(double) * 4 * (size_t)B * ld, 256);
-        L.off_scr = o;  // V, a*I and w [3][B][ld] complex (paired state: I and the three pairs, [4][B][ld])
-        o += align_up(sizeof(double2) * (pairs ? 4 : 3) * (size_t)B * ld, 256);
+        L.off_scr = o;  // V, a*I and w [3][B][ld] complex (paired state: I and the three pairs, [4][B][ld];
+                        // persistent teams: a*I, V, w and the three pairs, [6][B][ld])
+        o += align_up(sizeof(double2) * (teams ? 6 : pairs ? 4 : 3) * (size_t)B * ld, 256);
     }
     if (wide) {
         L.off_wcount = o;
@@ -679,19 +680,24 @@ int run_teams(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, int32_t 
     p.Ig = a.scratch;
     p.Vg = a.scratch + a.st_stride;
     p.Wg = a.scratch + 2 * a.st_stride;
+    p.P0 = a.scratch + 3 * a.st_stride;
+    p.P1 = a.scratch + 4 * a.st_stride;
+    p.P2 = a.scratch + 5 * a.st_stride;
     p.first_limit = (int64_t)(route.tail_first_wait_s * 1e9 / dev.ns_per_tick);
     p.limit = (int64_t)(route.tail_wait_s * 1e9 / dev.ns_per_tick);
     p.win = win;  // a route's team cap also caps the window (members then hold fewer buses)
     p.grid = grid;
     p.tmax = std::max(1, std::min(dpf::kTeamMaxMembers, grid / 2));
-    if (a.st_fresh) {
-        const int64_t words = 4 * (int64_t)B * a.ld;
-        hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, words,
-                           a.st);
-    }
+    // the state as pairs for the launch, and back to the caller's arrays after it
+    // (every entry, unfinished items included)
+    const dim3 pgrid((unsigned)((a.n_bus + 255) / 256), (unsigned)std::min<int32_t>(B, 65535));
+    hipLaunchKernelGGL(dpf::pair_in_kernel, pgrid, dim3(256), 0, st, a.n_bus, a.ld, B, a.vm, a.va, a.st,
+                       a.st_stride, a.st_fresh, p.P0, p.P1, p.P2);
     hipLaunchKernelGGL(dpf::team_plan_kernel, dim3(1), dim3(dpf::kPlanThreads), 0, st, n_sub, a.sub_off, a.n_bus,
                        a.sub_bw, B, p);
     hipLaunchKernelGGL(fn, dim3(grid), dim3(dpf::kTeamThreads), (size_t)lds, st, a, p);
+    hipLaunchKernelGGL(dpf::pair_out_kernel, pgrid, dim3(256), 0, st, a.n_bus, a.ld, B, a.vm, a.va, a.st,
+                       a.st_stride, p.P0, p.P1, p.P2);
     DPF_HIP(hipGetLastError());
     return DPF_OK;
 }
@@ -1473,7 +1479,7 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         DPF_HIP(hipStreamWaitEvent(dev.side, dev.ev_in, 0));
     }
     if (has_small) {
-        const dim3 pgrid((g->n_bus + 255) / 256, B);
+        const dim3 pgrid((g->n_bus + 255) / 256, std::min<int32_t>(B, 65535));
         double2 *P = a.scratch + a.st_stride;  // the pairs follow I in the scratch
         if (pairs)
             hipLaunchKernelGGL(dpf::pair_in_kernel, pgrid, dim3(256), 0, st, g->n_bus, (int64_t)ld, B, vm, va, a.st,

@@ -34,16 +34,17 @@ __global__ void pair_in_kernel(int32_t n, int64_t ld, int32_t B, const double *_
                                int32_t fresh, double2 *__restrict__ P0, double2 *__restrict__ P1,
                                double2 *__restrict__ P2) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t c = blockIdx.y;
-    if (i >= n || c >= B) return;
-    const int64_t o = (int64_t)c * ld + i;
-    P0[o] = make_double2(vm[o], va[o]);
-    if (fresh) {
-        P1[o] = make_double2(0.0, 0.0);
-        P2[o] = make_double2(0.0, 0.0);
-    } else {
-        P1[o] = make_double2(st[o], st[stride + o]);
-        P2[o] = make_double2(st[2 * stride + o], st[3 * stride + o]);
+    if (i >= n) return;
+    for (int32_t c = blockIdx.y; c < B; c += gridDim.y) {  // the grid's y extent may be below B
+        const int64_t o = (int64_t)c * ld + i;
+        P0[o] = make_double2(vm[o], va[o]);
+        if (fresh) {
+            P1[o] = make_double2(0.0, 0.0);
+            P2[o] = make_double2(0.0, 0.0);
+        } else {
+            P1[o] = make_double2(st[o], st[stride + o]);
+            P2[o] = make_double2(st[2 * stride + o], st[3 * stride + o]);
+        }
     }
 }
 
@@ -53,16 +54,17 @@ __global__ void pair_out_kernel(int32_t n, int64_t ld, int32_t B, double *__rest
                                 double *__restrict__ st, int64_t stride, const double2 *__restrict__ P0,
                                 const double2 *__restrict__ P1, const double2 *__restrict__ P2) {
     const int32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int32_t c = blockIdx.y;
-    if (i >= n || c >= B) return;
-    const int64_t o = (int64_t)c * ld + i;
-    const double2 p0 = P0[o], p1 = P1[o], p2 = P2[o];
-    vm[o] = p0.x;
-    va[o] = p0.y;
-    st[o] = p1.x;
-    st[stride + o] = p1.y;
-    st[2 * stride + o] = p2.x;
-    st[3 * stride + o] = p2.y;
+    if (i >= n) return;
+    for (int32_t c = blockIdx.y; c < B; c += gridDim.y) {
+        const int64_t o = (int64_t)c * ld + i;
+        const double2 p0 = P0[o], p1 = P1[o], p2 = P2[o];
+        vm[o] = p0.x;
+        va[o] = p0.y;
+        st[o] = p1.x;
+        st[stride + o] = p1.y;
+        st[2 * stride + o] = p2.x;
+        st[3 * stride + o] = p2.y;
+    }
 }
 
 // a.scratch holds [4][B][ld] complex: I of the A/W sweep, then P0, P1, P2

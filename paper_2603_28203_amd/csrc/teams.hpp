@@ -33,6 +33,10 @@
 //       |V| and theta, optimizer step; |V|, theta, moments and V = polar(|V|,
 //       theta) -> global; schedule step
 //   -- team barrier --
+// The per-bus state lives in the workspace as three 16-byte pairs (|V|, theta),
+// (m_vm, m_va), (s_vm, s_va), filled from the caller's arrays before the launch and
+// written back after it (pair_in_kernel / pair_out_kernel): three loads and three
+// stores per bus-iteration instead of six each.
 // What crosses a barrier is written and read with device-scope accesses (see
 // common.hpp) and each thread waits for its stores before the arrival is counted.
 // A team of one uses workgroup barriers only.
@@ -87,6 +91,7 @@ struct TeamArgs {
     long long *bar;        // [items][kTeamBarStride] arrival counter of each unit
     double2 *part;         // [tickets] member partials (loss sum, max|r|), unit u's at first[u]
     double2 *Ig, *Vg, *Wg; // [B][ld] a*I of the A sweep, V, exchanged w
+    double2 *P0, *P1, *P2; // [B][ld] the state as pairs (|V|, theta), (m_vm, m_va), (s_vm, s_va)
     int64_t first_limit;   // wall-clock ticks a unit's first barrier waits without progress
     int64_t limit;         // ... and every later barrier
     int32_t win;           // complex entries of the LDS window (followed in LDS by the
@@ -329,12 +334,9 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     }
 
     const int64_t cb = (int64_t)c * a.ld + s0;
-    double *__restrict__ vm_c = a.vm + cb;
-    double *__restrict__ va_c = a.va + cb;
-    double *__restrict__ mv_c = a.st + cb;
-    double *__restrict__ ma_c = a.st + a.st_stride + cb;
-    double *__restrict__ sv_c = a.st + 2 * a.st_stride + cb;
-    double *__restrict__ sa_c = a.st + 3 * a.st_stride + cb;
+    double2 *__restrict__ P0 = p.P0 + cb;
+    double2 *__restrict__ P1 = p.P1 + cb;
+    double2 *__restrict__ P2 = p.P2 + cb;
     double2 *__restrict__ Ig = p.Ig + cb;
     double2 *__restrict__ Vg = p.Vg + cb;
     double2 *__restrict__ Wg = p.Wg + cb;
@@ -448,9 +450,9 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
     // V of the member's rows for the team
     for (int il = rlo + tid; il < rhi; il += NT) {
         double sn, cs;
-        const double vmi = vm_c[il];
-        fast_sincos(va_c[il], sn, cs);
-        st2(rV, il, make_double2(vmi * cs, vmi * sn));
+        const double2 p0 = P0[il];
+        fast_sincos(p0.y, sn, cs);
+        st2(rV, il, make_double2(p0.x * cs, p0.x * sn));
     }
     long long nbar = 0;
     bool ok = true;
@@ -540,7 +542,8 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             if (il >= rhi) continue;
             const int8_t tk = btp[il];
             const double2 ai = Ig[il];
-            double vmi = vm_c[il], vai = va_c[il];
+            const double2 p0 = P0[il];
+            double vmi = p0.x, vai = p0.y;
             const int gsl = __builtin_amdgcn_readfirstlane(slice0 + (il >> 6));
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
@@ -557,21 +560,18 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
                 v = make_double2(vmi * cs0, vmi * sn0);
             }
             const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
-            if (tk == kPQ) {
-                const double g = (G.x * v.x + G.y * v.y) / vmi;
-                double mv = mv_c[il], sv = sv_c[il];
-                vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
-                vm_c[il] = vmi;
-                mv_c[il] = mv;
-                sv_c[il] = sv;
-            }
             if (tk != kSlack) {
+                const double2 p1 = P1[il], p2 = P2[il];
+                double mv = p1.x, ma = p1.y, sv = p2.x, sa = p2.y;
+                if (tk == kPQ) {
+                    const double g = (G.x * v.x + G.y * v.y) / vmi;
+                    vmi = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vmi, g, mv, sv);
+                }
                 const double g = G.y * v.x - G.x * v.y;
-                double ma = ma_c[il], sa = sa_c[il];
                 vai = opt_update(a.opt, sc.lr, a.b1, a.b2, a.eps, bc1, bc2, vai, g, ma, sa);
-                va_c[il] = vai;
-                ma_c[il] = ma;
-                sa_c[il] = sa;
+                P0[il] = make_double2(vmi, vai);
+                P1[il] = make_double2(mv, ma);
+                P2[il] = make_double2(sv, sa);
                 double sn, cs;
                 fast_sincos(vai, sn, cs);
                 st2(rV, il, make_double2(vmi * cs, vmi * sn));
