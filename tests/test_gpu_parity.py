@@ -1903,6 +1903,38 @@ def test_concurrent_persistent_team_calls(dpf):
         assert np.array_equal(together[k][0], alone[k][0]) and np.array_equal(together[k][1], alone[k][1]), k
 
 
+def test_persistent_teams_with_more_cases_than_a_grid_dimension(dpf):
+    """66 000 cases of a 120-bus grid, each on a team of two (a team cap of 64
+    buses): more cases than a launch's second grid dimension holds, which the
+    conversion of the state to and from pairs loops over; the first and last
+    cases equal the same cases solved in a call of their own, bit for bit."""
+    g = synth.config1(B=1, seed=9830, n_bus=120, n_branch=170, n_pv=20)["grid"]
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    Yg = dgrid(dpf, g)
+    Sd = cu(S, torch.complex128)
+    B = 66000
+    rng = np.random.default_rng(9830)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    opts = dpf.Options(lr=1e-3, tol=0.0, max_iter=3)
+    route = dpf.Route(team_cap=64)
+    print(f"persistent teams: {B} cases of {g.n_bus} buses", flush=True)
+    vm = cu(vm0); va = cu(va0)
+    r = dpf.solve(Yg, g.bus_type, Sd, vm, va, opts=opts, route=route)
+    torch.cuda.synchronize()
+    assert (r["iters"] == 3).all().item() and (r["status"] == dpf.MAX_ITER).all().item()
+    pick = [0, 1, B - 2, B - 1]
+    vs = cu(vm0[pick]); vas = cu(va0[pick])
+    rs = dpf.solve(Yg, g.bus_type, Sd, vs, vas, opts=opts, route=route)
+    torch.cuda.synchronize()
+    assert rs["iters"].tolist() == [3] * 4
+    assert torch.equal(vm[pick], vs) and torch.equal(va[pick], vas)
+    ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0[B - 1], va0[B - 1],
+                            oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=3))
+    assert np.abs(vm[B - 1].cpu().numpy() - ref["vm"]).max() < 1e-10
+    assert np.abs(va[B - 1].cpu().numpy() - ref["va"]).max() < 1e-10
+
+
 @pytest.mark.parametrize("opt", ["sgd", "rmsprop", "adam-constant"])
 def test_split_kernel_optimizers_and_shared_injections(handoff, opt):
     """The split kernel (every case handed over after 32 iterations, teams of up
