@@ -2304,3 +2304,51 @@ def test_random_grids_on_default_and_banded_paths(tuned, seed):
         for c in range(B):
             assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, (choice, c)
             assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, (choice, c)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_random_uneven_batches_on_persistent_teams(dpf, seed):
+    """Seeded random uneven batches on the persistent teams: 2 to 6 sub-grids of
+    40 to 3000 buses, each numbered either by the library's ordering (with a random
+    degree-grouping window) or at random (wide bandwidth, columns from global
+    memory), 1 or 2 cases with their own injections, and a random team cap (128 to
+    2048 buses, below the largest sub-grid, so sub-grids split over 1 to 24
+    members): every item follows the oracle for a few steps."""
+    rng = np.random.default_rng(33000 + seed)
+    k = int(rng.integers(2, 7))
+    grids = []
+    for j in range(k):
+        n = int(rng.integers(40, 3000))
+        base = synth.config1(B=1, seed=34000 + 10 * seed + j, n_bus=n, n_branch=int(n * rng.uniform(1.3, 1.8)),
+                             n_pv=max(1, n // 6))["grid"]
+        if rng.random() < 0.6:
+            perm = dpf.rcm_order(base.n_bus, base.f, base.t, group=int(rng.choice([0, 256, 1000])))[0]
+            base = renumber(base, perm)
+        grids.append(base)
+    B = 1 + seed % 2
+    off = np.cumsum([0] + [gg.n_bus for gg in grids])
+    # below the largest sub-grid, so that the call runs on the persistent teams
+    cap = min((128, 300, 700, 2048)[seed % 4], int(np.diff(off).max()) - 1)
+    cat = lambda key: np.concatenate([getattr(gg, key) + (o if key in ("f", "t") else 0) for gg, o in zip(grids, off)])
+    Yg = dpf.build_ybus(int(off[-1]), cat("f"), cat("t"), cat("r"), cat("x"), cat("b"))
+    S = np.stack([np.concatenate([oracle.injections(oracle.ybus_of(gg), gg.vm, gg.va) * rng.uniform(0.98, 1.02)
+                                  for gg in grids]) for _ in range(B)])
+    vm0 = np.stack([np.concatenate([gg.vm + rng.normal(0, 1e-2, gg.n_bus) * (gg.bus_type == 0) for gg in grids])
+                    for _ in range(B)])
+    va0 = np.stack([np.concatenate([gg.va + rng.normal(0, 1e-2, gg.n_bus) * (gg.bus_type != 2) for gg in grids])
+                    for _ in range(B)])
+    steps = int(rng.integers(3, 9))
+    print(f"random uneven batch seed {seed}: sizes {np.diff(off).tolist()} B={B} team cap {cap} steps {steps}",
+          flush=True)
+    vm = cu(vm0); va = cu(va0)
+    out = dpf.solve(Yg, cat("bus_type"), cu(S, torch.complex128), vm, va, sub_offset=off.tolist(),
+                    opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps), route=dpf.Route(team_cap=cap))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * (B * k)
+    for c in range(B):
+        for j, gg in enumerate(grids):
+            sl = slice(off[j], off[j + 1])
+            ref = oracle.solve_adam(oracle.ybus_of(gg), gg.bus_type, S[c, sl], vm0[c, sl], va0[c, sl],
+                                    oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+            assert np.abs(vm[c, sl].cpu().numpy() - ref["vm"]).max() < 1e-10, (c, j)
+            assert np.abs(va[c, sl].cpu().numpy() - ref["va"]).max() < 1e-10, (c, j)
