@@ -1024,6 +1024,45 @@ def test_series_windows_follow_the_warm_start_rule(dpf, window):
     assert np.all(out["done_ns"].cpu().numpy() > 0)
 
 
+@pytest.mark.parametrize("path", ["split", "teams"])
+def test_series_at_full_size(dpf, path):
+    """The time series of the benchmark at its full size (96 steps of the
+    9241-bus grid, renumbered with degree grouping in windows of 2560) in windows
+    of 16, on the split kernel from the first iteration (the benchmark's tail
+    settings) and on the persistent teams, 3 Adam steps per time step: every step
+    equals the oracle's solve from the start the rule prescribes (the base point
+    for window 0, else the device's own result for the last step of the window
+    before).  Each step is checked from the device's start rather than along the
+    oracle's own chain: every time step restarts Adam, whose first steps amplify
+    rounding-level differences, and over six chained windows those reach ~2e-10."""
+    cfg = synth.config3()
+    g0 = cfg["grid"]
+    perm = dpf.rcm_order(g0.n_bus, g0.f, g0.t, group=2560)[0]
+    g = renumber(g0, perm)
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    S = S0[None, :] * cfg["load_scale"][:, perm] + cfg["solar_p"][:, perm]
+    T, window, steps = S.shape[0], 16, 3
+    rng = np.random.default_rng(3100)
+    vm0 = g.vm + np.where(g.bus_type == 0, rng.normal(0, 1e-3, g.n_bus), 0.0)
+    va0 = g.va + np.where(g.bus_type != 2, rng.normal(0, 1e-3, g.n_bus), 0.0)
+    route = dpf.Route(tail_team=32, tail_chunk=4096, tail_slice_ms=10.0) if path == "split" else dpf.Route()
+    print(f"full time series on the {path} path", flush=True)
+    Yg = dgrid(dpf, g)
+    out = dpf.solve_series(Yg, g.bus_type, cu(S, torch.complex128), vm0, va0, window=window,
+                           opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps), route=route)
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * T
+    gvm = out["vm"].cpu().numpy(); gva = out["va"].cpu().numpy()
+    Yo = oracle.ybus_of(g)
+    opts = oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps)
+    for t in range(T):
+        t0 = t - t % window
+        sm, sa = (vm0, va0) if t0 == 0 else (gvm[t0 - 1], gva[t0 - 1])
+        r = oracle.solve_adam(Yo, g.bus_type, S[t], sm, sa, opts)
+        assert np.abs(gvm[t] - r["vm"]).max() < 1e-10, t
+        assert np.abs(gva[t] - r["va"]).max() < 1e-10, t
+
+
 def test_done_ns_orders_items_by_work(dpf):
     """Items that stop earlier report earlier completion times."""
     g = synth.config0(0)["grid"]
