@@ -315,12 +315,27 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    kernel plans team sizes and order from the sub-grid sizes and
  *                    bandwidths.  1: the multi-workgroup path (three kernels per
  *                    iteration, host polls every 32 iterations)
- * A call with tail_handoff > 0, a split-kernel start (tail_team > 0 and few large
- * items) or the multi-workgroup path (wide_host = 1 with items above the LDS or
- * team cap, or variant naming that path) BLOCKS the host until it is done and
- * cannot be captured in a graph; every other call, persistent teams included,
- * only enqueues work (one kernel launch for the items plus a few set-up kernels)
- * and can be captured.
+ *   tail_device    : 0 (default): the host plans every split-kernel launch of a
+ *                    handoff or split-kernel start (team table, items left) and
+ *                    waits for each.  1 (needs tail_team > 0, and a grid whose
+ *                    exchange vector fits one workgroup's LDS, else
+ *                    DPF_EUNSUPPORTED): the call enqueues a fixed sequence of
+ *                    launches, each planned on the device by a one-workgroup
+ *                    kernel from the paused items with the same rule (team sizes
+ *                    by remaining budget with a time slice, else equal), and
+ *                    nothing waits on the host; with a time slice there are 256
+ *                    launches (a launch with nothing left only starts and ends),
+ *                    without one enough for max_iter at tail_chunk iterations
+ *                    each, and a last one without limits.  tail_min_items is not
+ *                    used; an item whose team gives up at a barrier is planned
+ *                    again in the next launch, and one still paused after the
+ *                    last ends with DPF_UNFINISHED
+ * A call with tail_handoff > 0 or a split-kernel start (tail_team > 0 and few
+ * large items) without tail_device, or the multi-workgroup path (wide_host = 1
+ * with items above the LDS or team cap, or variant naming that path) BLOCKS the
+ * host until it is done and cannot be captured in a graph; every other call,
+ * persistent teams and tail_device included, only enqueues work and can be
+ * captured.
  * A field out of range makes the call return DPF_EINVAL.
  */
 typedef struct dpf_route {
@@ -335,6 +350,7 @@ typedef struct dpf_route {
     double tail_wait_s;
     int32_t case_order;
     int32_t wide_host;
+    int32_t tail_device;
 } dpf_route_t;
 
 /* Fill *route with the defaults (host; no device call). */

@@ -51,7 +51,8 @@ class _Opts(ctypes.Structure):
 class _Route(ctypes.Structure):
     _fields_ = [("variant", _i32), ("team_cap", _i32), ("tail_handoff", _i32), ("tail_team", _i32),
                 ("tail_chunk", _i32), ("tail_min_items", _i32), ("tail_slice_ms", _f64),
-                ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("wide_host", _i32)]
+                ("tail_first_wait_s", _f64), ("tail_wait_s", _f64), ("case_order", _i32), ("wide_host", _i32),
+                ("tail_device", _i32)]
 
 
 class _Trace(ctypes.Structure):
@@ -312,7 +313,9 @@ class Route:
     left to the multi-workgroup path, barrier wait bounds -- the case order
     (1 = descending initial max|dS|) and how sub-grids above one workgroup run
     (wide_host 0: persistent teams in the call's one launch, 1: the host-driven
-    multi-workgroup path).  The defaults equal dpf_route_default."""
+    multi-workgroup path), and who plans the split-kernel tail (tail_device 0:
+    the host, which blocks; 1: the device, so the call can be captured).  The
+    defaults equal dpf_route_default."""
     variant: int = -1
     team_cap: int = 0
     tail_handoff: int = 0
@@ -324,12 +327,13 @@ class Route:
     tail_wait_s: float = 5.0
     case_order: int = 0
     wide_host: int = 0
+    tail_device: int = 0
 
     def c(self) -> _Route:
         return _Route(int(self.variant), int(self.team_cap), int(self.tail_handoff), int(self.tail_team),
                       int(self.tail_chunk), int(self.tail_min_items), float(self.tail_slice_ms),
                       float(self.tail_first_wait_s), float(self.tail_wait_s), int(self.case_order),
-                      int(self.wide_host))
+                      int(self.wide_host), int(self.tail_device))
 
 
 def _route(route):
@@ -575,7 +579,7 @@ def route_default() -> Route:
     r = _Route()
     lib().dpf_route_default(ctypes.byref(r))
     return Route(r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items,
-                 r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.wide_host)
+                 r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.wide_host, r.tail_device)
 
 
 def split_stats() -> dict:

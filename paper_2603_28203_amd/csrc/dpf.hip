@@ -122,6 +122,7 @@ dpf_route_t default_route() {
     r.tail_wait_s = 5.0;
     r.case_order = 0;
     r.wide_host = 0;
+    r.tail_device = 0;
     return r;
 }
 
@@ -139,6 +140,8 @@ const char *route_error(const dpf_route_t &r) {
         return "route wait bounds must be in [0, 60] s";
     if (r.case_order < 0 || r.case_order > 1) return "route.case_order must be 0 or 1";
     if (r.wide_host < 0 || r.wide_host > 1) return "route.wide_host must be 0 or 1";
+    if (r.tail_device < 0 || r.tail_device > 1) return "route.tail_device must be 0 or 1";
+    if (r.tail_device == 1 && r.tail_team == 0) return "route.tail_device needs route.tail_team > 0";
     return nullptr;
 }
 
@@ -651,6 +654,73 @@ int run_split(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const De
 
 // Bytes of static LDS the persistent team kernel uses besides its window.
 constexpr int kTeamStaticLds = 2 * (dpf::kTeamThreads / dpf::kWave) * 8 + (dpf::kTeamThreads / dpf::kWave) * 4 + 64;
+
+// The split kernel for the paused items with every launch planned on the device
+// (route.tail_device): on `st`, a fixed sequence of (plan, split kernel, collect)
+// launches and no host wait, so the call can be captured.  Launches end after
+// `chunk` iterations or the time slice, as on the host; with a time slice there
+// are kTailDeviceSlices of them, without one enough for max_iter, and a last
+// launch without either limit.  A launch whose list is
+// empty costs its workgroups nothing but their start.  A case whose team gave up
+// at a barrier stays paused and is planned again; one still paused after the
+// last launch ends with DPF_UNFINISHED.  (The call checks beforehand that the
+// grid fits the split kernel.)
+constexpr int kTailDeviceSlices = 256;
+int run_split_device(const dpf::SolveArgs &a0, const SolveLayout &L, char *ws, const DeviceInfo &dev,
+                     int32_t *list, int32_t B, const dpf_route_t &route, hipStream_t st) {
+    dpf::SolveArgs a = a0;
+    a.handoff = 0;
+    const int32_t ns = (a.n_bus + dpf::kWave - 1) / dpf::kWave;
+    const size_t lds_x = (size_t)a.n_bus * 16 + (size_t)(a.n_bus + 31) / 32 * 4;
+    if (lds_x + 512 > (size_t)dev.lds_per_block) return fail(DPF_EUNSUPPORTED, "grid too large for route.tail_device");
+    const int32_t list_cap = (int32_t)std::min<size_t>((size_t)a.n_bus, ((size_t)dev.lds_per_block - 512 - lds_x) / 2);
+    const size_t lds = lds_x + align_up((size_t)list_cap * 2, 4);
+    constexpr int kSplitThreads = 512;
+    void (*fn)(dpf::SolveArgs, dpf::SplitArgs) = dpf::team_solve_split_kernel<kSplitThreads>;
+    DPF_HIP(hipFuncSetAttribute((const void *)fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+    int per_cu = 0;
+    DPF_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, kSplitThreads, lds));
+    const int64_t capacity = (int64_t)std::max(per_cu, 0) * dev.n_cu;
+    if (capacity < 1) return fail(DPF_EUNSUPPORTED, "the split kernel does not fit a compute unit");
+    const int32_t tmax = (int32_t)std::max<int64_t>(1, std::min<int64_t>(route.tail_team, ns));
+    int32_t *hdr = (int32_t *)ws;  // header words 6 (paused count) and 7 (abandoned flag)
+    dpf::SplitArgs p{};
+    p.n_list_dev = hdr + 6;
+    p.bar = (int32_t *)(ws + L.off_bar);
+    p.part = (double2 *)(ws + L.off_part);
+    p.first = (const int32_t *)(ws + L.off_tfirst);
+    p.Ig = a.scratch;
+    p.Wg = a.scratch + 2 * a.st_stride;
+    p.aborted = hdr + 7;
+    p.first_limit = (int64_t)(route.tail_first_wait_s * 1e9 / dev.ns_per_tick);
+    p.limit = (int64_t)(route.tail_wait_s * 1e9 / dev.ns_per_tick);
+    p.list_cap = list_cap;
+    const int64_t slice = route.tail_slice_ms > 0.0 ? (int64_t)(route.tail_slice_ms * 1e6 / dev.ns_per_tick) : 0;
+    const int64_t n_launch = slice > 0 ? kTailDeviceSlices + 1
+                                       : ((int64_t)a.max_iter + route.tail_chunk) / route.tail_chunk + 1;
+    // a grid that holds every team of a plan (at most capacity members, or one per
+    // case when there are more cases than that)
+    const unsigned grid = (unsigned)std::max<int64_t>(capacity, B);
+    hipLaunchKernelGGL(dpf::split_clear_kernel, dim3(1), dim3(64), 0, st, 1, 1, p.aborted);
+    int32_t *cur = list;
+    int32_t *other = (int32_t *)(list == (int32_t *)(ws + L.off_list) ? ws + L.off_list2 : ws + L.off_list);
+    for (int64_t k = 0; k < n_launch; ++k) {
+        const bool last = k == n_launch - 1;
+        hipLaunchKernelGGL(dpf::split_plan_kernel, dim3(1), dim3(dpf::kSplitPlanThreads), 0, st, cur, hdr + 6,
+                           a.iters, a.max_iter, (int32_t)capacity, tmax, slice > 0 ? 1 : 0, (int32_t *)p.first,
+                           p.bar);
+        p.list = cur;
+        p.slice = last ? 0 : slice;
+        p.chunk = last ? a.max_iter + 1 : route.tail_chunk;
+        hipLaunchKernelGGL(fn, dim3(grid), dim3(kSplitThreads), lds, st, a, p);
+        hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, st, B, a.status, other, hdr + 6);
+        std::swap(cur, other);
+    }
+    hipLaunchKernelGGL(dpf::split_unfinished_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, a.status);
+    DPF_HIP(hipGetLastError());
+    g_split_launches.fetch_add(n_launch);
+    return DPF_OK;
+}
 
 // Persistent teams (teams.hpp): every item of the call in one launch on `st`, with
 // a device-side plan; nothing waits on the host, so the call can be captured.
@@ -1310,6 +1380,9 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
     const Variant *v = plan.v;
     if (!v) return fail(DPF_EUNSUPPORTED, "no kernel variant");
     const bool handoff = plan.handoff > 0;
+    if (rt.tail_device == 1 && (handoff || plan.split_direct) &&
+        (size_t)g->n_bus * 16 + (size_t)(g->n_bus + 31) / 32 * 4 + 512 > (size_t)dev.lds_per_block)
+        return fail(DPF_EUNSUPPORTED, "route.tail_device: the grid is too large for the split kernel");
     const bool pairs = v->mode == dpf::kPair && has_small;
     const SolveLayout L = solve_layout(g, n_sub, sub_offset, B, ld, v->mode != dpf::kReg, cap,
                                        handoff || plan.split_direct, pairs, plan.teams);
@@ -1448,8 +1521,24 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         a.order = order;
     }
     if (plan.teams) return run_teams(a, L, ws, n_sub, B, dev, rt, st);
+    const bool tail_device = rt.tail_device == 1 && rt.tail_team > 0 && !has_wide;
     std::unique_lock<std::mutex> side_lock;  // concurrent blocking calls on one device take turns
-    if (has_wide || handoff || plan.split_direct) side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
+    if (has_wide || ((handoff || plan.split_direct) && !tail_device))
+        side_lock = std::unique_lock<std::mutex>(g_side_mu[dev.index]);
+    if (plan.split_direct && tail_device) {
+        // every item starts paused at iteration 0, listed on the device
+        int32_t *list = (int32_t *)(ws + L.off_list);
+        hipLaunchKernelGGL(dpf::split_start_kernel, dim3((B + 255) / 256), dim3(256), 0, st, B, a.ov, a.status,
+                           a.iters, list);
+        if (a.st_fresh) {
+            const int64_t words = 4 * (int64_t)B * ld;
+            hipLaunchKernelGGL(dpf::zero_f64_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, st, words,
+                               a.st);
+        }
+        hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, st, B, a.status, list, bad + 6);
+        DPF_HIP(hipGetLastError());
+        return run_split_device(a, L, ws, dev, list, B, rt, st);
+    }
     if (plan.split_direct) {
         // every item starts paused at iteration 0; the split kernel runs them, and any
         // it leaves (a team abandoned a barrier) finish on the multi-workgroup path
@@ -1511,6 +1600,14 @@ int dpf_solve_batch(const dpf_grid_t *g, int32_t n_sub, const int32_t *sub_offse
         if (rc2 != DPF_OK) return rc2;
         DPF_HIP(hipEventRecord(dev.ev_out, dev.side));
         DPF_HIP(hipStreamWaitEvent(st, dev.ev_out, 0));
+    }
+    if (handoff && tail_device) {
+        // the items the per-item kernels paused finish on the split kernel, every
+        // launch planned on the device
+        int32_t *list = (int32_t *)(ws + L.off_list);
+        hipLaunchKernelGGL(dpf::collect_paused_kernel, dim3(1), dim3(1024), 0, st, B, a.status, list, bad + 6);
+        DPF_HIP(hipGetLastError());
+        return run_split_device(a, L, ws, dev, list, B, rt, st);
     }
     if (handoff) {
         // the items the per-item kernels paused finish on the multi-workgroup path

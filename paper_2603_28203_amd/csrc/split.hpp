@@ -62,6 +62,7 @@ constexpr int32_t kBarStride = 64;
 struct SplitArgs {
     const int32_t *list;  // [n_list] paused case indices
     int32_t n_list;
+    const int32_t *n_list_dev;  // the list's length in device memory (planned on the device), or null
     const int32_t *first; // [n_list + 1] first workgroup of each team (sizes <= slices of the grid)
     int32_t chunk;        // iterations per launch
     int64_t slice;        // wall-clock ticks per launch, 0 = no limit
@@ -109,8 +110,11 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
 
     const int tid = threadIdx.x;
     const int lane = tid & (kWave - 1);
+    // a launch planned on the device has a fixed grid: workgroups past the table leave
+    const int32_t n_list = p.n_list_dev ? *p.n_list_dev : p.n_list;
+    if (n_list <= 0 || (int)blockIdx.x >= p.first[n_list]) return;
     int team = 0;  // largest k with first[k] <= blockIdx.x
-    for (int hi_k = p.n_list - 1; team < hi_k;) {
+    for (int hi_k = n_list - 1; team < hi_k;) {
         const int m = (team + hi_k + 1) >> 1;
         if (p.first[m] <= (int)blockIdx.x) team = m;
         else hi_k = m - 1;
@@ -460,6 +464,87 @@ __global__ void zero_f64_kernel(int64_t n, double *__restrict__ x) {
 __global__ void split_clear_kernel(int32_t n, int32_t stride, int32_t *__restrict__ bar) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) bar[(int64_t)i * stride] = 0;
+}
+
+// Team table of one split-kernel launch, planned on the device from the list of
+// paused cases (*count of them) by the rule the host otherwise applies: with
+// by_budget, team sizes in proportion to the square of each case's remaining
+// budget max_iter - iters (at least 1, at most tmax, together at most capacity,
+// the largest teams shrunk first when the floors overshoot); else equal teams
+// of min(tmax, capacity / cases).  first[k] is the first workgroup of team k;
+// the arrival counters of the listed teams are cleared.  One workgroup.
+constexpr int kSplitPlanThreads = 1024;
+__global__ __launch_bounds__(kSplitPlanThreads) void split_plan_kernel(
+    const int32_t *__restrict__ list, const int32_t *__restrict__ count, const int32_t *__restrict__ iters,
+    int32_t max_iter, int32_t capacity, int32_t tmax, int32_t by_budget, int32_t *__restrict__ first,
+    int32_t *__restrict__ bar) {
+    __shared__ double wpart[kSplitPlanThreads];
+    __shared__ long long tpart[kSplitPlanThreads];
+    __shared__ double sh_wsum;
+    const int tid = threadIdx.x;
+    const int n = *count;
+    const int per = (n + kSplitPlanThreads - 1) / kSplitPlanThreads;  // contiguous cases per thread
+    const int k0 = min(tid * per, n), k1 = min(k0 + per, n);
+    auto weight = [&](int k) {
+        const double r = (double)max(1, max_iter - iters[list[k]]);
+        return r * r;
+    };
+    const bool budget = by_budget && n <= capacity;
+    if (budget) {
+        double w = 0.0;
+        for (int k = k0; k < k1; ++k) w += weight(k);
+        wpart[tid] = w;
+        __syncthreads();
+        if (tid == 0) {  // the partials in thread order: the sum of the cases in list order
+            double t = 0.0;
+            for (int q = 0; q < kSplitPlanThreads; ++q) t += wpart[q];
+            sh_wsum = t;
+        }
+        __syncthreads();
+    }
+    // team sizes into first[k + 1], then their running sum
+    long long own = 0;
+    for (int k = k0; k < k1; ++k) {
+        long long t;
+        if (budget) t = min<long long>(max<long long>((long long)(weight(k) / sh_wsum * (double)capacity), 1), tmax);
+        else t = max(1, min(capacity / max(n, 1), tmax));
+        first[k + 1] = (int32_t)t;
+        own += t;
+    }
+    tpart[tid] = own;
+    __syncthreads();
+    if (tid == 0) {
+        long long total = 0;
+        for (int q = 0; q < kSplitPlanThreads; ++q) total += tpart[q];
+        while (budget && total > capacity) {  // the floor of 1 can overshoot: shrink the largest teams
+            int big = 0;
+            for (int k = 1; k < n; ++k)
+                if (first[k + 1] > first[big + 1]) big = k;
+            if (first[big + 1] <= 1) break;
+            --first[big + 1];
+            --total;
+        }
+        first[0] = 0;
+    }
+    __syncthreads();
+    own = 0;
+    for (int k = k0; k < k1; ++k) own += first[k + 1];
+    tpart[tid] = own;
+    __syncthreads();
+    long long before = 0;
+    for (int q = 0; q < tid; ++q) before += tpart[q];
+    for (int k = k0; k < k1; ++k) {
+        before += first[k + 1];
+        first[k + 1] = (int32_t)before;
+    }
+    for (int k = tid; k < n; k += kSplitPlanThreads) bar[(int64_t)k * kBarStride] = 0;
+}
+
+// after the last launch planned on the device: a case still paused (its team gave
+// up waiting at a barrier in every launch) ends with DPF_UNFINISHED
+__global__ void split_unfinished_kernel(int32_t B, int32_t *__restrict__ status) {
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < B && status[c] == kPaused) status[c] = DPF_UNFINISHED;
 }
 
 }  // namespace dpf

@@ -118,7 +118,8 @@ class _Route(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("team_cap", ctypes.c_int32), ("tail_handoff", ctypes.c_int32),
                 ("tail_team", ctypes.c_int32), ("tail_chunk", ctypes.c_int32), ("tail_min_items", ctypes.c_int32),
                 ("tail_slice_ms", ctypes.c_double), ("tail_first_wait_s", ctypes.c_double),
-                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("wide_host", ctypes.c_int32)]
+                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("wide_host", ctypes.c_int32),
+                ("tail_device", ctypes.c_int32)]
 
 
 def _ws_types(lib):
@@ -143,6 +144,7 @@ def test_route_defaults_and_field_checks(lib):
     assert (r.variant, r.team_cap, r.tail_handoff, r.tail_team, r.tail_chunk, r.tail_min_items) == (-1, 0, 0, 0,
                                                                                                     128, 0)
     assert (r.tail_slice_ms, r.tail_first_wait_s, r.tail_wait_s, r.case_order, r.wide_host) == (0.0, 1.0, 5.0, 0, 0)
+    assert r.tail_device == 0
     g = _Grid(9241, 41339, 10, 1, 1, 1, 0, None, None, None, None, None)
     ok = lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, ctypes.byref(r))
     assert ok == lib.dpf_solve_workspace_bytes(ctypes.byref(g), 1, None, 1024, 9241, None) > 0
@@ -150,7 +152,8 @@ def test_route_defaults_and_field_checks(lib):
            ("tail_team", 1025), ("tail_chunk", 0), ("tail_chunk", 65537), ("tail_min_items", -1),
            ("tail_slice_ms", -1.0), ("tail_slice_ms", 1001.0), ("tail_slice_ms", float("nan")),
            ("tail_first_wait_s", -1.0), ("tail_wait_s", 61.0), ("tail_first_wait_s", float("nan")),
-           ("case_order", 2), ("case_order", -1), ("wide_host", 2), ("wide_host", -1)]
+           ("case_order", 2), ("case_order", -1), ("wide_host", 2), ("wide_host", -1),
+           ("tail_device", 2), ("tail_device", -1), ("tail_device", 1)]  # 1 needs tail_team > 0
     for name, val in bad:
         rb = _default_route(lib)
         setattr(rb, name, val)

@@ -1744,6 +1744,142 @@ def test_tail_handoff_continues_on_the_multi_workgroup_path(handoff, kind, thres
     assert split_ran(dpf, stats) == (team > 0)
 
 
+def _tail_problem(dpf):
+    base = synth.config1(B=1, seed=9700, n_bus=700, n_branch=1120, n_pv=110)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S0 = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    B = 8
+    rng = np.random.default_rng(97)
+    S = np.tile(S0, (B, 1))
+    S[1, 7] = np.nan
+    nbr = synth.non_bridge_branches(g.n_bus, g.f, g.t)
+    outage = np.where(np.arange(B) % 2 == 0, -1, rng.choice(nbr, B)).astype(np.int32)
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    vm0[3], va0[3] = g.vm, g.va
+    outage[3] = -1
+    return g, S, outage, vm0, va0
+
+
+@pytest.mark.parametrize("kind", ["banded-pair", "streaming"])
+@pytest.mark.parametrize("threshold", [5, 64])
+@pytest.mark.parametrize("slice_ms", [0.0, 2.0])
+def test_device_planned_tail_tracks_oracle(handoff, kind, threshold, slice_ms):
+    """route.tail_device: the paused items finish on split-kernel launches that
+    the device plans (equal teams of up to 8 workgroups per 16-iteration launch,
+    or teams by remaining budget in 2 ms slices), with no host wait: statuses,
+    iteration counts, iterates and the plateau schedule equal the oracle's and
+    the same call without handoff."""
+    dpf = handoff
+    dpf.set_tail_team(8, 16, 3, slice_ms)
+    dpf.route.tail_device = 1
+    g, S, outage, vm0, va0 = _tail_problem(dpf)
+    B = S.shape[0]
+    steps = 100
+    pl = dict(sched=oracle.SCHED_PLATEAU, factor=0.5, patience=3, threshold=0.2, cooldown=2)
+    refs = [oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                              oracle.AdamOptions(lr=1e-3, tol=1e-9, max_iter=steps, **pl)) for c in range(B)]
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == kind and
+         (x["buses_per_thread"] == 0 or x["threads"] * x["buses_per_thread"] >= 256)][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    opts = dpf.Options(lr=1e-3, tol=1e-9, max_iter=steps, **pl)
+    res = {}
+    for h in (0, threshold):
+        dpf.set_tail_handoff(h)
+        print(f"device-planned tail: handoff {h} variant {v['index']} slice {slice_ms} ms", flush=True)
+        vm = cu(vm0); va = cu(va0)
+        sch = torch.tensor([[0.0, 1e-3, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+        out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                        sched_state=sch, opts=opts)
+        torch.cuda.synchronize()
+        assert out["status"].tolist() == [r["status"] for r in refs], h
+        assert out["iters"].tolist() == [r["iters"] for r in refs], h
+        for c in range(B):
+            if refs[c]["status"] == 2:
+                continue
+            assert np.abs(vm[c].cpu().numpy() - refs[c]["vm"]).max() < 1e-10, (h, c)
+            assert np.abs(va[c].cpu().numpy() - refs[c]["va"]).max() < 1e-10, (h, c)
+            assert sch[c, 1].item() == pytest.approx(refs[c]["lr"], rel=1e-15)
+            assert sch[c, 0].item() == refs[c]["iters"]
+        res[h] = (vm.cpu().numpy(), va.cpu().numpy())
+    d = max(np.abs(res[0][0] - res[threshold][0]).max(), np.abs(res[0][1] - res[threshold][1]).max())
+    assert d < 1e-12
+
+
+def test_device_planned_tail_replays_from_a_captured_graph(handoff):
+    """A handoff call with the device-planned tail only enqueues work: captured
+    once in a HIP graph and replayed three times (inputs restored between
+    replays, with other work and synchronisations in between), every replay
+    equals the eager call bit for bit."""
+    dpf = handoff
+    dpf.set_tail_team(8, 16, 0, 0.0)
+    dpf.route.tail_device = 1
+    dpf.set_tail_handoff(5)
+    g, S, outage, vm0, va0 = _tail_problem(dpf)
+    B = S.shape[0]
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-pair" and x["threads"] * x["buses_per_thread"] >= 256][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    opts = dpf.Options(lr=1e-3, tol=1e-9, max_iter=100)
+    bt = torch.tensor(g.bus_type, dtype=torch.int8, device="cuda")
+    Sd = cu(S, torch.complex128); od = cu(outage, torch.int32)
+    ws = dpf.SolveWorkspace()
+    outs = {k: torch.empty(B, dtype=dt, device="cuda") for k, dt in
+            (("iters", torch.int32), ("status", torch.int32), ("max_mis", torch.float64), ("loss", torch.float64))}
+    vm = cu(vm0); va = cu(va0)
+    print("device-planned tail: eager call", flush=True)
+    dpf.solve(Yg, bt, Sd, vm, va, outage=od, opts=opts, workspace=ws, outputs=outs)
+    torch.cuda.synchronize()
+    ref = (vm.clone(), va.clone(), {k: v_.clone() for k, v_ in outs.items()})
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        vm.copy_(cu(vm0)); va.copy_(cu(va0))
+        dpf.solve(Yg, bt, Sd, vm, va, outage=od, opts=opts, workspace=ws, outputs=outs)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dpf.solve(Yg, bt, Sd, vm, va, outage=od, opts=opts, workspace=ws, outputs=outs)
+    for rep in range(3):
+        vm.copy_(cu(vm0)); va.copy_(cu(va0))
+        torch.cuda.synchronize()
+        print(f"device-planned tail: replay {rep}", flush=True)
+        graph.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(vm, ref[0]) and torch.equal(va, ref[1]), rep
+        for k in ("iters", "status", "max_mis", "loss"):  # the case with a NaN injection reports NaN
+            assert np.array_equal(outs[k].cpu().numpy(), ref[2][k].cpu().numpy(), equal_nan=True), (rep, k)
+
+
+def test_device_planned_split_start_tracks_oracle(handoff):
+    """Few large items (two cases of a 3000-bus grid) start on the split kernel
+    with the device-planned launches: they follow the oracle."""
+    dpf = handoff
+    dpf.set_tail_team(16, 8, 0, 0.0)
+    dpf.route.tail_device = 1
+    base = synth.config1(B=1, seed=9710, n_bus=3000, n_branch=4500, n_pv=500)["grid"]
+    g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
+    S = oracle.injections(oracle.ybus_of(g), g.vm, g.va)
+    rng = np.random.default_rng(971)
+    B = 2
+    vm0 = g.vm[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type == 0)
+    va0 = g.va[None] + rng.normal(0, 1e-2, (B, g.n_bus)) * (g.bus_type != 2)
+    steps = 40
+    Yg = dgrid(dpf, g)
+    vm = cu(vm0); va = cu(va0)
+    print("device-planned split start", flush=True)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    assert out["iters"].tolist() == [steps] * B and out["status"].tolist() == [dpf.MAX_ITER] * B
+    for c in range(B):
+        ref = oracle.solve_adam(oracle.ybus_of(g), g.bus_type, S, vm0[c], va0[c],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+
+
 @pytest.mark.parametrize("team", [0, 3])
 def test_tail_handoff_with_caller_moments_and_resume(handoff, team):
     """With the caller's optimizer state, a handed-over call continues exactly

@@ -68,7 +68,8 @@ class Route(ctypes.Structure):
     _fields_ = [("variant", ctypes.c_int32), ("team_cap", ctypes.c_int32), ("tail_handoff", ctypes.c_int32),
                 ("tail_team", ctypes.c_int32), ("tail_chunk", ctypes.c_int32), ("tail_min_items", ctypes.c_int32),
                 ("tail_slice_ms", ctypes.c_double), ("tail_first_wait_s", ctypes.c_double),
-                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("wide_host", ctypes.c_int32)]
+                ("tail_wait_s", ctypes.c_double), ("case_order", ctypes.c_int32), ("wide_host", ctypes.c_int32),
+                ("tail_device", ctypes.c_int32)]
 
 L.dpf_solve_workspace_bytes.restype = ctypes.c_size_t
 L.dpf_solve_workspace_bytes.argtypes = [ctypes.POINTER(Grid), ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
