@@ -54,6 +54,9 @@ TAIL_TEAM = (32, 4096, 0, 10.0)
 # a severe outage that starts late would otherwise set the end of the step; measured
 # 6.12 s per step against 6.33 s in index order
 CASE_ORDER = 1
+# the tail's split-kernel launches are planned on the device, so that the call only
+# enqueues work (capturable); the host-planned tail measured the same
+TAIL_DEVICE = 1
 FP64_PEAK_TFLOPS = 78.6
 
 
@@ -170,6 +173,46 @@ def run_fused(Yg, bt, S, out, vm0, va0, opts, steps, warmup, route=None):
         log(f"fused step {s} ({'warmup' if s < warmup else 'timed'}): {t1 - t0:.3f} s, "
             f"converged {int((res['status'] == 0).sum())}/{B}, max iters {int(res['iters'].max())}")
     return times, kern, res, vm, va
+
+
+def headline_graph(Yg, bt, S, out, vm0, va0, opts, route, eager):
+    """The headline call captured once in a HIP graph and replayed once (its tail
+    planned on the device, so the call only enqueues work): replay time, converged
+    cases and how the replay compares with the eager timed call (the time slices of
+    the tail make team sizes, and so rounding, depend on timing)."""
+    import torch
+
+    import paper_2603_28203_amd as dpf
+
+    B = vm0.shape[0]
+    ws = dpf.SolveWorkspace()
+    outs = {k: torch.empty(B, dtype=dt, device="cuda") for k, dt in
+            (("iters", torch.int32), ("status", torch.int32), ("max_mis", torch.float64),
+             ("loss", torch.float64))}
+    vm, va = vm0.clone(), va0.clone()
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        dpf.solve(Yg, bt, S, vm, va, opts=opts, outage=out, workspace=ws, outputs=outs, route=route)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph):
+        dpf.solve(Yg, bt, S, vm, va, opts=opts, outage=out, workspace=ws, outputs=outs, route=route)
+    vm.copy_(vm0)
+    va.copy_(va0)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    graph.replay()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = outs["status"].cpu().numpy()
+    conv = int((st == 0).sum())
+    log(f"headline call replayed from a captured graph: {dt:.3f} s, converged {conv}/{B}")
+    return {"what": "the same call captured once in a HIP graph and replayed", "s": round(dt, 3),
+            "converged": conv, "solves_per_s": round(conv / dt, 2),
+            "statuses_equal_eager": bool(np.array_equal(st, eager["status"])),
+            "iters_equal_eager": bool(np.array_equal(outs["iters"].cpu().numpy(), eager["iters"]))}
 
 
 def autograd_per_iter(g, Yg, S, bt, out, vm0, va0, opts, iters, B):
@@ -331,6 +374,8 @@ def main():
     ap.add_argument("--tail-team", type=str, default=":".join(map(str, TAIL_TEAM)),
                     help="max_team:chunk:min_items:slice_ms of the split kernel for handed-over cases "
                          "(0:1:0:0 = off)")
+    ap.add_argument("--tail-device", type=int, default=TAIL_DEVICE, choices=(0, 1),
+                    help="1: the split-kernel tail is planned on the device (the call can be captured); 0: on the host")
     ap.add_argument("--case-order", type=int, default=CASE_ORDER,
                     help="1: start cases by descending initial max|dS|, 0: index order")
     ap.add_argument("--cases", type=int, default=1024)
@@ -408,9 +453,12 @@ def main():
         f"tail { {k: round(v * 1e3, 2) for k, v in tail['seconds'].items()} } ms / 100 it)")
     tt = args.tail_team.split(":")
     tail_team = [int(x) for x in tt[:3]] + [float(tt[3]) if len(tt) > 3 else 0.0]
+    tail_device = args.tail_device if tail_team[0] > 0 else 0
     route = dpf.Route(variant=choice, tail_handoff=args.handoff, tail_team=tail_team[0], tail_chunk=tail_team[1],
-                      tail_min_items=tail_team[2], tail_slice_ms=tail_team[3], case_order=args.case_order)
+                      tail_min_items=tail_team[2], tail_slice_ms=tail_team[3], case_order=args.case_order,
+                      tail_device=tail_device)
     times, kern, res, vm, va = run_fused(Yg, bt, S, out, vm0, va0, opts, args.steps, args.warmup, route)
+    graph_line = headline_graph(Yg, bt, S, out, vm0, va0, opts, route, res) if tail_device else None
     t_step = float(np.mean(times))
     t_kern = float(np.mean(kern))
     conv = int((res["status"] == 0).sum())
@@ -476,6 +524,8 @@ def main():
                    "tail_handoff": args.handoff,
                    "tail_team": {"max_team": tail_team[0], "chunk": tail_team[1], "min_items": tail_team[2],
                                  "slice_ms": tail_team[3]},
+                   "tail_planned_on": ("device (the call only enqueues work)" if tail_device else
+                                       "host (the call waits for every tail launch)"),
                    "case_order": "descending initial max|dS|" if args.case_order == 1 else "index",
                    "optimizer": {"lr": opts.lr, "betas": [opts.beta1, opts.beta2], "eps": opts.eps,
                                  "schedule": "plateau", "factor": opts.factor, "patience": opts.patience,
@@ -491,6 +541,8 @@ def main():
         "roofline": roofline,
         "solve_rate": solve_rate,
     }
+    if graph_line is not None:
+        line["graph_replay"] = graph_line
 
     if not args.no_autograd:
         log("autograd baseline: the N-1 batch per iteration, and a fixed 32-case sample to convergence")
