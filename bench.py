@@ -648,7 +648,7 @@ def base_injections(Yg, g):
     return dpf.mismatch_grad(Yg, g.bus_type, zero, vm_p, va_p, want_grad=False)["dS"][0].contiguous()
 
 
-def cfg3_series(cap, tail_team):
+def cfg3_series(cap, tail_team, tail_device=TAIL_DEVICE):
     """Time series on the 9241-bus grid: 96 quarter-hour steps, sequential
     warm-started solves (window 1) against windows of 16 steps solved as one
     batch, each step capped at `cap` Adam iterations."""
@@ -682,7 +682,7 @@ def cfg3_series(cap, tail_team):
         runs = [("sequential", 1, True), ("windows_of_16", 16, True)] + runs
     for name, window, split in runs:
         rt = dpf.Route(tail_team=tail_team[0], tail_chunk=tail_team[1], tail_min_items=tail_team[2],
-                       tail_slice_ms=tail_team[3]) if split else dpf.Route()
+                       tail_slice_ms=tail_team[3], tail_device=tail_device) if split else dpf.Route()
         dpf.solve_series(Yg, g.bus_type, S[:window], vm0, va0, window=window, opts=solve_options(10), route=rt)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
