@@ -1853,6 +1853,57 @@ def test_device_planned_tail_replays_from_a_captured_graph(handoff):
             assert np.array_equal(outs[k].cpu().numpy(), ref[2][k].cpu().numpy(), equal_nan=True), (rep, k)
 
 
+def test_device_planned_tail_with_zero_waits_ends_unfinished_and_continues(handoff):
+    """With zero barrier waits, teams of the device-planned tail give up at their
+    barriers (how many depends on timing): an item left paused after the last
+    launch reports DPF_UNFINISHED with the state of a whole iteration, and a
+    further call from that state (caller-owned moments and schedule) brings every
+    item to the oracle's 100-iteration solve."""
+    dpf = handoff
+    dpf.set_tail_team(8, 16, 0, 0.0)
+    dpf.route.tail_device = 1
+    dpf.set_tail_waits(0.0, 0.0)
+    dpf.set_tail_handoff(64)  # every item is handed over after its first 32 iterations
+    g, S, outage, vm0, va0 = _tail_problem(dpf)
+    B = S.shape[0]
+    # the perturbed starts with finite injections (case 3 starts at the planted state,
+    # where Adam amplifies rounding-level gradients)
+    keep = [c for c in range(B) if np.all(np.isfinite(S[c])) and c != 3]
+    S, outage, vm0, va0 = S[keep], outage[keep], vm0[keep], va0[keep]
+    B = len(keep)
+    steps = 100
+    Yg = dgrid(dpf, g)
+    v = [x for x in dpf.variants() if x["kind"] == "banded-pair" and x["threads"] * x["buses_per_thread"] >= 256][0]
+    dpf.lib().dpf_autotune_set(g.n_bus, v["index"])
+    vm = cu(vm0); va = cu(va0)
+    mom = torch.zeros((4, B, g.n_bus), dtype=torch.float64, device="cuda")
+    sch = torch.tensor([[0.0, 1e-3, float("inf"), 0.0, 1.0, 1.0]] * B, dtype=torch.float64, device="cuda")
+    print("device-planned tail with zero waits", flush=True)
+    out = dpf.solve(Yg, g.bus_type, cu(S, torch.complex128), vm, va, outage=cu(outage, torch.int32),
+                    adam_state=mom, sched_state=sch, opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps))
+    torch.cuda.synchronize()
+    st = out["status"].tolist(); its = out["iters"].tolist()
+    print(f"statuses {st}, iterations {its}", flush=True)
+    assert all(x in (dpf.MAX_ITER, dpf.UNFINISHED) for x in st)
+    assert all((x == dpf.MAX_ITER) == (n == steps) for x, n in zip(st, its)) and min(its) >= 32
+    dpf.set_tail_waits(1.0, 5.0)
+    for c in range(B):
+        if st[c] == dpf.UNFINISHED:  # continue this item alone from its saved state
+            vmc, vac = vm[c:c + 1].clone(), va[c:c + 1].clone()
+            momc = mom[:, c:c + 1].contiguous()
+            schc = sch[c:c + 1].clone()
+            r2 = dpf.solve(Yg, g.bus_type, cu(S[c:c + 1], torch.complex128), vmc, vac,
+                           outage=cu(outage[c:c + 1], torch.int32), adam_state=momc, sched_state=schc,
+                           opts=dpf.Options(lr=1e-3, tol=0.0, max_iter=steps - its[c]))
+            torch.cuda.synchronize()
+            assert r2["iters"].item() == steps - its[c] and r2["status"].item() == dpf.MAX_ITER
+            vm[c] = vmc[0]; va[c] = vac[0]
+        ref = oracle.solve_adam(oracle.ybus_of(g, skip=int(outage[c])), g.bus_type, S[c], vm0[c], va0[c],
+                                oracle.AdamOptions(lr=1e-3, tol=0.0, max_iter=steps))
+        assert np.abs(vm[c].cpu().numpy() - ref["vm"]).max() < 1e-10, c
+        assert np.abs(va[c].cpu().numpy() - ref["va"]).max() < 1e-10, c
+
+
 def test_device_planned_split_start_tracks_oracle(handoff):
     """Few large items (two cases of a 3000-bus grid) start on the split kernel
     with the device-planned launches: they follow the oracle."""
