@@ -2022,14 +2022,16 @@ def test_bench_configuration_at_full_size_with_handoff(handoff, kind, team, n_fi
     assert split_ran(dpf, stats) == (team > 0)
 
 
-@pytest.mark.parametrize("team", [0, 8])
-def test_concurrent_handoff_calls_on_two_streams(handoff, team):
+@pytest.mark.parametrize("team,device", [(0, 0), (8, 0), (8, 1)])
+def test_concurrent_handoff_calls_on_two_streams(handoff, team, device):
     """Two host threads, each with its own stream and workspace, run solves that
     hand their tail over at the same time; each result equals the same call run
-    alone (the side stream of the device is shared and taken in turns)."""
+    alone (the side stream of the device is shared and taken in turns; with the
+    tail planned on the device the two calls' launches simply interleave)."""
     import threading
     dpf = handoff
     dpf.set_tail_team(team, 64)
+    dpf.route.tail_device = device
     stats = dpf.split_stats()
     base = synth.config1(B=1, seed=9800, n_bus=700, n_branch=1120, n_pv=110)["grid"]
     g = renumber(base, dpf.rcm_order(base.n_bus, base.f, base.t)[0])
