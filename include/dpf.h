@@ -324,9 +324,10 @@ int dpf_param_grad(const dpf_grid_t *g, int32_t B, int32_t ld, const int8_t *bus
  *                    kernel from the paused items with the same rule (team sizes
  *                    by remaining budget with a time slice, else equal), and
  *                    nothing waits on the host; with a time slice there are 256
- *                    launches (a launch with nothing left only starts and ends),
- *                    without one enough for max_iter at tail_chunk iterations
- *                    each, and a last one without limits.  tail_min_items is not
+ *                    launches (a launch with nothing left only starts and ends;
+ *                    the tail is re-planned for 256 slices, whatever is left then
+ *                    runs on the last plan), without one enough for max_iter at
+ *                    tail_chunk iterations each, and a last one without limits.  tail_min_items is not
  *                    used; an item whose team gives up at a barrier is planned
  *                    again in the next launch, and one still paused after the
  *                    last ends with DPF_UNFINISHED
