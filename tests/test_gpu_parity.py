@@ -1967,18 +1967,21 @@ def test_tail_handoff_with_caller_moments_and_resume(handoff, team):
     assert split_ran(dpf, stats) == (team > 0)
 
 
-@pytest.mark.parametrize("kind,team,n_finite", [("banded-stream", 0, 124), ("banded-stream", 32, 124),
-                                                ("banded-stream", 16, 8), ("banded-pair", 32, 124)])
-def test_bench_configuration_at_full_size_with_handoff(handoff, kind, team, n_finite):
+@pytest.mark.parametrize("kind,team,n_finite,device", [("banded-stream", 0, 124, 0), ("banded-stream", 32, 124, 0),
+                                                       ("banded-stream", 16, 8, 0), ("banded-pair", 32, 124, 0),
+                                                       ("banded-pair", 32, 124, 1), ("banded-pair", 16, 8, 1)])
+def test_bench_configuration_at_full_size_with_handoff(handoff, kind, team, n_finite, device):
     """The bench's launch configuration at its full size: 1024 outage cases of
     the 9241-bus grid (RCM numbering degree-grouped in windows of 2560), the 1024 x 4 banded-stream
     kernel, the bench's optimizer settings and a tail handoff at 192 cases.  All
     but n_finite cases carry a non-finite injection and stop at once, so the
     others are handed over after 32 iterations (to the multi-workgroup path, or to
     the split kernel relaunched every 3 iterations: teams of 2 for 124 cases, of
-    16 for 8); sampled cases equal their oracle solves."""
+    16 for 8, planned by the host or on the device); sampled cases equal their
+    oracle solves."""
     dpf = handoff
     dpf.set_tail_team(team, 3)
+    dpf.route.tail_device = device
     stats = dpf.split_stats()
     cfg = synth.config2(B=1024)
     base = cfg["grid"]
