@@ -1024,12 +1024,13 @@ def test_series_windows_follow_the_warm_start_rule(dpf, window):
     assert np.all(out["done_ns"].cpu().numpy() > 0)
 
 
-@pytest.mark.parametrize("path", ["split", "teams"])
+@pytest.mark.parametrize("path", ["split", "split-device", "teams"])
 def test_series_at_full_size(dpf, path):
     """The time series of the benchmark at its full size (96 steps of the
     9241-bus grid, renumbered with degree grouping in windows of 2560) in windows
     of 16, on the split kernel from the first iteration (the benchmark's tail
-    settings) and on the persistent teams, 3 Adam steps per time step: every step
+    settings, launches planned by the host or on the device) and on the
+    persistent teams, 3 Adam steps per time step: every step
     equals the oracle's solve from the start the rule prescribes (the base point
     for window 0, else the device's own result for the last step of the window
     before).  Each step is checked from the device's start rather than along the
@@ -1045,7 +1046,8 @@ def test_series_at_full_size(dpf, path):
     rng = np.random.default_rng(3100)
     vm0 = g.vm + np.where(g.bus_type == 0, rng.normal(0, 1e-3, g.n_bus), 0.0)
     va0 = g.va + np.where(g.bus_type != 2, rng.normal(0, 1e-3, g.n_bus), 0.0)
-    route = dpf.Route(tail_team=32, tail_chunk=4096, tail_slice_ms=10.0) if path == "split" else dpf.Route()
+    route = (dpf.Route(tail_team=32, tail_chunk=4096, tail_slice_ms=10.0, tail_device=int(path == "split-device"))
+             if path.startswith("split") else dpf.Route())
     print(f"full time series on the {path} path", flush=True)
     Yg = dgrid(dpf, g)
     out = dpf.solve_series(Yg, g.bus_type, cu(S, torch.complex128), vm0, va0, window=window,
