@@ -392,6 +392,9 @@ def main():
                          "that rocprofv3 profiles for that kernel")
     ap.add_argument("--uneven-conv-cap", type=int, default=100000,
                     help="iteration cap of the uneven batch's run to convergence (0: skip it)")
+    ap.add_argument("--conv-cap", type=int, default=60000,
+                    help="iteration cap of the runs of the 1354-bus batch and of the time series (windows of 16) "
+                         "to the stop test (0: skip them)")
     ap.add_argument("--roofline-only", type=str, default=None, metavar="KIND",
                     help="only build the N-1 batch and run the roofline launch (all cases, 200 iterations, "
                          "warm-up then timed) on the 1024-thread, 4-bus variant of KIND (e.g. banded-pair): "
@@ -567,7 +570,7 @@ def main():
         line["speedup_vs_autograd"] = line["autograd"]["sample"]["speedup"]
 
         log("cfg1 comparison: 64 cases x 1354 buses, fused vs autograd per iteration")
-        line["cfg1"] = cfg1_comparison()
+        line["cfg1"] = cfg1_comparison(2000, args.conv_cap)
 
     if not args.no_extras:
         log("screening: the same N-1 batch at tol 1e-3 pu, 1000-iteration budget")
@@ -584,7 +587,7 @@ def main():
         log("graph: small solves issued eagerly vs replayed from a captured graph")
         line["graph"] = graph_replay()
         log("cfg3: time series, sequential vs windows of 16")
-        line["cfg3"] = cfg3_series(1000, tail_team)
+        line["cfg3"] = cfg3_series(1000, tail_team, conv_cap=args.conv_cap)
         log("cfg4: uneven batch of 129 grids")
         line["cfg4"] = cfg4_uneven(2000, args.uneven_conv_cap)
 
@@ -648,10 +651,12 @@ def base_injections(Yg, g):
     return dpf.mismatch_grad(Yg, g.bus_type, zero, vm_p, va_p, want_grad=False)["dS"][0].contiguous()
 
 
-def cfg3_series(cap, tail_team, tail_device=TAIL_DEVICE):
+def cfg3_series(cap, tail_team, tail_device=TAIL_DEVICE, conv_cap=0):
     """Time series on the 9241-bus grid: 96 quarter-hour steps, sequential
     warm-started solves (window 1) against windows of 16 steps solved as one
-    batch, each step capped at `cap` Adam iterations."""
+    batch, each step capped at `cap` Adam iterations.  With conv_cap > 0 the
+    windows of 16 run once more with that cap, to report how many steps reach
+    1e-6 pu and how long they take."""
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -695,6 +700,23 @@ def cfg3_series(cap, tail_team, tail_device=TAIL_DEVICE):
                      "iters_median": float(np.median(it)), "max_mis_median": float(np.median(r["max_mis"].cpu().numpy())),
                      "bus_iters_per_s": round(float(it.sum()) * g.n_bus / dt, 1)}
         log(f"cfg3 {name}: {dt:.2f} s, converged {int((st == 0).sum())}/96")
+    if conv_cap:
+        # the same windows (default routing: persistent teams) run to the stop
+        # test; a window starts from the previous window's last solution, so the
+        # call's time is the sum over the six windows of their slowest step
+        t0 = time.perf_counter()
+        r = dpf.solve_series(Yg, g.bus_type, S, vm0, va0, window=16, opts=solve_options(conv_cap))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it = r["iters"].cpu().numpy()
+        st = r["status"].cpu().numpy()
+        ok = st == 0
+        out["windows_of_16_to_convergence"] = {
+            "iter_cap": conv_cap, "s": round(dt, 3), "converged_steps": int(ok.sum()),
+            "converged_steps_per_s": round(int(ok.sum()) / dt, 2),
+            "iters_converged_p50_p90": ([float(np.percentile(it[ok], q)) for q in (50, 90)] if ok.any() else None),
+            "max_mis_median": float(np.median(r["max_mis"].cpu().numpy()))}
+        log(f"cfg3 windows of 16 to convergence: {dt:.2f} s, converged {int(ok.sum())}/96")
     return out
 
 
@@ -960,9 +982,12 @@ def copy_bandwidth(nbytes=1 << 30, reps=5):
 CFG1_ORDER_GROUP = 256
 
 
-def cfg1_comparison(iters=2000):
+def cfg1_comparison(iters=2000, conv_cap=0):
     """Fused solve kernel vs plain autograd on the 64-case 1354-bus batch
-    (flat start; neither reaches 1e-6 pu there, so per-iteration time)."""
+    (flat start; neither reaches 1e-6 pu within `iters` iterations there, so
+    per-iteration time).  With conv_cap > 0 the fused solve runs once more from
+    the flat start with the N-1 batch's optimizer settings and that cap, to
+    report how many cases reach 1e-6 pu and how long they take."""
     import torch
 
     import paper_2603_28203_amd as dpf
@@ -997,11 +1022,26 @@ def cfg1_comparison(iters=2000):
     ag.solve(vm, va, opts, time_only_iters=50)
     torch.cuda.synchronize()
     t_ag = (time.perf_counter() - t0) / 50
-    return {"workload": "64 cases x 1354 buses, flat start, Adam lr 1e-2",
-            "bus_order": f"reverse Cuthill-McKee, degree-grouped in windows of {CFG1_ORDER_GROUP} (bandwidth {bw})",
-            "fused_us_per_iter": round(t_fused * 1e6, 2), "autograd_us_per_iter": round(t_ag * 1e6, 1),
-            "speedup_per_iter": round(t_ag / t_fused, 1),
-            "converged_at_cap": int((o["status"] == 0).sum().item()), "cap": iters}
+    res = {"workload": "64 cases x 1354 buses, flat start, Adam lr 1e-2",
+           "bus_order": f"reverse Cuthill-McKee, degree-grouped in windows of {CFG1_ORDER_GROUP} (bandwidth {bw})",
+           "fused_us_per_iter": round(t_fused * 1e6, 2), "autograd_us_per_iter": round(t_ag * 1e6, 1),
+           "speedup_per_iter": round(t_ag / t_fused, 1),
+           "converged_at_cap": int((o["status"] == 0).sum().item()), "cap": iters}
+    if conv_cap:
+        t0 = time.perf_counter()
+        o = dpf.solve(Yg, g.bus_type, S, vm.clone(), va.clone(), opts=solve_options(conv_cap))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        it = o["iters"].cpu().numpy()
+        ok = o["status"].cpu().numpy() == 0
+        res["to_convergence"] = {
+            "optimizer": "the N-1 batch's settings (Adam lr 1e-4, betas 0.995, plateau patience 300), no re-tuning",
+            "iter_cap": conv_cap, "s": round(dt, 3), "converged": int(ok.sum()),
+            "solves_per_s": round(int(ok.sum()) / dt, 2),
+            "iters_converged_p50_p90": ([float(np.percentile(it[ok], q)) for q in (50, 90)] if ok.any() else None),
+            "max_mis_median": float(np.median(o["max_mis"].cpu().numpy()))}
+        log(f"cfg1 to convergence: {dt:.2f} s, converged {int(ok.sum())}/64")
+    return res
 
 
 if __name__ == "__main__":

@@ -350,11 +350,13 @@ def config2(seed: int = 2000, B: int = 1024, n_bus: int = 9241, n_branch: int = 
 
 
 def config3(seed: int = 3000, T: int = 96, n_bus: int = 9241, n_branch: int = 16049,
-            n_pv: int = 1445, window: int = 16) -> dict:
+            n_pv: int = 1445, window: int = 16, grid_seed: int = 2000) -> dict:
     """Time series: per-bus load factor 1 + 0.15 sin(2 pi t/96 + phi) + N(0, 0.02)
     on PQ buses, plus solar active injection peak * max(0, sin(pi (t-24)/48))
-    at 20% of the PQ buses (peak ~ U(0, 0.3) pu)."""
-    g = _pegase_like(seed, n_bus, n_branch, n_pv)
+    at 20% of the PQ buses (peak ~ U(0, 0.3) pu).  The grid is the N-1 batch's
+    (grid_seed, as config2 draws it); the loads and the solar buses come from
+    `seed`."""
+    g = _pegase_like(grid_seed, n_bus, n_branch, n_pv)
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(1)[0])
     pq = np.flatnonzero(g.bus_type == PQ)
     phi = rng.uniform(0.0, 2 * np.pi, size=g.n_bus)
