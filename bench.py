@@ -558,7 +558,7 @@ def main():
         line["autograd"] = {
             "per_iter_equal_batch": {"cases": B, "autograd_ms": round(t_it * 1e3, 3),
                                      "fused_ms": round(fused_ms, 4), "ratio": round(t_it * 1e3 / fused_ms, 1)},
-            "sample": {"cases": [int(c) for c in sample], "what": f"every {max(1, B // 32)}th case of the batch, "
+            "sample": {"cases": [int(c) for c in sample], "what": f"one case in {max(1, B // 32)} of the batch (indices 0, {max(1, B // 32)}, ...), "
                                                                   f"same inputs, options and {args.cap}-iteration cap",
                        "autograd": ag, "fused": fu,
                        "autograd_solves_per_s": round(ag_rate, 4),
