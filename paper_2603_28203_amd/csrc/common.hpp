@@ -39,6 +39,34 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
     return acc;
 }
 
+// acc + the products of one sliced-ELL row (entries base + q*kWave, q < w, w the
+// same in every lane of the wave) with the exchange vector get(col), added in
+// entry order as a plain loop adds them.  The loads of U entries are issued
+// together, the last group predicated: a row of up to U entries waits for the
+// cache once, and a longer one once per U entries (a loop unrolled by U with a
+// remainder loop waits once per remainder entry).
+template <int U, typename Get>
+__device__ __forceinline__ double2 sell_row(const double2 *__restrict__ val, const int32_t *__restrict__ col,
+                                            int base, int w, Get get, double2 acc) {
+    for (int q0 = 0; q0 < w; q0 += U) {
+        double2 v[U];
+        int32_t cc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            v[u] = make_double2(0.0, 0.0);
+            cc[u] = 0;
+            if (q0 + u < w) {
+                v[u] = val[base + (q0 + u) * kWave];
+                cc[u] = col[base + (q0 + u) * kWave];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (q0 + u < w) acc = cfma(v[u], get(cc[u]), acc);
+    }
+    return acc;
+}
+
 // Butterfly sum / max across the 64 lanes of a wave; every lane receives the
 // result and the combination order is fixed, so results are reproducible.
 __device__ __forceinline__ double wave_sum(double v) {

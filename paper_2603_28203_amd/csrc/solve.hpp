@@ -380,9 +380,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                 const int wdt = a.sell.width[gsl];
                 const int base = a.sell.start[gsl] * kWave + lane;
                 double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-                for (int q = 0; q < wdt; ++q)
-                    acc = cfma(a.sell.val[base + q * kWave], Xv[a.sell.col[base + q * kWave]], acc);
+                acc = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Xv[j]; }, acc);
                 if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
                 else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
                 const double2 v = REG ? V[k % KR] : Xv[il];
@@ -443,9 +441,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                 const int wdt = a.sell.width[gsl];
                 const int base = a.sell.start[gsl] * kWave + lane;
                 double2 h = make_double2(0.0, 0.0);
-#pragma unroll 4
-                for (int q = 0; q < wdt; ++q)
-                    h = cfma(a.sell.val[base + q * kWave], Xw[a.sell.col[base + q * kWave]], h);
+                h = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Xw[j]; }, h);
                 if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
                 else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
                 double2 v, ai;
@@ -657,8 +653,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 const int wdt = swidth[gsl];
                 const int base = sstart[gsl] * kWave + lane;
                 double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-                for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], Xv[scol[base + q * kWave]], acc);
+                acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return Xv[j]; }, acc);
                 if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
                 else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
                 const double2 v = Xv[il];
@@ -712,8 +707,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 const int wdt = swidth[gsl];
                 const int base = sstart[gsl] * kWave + lane;
                 double2 h = make_double2(0.0, 0.0);
-#pragma unroll 4
-                for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], Xw[scol[base + q * kWave]], h);
+                h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return Xw[j]; }, h);
                 if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
                 else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
                 const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
@@ -878,8 +872,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     const int wdt = swidth[gsl];
                     const int base = sstart[gsl] * kWave + lane;
                     double2 acc = make_double2(0.0, 0.0);
-#pragma unroll 4
-                    for (int q = 0; q < wdt; ++q) acc = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], acc);
+                    acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, acc);
                     if (il == of) acc = csub(acc, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
                     else if (il == ot) acc = csub(acc, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
                     const double2 v = X[il];
@@ -947,8 +940,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     const int wdt = swidth[gsl];
                     const int base = sstart[gsl] * kWave + lane;
                     double2 h = make_double2(0.0, 0.0);
-#pragma unroll 4
-                    for (int q = 0; q < wdt; ++q) h = cfma(sval[base + q * kWave], X[scol[base + q * kWave]], h);
+                    h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, h);
                     if (il == of) h = csub(h, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
                     else if (il == ot) h = csub(h, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
                     double2 v;
