@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace dpf {
 
@@ -41,29 +42,50 @@ __device__ __forceinline__ double2 cfma(double2 a, double2 b, double2 acc) {
 
 // acc + the products of one sliced-ELL row (entries base + q*kWave, q < w, w the
 // same in every lane of the wave) with the exchange vector get(col), added in
-// entry order as a plain loop adds them.  The loads of U entries are issued
-// together, the last group predicated: a row of up to U entries waits for the
-// cache once, and a longer one once per U entries (a loop unrolled by U with a
-// remainder loop waits once per remainder entry).
-template <int U, typename Get>
+// entry order as a plain loop adds them.  Entries go in groups of U whose loads
+// are issued together, the last, partial group predicated instead of being left
+// to a remainder loop: a row of up to U entries waits for the cache once and a
+// longer one once per U entries (a loop unrolled by U with a remainder loop waits
+// once per remainder entry).  Two forms, each the faster one where it is used:
+//  - JOINT (kernels with few waves per CU and registers to spare): full groups
+//    run unpredicated, and the gathers of a group are issued together (a missing
+//    entry of the last group gathers the lane's own row `own`, always a valid
+//    column, and adds nothing);
+//  - otherwise (1024-thread kernels, where other waves hide the gathers and
+//    registers are short): every group predicated, each gather in its own step.
+template <int U, bool JOINT, typename Get>
 __device__ __forceinline__ double2 sell_row(const double2 *__restrict__ val, const int32_t *__restrict__ col,
-                                            int base, int w, Get get, double2 acc) {
-    for (int q0 = 0; q0 < w; q0 += U) {
+                                            int base, int w, int own, Get get, double2 acc) {
+    auto group = [&](int q0, auto full) {
+        constexpr bool FULL = decltype(full)::value;
         double2 v[U];
         int32_t cc[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             v[u] = make_double2(0.0, 0.0);
-            cc[u] = 0;
-            if (q0 + u < w) {
+            cc[u] = own;
+            if (FULL || q0 + u < w) {
                 v[u] = val[base + (q0 + u) * kWave];
                 cc[u] = col[base + (q0 + u) * kWave];
             }
         }
+        if constexpr (JOINT) {
+            double2 x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-            if (q0 + u < w) acc = cfma(v[u], get(cc[u]), acc);
-    }
+            for (int u = 0; u < U; ++u) x[u] = get(cc[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (FULL || q0 + u < w) acc = cfma(v[u], x[u], acc);
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (FULL || q0 + u < w) acc = cfma(v[u], get(cc[u]), acc);
+        }
+    };
+    int q0 = 0;
+    if constexpr (JOINT)
+        for (; q0 + U <= w; q0 += U) group(q0, std::true_type{});
+    for (; q0 < w; q0 += U) group(q0, std::false_type{});
     return acc;
 }
 

@@ -380,7 +380,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                 const int wdt = a.sell.width[gsl];
                 const int base = a.sell.start[gsl] * kWave + lane;
                 double2 acc = make_double2(0.0, 0.0);
-                acc = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Xv[j]; }, acc);
+                acc = sell_row<4, true>(a.sell.val, a.sell.col, base, wdt, il, [&](int j) { return Xv[j]; }, acc);
                 if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
                 else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
                 const double2 v = REG ? V[k % KR] : Xv[il];
@@ -441,7 +441,7 @@ __global__ __launch_bounds__(NT) void team_solve_kernel(SolveArgs a) {
                 const int wdt = a.sell.width[gsl];
                 const int base = a.sell.start[gsl] * kWave + lane;
                 double2 h = make_double2(0.0, 0.0);
-                h = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Xw[j]; }, h);
+                h = sell_row<4, true>(a.sell.val, a.sell.col, base, wdt, il, [&](int j) { return Xw[j]; }, h);
                 if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
                 else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
                 double2 v, ai;
@@ -653,7 +653,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 const int wdt = swidth[gsl];
                 const int base = sstart[gsl] * kWave + lane;
                 double2 acc = make_double2(0.0, 0.0);
-                acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return Xv[j]; }, acc);
+                acc = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return Xv[j]; }, acc);
                 if (il == of) acc = csub(acc, csub(cmul(oyd, Xv[of]), cmul(oy, Xv[ot])));
                 else if (il == ot) acc = csub(acc, csub(cmul(oyd, Xv[ot]), cmul(oy, Xv[of])));
                 const double2 v = Xv[il];
@@ -707,7 +707,7 @@ __global__ __launch_bounds__(NT) void team_solve_stream_kernel(SolveArgs a) {
                 const int wdt = swidth[gsl];
                 const int base = sstart[gsl] * kWave + lane;
                 double2 h = make_double2(0.0, 0.0);
-                h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return Xw[j]; }, h);
+                h = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return Xw[j]; }, h);
                 if (il == of) h = csub(h, csub(cmul(oyd, Xw[of]), cmul(oy, Xw[ot])));
                 else if (il == ot) h = csub(h, csub(cmul(oyd, Xw[ot]), cmul(oy, Xw[of])));
                 const double2 G = make_double2(ai.x + h.x, ai.y - h.y);
@@ -872,7 +872,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     const int wdt = swidth[gsl];
                     const int base = sstart[gsl] * kWave + lane;
                     double2 acc = make_double2(0.0, 0.0);
-                    acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, acc);
+                    acc = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return X[j]; }, acc);
                     if (il == of) acc = csub(acc, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
                     else if (il == ot) acc = csub(acc, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
                     const double2 v = X[il];
@@ -940,7 +940,7 @@ __global__ __launch_bounds__(NT) void team_solve_band_kernel(SolveArgs a) {
                     const int wdt = swidth[gsl];
                     const int base = sstart[gsl] * kWave + lane;
                     double2 h = make_double2(0.0, 0.0);
-                    h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, h);
+                    h = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return X[j]; }, h);
                     if (il == of) h = csub(h, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
                     else if (il == ot) h = csub(h, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
                     double2 v;

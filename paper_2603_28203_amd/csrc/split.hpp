@@ -295,7 +295,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 acc = make_double2(0.0, 0.0);
-            acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, acc);
+            acc = sell_row<4, true>(sval, scol, base, wdt, il, [&](int j) { return X[j]; }, acc);
             if (il == of) acc = csub(acc, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
             else if (il == ot) acc = csub(acc, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
             const double2 v = X[il];
@@ -389,7 +389,7 @@ __global__ __launch_bounds__(NT) void team_solve_split_kernel(SolveArgs a, Split
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 h = make_double2(0.0, 0.0);
-            h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return X[j]; }, h);
+            h = sell_row<4, true>(sval, scol, base, wdt, il, [&](int j) { return X[j]; }, h);
             if (il == of) h = csub(h, csub(cmul(oyd, X[of]), cmul(oy, X[ot])));
             else if (il == ot) h = csub(h, csub(cmul(oyd, X[ot]), cmul(oy, X[of])));
             double2 v;

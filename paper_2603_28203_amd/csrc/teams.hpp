@@ -475,7 +475,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 acc = make_double2(0.0, 0.0);
-            acc = sell_row<4>(sval, scol, base, wdt, [&](int j) { return xat(j, rV); }, acc);
+            acc = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return xat(j, rV); }, acc);
             if (il == of) acc = csub(acc, csub(cmul(oyd, xat(of, rV)), cmul(oy, xat(ot, rV))));
             else if (il == ot) acc = csub(acc, csub(cmul(oyd, xat(ot, rV)), cmul(oy, xat(of, rV))));
             const double2 v = xat(il, rV);
@@ -547,7 +547,7 @@ __device__ __forceinline__ void team_member(const SolveArgs &a, const TeamArgs &
             const int wdt = swidth[gsl];
             const int base = sstart[gsl] * kWave + lane;
             double2 h = make_double2(0.0, 0.0);
-            h = sell_row<4>(sval, scol, base, wdt, [&](int j) { return xat(j, rW); }, h);
+            h = sell_row<4, false>(sval, scol, base, wdt, il, [&](int j) { return xat(j, rW); }, h);
             if (il == of) h = csub(h, csub(cmul(oyd, xat(of, rW)), cmul(oy, xat(ot, rW))));
             else if (il == ot) h = csub(h, csub(cmul(oyd, xat(ot, rW)), cmul(oy, xat(of, rW))));
             // V of this row, rebuilt from |V| and theta (the same bits the owner published)

@@ -195,7 +195,7 @@ __global__ __launch_bounds__(256) void wide_phase_a_kernel(WideArgs a) {
         const int wdt = a.sell.width[w.g];
         const int base = a.sell.start[w.g] * kWave + lane;
         double2 acc = make_double2(0.0, 0.0);
-        acc = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Vc[w.lo + j]; }, acc);
+        acc = sell_row<4, true>(a.sell.val, a.sell.col, base, wdt, r - w.lo, [&](int j) { return Vc[w.lo + j]; }, acc);
         acc = csub(acc, wide_outage_term(a, w.c, r, Vc));
         const int8_t tk = a.bt[r];
         const double2 v = Vc[r];
@@ -297,7 +297,7 @@ __global__ __launch_bounds__(256) void wide_phase_b_kernel(WideArgs a) {
     const int wdt = a.sell.width[w.g];
     const int base = a.sell.start[w.g] * kWave + lane;
     double2 h = make_double2(0.0, 0.0);
-    h = sell_row<4>(a.sell.val, a.sell.col, base, wdt, [&](int j) { return Wc[w.lo + j]; }, h);
+    h = sell_row<4, true>(a.sell.val, a.sell.col, base, wdt, r - w.lo, [&](int j) { return Wc[w.lo + j]; }, h);
     h = csub(h, wide_outage_term(a, w.c, r, Wc));
     const int64_t o = (int64_t)w.c * a.ld + r;
     const double2 ai = a.aIg[o];
